@@ -1,0 +1,264 @@
+/*
+ * sblm.h -- C ABI of libsblm: batched fitness evaluation and evolutionary
+ * fitting of static binary-lens (SBLM) point-source microlensing lightcurves
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Rajpaul (2012), "Evolutionary algorithm-based
+ * analysis of gravitational microlensing lightcurves":
+ *   - forward model: source trajectory (Sec. 2.2, Eq. sourcePos and the
+ *     dimensionless time tau), the binary lens equation (Eq. lensing), its
+ *     fifth-order complex polynomial form (Eq. lensingPoly), rejection of the
+ *     two spurious roots by substitution into the lens equation, and the
+ *     magnification A = sum_i 1/|det J_i| (Sec. 2.2, per-image amplification);
+ *   - fitness: chi^2 (Sec. 4.1) of the blended flux model F = Fs*A + Fb
+ *     (Sec. 4.4, Eq. blend, with Fs and Fb obtained by linear least squares);
+ *   - optimiser: the array-style evolutionary algorithm of Appendix A
+ *     (initialisation A.1, encoding A.2, ranking A.3, tournament selection
+ *     A.4, reproduction with elitism A.5, creep and jump mutation A.6,
+ *     stagnation handling and restarts A.7).
+ *
+ * Conventions shared by every entry point
+ *   - Parameter vector theta (decoded, physical), always stored as six
+ *     contiguous planes (structure of arrays), plane j holding parameter j of
+ *     every individual:
+ *        j = 0  log10 q   mass ratio secondary/primary, q = 10^(log10 q)
+ *        j = 1  d         lens separation (paper's a), primary-theta_E units
+ *        j = 2  u0        impact parameter (paper's b) w.r.t. the primary
+ *        j = 3  alpha     trajectory angle (paper's theta), radians
+ *        j = 4  tE        Einstein crossing time, days
+ *        j = 5  t0        time of closest approach to the primary (paper's
+ *                         t_m), days
+ *     Origin at the primary lens, secondary on the +x axis at z = d.
+ *   - All array arguments are DEVICE pointers on the current HIP device
+ *     unless stated otherwise; the caller owns them and keeps them alive
+ *     until the work queued on `stream` has completed.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     Every call only enqueues work and returns; results are valid once the
+ *     stream has been synchronised.
+ *   - Every call returns an sblm_status.  Argument errors are detected on the
+ *     host before anything is launched; nothing aborts or throws across the
+ *     ABI.  sblm_last_error() returns a thread-local message describing the
+ *     last failure of the calling thread.
+ *   - Numerical events (a degree drop of the lens polynomial, an iteration
+ *     cap reached, a degenerate least-squares system, NaN fitness) are not
+ *     errors; they are counted in the optional sblm_stats block.
+ */
+#ifndef SBLM_H
+#define SBLM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SBLM_OK = 0,
+  SBLM_EINVAL = -1,  /* bad argument (null pointer, size out of range)     */
+  SBLM_EDEVICE = -2, /* a HIP runtime call or kernel launch failed          */
+  SBLM_ENOMEM = -3,  /* device allocation failed (ea_create only)           */
+  SBLM_ESTATE = -4,  /* state object invalid or snapshot does not match     */
+  SBLM_ERANGE = -5   /* size beyond a documented limit                      */
+} sblm_status;
+
+typedef enum {
+  SBLM_FP64 = 0,  /* root solve, polish, image test, det J and chi^2 in FP64 */
+  SBLM_MIXED = 1  /* FP32 root solve, FP64 polish / image test / det J / chi^2 */
+} sblm_mode;
+
+#define SBLM_NPAR 6
+
+/* Device-side counters of numerical events, accumulated (not reset) by every
+ * call that receives a non-NULL pointer.  64-bit device integers. */
+typedef struct {
+  unsigned long long n_solves;     /* polynomials solved                      */
+  unsigned long long n_iter;       /* simultaneous-iteration sweeps, summed   */
+  unsigned long long n_capped;     /* solves that hit the iteration cap       */
+  unsigned long long n_fallback;   /* MIXED: lanes re-solved in FP64          */
+  unsigned long long n_degree4;    /* leading coefficient negligible          */
+  unsigned long long n_degenerate; /* chi^2 fits with a singular 2x2 system   */
+} sblm_stats;
+
+/* Ragged batch of lightcurves in CSR form.  Lightcurve k owns epochs
+ * [off[k], off[k+1]) of t, y and w.  off is a DEVICE array of n_lc+1
+ * non-decreasing int64 values with off[0] = 0; t in days, y the observed
+ * flux, w = 1/sigma^2 the statistical weight (w >= 0). */
+typedef struct {
+  int32_t n_lc;
+  const int64_t* off;
+  const double* t;
+  const double* y;
+  const double* w;
+} sblm_lcs;
+
+/*
+ * sblm_magnify -- magnification of every (individual, epoch) pair.
+ * Defines: Sec. 2.2 (Eq. sourcePos, tau, Eq. lensing, Eq. lensingPoly, the
+ * spurious-root elimination and the per-image amplification, with det J
+ * = 1 - |1/conj(z)^2 + q/(d - conj(z))^2|^2).
+ *   theta  [6][n]      decoded parameters (layout above)
+ *   n      individuals, 1 <= n <= 2^26
+ *   t      [n_t]       epochs (days), shared by all individuals
+ *   n_t    epochs, 0 <= n_t <= 2^24 (n_t = 0 is a no-op)
+ *   mode   SBLM_FP64 or SBLM_MIXED
+ *   A      [n][n_t]    out: total magnification of the accepted images
+ *   n_img  [n][n_t]    out (nullable): accepted image count, 3 or 5
+ *   stats  (nullable)  device counters, see sblm_stats
+ * Errors: SBLM_EINVAL for null theta/t/A with n_t > 0, n < 1 or a bad mode;
+ * SBLM_ERANGE for sizes beyond the limits; SBLM_EDEVICE on launch failure.
+ */
+int sblm_magnify(const double* theta, int64_t n, const double* t, int64_t n_t,
+                 int mode, double* A, int8_t* n_img, sblm_stats* stats,
+                 void* stream);
+
+/*
+ * sblm_chi2 -- fitness of a population against a ragged batch.
+ * Defines: Sec. 4.1 (chi^2 minimisation) with the blend model of Sec. 4.4
+ * (Eq. blend) written in flux, F_k = Fs*A_k + Fb, Fs and Fb profiled by the
+ * weighted linear least-squares solution for every individual:
+ *     chi2 = min_{Fs,Fb} sum_k w_k (y_k - Fs*A_k - Fb)^2.
+ * If the 2x2 normal matrix is singular to 1e-14 relative
+ * (det <= 1e-14 * sum(wA^2) * sum(w)), the fit falls back to Fs = 0,
+ * Fb = weighted mean of y.
+ *   lcs    ragged lightcurves (device CSR, see sblm_lcs); 1 <= n_lc <= 2^20,
+ *          every lightcurve at most 2^20 epochs
+ *   theta  [6][n_lc*pop] decoded parameters; individual i is fitted to
+ *          lightcurve i / pop
+ *   pop    individuals per lightcurve, 1 <= pop <= 65536
+ *   mode   SBLM_FP64 or SBLM_MIXED
+ *   chi2, Fs, Fb  [n_lc*pop] out
+ *   stats  (nullable)  device counters
+ * An empty lightcurve gives chi2 = 0, Fs = 0, Fb = 0.
+ * Errors: SBLM_EINVAL (null pointers, n_lc < 1, pop < 1, bad mode),
+ * SBLM_ERANGE, SBLM_EDEVICE.
+ */
+int sblm_chi2(const sblm_lcs* lcs, const double* theta, int32_t pop, int mode,
+              double* chi2, double* Fs, double* Fb, sblm_stats* stats,
+              void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Evolutionary algorithm (Appendix A)                                     */
+/* ---------------------------------------------------------------------- */
+
+/* Random numbers.  Every random draw of the EA is one 64-bit word of the
+ * Philox4x64-10 counter-based generator (Salmon, Moraes, Dror & Shaw 2011)
+ * with key = (seed, lightcurve index) and counter = (generation, purpose,
+ * row, j / 4), word j % 4.  Purposes: 1 initialisation (row = individual,
+ * j = gene), 2 tournament (row = pairing, j = draw), 3 crossover mode and
+ * weights (row = pairing, j = 0 mode, 1 + g weight of gene g), 4 creep
+ * (row = offspring, j = 2g sign, 2g + 1 step), 5 jump (row = offspring,
+ * j = 2g trigger, 2g + 1 new value).  A word x maps to the open unit
+ * interval as ((x >> 12) + 0.5) * 2^-52 and to {0..n-1} as
+ * ((x >> 32) * n) >> 32. */
+#define EA_PURPOSE_INIT 1
+#define EA_PURPOSE_TOURN 2
+#define EA_PURPOSE_MODE 3
+#define EA_PURPOSE_CREEP 4
+#define EA_PURPOSE_JUMP 5
+
+typedef struct {
+  int32_t pop;           /* N_pop, 2 <= pop <= 1024                        */
+  int32_t n_tourn;       /* N_tourn; 0 selects ceil(pop / 25) (Sec. A.4)    */
+  double p_mut0;         /* initial jump probability (Sec. A.6), e.g. 0.01 */
+  double p_mut_min;      /* floor of the throttled probability             */
+  double p_mut_max;      /* ceiling of the boosted probability             */
+  double stag_frac;      /* relative improvement threshold (Sec. A.7), 0.01 */
+  int32_t stag_window;   /* generations looked back (Sec. A.7), 10         */
+  int32_t restart_after; /* consecutive stagnation flags before a restart  */
+  double lo[SBLM_NPAR];  /* Omega_j = [lo_j, hi_j] (Sec. A.2)              */
+  double hi[SBLM_NPAR];
+  int32_t mode;          /* sblm_mode used by ea_fit's fitness evaluation  */
+} ea_config;
+
+/* Fills cfg with the defaults used by this library: pop 256, N_tourn =
+ * ceil(pop/25), p_mut0 0.01, p_mut in [1e-4, 0.5], 1% over 10 generations,
+ * restart after 10 consecutive flags, Omega = {log10 q in [-3,0], d in
+ * [0.5,2], u0 in [0,0.5], alpha in [0,2pi], tE in [10,100], t0 in [-10,10]},
+ * FP64 fitness.  Host pointer. */
+void ea_default_config(ea_config* cfg);
+
+typedef struct ea_state ea_state; /* opaque */
+
+/* Per-lightcurve summary, host-side copy (ea_summary). */
+typedef struct {
+  double best_chi2;      /* best chi^2 seen since ea_create (all restarts) */
+  double best_Fs, best_Fb;
+  double best_theta[SBLM_NPAR]; /* decoded parameters of that individual  */
+  int64_t best_gen;      /* generation at which it was first seen         */
+  double p_mut;          /* current jump probability                      */
+  int32_t stag_count;    /* consecutive stagnation flags                  */
+  int32_t n_restarts;
+  int64_t gen;           /* generations completed                         */
+  int64_t gen_restart;   /* first generation of the current sequence      */
+} ea_lc_summary;
+
+/*
+ * ea_create -- allocate the device workspace of a fit of lcs->n_lc
+ * independent lightcurves and initialise generation 0 (Sec. A.1: rows
+ * i < pop/2 uniform, row i + pop/2 = 1 - row i, an odd last row uniform).
+ *   cfg    host pointer, validated (pop range, lo < hi, 0 < p_mut, ...)
+ *   lcs    host pointer to a descriptor of device CSR arrays; the arrays
+ *          must stay alive and unchanged for the life of the state
+ *   seed   64-bit seed (Philox key word 0)
+ *   out    host pointer receiving the new state
+ * The only entry point that allocates device memory.  Errors: SBLM_EINVAL,
+ * SBLM_ERANGE, SBLM_ENOMEM, SBLM_EDEVICE.
+ */
+int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t seed,
+              ea_state** out);
+
+/*
+ * ea_generation -- one generation of Appendix A after the fitness of the
+ * current population is known: rank (stable, NaN ranks last), update the
+ * best-ever record, fill rows 1..pop-1 with offspring of tournament-selected
+ * pairs (row 0 keeps the fittest individual), apply creep then jump mutation
+ * to every offspring gene, then the stagnation test, the p_mut update and a
+ * restart when the flags have repeated restart_after times.
+ *   chi2, Fs, Fb  [n_lc*pop] device, fitness of the current population in
+ *          its current row order (as written by sblm_chi2 or ea_evaluate)
+ * Errors: SBLM_EINVAL, SBLM_ESTATE, SBLM_EDEVICE.
+ */
+int ea_generation(ea_state* st, const double* chi2, const double* Fs,
+                  const double* Fb, void* stream);
+
+/* ea_evaluate -- decode the current population (Eq. EMMA-encoding) and
+ * write its fitness into the state's own chi2/Fs/Fb buffers (the same
+ * computation as sblm_chi2 in cfg->mode). */
+int ea_evaluate(ea_state* st, sblm_stats* stats, void* stream);
+
+/*
+ * ea_fit -- run n_gen generations, each = ea_evaluate + ea_generation on the
+ * state's own buffers, replayed from one captured HIP graph.
+ *   n_gen  >= 0
+ * Errors: SBLM_EINVAL, SBLM_ESTATE, SBLM_EDEVICE.
+ */
+int ea_fit(ea_state* st, int32_t n_gen, sblm_stats* stats, void* stream);
+
+/* Device pointers into the state (valid until ea_destroy):
+ * P [6][n_lc*pop] encoded population, chi2/Fs/Fb [n_lc*pop] the buffers
+ * ea_evaluate writes.  Any pointer argument may be NULL. */
+int ea_buffers(ea_state* st, double** P, double** chi2, double** Fs,
+               double** Fb);
+
+/* Copies the per-lightcurve summaries to host memory out[n_lc].
+ * Synchronises `stream`. */
+int ea_summary(ea_state* st, ea_lc_summary* out, void* stream);
+
+/* Snapshot of the whole state (config, seed, population and per-lightcurve
+ * records) into host memory.  With buf == NULL, *len receives the size.
+ * Synchronises `stream`.  ea_load restores a snapshot into a state created
+ * with the same config, lightcurve count and seed; the continued run is
+ * bit-identical to an uninterrupted one. */
+int ea_save(ea_state* st, void* buf, size_t* len, void* stream);
+int ea_load(ea_state* st, const void* buf, size_t len, void* stream);
+
+void ea_destroy(ea_state* st);
+
+/* Thread-local description of the last error of this thread. */
+const char* sblm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SBLM_H */

@@ -1,0 +1,295 @@
+"""Pins of the FP64 oracle's forward model and chi^2 against facts fixed by
+the physics and mathematics of Sec. 2.2 / Sec. 4.4 (not against itself)."""
+import mpmath
+import numpy as np
+import pytest
+
+import oracle as O
+
+
+def paczynski(u):
+    """Single point-lens magnification (textbook closed form)."""
+    return (u * u + 2.0) / (u * np.sqrt(u * u + 4.0))
+
+
+# ---------------------------------------------------------------- trajectory
+
+def test_source_position_closed_form():
+    # |zeta|^2 = tau^2 + u0^2 for a straight trajectory at impact u0, and
+    # zeta(t0) = u0 exp(i alpha) (Eq. sourcePos)
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        t, u0, al, tE, t0 = rng.uniform(-50, 50), rng.uniform(0, 1), rng.uniform(0, 6.3), \
+            rng.uniform(5, 100), rng.uniform(-20, 20)
+        z = O.source_position(t, u0, al, tE, t0)
+        tau = (t - t0) / tE
+        assert abs(abs(z) ** 2 - (tau * tau + u0 * u0)) < 1e-12 * (1 + tau * tau)
+        z0 = O.source_position(t0, u0, al, tE, t0)
+        assert abs(z0 - u0 * np.exp(1j * al)) < 1e-15
+
+
+# ---------------------------------------------------------------- polynomial
+
+def test_leading_coefficient_identity():
+    # the z^5 coefficient of (zeta - z) N (N - dD) is -conj(zeta) (conj(zeta) - d)
+    rng = np.random.default_rng(4)
+    for _ in range(100):
+        zeta = complex(*rng.uniform(-2, 2, 2))
+        d, q = rng.uniform(0.5, 2), 10 ** rng.uniform(-3, 0)
+        c = O.lens_poly(zeta, d, q)
+        w = np.conj(zeta)
+        assert abs(c[5] - (-w * (w - d))) < 1e-14 * (1 + abs(c[5]))
+
+
+def test_q0_factorisation():
+    # at q = 0 the quintic factors as (z-d)^2 (w z + 1 - d z)(-w z^2 + |zeta|^2 z + zeta)
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        zeta = complex(*rng.uniform(-2, 2, 2))
+        d = rng.uniform(0.5, 2)
+        w = np.conj(zeta)
+        f = np.polymul(np.polymul([1, -2 * d, d * d], [w - d, 1]),
+                       [-w, abs(zeta) ** 2, zeta])  # highest power first
+        c = O.lens_poly(zeta, d, 0.0)
+        assert np.allclose(c[::-1], f, rtol=0, atol=1e-13 * np.max(np.abs(f)))
+
+
+def test_forward_substitution():
+    # any z off the lenses is an image of zeta := lens map(z): z must be a
+    # root of the polynomial and one of the accepted images
+    rng = np.random.default_rng(6)
+    for _ in range(1500):
+        d, q = rng.uniform(0.5, 2), 10 ** rng.uniform(-3, 0)
+        z = complex(*rng.uniform(-2.5, 2.5, 2))
+        if min(abs(z), abs(z - d)) < 0.05:
+            continue
+        zb = np.conj(z)
+        zeta = z - 1 / zb + q / (d - zb)
+        c = O.lens_poly(zeta, d, q)
+        scale = np.sum(np.abs(c) * abs(z) ** np.arange(6))
+        assert abs(np.polyval(c[::-1], z)) <= 1e-13 * scale
+        imgs, _, _ = O.images(zeta, d, q)
+        assert np.min(np.abs(imgs - z)) < 1e-8 * max(1.0, abs(z))
+
+
+def test_roots_against_lapack_and_mpmath():
+    # companion-matrix eigenvalues (LAPACK) and 40-digit mpmath roots
+    rng = np.random.default_rng(7)
+    mpmath.mp.dps = 40
+    for k in range(60):
+        if k % 2:
+            c = rng.normal(size=6) + 1j * rng.normal(size=6)
+        else:
+            zeta = complex(*rng.uniform(-1.5, 2.5, 2))
+            c = O.lens_poly(zeta, rng.uniform(0.5, 2), 10 ** rng.uniform(-3, 0))
+        r = O.poly_roots(c)
+        ref = np.roots(c[::-1])
+        assert np.max(np.min(np.abs(r[:, None] - ref[None, :]), axis=1)) < 1e-8
+        exact = mpmath.polyroots([mpmath.mpc(x.real, x.imag) for x in c[::-1]],
+                                 maxsteps=200, extraprec=200)
+        exact = np.array([complex(x) for x in exact])
+        # each oracle root matches a distinct exact root
+        dist = np.abs(r[:, None] - exact[None, :])
+        assert sorted(np.argmin(dist, axis=1).tolist()) == list(range(5))
+        assert np.max(np.min(dist, axis=1)) < 1e-11 * max(1.0, np.max(np.abs(exact)))
+
+
+# ---------------------------------------------------------------- images / A
+
+def test_q0_images_give_paczynski():
+    # at q = 0 the two roots that satisfy the lens equation are the single
+    # lens images and sum 1/|det J| is the point-lens magnification
+    d = 1.3
+    for u in (0.02, 0.05, 0.3, 1.0, 2.0, 5.0):
+        for ang in (0.0, 0.7, 2.5):
+            zeta = u * np.exp(1j * ang)
+            c = O.lens_poly(zeta, d, 0.0)
+            roots = O.poly_roots(c)
+            zb = np.conj(roots)
+            res = np.abs(zeta - roots + 1 / zb)
+            true = roots[res < 1e-10]
+            assert true.size == 2
+            A = np.sum(1 / np.abs(1 - 1 / np.abs(true) ** 4))
+            # coefficient rounding moves the roots by ~1e-15 relative; near
+            # the Einstein ring that is amplified by ~A^2
+            assert abs(A / paczynski(u) - 1) < 1e-13 * max(10.0, A * A)
+
+
+@pytest.mark.parametrize("u", [0.05, 0.3, 1.0, 2.0])
+def test_small_q_paczynski_limit(u):
+    # A -> A_pac as q -> 0, with a deviation linear in q
+    d, ang = 1.3, 0.7
+    zeta = u * np.exp(1j * ang)
+    dev = []
+    for q in (1e-6, 1e-5, 1e-4):
+        A, n = O.point_magnification(zeta, d, q)
+        assert n == 3
+        dev.append(A / paczynski(u) - 1)
+    assert abs(dev[0]) < 20e-6
+    # first order in q: deviations scale by 10 per decade of q
+    assert abs(dev[1] / dev[0] - 10) < 0.05 and abs(dev[2] / dev[1] - 10) < 0.5
+
+
+def test_index_theorem_and_image_count():
+    # two point lenses: negative-parity images outnumber positive ones by 1;
+    # image count is 3 or 5; A >= 1, and A >= 3 with five images; with five
+    # images sum_i 1/det J_i = 1 (Witt & Mao 1995)
+    rng = np.random.default_rng(8)
+    n5 = 0
+    for _ in range(4000):
+        d, q = rng.uniform(0.5, 2), 10 ** rng.uniform(-3, 0)
+        zeta = complex(rng.uniform(-1.0, d + 0.5), rng.uniform(-0.8, 0.8))
+        imgs, dj, _ = O.images(zeta, d, q)
+        assert len(imgs) in (3, 5)
+        assert np.sum(dj < 0) - np.sum(dj > 0) == 1
+        A = np.sum(1 / np.abs(dj))
+        assert A >= 1.0
+        if len(imgs) == 5:
+            n5 += 1
+            assert A >= 3.0
+            assert abs(np.sum(1 / dj) - 1) < 1e-8
+    assert n5 > 20
+
+
+def test_symmetries():
+    rng = np.random.default_rng(9)
+    for _ in range(300):
+        d, q = rng.uniform(0.5, 2), 10 ** rng.uniform(-3, 0)
+        zeta = complex(rng.uniform(-1, 2.5), rng.uniform(-1, 1))
+        A, n = O.point_magnification(zeta, d, q)
+        A2, n2 = O.point_magnification(np.conj(zeta), d, q)
+        assert n == n2 and abs(A2 / A - 1) < 1e-9
+        # equal masses: mirror symmetry about x = d/2
+        A3, n3 = O.point_magnification(zeta, d, 1.0)
+        A4, n4 = O.point_magnification(d - np.conj(zeta), d, 1.0)
+        assert n3 == n4 and abs(A4 / A3 - 1) < 1e-9
+
+
+def test_far_field():
+    # far from the lenses the primary-plane image gains (1+q)^2/|zeta|^4 and
+    # the faint image beside each lens of mass m adds m^2/|zeta|^4, so
+    # A - 1 -> ((1+q)^2 + 1 + q^2) / |zeta|^4 (distances from the centre of mass)
+    for q in (1e-3, 0.1, 1.0):
+        for r in (60.0, 120.0):
+            zeta = r * np.exp(0.3j) + 0.5
+            A, n = O.point_magnification(zeta, 1.0, q)
+            approx = ((1 + q) ** 2 + 1 + q * q) / abs(zeta - q / (1 + q)) ** 4
+            assert n == 3 and abs((A - 1) / approx - 1) < 0.01
+
+
+def test_inverse_ray_shooting():
+    # brute force: shoot a uniform ray grid through the lens equation and
+    # count rays landing in a small source disc; away from caustics this is
+    # the point-source magnification to within the disc averaging (~1-2%)
+    h, rho = 0.002, 0.02
+    cases = [(1.2, 0.5, 0.3 + 0.25j), (0.8, 0.05, 0.15 - 0.3j), (1.6, 1.0, 1.1 + 0.45j)]
+    for d, q, zeta in cases:
+        imgs, dj, _ = O.images(zeta, d, q)
+        assert np.min(np.abs(dj)) > 0.2  # not near a critical curve
+        A_pt = np.sum(1 / np.abs(dj))
+        hits = 0
+        xs = np.arange(-3.0, d + 3.0, h) + h / 2
+        for x0 in range(0, xs.size, 500):
+            X, Y = np.meshgrid(xs[x0:x0 + 500], xs - 1.5 - 0.0, indexing="ij")
+            Z = X + 1j * (Y - (xs.mean() - 1.5 - 0.0) + 0.0)
+            Zb = np.conj(Z)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                S = Z - 1 / Zb + q / (d - Zb)
+            hits += np.count_nonzero(np.abs(S - zeta) < rho)
+        A_rs = hits * h * h / (np.pi * rho * rho)
+        assert abs(A_rs / A_pt - 1) < 0.03, (A_rs, A_pt)
+
+
+def _caustic_winding(d, q, zeta_pts, n_phi=4000):
+    """Total winding number of the caustic curves around each point.
+
+    Tracks the four critical-curve branches continuously in phi (roots of
+    the quartic exp(i phi) z^2 (z-d)^2 - (z-d)^2 - q z^2) and sums the change
+    of arg(caustic - zeta) along all of them (the union is closed)."""
+    phis = np.linspace(0, 2 * np.pi, n_phi + 1)
+    prev = None
+    branches = []
+    for phi in phis:
+        e = np.exp(1j * phi)
+        r = np.roots([e, -2 * d * e, e * d * d - 1 - q, 2 * d, -d * d])
+        if prev is not None:  # continuation: match to the previous roots
+            order = []
+            for p in prev:
+                k = int(np.argmin(np.abs(r - p) + 1e9 * np.isin(np.arange(4), order)))
+                order.append(k)
+            r = r[order]
+        prev = r
+        branches.append(r)
+    Z = np.array(branches)  # [n_phi+1][4]
+    Zb = np.conj(Z)
+    C = Z - 1 / Zb + q / (d - Zb)
+    out = []
+    for zeta in zeta_pts:
+        ang = np.unwrap(np.angle(C - zeta), axis=0)
+        out.append(np.sum(ang[-1] - ang[0]) / (2 * np.pi))
+    return np.array(out)
+
+
+def test_image_count_matches_caustic_winding():
+    # five images exactly where the point lies inside a caustic curve
+    rng = np.random.default_rng(10)
+    for d, q in [(1.0, 1.0), (0.8, 0.3), (1.4, 0.1)]:
+        zc, _ = O.caustic_points(d, q, 40, rng)
+        pts = zc + 0.02 * np.exp(1j * rng.uniform(0, 2 * np.pi, zc.size))
+        pts = np.concatenate([pts, complex(rng.uniform(-0.3, d + 0.3), 0)
+                              + 0.1j * rng.uniform(-1, 1, 40)])
+        wind = _caustic_winding(d, q, pts)
+        for z, wn in zip(pts, wind):
+            _, n = O.point_magnification(z, d, q)
+            assert abs(wn - round(wn)) < 1e-6
+            assert (n == 5) == (round(wn) != 0), (d, q, z, wn, n)
+
+
+# ---------------------------------------------------------------- chi^2
+
+def test_lsq_against_lstsq():
+    rng = np.random.default_rng(11)
+    for _ in range(50):
+        n = int(rng.integers(5, 400))
+        A = 1 + rng.gamma(1.0, 2.0, n)
+        w = rng.uniform(0.5, 2.0, n) * 1e4
+        y = 0.8 * A + 0.3 + rng.normal(size=n) / np.sqrt(w)
+        c2, fs, fb = O.lsq_chi2(A, y, w)
+        sw = np.sqrt(w)
+        X = np.stack([A * sw, sw], 1)
+        sol, res, *_ = np.linalg.lstsq(X, y * sw, rcond=None)
+        assert abs(fs - sol[0]) < 1e-9 * abs(sol[0]) + 1e-12
+        assert abs(fb - sol[1]) < 1e-9 * max(abs(sol[1]), 1e-3)
+        assert abs(c2 - res[0]) < 1e-9 * res[0]
+
+
+def test_noise_free_recovery_and_degenerate_fallback():
+    rng = np.random.default_rng(12)
+    A = 1 + rng.gamma(1.0, 2.0, 300)
+    w = np.full(300, 1e4)
+    c2, fs, fb = O.lsq_chi2(A, 1.0 * A + 0.25, w)
+    assert c2 < 1e-18 * np.sum(w) and abs(fs - 1) < 1e-12 and abs(fb - 0.25) < 1e-12
+    # constant magnification: singular normal matrix -> Fs = 0, Fb = mean y
+    y = rng.normal(size=300)
+    c2, fs, fb = O.lsq_chi2(np.full(300, 1.7), y, w)
+    assert fs == 0.0 and abs(fb - y.mean()) < 1e-12
+    assert abs(c2 - np.sum(w * (y - y.mean()) ** 2)) < 1e-9 * c2
+    # empty lightcurve
+    assert O.lsq_chi2(np.zeros(0), np.zeros(0), np.zeros(0)) == (0.0, 0.0, 0.0)
+
+
+def test_batched_chi2_matches_single():
+    from paper_1208_4830_amd import inputs
+    wl = inputs.uniform_workload(1, 3, 50)
+    rng = np.random.default_rng(13)
+    pop = 4
+    th = inputs.draw_theta(rng, 3 * pop)
+    w = np.ones(wl.t.size)
+    y = rng.normal(size=wl.t.size) + 2
+    c, fs, fb = O.chi2(wl.off, wl.t, y, w, th, pop, nthreads=3)
+    for i in range(3 * pop):
+        lc = i // pop
+        sl = slice(wl.off[lc], wl.off[lc + 1])
+        A, _ = O.magnify(th[:, i:i + 1], wl.t[sl], nthreads=1)
+        ref = O.lsq_chi2(A[0], y[sl], w[sl])
+        assert (c[i], fs[i], fb[i]) == ref
