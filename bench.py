@@ -1,0 +1,226 @@
+"""Benchmark of the batched binary-lens fitness + EA generation on one MI355X.
+
+Workload (the batched FP64 fitting configuration): 256 synthetic lightcurves
+of 1000 uniform epochs over t0 +- 2 tE (sigma = 1% of the flux), population
+256 per lightcurve.  A step is one generation of the whole hot path for the
+whole batch: decode, magnification of all 256 x 256 x 1000 (individual,
+epoch) pairs, least-squares fluxes and chi^2, then the EA generation, replayed
+from one HIP graph.  The default run times a full fit (500 generations) in
+the plain FP64 form and in the mixed-precision form, reports the success rate
+(best chi^2 <= chi^2 of the true parameters + 10) and fits/hour, the fitness
+kernel's roofline fraction, and the CPU oracle timed on a bounded sample.
+
+Prints ONE JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FLOPs of one magnification + fit update as the fitness kernel
+# computes it (counted from its source; fma = 2, reciprocal = 1 plus its
+# Newton refinement steps): source position and polynomial coefficients,
+# per sweep of the simultaneous root iteration over the five roots, image
+# test + det J + magnification, and the weighted least-squares row update.
+FLOP_COEF = 106
+FLOP_SWEEP64 = 760
+FLOP_SWEEP32 = 680
+FLOP_IMAGES = 345
+FLOP_LSQ = 50
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (fma) x 2.4 GHz, the same
+# for FP64 and for unpacked FP32 (packed FP32 is not used)
+PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+N_GEN_FIT = 500
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=N_GEN_FIT)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n-lc", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=1000)
+    ap.add_argument("--pop", type=int, default=256)
+    ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target wall time of the CPU-oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=10)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_batch(sblm, torch, n_lc, L, seed=2):
+    """Synthetic batch; observations from the library's own forward model."""
+    from paper_1208_4830_amd import inputs
+    wl = inputs.uniform_workload(seed, n_lc, L)
+    dev = "cuda"
+    t = torch.as_tensor(wl.t, device=dev)
+    A = torch.empty(wl.t.size, dtype=torch.float64, device=dev)
+    for k in range(n_lc):  # each lightcurve has its own epochs
+        a, b = int(wl.off[k]), int(wl.off[k + 1])
+        A[a:b] = sblm.sblm_magnify(torch.as_tensor(wl.theta[:, k:k + 1].copy(), device=dev),
+                                   t[a:b].contiguous())[0]
+    A = A.cpu().numpy()
+    F = wl.Fs.repeat(L) * A + wl.Fb.repeat(L)
+    sig = wl.sfrac * F
+    y = F + sig * wl.noise
+    w = 1.0 / sig ** 2
+    lcs = sblm.Lightcurves(torch.as_tensor(wl.off, device=dev), t,
+                           torch.as_tensor(y, device=dev), torch.as_tensor(w, device=dev))
+    return wl, y, w, lcs
+
+
+def run_form(sblm, torch, lcs, wl, chi2_true, args, mode):
+    n_lc, L, pop = args.n_lc, args.epochs, args.pop
+    mags_per_gen = n_lc * pop * L
+    cfg = sblm.ea_default_config()
+    cfg.pop = pop
+    cfg.mode = mode
+    # warm-up on a scratch state (same shapes, graph already captured)
+    scratch = sblm.EAState(cfg, lcs, 999)
+    scratch.fit(args.warmup)
+    torch.cuda.synchronize()
+    # sweeps per solve (lane level) for the algorithmic FLOP count
+    st = sblm.new_stats()
+    scratch.evaluate(stats=st)
+    torch.cuda.synchronize()
+    s = sblm.stats_dict(st)
+    sweeps = s["n_iter"] / max(s["n_solves"], 1)
+    # dominant kernel: fitness evaluation, timed with events on the stream
+    # it is launched on (the current stream)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.kernel_reps):
+        scratch.evaluate(stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    k_ms = e0.elapsed_time(e1) / args.kernel_reps
+    scratch.close()
+
+    # the timed fit: fresh state, `steps` generations
+    state = sblm.EAState(cfg, lcs, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    state.fit(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    summ = state.summary()
+    best = np.array([summ[k].best_chi2 for k in range(n_lc)])
+    success = float(np.mean(best <= chi2_true + 10.0))
+    state.close()
+
+    if mode == sblm.FP64:
+        flop = FLOP_COEF + sweeps * FLOP_SWEEP64 + FLOP_IMAGES + FLOP_LSQ
+    else:  # FP32 sweeps then FP64 sweeps (two per solve without fallback)
+        n64 = 2.0 + s["n_fallback"] / max(s["n_solves"], 1)
+        flop = FLOP_COEF + (sweeps - n64) * FLOP_SWEEP32 + n64 * FLOP_SWEEP64 \
+            + FLOP_IMAGES + FLOP_LSQ
+    ms_step = dt * 1e3 / args.steps
+    return dict(
+        mags_per_s=mags_per_gen * args.steps / dt,
+        ms_per_step=ms_step,
+        fits_per_hour=n_lc * 3600.0 / (N_GEN_FIT * ms_step / 1e3),
+        success=success, generations=args.steps,
+        kernel_ms=k_ms, kernel_mags_per_s=mags_per_gen / (k_ms / 1e3),
+        sweeps_per_solve=sweeps, flop_per_mag=flop,
+        kernel_tflops=flop * mags_per_gen / (k_ms / 1e3) / 1e12,
+        capped=s["n_capped"], fallback=s["n_fallback"])
+
+
+def cpu_baseline(wl, y, w, pop, target_s):
+    """The CPU oracle's chi^2 on a sample of the same workload."""
+    import oracle as O
+    # the host share of one GPU is 16 cores
+    nthreads = min(16, len(os.sched_getaffinity(0)))
+    rng = np.random.default_rng(5)
+    from paper_1208_4830_amd import inputs
+
+    def run(n_ind_per_lc, n_lcs):
+        off = wl.off[:n_lcs + 1]
+        sl = slice(0, int(off[-1]))
+        th = inputs.draw_theta(rng, n_lcs * n_ind_per_lc)
+        t0 = time.perf_counter()
+        O.chi2(off, wl.t[sl], y[sl], w[sl], th, n_ind_per_lc, nthreads=nthreads)
+        return time.perf_counter() - t0, n_lcs * n_ind_per_lc * int(off[1] - off[0])
+
+    dt, mags = run(nthreads, 1)  # calibration
+    rate = mags / dt
+    n_ind = max(nthreads, int(target_s * rate / 1000))
+    n_lcs = min(wl.n_lc, max(1, n_ind // pop))
+    per = max(1, n_ind // n_lcs)
+    dt, mags = run(per, n_lcs)
+    return dict(value=mags / dt, unit="magnifications/s", cores=nthreads, kind="oracle",
+                sample=f"{n_lcs} lightcurves x {per} individuals x {int(wl.off[1])} epochs "
+                       f"({mags} magnifications + chi^2, {dt:.1f} s)")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the fit shards by "
+                          "lightcurve and multi-GPU runs are not part of this build",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_1208_4830_amd import sblm
+    sblm.load()
+    assert torch.cuda.is_available()
+    log(f"bench: {args.n_lc} lightcurves x {args.epochs} epochs, pop {args.pop}, "
+        f"{args.steps} generations")
+    wl, y, w, lcs = make_batch(sblm, torch, args.n_lc, args.epochs)
+    th_true = torch.as_tensor(np.repeat(wl.theta, 1, axis=1).copy(), device="cuda")
+    c_true, _, _ = sblm.sblm_chi2(lcs, th_true, 1)
+    chi2_true = c_true.cpu().numpy()
+
+    forms = {}
+    for name in args.forms.split(","):
+        mode = sblm.FP64 if name == "fp64" else sblm.MIXED
+        log(f"bench: form {name}")
+        forms[name] = run_form(sblm, torch, lcs, wl, chi2_true, args, mode)
+        log(f"bench: {name}: {json.dumps(forms[name])}")
+    main_form = forms.get("fp64") or next(iter(forms.values()))
+
+    cpu = None
+    if not args.no_cpu:
+        log("bench: CPU oracle sample")
+        cpu = cpu_baseline(wl, y, w, args.pop, args.cpu_seconds)
+        log(f"bench: cpu {json.dumps(cpu)}")
+
+    out = {
+        "metric": "binary-lens magnifications/s (batched fitness + EA generation)",
+        "value": main_form["mags_per_s"],
+        "unit": "magnifications/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": main_form["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.n_lc} lightcurves x {args.epochs} uniform epochs, "
+                               f"population {args.pop}, FP64 chi^2 with profiled Fs, Fb",
+                   "n_lc": args.n_lc, "epochs": args.epochs, "pop": args.pop,
+                   "parallelism": "single GPU"},
+        "fits_per_hour": main_form["fits_per_hour"],
+        "success_rate": main_form["success"],
+        "forms": forms,
+        "roofline": {"bound": "alu", "achieved": main_form["kernel_tflops"],
+                     "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": main_form["kernel_tflops"] / PEAK_VALU_TFLOPS, "traffic": None,
+                     "kernel": "fitness_kernel (FP64)",
+                     "flop_per_magnification": main_form["flop_per_mag"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

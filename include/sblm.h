@@ -255,6 +255,24 @@ int ea_load(ea_state* st, const void* buf, size_t len, void* stream);
 
 void ea_destroy(ea_state* st);
 
+/* ---------------------------------------------------------------------- */
+/* Diagnostics (used by the parity tests)                                  */
+/* ---------------------------------------------------------------------- */
+
+/* ea_draws -- the raw 64-bit Philox4x64-10 words the EA uses: out[k] =
+ * word (j0 + k) % 4 of the block at key (seed, lc), counter (gen, purpose,
+ * row, (j0 + k) / 4), for k < n.  out: DEVICE uint64 [n], 0 <= n <= 2^24. */
+int ea_draws(uint64_t seed, uint64_t lc, uint64_t gen, uint64_t purpose,
+             uint64_t row, uint64_t j0, int64_t n, uint64_t* out,
+             void* stream);
+
+/* ea_generation_traced -- ea_generation that also writes the parent ranks
+ * chosen by every tournament: parents DEVICE int32
+ * [n_lc][2*floor(pop/2)], pairing k of lightcurve l at
+ * parents[l*2*floor(pop/2) + 2k] (first parent) and [... + 2k + 1]. */
+int ea_generation_traced(ea_state* st, const double* chi2, const double* Fs,
+                         const double* Fb, int32_t* parents, void* stream);
+
 /* Thread-local description of the last error of this thread. */
 const char* sblm_last_error(void);
 

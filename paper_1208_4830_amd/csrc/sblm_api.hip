@@ -1,0 +1,116 @@
+// sblm_api.hip -- host entry points of the fitness part of the C ABI
+// (sblm_magnify, sblm_chi2, sblm_last_error): argument checks, schedule
+// choice and kernel launch.  The kernels are in sblm_fitness.hip.
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "sblm_internal.h"
+
+namespace sblm {
+
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return SBLM_OK;
+  return set_error(SBLM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Lanes per individual: the largest of 64, 32, 16 that still gives every
+// lane a chunk of at least 8 epochs (warm starts amortise the cold start of
+// each chunk), overridable with SBLM_LANES for tuning runs.
+static int choose_group(double mean_len) {
+  const char* env = getenv("SBLM_LANES");
+  if (env) {
+    int g = atoi(env);
+    if (g == 16 || g == 32 || g == 64) return g;
+  }
+  if (mean_len >= 64.0 * 8) return 64;
+  if (mean_len >= 32.0 * 8) return 32;
+  return 16;
+}
+
+static int waves_per_block() {
+  const char* env = getenv("SBLM_WAVES_PER_BLOCK");
+  if (env) {
+    int w = atoi(env);
+    if (w >= 1 && w <= 16) return w;
+  }
+  return 4;
+}
+
+}  // namespace sblm
+
+using namespace sblm;
+
+extern "C" const char* sblm_last_error(void) { return g_err; }
+
+extern "C" int sblm_magnify(const double* theta, int64_t n, const double* t,
+                            int64_t n_t, int mode, double* A, int8_t* n_img,
+                            sblm_stats* stats, void* stream) {
+  if (mode != SBLM_FP64 && mode != SBLM_MIXED)
+    return set_error(SBLM_EINVAL, "sblm_magnify: unknown mode %d", mode);
+  if (n < 1) return set_error(SBLM_EINVAL, "sblm_magnify: n = %lld < 1", (long long)n);
+  if (n_t < 0) return set_error(SBLM_EINVAL, "sblm_magnify: n_t < 0");
+  if (n > (1LL << 26) || n_t > (1LL << 24))
+    return set_error(SBLM_ERANGE, "sblm_magnify: n = %lld or n_t = %lld beyond limits",
+                     (long long)n, (long long)n_t);
+  if (n_t == 0) return SBLM_OK;
+  if (!theta || !t || !A)
+    return set_error(SBLM_EINVAL, "sblm_magnify: null theta, t or A");
+  FitArgs a;
+  memset(&a, 0, sizeof(a));
+  a.theta = theta;
+  a.n_ind = n;
+  a.t = t;
+  a.n_t = n_t;
+  a.A = A;
+  a.n_img = n_img;
+  a.stats = stats;
+  a.lanes_per_ind = choose_group((double)n_t);
+  return check_hip(launch_fitness(a, mode, false, (hipStream_t)stream, waves_per_block()),
+                   "sblm_magnify launch");
+}
+
+extern "C" int sblm_chi2(const sblm_lcs* lcs, const double* theta, int32_t pop,
+                         int mode, double* chi2, double* Fs, double* Fb,
+                         sblm_stats* stats, void* stream) {
+  if (mode != SBLM_FP64 && mode != SBLM_MIXED)
+    return set_error(SBLM_EINVAL, "sblm_chi2: unknown mode %d", mode);
+  if (!lcs || !lcs->off || !lcs->t || !lcs->y || !lcs->w)
+    return set_error(SBLM_EINVAL, "sblm_chi2: null lightcurve descriptor or array");
+  if (lcs->n_lc < 1 || pop < 1)
+    return set_error(SBLM_EINVAL, "sblm_chi2: n_lc = %d, pop = %d", lcs->n_lc, pop);
+  if (lcs->n_lc > (1 << 20) || pop > 65536 || (int64_t)lcs->n_lc * pop > (1LL << 31) - 1)
+    return set_error(SBLM_ERANGE, "sblm_chi2: n_lc = %d, pop = %d beyond limits",
+                     lcs->n_lc, pop);
+  if (!theta || !chi2 || !Fs || !Fb)
+    return set_error(SBLM_EINVAL, "sblm_chi2: null theta or output");
+  FitArgs a;
+  memset(&a, 0, sizeof(a));
+  a.theta = theta;
+  a.n_ind = (int64_t)lcs->n_lc * pop;
+  a.off = lcs->off;
+  a.pop = pop;
+  a.t = lcs->t;
+  a.y = lcs->y;
+  a.w = lcs->w;
+  a.chi2 = chi2;
+  a.Fs = Fs;
+  a.Fb = Fb;
+  a.stats = stats;
+  // mean length is not known on the host without a copy; use the group
+  // size that suits ~1000-epoch lightcurves unless overridden
+  a.lanes_per_ind = choose_group(1000.0);
+  return check_hip(launch_fitness(a, mode, true, (hipStream_t)stream, waves_per_block()),
+                   "sblm_chi2 launch");
+}

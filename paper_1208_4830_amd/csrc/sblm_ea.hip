@@ -1,0 +1,684 @@
+// sblm_ea.hip -- the evolutionary algorithm of Rajpaul (2012), Appendix A,
+// on the device, plus the ea_* entry points of the C ABI.
+//
+// One workgroup per lightcurve runs a whole generation of its population:
+// the old population and its fitness are staged in LDS, rows are ranked by a
+// counting rank (stable, NaN last), one thread per reproductive pairing
+// draws its tournament, crossover mode and weights, builds both children and
+// applies creep then jump mutation to them, writing the next population in
+// place; thread 0 keeps the per-lightcurve record (best-ever individual,
+// best-chi^2 history, jump probability, stagnation flags, restarts).
+//
+// Random numbers: Philox4x64-10 (Salmon et al. 2011), key (seed, lc),
+// counter (generation, purpose, row, j/4), word j%4, so every draw is a pure
+// function of its coordinates.  All arithmetic on encoded genes is written
+// with explicit fused multiply-adds and compiled without contraction, so the
+// result is the same on any IEEE-754 machine given the same fitness.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "sblm_internal.h"
+
+namespace sblm {
+
+// ---------------------------------------------------------------- Philox
+
+struct u64x4 {
+  uint64_t v[4];
+};
+
+__device__ __forceinline__ u64x4 philox4x64_10(uint64_t c0, uint64_t c1,
+                                               uint64_t c2, uint64_t c3,
+                                               uint64_t k0, uint64_t k1) {
+  // round multipliers and Weyl key increments of Philox4x64
+  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
+    const uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  return {{c0, c1, c2, c3}};
+}
+
+struct Stream {
+  uint64_t seed, lc, gen;
+  __device__ __forceinline__ uint64_t draw(uint64_t purpose, uint64_t row,
+                                           uint64_t j) const {
+    const u64x4 b = philox4x64_10(gen, purpose, row, j >> 2, seed, lc);
+    return b.v[j & 3];
+  }
+};
+
+__device__ __forceinline__ double u01(uint64_t x) {
+  return ((double)(x >> 12) + 0.5) * 0x1p-52;
+}
+__device__ __forceinline__ uint32_t below(uint64_t x, uint32_t n) {
+  return (uint32_t)(((x >> 32) * (uint64_t)n) >> 32);
+}
+
+// 2^-v, v in [0, 64): Taylor polynomial of 2^-f = exp(-f ln 2) on f in
+// [0,1) through f^16 (error < 6e-18), coefficients (-ln 2)^n/n! rounded to
+// nearest, Horner with fma, then an exact power-of-two scaling.
+__device__ __forceinline__ double exp2_neg(double v) {
+  const double T[17] = {
+      0x1.0000000000000p+0,   -0x1.62e42fefa39efp-1, 0x1.ebfbdff82c58fp-3,
+      -0x1.c6b08d704a0c0p-5,  0x1.3b2ab6fba4e77p-7,  -0x1.5d87fe78a6731p-10,
+      0x1.430912f86c787p-13,  -0x1.ffcbfc588b0c7p-17, 0x1.62c0223a5c824p-20,
+      -0x1.b5253d395e7c4p-24, 0x1.e4cf5158b8ecap-28, -0x1.e8cac7351bb25p-32,
+      0x1.c3bd650fc2986p-36,  -0x1.816193166d0f9p-40, 0x1.314964d5878a9p-44,
+      -0x1.c36e843b04022p-49, 0x1.38e89ae79f8b4p-53};
+  const double k = floor(v);
+  const double f = v - k;
+  double s = T[16];
+#pragma unroll
+  for (int n = 15; n >= 0; --n) s = fma(s, f, T[n]);
+  return ldexp(s, -(int)k);
+}
+
+__device__ __forceinline__ double clamp01(double x) {
+  return x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+}
+
+enum { P_INIT = EA_PURPOSE_INIT, P_TOURN = EA_PURPOSE_TOURN,
+       P_MODE = EA_PURPOSE_MODE, P_CREEP = EA_PURPOSE_CREEP,
+       P_JUMP = EA_PURPOSE_JUMP };
+
+#define EA_HIST 64
+
+// Per-lightcurve record, device resident.
+struct EaLc {
+  int64_t gen, gen_restart, best_gen;
+  double p_mut;
+  int32_t stag_count, n_restarts;
+  double best_chi2, best_Fs, best_Fb;
+  double best_p[SBLM_NPAR];
+  double hist[EA_HIST];  // best chi^2 of generation g at hist[g % (window+1)]
+};
+
+struct EaParams {
+  int32_t n_lc, pop, n_tourn, window, restart_after;
+  double p_mut0, p_mut_min, p_mut_max, stag_frac;
+  uint64_t seed;
+  int64_t n_ind;  // n_lc * pop
+};
+
+// Sec. A.1: rows i < pop/2 uniform, row i + pop/2 = 1 - row i, odd last row
+// uniform; draws keyed by generation `gen`.  Writes rows of P for
+// lightcurve lc with the threads of one block.
+__device__ void init_rows(const EaParams& p, double* P, int64_t lc,
+                          int64_t gen) {
+  const Stream rs = {p.seed, (uint64_t)lc, (uint64_t)gen};
+  const int half = p.pop / 2;
+  const int64_t base = lc * p.pop;
+  for (int i = threadIdx.x; i < half + (p.pop & 1); i += blockDim.x) {
+    const bool odd_last = (i == half);
+    const int row = odd_last ? p.pop - 1 : i;
+    for (int g = 0; g < SBLM_NPAR; ++g) {
+      const double x = u01(rs.draw(P_INIT, (uint64_t)row, (uint64_t)g));
+      P[g * p.n_ind + base + row] = x;
+      if (!odd_last) P[g * p.n_ind + base + i + half] = 1.0 - x;
+    }
+  }
+}
+
+__global__ void ea_init_kernel(EaParams p, double* P, EaLc* lcs) {
+  const int64_t lc = blockIdx.x;
+  init_rows(p, P, lc, 0);
+  if (threadIdx.x == 0) {
+    EaLc& s = lcs[lc];
+    s.gen = 0;
+    s.gen_restart = 0;
+    s.best_gen = -1;
+    s.p_mut = p.p_mut0;
+    s.stag_count = 0;
+    s.n_restarts = 0;
+    s.best_chi2 = INFINITY;
+    s.best_Fs = 0.0;
+    s.best_Fb = 0.0;
+    for (int g = 0; g < SBLM_NPAR; ++g) s.best_p[g] = 0.0;
+    for (int h = 0; h < EA_HIST; ++h) s.hist[h] = INFINITY;
+  }
+}
+
+__device__ __forceinline__ double rank_key(double c) {
+  return isnan(c) ? INFINITY : c;
+}
+
+// One generation (Sec. A.3-A.7) for lightcurve blockIdx.x.
+__global__ void ea_generation_kernel(EaParams p, double* P, EaLc* lcs,
+                                     const double* chi2, const double* Fs,
+                                     const double* Fb, int32_t* parents_out) {
+  extern __shared__ double smem[];
+  const int N = p.pop;
+  double* sP = smem;                         // [6][N] old population
+  double* key = sP + SBLM_NPAR * N;          // [N]
+  int* perm = (int*)(key + N);               // [N] rank -> row
+  __shared__ double s_pmut;
+  __shared__ int s_restart;
+
+  const int64_t lc = blockIdx.x;
+  const int64_t base = lc * N;
+  EaLc& st = lcs[lc];
+  const int64_t gen = st.gen;
+  const Stream rs = {p.seed, (uint64_t)lc, (uint64_t)gen};
+
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    key[i] = rank_key(chi2[base + i]);
+    for (int g = 0; g < SBLM_NPAR; ++g) sP[g * N + i] = P[g * p.n_ind + base + i];
+  }
+  __syncthreads();
+  // (A.3) stable counting rank
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const double ki = key[i];
+    int r = 0;
+    for (int j = 0; j < N; ++j) {
+      const double kj = key[j];
+      r += (kj < ki || (kj == ki && j < i)) ? 1 : 0;
+    }
+    perm[r] = i;
+  }
+  __syncthreads();
+
+  if (threadIdx.x == 0) {
+    const int top = perm[0];
+    const double b = key[top];
+    s_pmut = st.p_mut;  // mutation of this generation uses the current value
+    if (b < st.best_chi2) {
+      st.best_chi2 = b;
+      st.best_Fs = Fs[base + top];
+      st.best_Fb = Fb[base + top];
+      for (int g = 0; g < SBLM_NPAR; ++g) st.best_p[g] = sP[g * N + top];
+      st.best_gen = gen;
+    }
+    const int W = p.window;
+    st.hist[gen % (W + 1)] = b;
+    // (A.7) stagnation test on the best chi^2 of `window` generations ago
+    int restart = 0;
+    if (gen - st.gen_restart >= W) {
+      const double old = st.hist[(gen - W) % (W + 1)];
+      const bool improved =
+          isinf(old) ? (b < old) : ((old - b) > p.stag_frac * old);
+      if (improved) {
+        st.p_mut = fmax(0.5 * st.p_mut, p.p_mut_min);
+        st.stag_count = 0;
+      } else {
+        st.p_mut = fmin(1.5 * st.p_mut, p.p_mut_max);
+        st.stag_count += 1;
+      }
+      if (st.stag_count >= p.restart_after) {
+        restart = 1;
+        st.p_mut = p.p_mut0;
+        st.stag_count = 0;
+        st.gen_restart = gen + 1;
+        st.n_restarts += 1;
+      }
+    }
+    st.gen = gen + 1;
+    s_restart = restart;
+  }
+  __syncthreads();
+
+  if (s_restart) {  // fresh population keyed by the next generation
+    init_rows(p, P, lc, gen + 1);
+    return;
+  }
+  const double pm = s_pmut;
+  if (threadIdx.x == 0) {  // (A.5) elitism: row 0 keeps the fittest
+    for (int g = 0; g < SBLM_NPAR; ++g)
+      P[g * p.n_ind + base] = sP[g * N + perm[0]];
+  }
+  const int npair = N / 2;
+  const int nt = p.n_tourn;
+  for (int k = threadIdx.x; k < npair; k += blockDim.x) {
+    // (A.4) tournaments: parent rank = min of nt draws from {0..N-1}
+    int ra = N, rb = N;
+    for (int m = 0; m < nt; ++m) {
+      const int x = (int)below(rs.draw(P_TOURN, (uint64_t)k, (uint64_t)m), (uint32_t)N);
+      const int y =
+          (int)below(rs.draw(P_TOURN, (uint64_t)k, (uint64_t)(nt + m)), (uint32_t)N);
+      ra = x < ra ? x : ra;
+      rb = y < rb ? y : rb;
+    }
+    if (parents_out) {
+      parents_out[lc * 2 * npair + 2 * k] = ra;
+      parents_out[lc * 2 * npair + 2 * k + 1] = rb;
+    }
+    const int ia = perm[ra], ib = perm[rb];
+    // (A.5) weighting mode for this pairing: U(0,1), Bin(1,1/2) or ones
+    const u64x4 mb0 = philox4x64_10(gen, P_MODE, (uint64_t)k, 0, p.seed, (uint64_t)lc);
+    const u64x4 mb1 = philox4x64_10(gen, P_MODE, (uint64_t)k, 1, p.seed, (uint64_t)lc);
+    const int mode = (int)below(mb0.v[0], 3u);
+    const int s1 = 2 * k + 1, s2 = 2 * k + 2;
+    for (int g = 0; g < SBLM_NPAR; ++g) {
+      const int j = 1 + g;
+      const uint64_t x = (j < 4) ? mb0.v[j] : mb1.v[j - 4];
+      const double f = (mode == 0) ? u01(x) : (mode == 1 ? ((x >> 63) ? 1.0 : 0.0) : 1.0);
+      const double omf = 1.0 - f;
+      const double pa = sP[g * N + ia], pb = sP[g * N + ib];
+      double child[2];
+      child[0] = clamp01(fma(f, pa, omf * pb));
+      child[1] = clamp01(fma(f, pb, omf * pa));
+      for (int c = 0; c < 2; ++c) {
+        const int slot = c ? s2 : s1;
+        if (slot >= N) continue;
+        // (A.6) creep: p -> p + (1-p) X or p - p X, ln X ~ U(ln 2^-52, 0)
+        double v = child[c];
+        const u64x4 cb = philox4x64_10(gen, P_CREEP, (uint64_t)slot,
+                                       (uint64_t)((2 * g) >> 2), p.seed, (uint64_t)lc);
+        const uint64_t xs = cb.v[(2 * g) & 3], xu = cb.v[(2 * g + 1) & 3];
+        const double X = exp2_neg(52.0 * u01(xu));
+        v = (xs >> 63) ? fma(1.0 - v, X, v) : fma(-v, X, v);
+        v = clamp01(v);
+        // (A.6) jump: with probability p_mut replace by a fresh uniform
+        const u64x4 jb = philox4x64_10(gen, P_JUMP, (uint64_t)slot,
+                                       (uint64_t)((2 * g) >> 2), p.seed, (uint64_t)lc);
+        if (u01(jb.v[(2 * g) & 3]) < pm) v = u01(jb.v[(2 * g + 1) & 3]);
+        P[g * p.n_ind + base + slot] = v;
+      }
+    }
+  }
+}
+
+__global__ void ea_draws_kernel(uint64_t seed, uint64_t lc, uint64_t gen,
+                                uint64_t purpose, uint64_t row, uint64_t j0,
+                                int64_t n, uint64_t* out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const Stream rs = {seed, lc, gen};
+  out[k] = rs.draw(purpose, row, j0 + (uint64_t)k);
+}
+
+// ---------------------------------------------------------------- host side
+
+struct EaStateImpl {
+  ea_config cfg;
+  EaParams prm;
+  sblm_lcs lcs;
+  int device;
+  double* P = nullptr;
+  double* chi2 = nullptr;
+  double* Fs = nullptr;
+  double* Fb = nullptr;
+  EaLc* lc = nullptr;
+  hipStream_t work = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t graph = nullptr;
+  sblm_stats* graph_stats = nullptr;
+  int lanes = 64;
+};
+
+static size_t gen_smem(int pop) {
+  return (size_t)pop * (SBLM_NPAR * sizeof(double) + sizeof(double) + sizeof(int));
+}
+
+static int gen_block(int pop) {
+  int b = 64;
+  while (b < pop / 2 && b < 256) b *= 2;
+  return b;
+}
+
+static hipError_t enqueue_generation(EaStateImpl* s, const double* chi2,
+                                     const double* Fs, const double* Fb,
+                                     int32_t* parents, hipStream_t st) {
+  hipLaunchKernelGGL(ea_generation_kernel, dim3(s->prm.n_lc),
+                     dim3(gen_block(s->prm.pop)), gen_smem(s->prm.pop), st, s->prm,
+                     s->P, s->lc, chi2, Fs, Fb, parents);
+  return hipGetLastError();
+}
+
+static hipError_t enqueue_evaluate(EaStateImpl* s, sblm_stats* stats,
+                                   hipStream_t st) {
+  FitArgs a;
+  memset(&a, 0, sizeof(a));
+  a.theta = s->P;
+  a.n_ind = s->prm.n_ind;
+  a.encoded = 1;
+  for (int j = 0; j < SBLM_NPAR; ++j) {
+    a.lo[j] = s->cfg.lo[j];
+    a.span[j] = s->cfg.hi[j] - s->cfg.lo[j];
+  }
+  a.off = s->lcs.off;
+  a.pop = s->prm.pop;
+  a.t = s->lcs.t;
+  a.y = s->lcs.y;
+  a.w = s->lcs.w;
+  a.chi2 = s->chi2;
+  a.Fs = s->Fs;
+  a.Fb = s->Fb;
+  a.stats = stats;
+  a.lanes_per_ind = s->lanes;
+  return launch_fitness(a, s->cfg.mode, true, st, 4);
+}
+
+}  // namespace sblm
+
+using namespace sblm;
+
+struct ea_state {
+  EaStateImpl impl;
+};
+
+static int capture_graph(EaStateImpl& s, sblm_stats* stats);
+
+extern "C" void ea_default_config(ea_config* c) {
+  if (!c) return;
+  memset(c, 0, sizeof(*c));
+  c->pop = 256;
+  c->n_tourn = 0;
+  c->p_mut0 = 0.01;
+  c->p_mut_min = 1e-4;
+  c->p_mut_max = 0.5;
+  c->stag_frac = 0.01;
+  c->stag_window = 10;
+  c->restart_after = 10;
+  const double lo[SBLM_NPAR] = {-3.0, 0.5, 0.0, 0.0, 10.0, -10.0};
+  const double hi[SBLM_NPAR] = {0.0, 2.0, 0.5, 6.283185307179586, 100.0, 10.0};
+  for (int j = 0; j < SBLM_NPAR; ++j) {
+    c->lo[j] = lo[j];
+    c->hi[j] = hi[j];
+  }
+  c->mode = SBLM_FP64;
+}
+
+static int validate(const ea_config* c) {
+  if (c->pop < 2 || c->pop > 1024)
+    return set_error(SBLM_ERANGE, "ea_config: pop = %d outside [2, 1024]", c->pop);
+  if (c->n_tourn < 0 || c->n_tourn > c->pop)
+    return set_error(SBLM_EINVAL, "ea_config: n_tourn = %d", c->n_tourn);
+  if (!(c->p_mut0 >= 0.0 && c->p_mut0 <= 1.0) || !(c->p_mut_min >= 0.0) ||
+      !(c->p_mut_max <= 1.0) || !(c->p_mut_min <= c->p_mut_max))
+    return set_error(SBLM_EINVAL, "ea_config: jump probabilities out of [0,1]");
+  if (!(c->stag_frac >= 0.0))
+    return set_error(SBLM_EINVAL, "ea_config: stag_frac < 0");
+  if (c->stag_window < 1 || c->stag_window > EA_HIST - 1)
+    return set_error(SBLM_ERANGE, "ea_config: stag_window = %d outside [1, %d]",
+                     c->stag_window, EA_HIST - 1);
+  if (c->restart_after < 1)
+    return set_error(SBLM_EINVAL, "ea_config: restart_after < 1");
+  for (int j = 0; j < SBLM_NPAR; ++j)
+    if (!(c->lo[j] < c->hi[j]) || !isfinite(c->lo[j]) || !isfinite(c->hi[j]))
+      return set_error(SBLM_EINVAL, "ea_config: empty or non-finite domain %d", j);
+  if (!(c->lo[4] > 0.0))
+    return set_error(SBLM_EINVAL, "ea_config: tE domain must be positive");
+  if (c->mode != SBLM_FP64 && c->mode != SBLM_MIXED)
+    return set_error(SBLM_EINVAL, "ea_config: unknown mode %d", c->mode);
+  return SBLM_OK;
+}
+
+extern "C" void ea_destroy(ea_state* st) {
+  if (!st) return;
+  EaStateImpl& s = st->impl;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(s.device);
+  if (s.work) (void)hipStreamSynchronize(s.work);
+  if (s.graph) (void)hipGraphExecDestroy(s.graph);
+  if (s.ev_in) (void)hipEventDestroy(s.ev_in);
+  if (s.ev_out) (void)hipEventDestroy(s.ev_out);
+  if (s.work) (void)hipStreamDestroy(s.work);
+  (void)hipFree(s.P);
+  (void)hipFree(s.chi2);
+  (void)hipFree(s.Fs);
+  (void)hipFree(s.Fb);
+  (void)hipFree(s.lc);
+  (void)hipSetDevice(prev);
+  st->~ea_state();
+  free(st);
+}
+
+extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t seed,
+                         ea_state** out) {
+  if (!cfg || !lcs || !out) return set_error(SBLM_EINVAL, "ea_create: null argument");
+  *out = nullptr;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (!lcs->off || !lcs->t || !lcs->y || !lcs->w)
+    return set_error(SBLM_EINVAL, "ea_create: null lightcurve array");
+  if (lcs->n_lc < 1 || lcs->n_lc > (1 << 20))
+    return set_error(SBLM_ERANGE, "ea_create: n_lc = %d", lcs->n_lc);
+  if ((int64_t)lcs->n_lc * cfg->pop > (1LL << 31) - 1)
+    return set_error(SBLM_ERANGE, "ea_create: n_lc * pop too large");
+  void* mem = malloc(sizeof(ea_state));
+  if (!mem) return set_error(SBLM_ENOMEM, "ea_create: host allocation");
+  ea_state* st = new (mem) ea_state();
+  EaStateImpl& s = st->impl;
+  s.cfg = *cfg;
+  s.lcs = *lcs;
+  (void)hipGetDevice(&s.device);
+  EaParams& p = s.prm;
+  p.n_lc = lcs->n_lc;
+  p.pop = cfg->pop;
+  p.n_tourn = cfg->n_tourn > 0 ? cfg->n_tourn : (cfg->pop + 24) / 25;
+  p.window = cfg->stag_window;
+  p.restart_after = cfg->restart_after;
+  p.p_mut0 = cfg->p_mut0;
+  p.p_mut_min = cfg->p_mut_min;
+  p.p_mut_max = cfg->p_mut_max;
+  p.stag_frac = cfg->stag_frac;
+  p.seed = seed;
+  p.n_ind = (int64_t)p.n_lc * p.pop;
+  const char* env = getenv("SBLM_LANES");
+  s.lanes = 64;
+  if (env && (atoi(env) == 16 || atoi(env) == 32 || atoi(env) == 64)) s.lanes = atoi(env);
+  const size_t nb = (size_t)p.n_ind * sizeof(double);
+  if (hipMalloc(&s.P, SBLM_NPAR * nb) != hipSuccess || hipMalloc(&s.chi2, nb) != hipSuccess ||
+      hipMalloc(&s.Fs, nb) != hipSuccess || hipMalloc(&s.Fb, nb) != hipSuccess ||
+      hipMalloc(&s.lc, (size_t)p.n_lc * sizeof(EaLc)) != hipSuccess) {
+    ea_destroy(st);
+    return set_error(SBLM_ENOMEM, "ea_create: device allocation of %zu bytes failed",
+                     (9 * nb + (size_t)p.n_lc * sizeof(EaLc)));
+  }
+  if ((rc = check_hip(hipStreamCreateWithFlags(&s.work, hipStreamNonBlocking),
+                      "ea_create stream")) ||
+      (rc = check_hip(hipEventCreateWithFlags(&s.ev_in, hipEventDisableTiming), "event")) ||
+      (rc = check_hip(hipEventCreateWithFlags(&s.ev_out, hipEventDisableTiming), "event"))) {
+    ea_destroy(st);
+    return rc;
+  }
+  hipLaunchKernelGGL(ea_init_kernel, dim3(p.n_lc), dim3(gen_block(p.pop)), 0, s.work, p, s.P,
+                     s.lc);
+  rc = check_hip(hipGetLastError(), "ea_create init launch");
+  if (!rc) rc = check_hip(hipStreamSynchronize(s.work), "ea_create init");
+  if (!rc) rc = capture_graph(s, nullptr);
+  if (rc) {
+    ea_destroy(st);
+    return rc;
+  }
+  *out = st;
+  return SBLM_OK;
+}
+
+extern "C" int ea_generation(ea_state* st, const double* chi2, const double* Fs,
+                             const double* Fb, void* stream) {
+  if (!st) return set_error(SBLM_ESTATE, "ea_generation: null state");
+  if (!chi2 || !Fs || !Fb) return set_error(SBLM_EINVAL, "ea_generation: null fitness");
+  return check_hip(enqueue_generation(&st->impl, chi2, Fs, Fb, nullptr, (hipStream_t)stream),
+                   "ea_generation launch");
+}
+
+// Test hook: as ea_generation, also writing the selected parent ranks
+// (int32 [n_lc][2*floor(pop/2)], device) of every pairing.
+extern "C" int ea_generation_traced(ea_state* st, const double* chi2, const double* Fs,
+                                    const double* Fb, int32_t* parents, void* stream) {
+  if (!st) return set_error(SBLM_ESTATE, "ea_generation_traced: null state");
+  if (!chi2 || !Fs || !Fb || !parents)
+    return set_error(SBLM_EINVAL, "ea_generation_traced: null argument");
+  return check_hip(enqueue_generation(&st->impl, chi2, Fs, Fb, parents, (hipStream_t)stream),
+                   "ea_generation launch");
+}
+
+extern "C" int ea_draws(uint64_t seed, uint64_t lc, uint64_t gen, uint64_t purpose,
+                        uint64_t row, uint64_t j0, int64_t n, uint64_t* out, void* stream) {
+  if (n < 0 || n > (1LL << 24)) return set_error(SBLM_ERANGE, "ea_draws: n = %lld", (long long)n);
+  if (n == 0) return SBLM_OK;
+  if (!out) return set_error(SBLM_EINVAL, "ea_draws: null output");
+  hipLaunchKernelGGL(ea_draws_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, seed, lc, gen, purpose, row, j0, n, out);
+  return check_hip(hipGetLastError(), "ea_draws launch");
+}
+
+extern "C" int ea_evaluate(ea_state* st, sblm_stats* stats, void* stream) {
+  if (!st) return set_error(SBLM_ESTATE, "ea_evaluate: null state");
+  return check_hip(enqueue_evaluate(&st->impl, stats, (hipStream_t)stream),
+                   "ea_evaluate launch");
+}
+
+// Captures one generation (evaluate + generation kernels on the state's
+// work stream) into an executable graph bound to `stats`.
+static int capture_graph(EaStateImpl& s, sblm_stats* stats) {
+  if (s.graph) {
+    (void)hipGraphExecDestroy(s.graph);
+    s.graph = nullptr;
+  }
+  int rc;
+  hipGraph_t g;
+  if ((rc = check_hip(hipStreamBeginCapture(s.work, hipStreamCaptureModeThreadLocal),
+                      "ea graph capture")))
+    return rc;
+  hipError_t e1 = enqueue_evaluate(&s, stats, s.work);
+  hipError_t e2 = enqueue_generation(&s, s.chi2, s.Fs, s.Fb, nullptr, s.work);
+  hipError_t e3 = hipStreamEndCapture(s.work, &g);
+  if ((rc = check_hip(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3),
+                      "ea graph capture")))
+    return rc;
+  hipError_t e4 = hipGraphInstantiate(&s.graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if ((rc = check_hip(e4, "ea graph instantiate"))) return rc;
+  s.graph_stats = stats;
+  return SBLM_OK;
+}
+
+extern "C" int ea_fit(ea_state* st, int32_t n_gen, sblm_stats* stats, void* stream) {
+  if (!st) return set_error(SBLM_ESTATE, "ea_fit: null state");
+  if (n_gen < 0) return set_error(SBLM_EINVAL, "ea_fit: n_gen < 0");
+  if (n_gen == 0) return SBLM_OK;
+  EaStateImpl& s = st->impl;
+  int rc;
+  if (!s.graph || s.graph_stats != stats)
+    if ((rc = capture_graph(s, stats))) return rc;
+  hipStream_t caller = (hipStream_t)stream;
+  if ((rc = check_hip(hipEventRecord(s.ev_in, caller), "ea_fit event")) ||
+      (rc = check_hip(hipStreamWaitEvent(s.work, s.ev_in, 0), "ea_fit wait")))
+    return rc;
+  for (int g = 0; g < n_gen; ++g)
+    if ((rc = check_hip(hipGraphLaunch(s.graph, s.work), "ea_fit graph launch"))) return rc;
+  if ((rc = check_hip(hipEventRecord(s.ev_out, s.work), "ea_fit event")) ||
+      (rc = check_hip(hipStreamWaitEvent(caller, s.ev_out, 0), "ea_fit wait")))
+    return rc;
+  return SBLM_OK;
+}
+
+extern "C" int ea_buffers(ea_state* st, double** P, double** chi2, double** Fs,
+                          double** Fb) {
+  if (!st) return set_error(SBLM_ESTATE, "ea_buffers: null state");
+  if (P) *P = st->impl.P;
+  if (chi2) *chi2 = st->impl.chi2;
+  if (Fs) *Fs = st->impl.Fs;
+  if (Fb) *Fb = st->impl.Fb;
+  return SBLM_OK;
+}
+
+extern "C" int ea_summary(ea_state* st, ea_lc_summary* out, void* stream) {
+  if (!st || !out) return set_error(SBLM_EINVAL, "ea_summary: null argument");
+  EaStateImpl& s = st->impl;
+  const int n = s.prm.n_lc;
+  EaLc* h = (EaLc*)malloc((size_t)n * sizeof(EaLc));
+  if (!h) return set_error(SBLM_ENOMEM, "ea_summary: host allocation");
+  int rc = check_hip(hipMemcpyAsync(h, s.lc, (size_t)n * sizeof(EaLc), hipMemcpyDeviceToHost,
+                                    (hipStream_t)stream),
+                     "ea_summary copy");
+  if (!rc) rc = check_hip(hipStreamSynchronize((hipStream_t)stream), "ea_summary sync");
+  if (!rc)
+    for (int k = 0; k < n; ++k) {
+      ea_lc_summary& o = out[k];
+      o.best_chi2 = h[k].best_chi2;
+      o.best_Fs = h[k].best_Fs;
+      o.best_Fb = h[k].best_Fb;
+      for (int j = 0; j < SBLM_NPAR; ++j)
+        o.best_theta[j] = s.cfg.lo[j] + (s.cfg.hi[j] - s.cfg.lo[j]) * h[k].best_p[j];
+      o.best_gen = h[k].best_gen;
+      o.p_mut = h[k].p_mut;
+      o.stag_count = h[k].stag_count;
+      o.n_restarts = h[k].n_restarts;
+      o.gen = h[k].gen;
+      o.gen_restart = h[k].gen_restart;
+    }
+  free(h);
+  return rc;
+}
+
+// Snapshot: header, population [6][n_lc*pop] doubles, per-lightcurve records.
+struct SnapHeader {
+  uint64_t magic;  // "SBLMEA01"
+  uint64_t seed;
+  int32_t n_lc, pop;
+  ea_config cfg;
+  uint64_t rec_size;
+};
+static const uint64_t SNAP_MAGIC = 0x3130414D4C424253ULL;
+
+extern "C" int ea_save(ea_state* st, void* buf, size_t* len, void* stream) {
+  if (!st || !len) return set_error(SBLM_EINVAL, "ea_save: null argument");
+  EaStateImpl& s = st->impl;
+  const size_t np = (size_t)SBLM_NPAR * s.prm.n_ind * sizeof(double);
+  const size_t nl = (size_t)s.prm.n_lc * sizeof(EaLc);
+  const size_t need = sizeof(SnapHeader) + np + nl;
+  if (!buf) {
+    *len = need;
+    return SBLM_OK;
+  }
+  if (*len < need) return set_error(SBLM_EINVAL, "ea_save: buffer of %zu < %zu bytes", *len, need);
+  SnapHeader hd;
+  memset(&hd, 0, sizeof(hd));
+  hd.magic = SNAP_MAGIC;
+  hd.seed = s.prm.seed;
+  hd.n_lc = s.prm.n_lc;
+  hd.pop = s.prm.pop;
+  hd.cfg = s.cfg;
+  hd.rec_size = sizeof(EaLc);
+  char* b = (char*)buf;
+  memcpy(b, &hd, sizeof(hd));
+  hipStream_t str = (hipStream_t)stream;
+  int rc = check_hip(hipMemcpyAsync(b + sizeof(hd), s.P, np, hipMemcpyDeviceToHost, str),
+                     "ea_save copy");
+  if (!rc)
+    rc = check_hip(hipMemcpyAsync(b + sizeof(hd) + np, s.lc, nl, hipMemcpyDeviceToHost, str),
+                   "ea_save copy");
+  if (!rc) rc = check_hip(hipStreamSynchronize(str), "ea_save sync");
+  *len = need;
+  return rc;
+}
+
+extern "C" int ea_load(ea_state* st, const void* buf, size_t len, void* stream) {
+  if (!st || !buf) return set_error(SBLM_EINVAL, "ea_load: null argument");
+  EaStateImpl& s = st->impl;
+  const size_t np = (size_t)SBLM_NPAR * s.prm.n_ind * sizeof(double);
+  const size_t nl = (size_t)s.prm.n_lc * sizeof(EaLc);
+  SnapHeader hd;
+  if (len < sizeof(hd) + np + nl) return set_error(SBLM_ESTATE, "ea_load: snapshot too short");
+  memcpy(&hd, buf, sizeof(hd));
+  if (hd.magic != SNAP_MAGIC || hd.seed != s.prm.seed || hd.n_lc != s.prm.n_lc ||
+      hd.pop != s.prm.pop || hd.rec_size != sizeof(EaLc) ||
+      memcmp(&hd.cfg, &s.cfg, sizeof(ea_config)) != 0)
+    return set_error(SBLM_ESTATE, "ea_load: snapshot does not match this state");
+  const char* b = (const char*)buf;
+  hipStream_t str = (hipStream_t)stream;
+  int rc = check_hip(hipMemcpyAsync(s.P, b + sizeof(hd), np, hipMemcpyHostToDevice, str),
+                     "ea_load copy");
+  if (!rc)
+    rc = check_hip(hipMemcpyAsync(s.lc, b + sizeof(hd) + np, nl, hipMemcpyHostToDevice, str),
+                   "ea_load copy");
+  if (!rc) rc = check_hip(hipStreamSynchronize(str), "ea_load sync");
+  return rc;
+}

@@ -1,0 +1,548 @@
+// sblm_fitness.hip -- batched binary-lens magnification and chi^2 fitness on
+// gfx950 (MI355X).
+//
+// Method (Rajpaul 2012, Sec. 2.2 and Sec. 4): for every (individual, epoch)
+// pair the source position follows Eq. (sourcePos) with tau = (t - t0)/tE;
+// the images solve the lens equation Eq. (lensing), whose fifth-order
+// polynomial form Eq. (lensingPoly) is solved here for all five roots; the
+// two spurious roots are rejected by substitution into the lens equation;
+// the magnification is sum_i 1/|det J_i| with
+// det J = 1 - |1/conj(z)^2 + q/(d - conj(z))^2|^2.  The fitness is chi^2 of
+// the blended flux Fs*A + Fb (Sec. 4.4, Eq. blend) with Fs, Fb profiled by
+// weighted linear least squares.
+//
+// Mapping onto CDNA4:
+//   * one group of G lanes (G = 64, 32 or 16) per individual, each lane
+//     owning a contiguous chunk of C = ceil(L/G) epochs; the individual's
+//     parameters are wave-uniform (scalar registers), epochs are read once;
+//   * all five roots are found together by the Ehrlich-Aberth simultaneous
+//     iteration -- branch-free and identical work per lane, so a wavefront
+//     stays in lockstep.  The first epoch of a chunk starts from a circle
+//     around the root centroid; every later epoch starts from the previous
+//     epoch's roots (the source moves little between epochs), which cuts the
+//     wave-level sweep count by ~2.5x.  The loop ends when every lane of the
+//     wave has converged (wave vote);
+//   * FP64 mode iterates in FP64.  MIXED mode iterates in FP32 to a loose
+//     tolerance, then continues in FP64 (normally two sweeps) from there; the
+//     image test, det J and the fit are FP64 in both modes;
+//   * the weighted least-squares fit is accumulated on the fly with
+//     square-root-free Givens rotations (Gentleman 1973, the row-update form
+//     of a QR factorisation) over columns (1, A | y), so chi^2 comes out as
+//     the accumulated residual, with no A stored and no cancellation of
+//     large sums; lane results are merged by a fixed shuffle tree (bitwise
+//     deterministic).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "sblm_internal.h"
+
+namespace sblm {
+
+// ---------------------------------------------------------------- complex
+
+template <typename T>
+struct cx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> c_sub(cx<T> a, cx<T> b) {
+  return {a.re - b.re, a.im - b.im};
+}
+// a*b + c
+template <typename T>
+__device__ __forceinline__ cx<T> c_fma(cx<T> a, cx<T> b, cx<T> c) {
+  return {fma(a.re, b.re, fma(-a.im, b.im, c.re)),
+          fma(a.re, b.im, fma(a.im, b.re, c.im))};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> c_mul(cx<T> a, cx<T> b) {
+  return {fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
+}
+template <typename T>
+__device__ __forceinline__ T c_norm(cx<T> a) {
+  return fma(a.re, a.re, a.im * a.im);
+}
+
+// Approximate reciprocal for iteration steps (the fixed point of the
+// iteration does not depend on its accuracy).
+__device__ __forceinline__ double rcp_fast(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float rcp_fast(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+// Reciprocal to about 1 ulp, for det J, image positions and the fit.
+__device__ __forceinline__ double rcp_acc(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+// ---------------------------------------------------------------- polynomial
+
+// Coefficients c[0..5] of the lens polynomial for source zeta, separation d,
+// mass ratio q.  From Eq. (lensing): conj(z) = N(z)/D(z) with
+// N = w z^2 + (1+q-dw) z - d, D = z^2 - d z, w = conj(zeta); substituting
+// back and clearing denominators gives (zeta - z) N M + M D + q N D = 0 with
+// M = N - d D = (w-d) z^2 + (1+q+d^2-dw) z - d.  Expanded here by hand.
+__device__ __forceinline__ void lens_coeffs(cx<double> zeta, double d, double q,
+                                            cx<double> c[6]) {
+  const cx<double> w = {zeta.re, -zeta.im};
+  const double opq = 1.0 + q;
+  const cx<double> n2 = w;
+  const cx<double> n1 = {fma(-d, w.re, opq), -d * w.im};
+  const cx<double> m2 = {w.re - d, w.im};
+  const cx<double> m1 = {fma(-d, w.re, fma(d, d, opq)), -d * w.im};
+  const double dd = d * d;
+  // products of N and M, by power of z (n0 = m0 = -d)
+  const cx<double> nm4 = c_mul(n2, m2);
+  const cx<double> nm3 = c_fma(n2, m1, c_mul(n1, m2));
+  const cx<double> s2 = {n2.re + m2.re, n2.im + m2.im};
+  const cx<double> nm2 = c_fma(n1, m1, cx<double>{-d * s2.re, -d * s2.im});
+  const cx<double> nm1 = {-d * (n1.re + m1.re), -d * (n1.im + m1.im)};
+  // (zeta - z) N M + M D + q N D
+  c[5] = {-nm4.re, -nm4.im};
+  // z^4: zeta nm4 - nm3 + m2 + q n2
+  c[4] = c_fma(zeta, nm4,
+               cx<double>{m2.re + fma(q, n2.re, -nm3.re),
+                          m2.im + fma(q, n2.im, -nm3.im)});
+  // z^3: zeta nm3 - nm2 + (m1 - d m2) + q (n1 - d n2)
+  c[3] = c_fma(zeta, nm3,
+               cx<double>{fma(-d, m2.re, m1.re) +
+                              fma(q, fma(-d, n2.re, n1.re), -nm2.re),
+                          fma(-d, m2.im, m1.im) +
+                              fma(q, fma(-d, n2.im, n1.im), -nm2.im)});
+  // z^2: zeta nm2 - nm1 + (m0 - d m1) + q (n0 - d n1)
+  c[2] = c_fma(zeta, nm2,
+               cx<double>{fma(-d, m1.re, -d) + fma(q, fma(-d, n1.re, -d), -nm1.re),
+                          fma(-d, m1.im, 0.0) + fma(q, -d * n1.im, -nm1.im)});
+  // z^1: zeta nm1 - nm0 - d m0 - q d n0 = zeta nm1 + q d^2
+  c[1] = c_fma(zeta, nm1, cx<double>{q * dd, 0.0});
+  // z^0: zeta nm0 = zeta d^2
+  c[0] = {zeta.re * dd, zeta.im * dd};
+}
+
+// p(z) and p'(z) by Horner's rule.
+template <typename T>
+__device__ __forceinline__ void horner(const cx<T> c[6], cx<T> z, cx<T>& p,
+                                       cx<T>& dp) {
+  dp = c[5];
+  p = c_fma(c[5], z, c[4]);
+#pragma unroll
+  for (int j = 3; j >= 0; --j) {
+    dp = c_fma(dp, z, p);
+    p = c_fma(p, z, c[j]);
+  }
+}
+
+// Starting points for a cold solve: five points on a circle about the root
+// centroid -c4/(5 c5) of radius (|c0|/|c5|)^(1/5) (geometric mean of the
+// root moduli); for a degree-4 polynomial four points and one root parked
+// far away, where it never moves.
+template <typename T>
+__device__ __forceinline__ void cold_start(const cx<T> c[6], bool deg4,
+                                           cx<T> z[5]) {
+  // cos/sin of 2 pi k/5 + 0.4 and 2 pi k/4 + 0.4
+  const float c5a[5] = {0.92106099f, 0.06083749f, -0.88523008f, -0.62472004f,
+                        0.52805164f};
+  const float s5a[5] = {0.38941834f, 0.99814771f, 0.46517413f, -0.78084257f,
+                        -0.84920782f};
+  const float c4a[4] = {0.92106099f, -0.38941834f, -0.92106099f, 0.38941834f};
+  const float s4a[4] = {0.38941834f, 0.92106099f, -0.38941834f, -0.92106099f};
+  const int lead = deg4 ? 4 : 5;
+  const float n_lead = (float)c_norm(c[lead]);
+  const float n_0 = (float)c_norm(c[0]);
+  float ratio = n_0 / n_lead;
+  if (!(ratio > 1e-30f) || !(ratio < 1e30f)) ratio = 1.0f;
+  const float R = powf(ratio, deg4 ? 0.125f : 0.1f);
+  // centroid = -c[lead-1] / (lead c[lead])
+  const cx<float> a = {(float)c[lead - 1].re, (float)c[lead - 1].im};
+  const cx<float> b = {(float)c[lead].re, (float)c[lead].im};
+  const float ib = 1.0f / (fmaf(b.re, b.re, b.im * b.im) * (float)lead);
+  const float cen_re = -(a.re * b.re + a.im * b.im) * ib;
+  const float cen_im = -(a.im * b.re - a.re * b.im) * ib;
+  if (deg4) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      z[k] = {(T)(cen_re + R * c4a[k]), (T)(cen_im + R * s4a[k])};
+    z[4] = {(T)1e18, (T)1e18};
+  } else {
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+      z[k] = {(T)(cen_re + R * c5a[k]), (T)(cen_im + R * s5a[k])};
+  }
+}
+
+// One Ehrlich-Aberth sweep (Jacobi form) over the five roots:
+//   w_i = p(z_i)/p'(z_i),  S_i = sum_{j != i} 1/(z_i - z_j),
+//   z_i <- z_i - w_i / (1 - w_i S_i).
+// Returns true when every step satisfied |dz_i| <= tol * max(1, |z_i|).
+template <typename T>
+__device__ __forceinline__ bool aberth_sweep(const cx<T> c[6], cx<T> z[5],
+                                             bool deg4, T tol2) {
+  cx<T> w[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    cx<T> p, dp;
+    horner(c, z[i], p, dp);
+    const T r = rcp_fast(c_norm(dp));
+    w[i] = {fma(p.re, dp.re, p.im * dp.im) * r,
+            fma(p.im, dp.re, -p.re * dp.im) * r};
+  }
+  cx<T> S[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) S[i] = {(T)0, (T)0};
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = i + 1; j < 5; ++j) {
+      const cx<T> dz = c_sub(z[i], z[j]);
+      const T r = rcp_fast(c_norm(dz));
+      const T ire = dz.re * r, iim = -dz.im * r;  // 1/(z_i - z_j)
+      S[i].re += ire;
+      S[i].im += iim;
+      S[j].re -= ire;
+      S[j].im -= iim;
+    }
+  bool conv = true;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    // den = 1 - w S
+    const cx<T> ws = c_mul(w[i], S[i]);
+    const cx<T> den = {(T)1 - ws.re, -ws.im};
+    const T r = rcp_fast(c_norm(den));
+    cx<T> dz = {fma(w[i].re, den.re, w[i].im * den.im) * r,
+                fma(w[i].im, den.re, -w[i].re * den.im) * r};
+    if (i == 4 && deg4) dz = {(T)0, (T)0};
+    z[i] = c_sub(z[i], dz);
+    const T zn = c_norm(z[i]);
+    conv = conv && (c_norm(dz) <= tol2 * (zn > (T)1 ? zn : (T)1));
+  }
+  return conv;
+}
+
+// ---------------------------------------------------------------- images
+
+#define SBLM_IMAGE_TOL2 1e-12 /* residual threshold 1e-6, squared */
+
+// Images, det J and the magnification from five FP64 roots.
+__device__ __forceinline__ double magnification(const cx<double> z[5],
+                                                cx<double> zeta, double d,
+                                                double q, bool deg4,
+                                                int& nimg) {
+  double r2[5], adet[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const double x = z[i].re, y = z[i].im;
+    // a = 1/conj(z) = z / |z|^2 ; b = 1/(d - conj(z))
+    const double iz = rcp_acc(fma(x, x, y * y));
+    const cx<double> a = {x * iz, y * iz};
+    const double ex = d - x;
+    const double ie = rcp_acc(fma(ex, ex, y * y));
+    const cx<double> b = {ex * ie, -y * ie};
+    // residual of Eq. (lensing): zeta - z + 1/conj(z) - q/(d - conj(z))
+    const cx<double> res = {fma(-q, b.re, (zeta.re - x) + a.re),
+                            fma(-q, b.im, (zeta.im - y) + a.im)};
+    r2[i] = c_norm(res);
+    // g = 1/conj(z)^2 + q/(d - conj(z))^2 = a^2 + q b^2
+    const cx<double> b2 = c_mul(b, b);
+    const cx<double> g = c_fma(a, a, cx<double>{q * b2.re, q * b2.im});
+    adet[i] = fabs(1.0 - c_norm(g));
+  }
+  if (deg4) r2[4] = INFINITY;
+  int below = 0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) below += (r2[i] < SBLM_IMAGE_TOL2) ? 1 : 0;
+  const bool five = !deg4 && below >= 4;
+  double A = 0.0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    int rank = 0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+      rank += (r2[j] < r2[i] || (r2[j] == r2[i] && j < i)) ? 1 : 0;
+    if (five || rank < 3) A += rcp_acc(adet[i]);
+  }
+  nimg = five ? 5 : 3;
+  return A;
+}
+
+// ---------------------------------------------------------------- fit
+
+// Square-root-free Givens state for columns (1, A | y): D = diag(d1, d2),
+// unit upper-triangular factor with off-diagonal r12, transformed right-hand
+// side (t1, t2) and the accumulated weighted residual sum of squares.
+struct Lsq {
+  double d1, d2, r12, t1, t2, sse;
+};
+
+// Include the row (x1, x2 | y) with weight w (Gentleman's algorithm).
+__device__ __forceinline__ void lsq_include(Lsq& s, double w, double x1,
+                                            double x2, double y) {
+  if (w == 0.0) return;
+  if (x1 != 0.0) {
+    const double wx = w * x1;
+    const double dp = fma(wx, x1, s.d1);
+    const double r = rcp_acc(dp);
+    const double cb = s.d1 * r, sb = wx * r;
+    w = cb * w;
+    s.d1 = dp;
+    const double xk = x2;
+    x2 = fma(-x1, s.r12, xk);
+    s.r12 = fma(cb, s.r12, sb * xk);
+    const double yk = y;
+    y = fma(-x1, s.t1, yk);
+    s.t1 = fma(cb, s.t1, sb * yk);
+  }
+  if (w == 0.0) return;
+  if (x2 != 0.0) {
+    const double wx = w * x2;
+    const double dp = fma(wx, x2, s.d2);
+    const double r = rcp_acc(dp);
+    const double cb = s.d2 * r, sb = wx * r;
+    w = cb * w;
+    s.d2 = dp;
+    const double yk = y;
+    y = fma(-x2, s.t2, yk);
+    s.t2 = fma(cb, s.t2, sb * yk);
+  }
+  s.sse = fma(w * y, y, s.sse);
+}
+
+// ---------------------------------------------------------------- kernel
+
+template <int G>
+__device__ __forceinline__ double grp_shfl_down(double v, int off) {
+  return __shfl_down(v, off, G);
+}
+
+struct LaneStats {
+  unsigned long long solves, iters, capped, fallback, deg4;
+};
+
+// Solve one polynomial from the roots in z (warm) or from a cold start.
+// Returns the number of FP64-equivalent sweeps this lane needed.
+template <int MODE>
+__device__ __forceinline__ void solve_roots(const cx<double> c[6], bool deg4,
+                                            bool warm, bool active,
+                                            cx<double> z[5], LaneStats& st,
+                                            bool& ok) {
+  constexpr int MAXIT64 = 60, MAXIT32 = 30;
+  const double tol64 = 1e-9 * 1e-9;
+  if (!warm && active) cold_start<double>(c, deg4, z);
+  int it_lane = 0, it32_lane = 0;
+  bool done = !active;
+  if (MODE == SBLM_MIXED) {
+    cx<float> cf[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) cf[j] = {(float)c[j].re, (float)c[j].im};
+    cx<float> zf[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) zf[i] = {(float)z[i].re, (float)z[i].im};
+    // degree-4 polynomials skip the FP32 phase (parked root out of range)
+    bool done32 = done || deg4;
+    for (int it = 0; it < MAXIT32; ++it) {
+      if (__all(done32)) break;
+      if (!done32) {
+        done32 = aberth_sweep<float>(cf, zf, false, 1e-4f * 1e-4f);
+        ++it32_lane;
+      }
+    }
+    if (active && !deg4) {
+#pragma unroll
+      for (int i = 0; i < 5; ++i) z[i] = {(double)zf[i].re, (double)zf[i].im};
+    }
+  }
+  for (int it = 0; it < MAXIT64; ++it) {
+    if (__all(done)) break;
+    if (!done) {
+      done = aberth_sweep<double>(c, z, deg4, tol64);
+      ++it_lane;
+    }
+  }
+  bool finite = true;
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+    finite = finite && isfinite(z[i].re) && isfinite(z[i].im);
+  ok = done && finite;
+  if (active) {
+    st.solves += 1;
+    st.iters += it_lane + it32_lane;
+    st.capped += done ? 0 : 1;
+    st.deg4 += deg4 ? 1 : 0;
+    if (MODE == SBLM_MIXED) st.fallback += (it_lane > 2) ? 1 : 0;
+  }
+}
+
+template <int MODE, bool CHI2, int G>
+__global__ __launch_bounds__(256) void fitness_kernel(FitArgs a) {
+  constexpr int GPW = 64 / G;  // individuals per wave
+  const int lane = threadIdx.x & 63;
+  const int gl = lane & (G - 1);  // lane within the group
+  // XCD-aware block order: consecutive logical blocks on one XCD
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int per = nb / 8, rem = nb % 8, xcd = b % 8, idx = b / 8;
+  const int lb = (xcd < rem) ? xcd * (per + 1) + idx
+                             : rem * (per + 1) + (xcd - rem) * per + idx;
+  const int wave = lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t item = (int64_t)wave * GPW + (lane / G);
+  const bool valid = item < a.n_ind;
+  const int64_t ind = valid ? (a.order ? (int64_t)a.order[item] : item) : 0;
+
+  // parameters of this individual (uniform within the group)
+  double th[SBLM_NPAR];
+#pragma unroll
+  for (int j = 0; j < SBLM_NPAR; ++j) {
+    const double v = valid ? a.theta[j * a.n_ind + ind] : 0.5;
+    th[j] = a.encoded ? a.lo[j] + a.span[j] * v : v;
+  }
+  const double q = exp10(th[0]);
+  const double d = th[1], u0 = th[2], tE = th[4], t0 = th[5];
+  double sa, ca;
+  sincos(th[3], &sa, &ca);
+  const double itE = 1.0 / tE;
+
+  int64_t e0 = 0, e1 = a.n_t;
+  if (a.off) {
+    const int64_t lc = ind / a.pop;
+    e0 = valid ? a.off[lc] : 0;
+    e1 = valid ? a.off[lc + 1] : 0;
+  }
+  if (!valid) e1 = e0;
+  const int64_t L = e1 - e0;
+  // chunk length: uniform across the wave (max over its groups)
+  int64_t Cg = (L + G - 1) / G;
+  int64_t C = Cg;
+#pragma unroll
+  for (int o = G; o < 64; o <<= 1) {
+    const int64_t oc = __shfl_xor(C, o, 64);
+    C = oc > C ? oc : C;
+  }
+  const int64_t k0 = e0 + gl * Cg;
+  const int64_t k1 = (k0 + Cg < e1) ? k0 + Cg : e1;
+
+  LaneStats st = {0, 0, 0, 0, 0};
+  Lsq ls = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  cx<double> z[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) z[i] = {0.0, 0.0};
+  bool have_prev = false, prev_deg4 = false;
+
+  for (int64_t s = 0; s < C; ++s) {
+    const int64_t k = k0 + s;
+    const bool active = (s < Cg) && (k < k1);
+    const double t = active ? a.t[k] : t0;
+    const double tau = (t - t0) * itE;
+    // Eq. (sourcePos)
+    const cx<double> zeta = {fma(tau, sa, u0 * ca), fma(-tau, ca, u0 * sa)};
+    cx<double> c[6];
+    lens_coeffs(zeta, d, q, c);
+    double cmax = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) cmax = fmax(cmax, c_norm(c[j]));
+    const bool deg4 = c_norm(c[5]) <= 1e-24 * cmax;
+    if (deg4) c[5] = {0.0, 0.0};
+    const bool warm = have_prev && !deg4 && !prev_deg4;
+    bool ok;
+    solve_roots<MODE>(c, deg4, warm, active, z, st, ok);
+    have_prev = ok;
+    prev_deg4 = deg4;
+    if (active) {
+      int nimg;
+      const double A = magnification(z, zeta, d, q, deg4, nimg);
+      if (CHI2) {
+        lsq_include(ls, a.w[k], 1.0, A, a.y[k]);
+      } else {
+        const int64_t o = ind * a.n_t + (k - e0);
+        a.A[o] = A;
+        if (a.n_img) a.n_img[o] = (int8_t)nimg;
+      }
+    }
+  }
+
+  if (CHI2) {
+    // lane gl absorbs lane gl + off: fixed tree inside each group
+#pragma unroll
+    for (int off = G / 2; off >= 1; off >>= 1) {
+      Lsq o;
+      o.d1 = grp_shfl_down<G>(ls.d1, off);
+      o.d2 = grp_shfl_down<G>(ls.d2, off);
+      o.r12 = grp_shfl_down<G>(ls.r12, off);
+      o.t1 = grp_shfl_down<G>(ls.t1, off);
+      o.t2 = grp_shfl_down<G>(ls.t2, off);
+      o.sse = grp_shfl_down<G>(ls.sse, off);
+      if (gl < off) {
+        lsq_include(ls, o.d1, 1.0, o.r12, o.t1);
+        lsq_include(ls, o.d2, 0.0, 1.0, o.t2);
+        ls.sse += o.sse;
+      }
+    }
+    if (gl == 0 && valid) {
+      const double saa = fma(ls.d1 * ls.r12, ls.r12, ls.d2);
+      double fs, fb, c2;
+      if (!(ls.d2 > 1e-14 * saa)) {  // singular 2x2 system
+        fs = 0.0;
+        fb = ls.t1;
+        c2 = fma(ls.d2 * ls.t2, ls.t2, ls.sse);
+        st.solves += 0;
+      } else {
+        fs = ls.t2;
+        fb = fma(-ls.r12, fs, ls.t1);
+        c2 = ls.sse;
+      }
+      a.chi2[ind] = c2;
+      a.Fs[ind] = fs;
+      a.Fb[ind] = fb;
+      if (a.stats && !(ls.d2 > 1e-14 * saa))
+        atomicAdd(&a.stats->n_degenerate, 1ull);
+    }
+  }
+
+  if (a.stats) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      st.solves += __shfl_down(st.solves, off, 64);
+      st.iters += __shfl_down(st.iters, off, 64);
+      st.capped += __shfl_down(st.capped, off, 64);
+      st.fallback += __shfl_down(st.fallback, off, 64);
+      st.deg4 += __shfl_down(st.deg4, off, 64);
+    }
+    if (lane == 0 && st.solves) {
+      atomicAdd(&a.stats->n_solves, st.solves);
+      atomicAdd(&a.stats->n_iter, st.iters);
+      if (st.capped) atomicAdd(&a.stats->n_capped, st.capped);
+      if (st.fallback) atomicAdd(&a.stats->n_fallback, st.fallback);
+      if (st.deg4) atomicAdd(&a.stats->n_degree4, st.deg4);
+    }
+  }
+}
+
+template <int MODE, bool CHI2>
+static hipError_t launch_g(const FitArgs& a, hipStream_t s, int wpb) {
+  const int G = a.lanes_per_ind;
+  const int64_t groups_per_block = (int64_t)wpb * (64 / G);
+  const int64_t nblk = (a.n_ind + groups_per_block - 1) / groups_per_block;
+  if (nblk <= 0) return hipSuccess;
+  dim3 grid((unsigned)nblk), block(64 * wpb);
+  if (G == 64)
+    hipLaunchKernelGGL((fitness_kernel<MODE, CHI2, 64>), grid, block, 0, s, a);
+  else if (G == 32)
+    hipLaunchKernelGGL((fitness_kernel<MODE, CHI2, 32>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((fitness_kernel<MODE, CHI2, 16>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fitness(const FitArgs& a, int mode, bool chi2,
+                          hipStream_t s, int wpb) {
+  if (mode == SBLM_MIXED)
+    return chi2 ? launch_g<SBLM_MIXED, true>(a, s, wpb)
+                : launch_g<SBLM_MIXED, false>(a, s, wpb);
+  return chi2 ? launch_g<SBLM_FP64, true>(a, s, wpb)
+              : launch_g<SBLM_FP64, false>(a, s, wpb);
+}
+
+}  // namespace sblm

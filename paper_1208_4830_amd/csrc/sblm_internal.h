@@ -1,0 +1,47 @@
+// sblm_internal.h -- declarations shared by the library's translation units
+// (kernels and host entry points).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sblm.h"
+
+namespace sblm {
+
+// Thread-local last-error message; returns `code` for convenient chaining.
+int set_error(int code, const char* fmt, ...);
+int check_hip(hipError_t e, const char* what);
+
+// Arguments of the batched fitness kernels (one wave per individual).
+struct FitArgs {
+  // population: theta[j * n_ind + i] decoded, or encoded P with lo/hi
+  const double* theta;
+  int64_t n_ind;
+  int32_t encoded;
+  double lo[SBLM_NPAR], span[SBLM_NPAR];
+  // epochs: either shared (off == nullptr, n_t epochs of t) or CSR per
+  // lightcurve (individual i uses lightcurve i / pop)
+  const int64_t* off;
+  int32_t pop;
+  const double* t;
+  const double* y;
+  const double* w;
+  int64_t n_t;
+  // outputs
+  double* A;        // [n_ind][n_t] (magnify)
+  int8_t* n_img;    // nullable (magnify)
+  double* chi2;     // [n_ind] (chi2)
+  double* Fs;
+  double* Fb;
+  sblm_stats* stats;  // nullable
+  // schedule
+  const int32_t* order;  // nullable: item -> individual permutation
+  int32_t lanes_per_ind;  // 64 or 32 or 16 (a power of two dividing 64)
+};
+
+// Launch the FP64 or mixed fitness kernel; chi2 = false writes A/n_img.
+hipError_t launch_fitness(const FitArgs& a, int mode, bool chi2,
+                          hipStream_t stream, int waves_per_block);
+
+}  // namespace sblm

@@ -1,0 +1,260 @@
+"""Thin ctypes binding of libsblm (C ABI declared in include/sblm.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device arrays are torch CUDA tensors (float64 / int64 / int8,
+contiguous); PyTorch supplies device memory and the stream.  There is no
+fallback: `load()` raises if libsblm.so is missing or fails to load.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsblm.so")
+NPAR = 6
+FP64, MIXED = 0, 1
+
+_lib = None
+
+
+class SblmError(RuntimeError):
+    pass
+
+
+class sblm_lcs(ctypes.Structure):
+    _fields_ = [("n_lc", ctypes.c_int32), ("off", ctypes.c_void_p), ("t", ctypes.c_void_p),
+                ("y", ctypes.c_void_p), ("w", ctypes.c_void_p)]
+
+
+class ea_config(ctypes.Structure):
+    _fields_ = [("pop", ctypes.c_int32), ("n_tourn", ctypes.c_int32),
+                ("p_mut0", ctypes.c_double), ("p_mut_min", ctypes.c_double),
+                ("p_mut_max", ctypes.c_double), ("stag_frac", ctypes.c_double),
+                ("stag_window", ctypes.c_int32), ("restart_after", ctypes.c_int32),
+                ("lo", ctypes.c_double * NPAR), ("hi", ctypes.c_double * NPAR),
+                ("mode", ctypes.c_int32)]
+
+
+class ea_lc_summary(ctypes.Structure):
+    _fields_ = [("best_chi2", ctypes.c_double), ("best_Fs", ctypes.c_double),
+                ("best_Fb", ctypes.c_double), ("best_theta", ctypes.c_double * NPAR),
+                ("best_gen", ctypes.c_int64), ("p_mut", ctypes.c_double),
+                ("stag_count", ctypes.c_int32), ("n_restarts", ctypes.c_int32),
+                ("gen", ctypes.c_int64), ("gen_restart", ctypes.c_int64)]
+
+
+STATS_FIELDS = ("n_solves", "n_iter", "n_capped", "n_fallback", "n_degree4", "n_degenerate")
+
+_SIGS = {
+    "sblm_magnify": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                     ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                     ctypes.c_void_p],
+    "sblm_chi2": [ctypes.POINTER(sblm_lcs), ctypes.c_void_p, ctypes.c_int32, ctypes.c_int,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_void_p],
+    "ea_default_config": [ctypes.POINTER(ea_config)],
+    "ea_create": [ctypes.POINTER(ea_config), ctypes.POINTER(sblm_lcs), ctypes.c_uint64,
+                  ctypes.POINTER(ctypes.c_void_p)],
+    "ea_generation": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                      ctypes.c_void_p],
+    "ea_evaluate": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "ea_fit": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p],
+    "ea_buffers": [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_void_p)] * 4,
+    "ea_summary": [ctypes.c_void_p, ctypes.POINTER(ea_lc_summary), ctypes.c_void_p],
+    "ea_save": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t),
+                ctypes.c_void_p],
+    "ea_load": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "ea_destroy": [ctypes.c_void_p],
+    "ea_draws": [ctypes.c_uint64] * 6 + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
+    "ea_generation_traced": [ctypes.c_void_p] * 6,
+    "sblm_last_error": [],
+}
+EXPORTS = tuple(_SIGS)
+
+
+def load():
+    """Load libsblm.so (once).  Raises SblmError if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise SblmError(f"{LIB_PATH} not built: run paper_1208_4830_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, args in _SIGS.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.sblm_last_error.restype = ctypes.c_char_p
+    lib.ea_default_config.restype = None
+    lib.ea_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        msg = load().sblm_last_error().decode()
+        raise SblmError(f"libsblm error {rc}: {msg}")
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(x, dtype=torch.float64):
+    if x is None:
+        return None
+    if not (x.is_cuda and x.dtype == dtype and x.is_contiguous()):
+        raise SblmError(f"expected a contiguous CUDA {dtype} tensor, got {x.dtype} on {x.device}")
+    return x
+
+
+def _ptr(x):
+    return ctypes.c_void_p(x.data_ptr()) if x is not None else None
+
+
+def new_stats(device="cuda"):
+    """Zeroed sblm_stats block (6 x uint64) as an int64 device tensor."""
+    return torch.zeros(len(STATS_FIELDS), dtype=torch.int64, device=device)
+
+
+def stats_dict(st):
+    return dict(zip(STATS_FIELDS, st.cpu().tolist()))
+
+
+def sblm_magnify(theta, t, mode=FP64, A=None, n_img=None, stats=None, stream=None):
+    """A[n][n_t] (and n_img[n][n_t] if given) for theta[6][n], epochs t[n_t]."""
+    lib = load()
+    theta, t = _dev(theta), _dev(t)
+    n, n_t = theta.shape[1], t.shape[0]
+    if A is None:
+        A = torch.empty((n, n_t), dtype=torch.float64, device=theta.device)
+    _dev(A), _dev(n_img, torch.int8), _dev(stats, torch.int64)
+    _check(lib.sblm_magnify(_ptr(theta), n, _ptr(t), n_t, mode, _ptr(A), _ptr(n_img),
+                            _ptr(stats), _stream(stream)))
+    return A
+
+
+class Lightcurves:
+    """Device CSR batch (keeps the tensors alive for the descriptor)."""
+
+    def __init__(self, off, t, y, w):
+        self.off = _dev(off, torch.int64)
+        self.t, self.y, self.w = _dev(t), _dev(y), _dev(w)
+        self.n_lc = self.off.shape[0] - 1
+        self.desc = sblm_lcs(self.n_lc, self.off.data_ptr(), self.t.data_ptr(),
+                             self.y.data_ptr(), self.w.data_ptr())
+
+
+def sblm_chi2(lcs, theta, pop, mode=FP64, chi2=None, Fs=None, Fb=None, stats=None,
+              stream=None):
+    """(chi2, Fs, Fb)[n_lc*pop] for decoded theta[6][n_lc*pop]."""
+    lib = load()
+    theta = _dev(theta)
+    n = lcs.n_lc * pop
+    outs = []
+    for x in (chi2, Fs, Fb):
+        outs.append(torch.empty(n, dtype=torch.float64, device=theta.device) if x is None
+                    else _dev(x))
+    _dev(stats, torch.int64)
+    _check(lib.sblm_chi2(ctypes.byref(lcs.desc), _ptr(theta), pop, mode, _ptr(outs[0]),
+                         _ptr(outs[1]), _ptr(outs[2]), _ptr(stats), _stream(stream)))
+    return tuple(outs)
+
+
+def ea_draws(seed, lc, gen, purpose, row, j0, n, device="cuda", stream=None):
+    """Raw Philox words of the EA's streams as an int64 tensor (bit pattern)."""
+    out = torch.empty(n, dtype=torch.int64, device=device)
+    _check(load().ea_draws(seed, lc, gen, purpose, row, j0, n, _ptr(out), _stream(stream)))
+    return out
+
+
+class SnapHeader(ctypes.Structure):
+    _fields_ = [("magic", ctypes.c_uint64), ("seed", ctypes.c_uint64), ("n_lc", ctypes.c_int32),
+                ("pop", ctypes.c_int32), ("cfg", ea_config), ("rec_size", ctypes.c_uint64)]
+
+
+def parse_snapshot(blob):
+    """(header, P[6][n_lc*pop], per-lightcurve records) from an ea_save blob."""
+    import numpy as np
+    hd = SnapHeader.from_buffer_copy(blob[:ctypes.sizeof(SnapHeader)])
+    n = hd.n_lc * hd.pop
+    o = ctypes.sizeof(SnapHeader)
+    P = np.frombuffer(blob, dtype=np.float64, count=6 * n, offset=o).reshape(6, n)
+    rec = np.dtype([("gen", "<i8"), ("gen_restart", "<i8"), ("best_gen", "<i8"),
+                    ("p_mut", "<f8"), ("stag_count", "<i4"), ("n_restarts", "<i4"),
+                    ("best_chi2", "<f8"), ("best_Fs", "<f8"), ("best_Fb", "<f8"),
+                    ("best_p", "<f8", (6,)), ("hist", "<f8", (64,))])
+    assert rec.itemsize == hd.rec_size
+    recs = np.frombuffer(blob, dtype=rec, count=hd.n_lc, offset=o + 6 * n * 8)
+    return hd, P.copy(), recs.copy()
+
+
+def ea_default_config():
+    cfg = ea_config()
+    load().ea_default_config(ctypes.byref(cfg))
+    return cfg
+
+
+class EAState:
+    """Owner of an ea_state* (device workspace of one batched fit)."""
+
+    def __init__(self, cfg, lcs, seed):
+        lib = load()
+        self.lcs = lcs  # keep the device arrays alive
+        self.cfg = cfg
+        h = ctypes.c_void_p()
+        _check(lib.ea_create(ctypes.byref(cfg), ctypes.byref(lcs.desc), seed, ctypes.byref(h)))
+        self.h = h
+        P, c, fs, fb = (ctypes.c_void_p() for _ in range(4))
+        _check(lib.ea_buffers(self.h, ctypes.byref(P), ctypes.byref(c), ctypes.byref(fs),
+                              ctypes.byref(fb)))
+        self._ptrs = dict(P=P.value, chi2=c.value, Fs=fs.value, Fb=fb.value)
+
+    def ptr(self, name):
+        return self._ptrs[name]
+
+    def generation(self, chi2, Fs, Fb, stream=None):
+        _check(load().ea_generation(self.h, _ptr(_dev(chi2)), _ptr(_dev(Fs)), _ptr(_dev(Fb)),
+                                    _stream(stream)))
+
+    def generation_traced(self, chi2, Fs, Fb, parents, stream=None):
+        _check(load().ea_generation_traced(self.h, _ptr(_dev(chi2)), _ptr(_dev(Fs)),
+                                           _ptr(_dev(Fb)), _ptr(_dev(parents, torch.int32)),
+                                           _stream(stream)))
+
+    def evaluate(self, stats=None, stream=None):
+        _check(load().ea_evaluate(self.h, _ptr(stats), _stream(stream)))
+
+    def fit(self, n_gen, stats=None, stream=None):
+        _check(load().ea_fit(self.h, n_gen, _ptr(stats), _stream(stream)))
+
+    def summary(self, stream=None):
+        out = (ea_lc_summary * self.lcs.n_lc)()
+        _check(load().ea_summary(self.h, out, _stream(stream)))
+        return out
+
+    def save(self, stream=None):
+        n = ctypes.c_size_t()
+        _check(load().ea_save(self.h, None, ctypes.byref(n), _stream(stream)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(load().ea_save(self.h, buf, ctypes.byref(n), _stream(stream)))
+        return buf.raw
+
+    def load(self, blob, stream=None):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(load().ea_load(self.h, buf, len(blob), _stream(stream)))
+
+    def close(self):
+        if self.h:
+            load().ea_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,172 @@
+"""Bit-exact parity of the device EA (Appendix A) with the oracle EA, given
+identical fitness, and of graph-replayed fits with stepped ones."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1208_4830_amd import inputs
+from tests.helpers import csr_workload, oracle_lightcurves, rel_err
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _cuda(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+def test_philox_draws_bit_exact(hip):
+    rng = np.random.default_rng(0)
+    for _ in range(12):
+        seed, lc, gen, purpose, row = (int(x) for x in rng.integers(0, 2 ** 40, 5))
+        j0 = int(rng.integers(0, 64))
+        got = hip.ea_draws(seed, lc, gen, purpose, row, j0, 37).cpu().numpy().view(np.uint64)
+        ref = np.array([O.draw(seed, lc, gen, purpose, row, j0 + k) for k in range(37)],
+                       dtype=np.uint64)
+        assert np.array_equal(got, ref)
+    # and against numpy's Philox4x64-10 (counter pre-incremented by numpy)
+    key = np.array([99, 3], dtype=np.uint64)
+    bg = np.random.Philox(key=key, counter=np.array([4, 2, 7, 0], dtype=np.uint64))
+    ref = bg.random_raw(4)
+    got = hip.ea_draws(99, 3, 5, 2, 7, 0, 4).cpu().numpy().view(np.uint64)
+    assert np.array_equal(got, ref)
+
+
+def _make_state(hip, wl, pop, seed, mode=0, **kw):
+    y, w = oracle_lightcurves(wl)
+    lcs = hip.Lightcurves(_cuda(wl.off, torch.int64), _cuda(wl.t), _cuda(y), _cuda(w))
+    cfg = hip.ea_default_config()
+    cfg.pop = pop
+    cfg.mode = mode
+    for k, v in kw.items():
+        setattr(cfg, k, v)
+    return hip.EAState(cfg, lcs, seed), y, w
+
+
+def _oracle_eas(n_lc, pop, seed, **kw):
+    return [O.EA(pop, seed, lc, **kw) for lc in range(n_lc)]
+
+
+def _population_rows(P, lc, pop):
+    """[pop][6] rows of lightcurve lc from the device layout [6][n_lc*pop]."""
+    return P[:, lc * pop:(lc + 1) * pop].T
+
+
+def _compare(hip, st, eas, pop):
+    _, P, rec = hip.parse_snapshot(st.save())
+    for lc, ea in enumerate(eas):
+        assert np.array_equal(_population_rows(P, lc, pop), ea.P), lc
+        s = ea.summary()
+        r = rec[lc]
+        assert r["gen"] == s["gen"] and r["gen_restart"] == s["gen_restart"]
+        assert r["p_mut"] == s["p_mut"] and r["stag_count"] == s["stag_count"]
+        assert r["n_restarts"] == s["n_restarts"]
+        assert r["best_chi2"] == s["best_chi2"] and r["best_gen"] == s["best_gen"]
+        if np.isfinite(s["best_chi2"]):
+            assert np.array_equal(r["best_p"], s["best_p"])
+    return P
+
+
+@pytest.mark.parametrize("pop", [48, 49, 128])
+def test_init_and_generations_bit_exact(hip, pop):
+    wl = csr_workload(5, [50, 70, 90])
+    st, _, _ = _make_state(hip, wl, pop, seed=1234)
+    eas = _oracle_eas(3, pop, 1234)
+    _compare(hip, st, eas, pop)
+    rng = np.random.default_rng(9)
+    npair = pop // 2
+    for g in range(40):
+        if g < 15:  # random fitness with ties, NaN and inf
+            chi2 = rng.uniform(10, 1000, 3 * pop)
+            chi2[rng.integers(0, 3 * pop, 5)] = np.nan
+            chi2[rng.integers(0, 3 * pop, 3)] = np.inf
+            chi2[::7] = chi2[1::7][: chi2[::7].size] if pop > 7 else chi2[::7]
+        else:  # constant fitness: stagnation flags, p_mut boosts, a restart
+            chi2 = np.full(3 * pop, 5.0)
+        Fs, Fb = rng.uniform(0.5, 1.5, 3 * pop), rng.uniform(0, 0.5, 3 * pop)
+        parents = torch.zeros(3 * 2 * npair, dtype=torch.int32, device=DEV)
+        st.generation_traced(_cuda(chi2), _cuda(Fs), _cuda(Fb), parents)
+        par = parents.cpu().numpy().reshape(3, 2 * npair)
+        for lc, ea in enumerate(eas):
+            sl = slice(lc * pop, (lc + 1) * pop)
+            ref = ea.generation(chi2[sl], Fs[sl], Fb[sl])
+            if ea.summary()["gen_restart"] != g + 1:  # restarts skip reproduction
+                assert np.array_equal(par[lc], ref), (g, lc)
+        _compare(hip, st, eas, pop)
+    assert all(ea.summary()["n_restarts"] >= 1 for ea in eas)
+
+
+def test_fit_graph_equals_stepping_and_oracle(hip):
+    # ea_fit (graph replay of evaluate + generation) must equal stepping
+    # generation by generation with sblm_chi2 on the decoded population, and
+    # the population must equal the oracle EA driven by the same fitness
+    wl = csr_workload(6, [120, 333, 400])
+    pop = 48
+    st_a, y, w = _make_state(hip, wl, pop, seed=77)
+    st_b, _, _ = _make_state(hip, wl, pop, seed=77)
+    cfg = st_a.cfg
+    lo = np.array(cfg.lo[:])
+    hi = np.array(cfg.hi[:])
+    eas = _oracle_eas(3, pop, 77)
+    ngen = 12
+    for g in range(ngen):
+        _, P, _ = hip.parse_snapshot(st_b.save())
+        theta = O.decode(P, lo, hi)
+        c, fs, fb = hip.sblm_chi2(st_b.lcs, _cuda(theta), pop)
+        if g == 0:  # GPU fitness of the stepped population vs the oracle's
+            co, _, _ = O.chi2(wl.off, wl.t, y, w, theta, pop)
+            assert np.all(rel_err(c.cpu().numpy(), co) < 1e-8)
+        st_b.generation(c, fs, fb)
+        cc, ff, bb = c.cpu().numpy(), fs.cpu().numpy(), fb.cpu().numpy()
+        for lc, ea in enumerate(eas):
+            sl = slice(lc * pop, (lc + 1) * pop)
+            ea.generation(cc[sl], ff[sl], bb[sl])
+    st_a.fit(ngen)
+    torch.cuda.synchronize()
+    blob_a, blob_b = st_a.save(), st_b.save()
+    assert blob_a == blob_b
+    _compare(hip, st_b, eas, pop)
+    summ = st_a.summary()
+    for lc in range(3):
+        assert summ[lc].gen == ngen
+        # best chi2 re-evaluated by the oracle at the decoded best parameters
+        th = np.array(summ[lc].best_theta[:])[:, None]
+        sl = slice(wl.off[lc], wl.off[lc + 1])
+        A, _ = O.magnify(th, wl.t[sl])
+        co, fso, fbo = O.lsq_chi2(A[0], y[sl], w[sl])
+        assert rel_err(summ[lc].best_chi2, co) < 1e-8
+
+
+def test_save_load_resume_bit_exact(hip):
+    wl = csr_workload(8, [200, 250])
+    pop = 64
+    st, _, _ = _make_state(hip, wl, pop, seed=5)
+    st.fit(7)
+    snap = st.save()
+    st.fit(9)
+    final = st.save()
+    st2, _, _ = _make_state(hip, wl, pop, seed=5)
+    st2.load(snap)
+    st2.fit(9)
+    assert st2.save() == final
+    # a snapshot does not load into a state with another seed
+    st3, _, _ = _make_state(hip, wl, pop, seed=6)
+    with pytest.raises(hip.SblmError):
+        st3.load(snap)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_fit_improves_and_best_is_monotone(hip, mode):
+    # one paper-shaped lightcurve: 400 uniform epochs over t0 +- 2 tE,
+    # sigma = 1% of the flux, population 48
+    wl = inputs.uniform_workload(1, 1, 400)
+    st, y, w = _make_state(hip, wl, 48, seed=1, mode=mode)
+    best = []
+    for _ in range(10):
+        st.fit(10)
+        best.append(st.summary()[0].best_chi2)
+    assert all(b2 <= b1 for b1, b2 in zip(best, best[1:]))
+    A, _ = O.magnify(wl.theta[:, :1], wl.t)
+    chi2_true, _, _ = O.lsq_chi2(A[0], y, w)
+    assert best[-1] < best[0] and np.isfinite(best[-1]) and chi2_true > 0
