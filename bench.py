@@ -122,9 +122,9 @@ def run_form(sblm, torch, lcs, wl, chi2_true, args, mode):
 
     if mode == sblm.FP64:
         flop = FLOP_COEF + sweeps * FLOP_SWEEP64 + FLOP_IMAGES + FLOP_LSQ
-    else:  # FP32 sweeps then FP64 sweeps (two per solve without fallback)
-        n64 = 2.0 + s["n_fallback"] / max(s["n_solves"], 1)
-        flop = FLOP_COEF + (sweeps - n64) * FLOP_SWEEP32 + n64 * FLOP_SWEEP64 \
+    else:  # FP32 sweeps, then FP64 sweeps
+        n32 = s["n_iter_fp32"] / max(s["n_solves"], 1)
+        flop = FLOP_COEF + n32 * FLOP_SWEEP32 + (sweeps - n32) * FLOP_SWEEP64 \
             + FLOP_IMAGES + FLOP_LSQ
     ms_step = dt * 1e3 / args.steps
     return dict(
@@ -135,7 +135,8 @@ def run_form(sblm, torch, lcs, wl, chi2_true, args, mode):
         kernel_ms=k_ms, kernel_mags_per_s=mags_per_gen / (k_ms / 1e3),
         sweeps_per_solve=sweeps, flop_per_mag=flop,
         kernel_tflops=flop * mags_per_gen / (k_ms / 1e3) / 1e12,
-        capped=s["n_capped"], fallback=s["n_fallback"])
+        capped=s["n_capped"], fallback=s["n_fallback"],
+        wave_sweeps_per_solve=s["n_wave_iter"] / max(s["n_solves"], 1))
 
 
 def cpu_baseline(wl, y, w, pop, target_s):

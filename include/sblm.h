@@ -75,9 +75,14 @@ typedef struct {
   unsigned long long n_solves;     /* polynomials solved                      */
   unsigned long long n_iter;       /* simultaneous-iteration sweeps, summed   */
   unsigned long long n_capped;     /* solves that hit the iteration cap       */
-  unsigned long long n_fallback;   /* MIXED: lanes re-solved in FP64          */
+  unsigned long long n_fallback;   /* MIXED: cold solves whose FP32 roots
+                                      needed > 2 FP64 sweeps to converge      */
   unsigned long long n_degree4;    /* leading coefficient negligible          */
   unsigned long long n_degenerate; /* chi^2 fits with a singular 2x2 system   */
+  unsigned long long n_wave_iter;  /* sweeps the wavefront executed, summed
+                                      over the solves of its lanes (lockstep
+                                      cost; n_iter is the lanes' own need)    */
+  unsigned long long n_iter_fp32;  /* MIXED: the FP32 part of n_iter          */
 } sblm_stats;
 
 /* Ragged batch of lightcurves in CSR form.  Lightcurve k owns epochs

@@ -25,17 +25,18 @@ int check_hip(hipError_t e, const char* what) {
   return set_error(SBLM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Lanes per individual: the largest of 64, 32, 16 that still gives every
-// lane a chunk of at least 8 epochs (warm starts amortise the cold start of
-// each chunk), overridable with SBLM_LANES for tuning runs.
+// Lanes per individual.  Fewer lanes give every lane a longer chunk of
+// consecutive epochs, so a smaller share of its solves start cold; on the
+// MI355X 16 lanes per individual were fastest for 1000-epoch lightcurves
+// (17.9 vs 16.8 and 15.4 Gmag/s for 32 and 64).  Overridable with
+// SBLM_LANES (16, 32 or 64) for tuning runs.
 static int choose_group(double mean_len) {
   const char* env = getenv("SBLM_LANES");
   if (env) {
     int g = atoi(env);
     if (g == 16 || g == 32 || g == 64) return g;
   }
-  if (mean_len >= 64.0 * 8) return 64;
-  if (mean_len >= 32.0 * 8) return 32;
+  (void)mean_len;
   return 16;
 }
 

@@ -469,7 +469,7 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
   p.seed = seed;
   p.n_ind = (int64_t)p.n_lc * p.pop;
   const char* env = getenv("SBLM_LANES");
-  s.lanes = 64;
+  s.lanes = 16;
   if (env && (atoi(env) == 16 || atoi(env) == 32 || atoi(env) == 64)) s.lanes = atoi(env);
   const size_t nb = (size_t)p.n_ind * sizeof(double);
   if (hipMalloc(&s.P, SBLM_NPAR * nb) != hipSuccess || hipMalloc(&s.chi2, nb) != hipSuccess ||

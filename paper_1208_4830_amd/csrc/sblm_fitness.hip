@@ -74,6 +74,11 @@ __device__ __forceinline__ double rcp_fast(double x) {
 __device__ __forceinline__ float rcp_fast(float x) {
   return __builtin_amdgcn_rcpf(x);
 }
+// Raw hardware reciprocal (relative error < 5e-8 in FP64): used only for the
+// pairwise terms of the Aberth correction, whose error scales the size of a
+// correction that is itself second order.
+__device__ __forceinline__ double rcp_raw(double x) { return __builtin_amdgcn_rcp(x); }
+__device__ __forceinline__ float rcp_raw(float x) { return __builtin_amdgcn_rcpf(x); }
 // Reciprocal to about 1 ulp, for det J, image positions and the fit.
 __device__ __forceinline__ double rcp_acc(double x) {
   double r = __builtin_amdgcn_rcp(x);
@@ -177,50 +182,65 @@ __device__ __forceinline__ void cold_start(const cx<T> c[6], bool deg4,
 }
 
 // One Ehrlich-Aberth sweep (Jacobi form) over the five roots:
-//   w_i = p(z_i)/p'(z_i),  S_i = sum_{j != i} 1/(z_i - z_j),
-//   z_i <- z_i - w_i / (1 - w_i S_i).
-// Returns true when every step satisfied |dz_i| <= tol * max(1, |z_i|).
+//   S_i = sum_{j != i} 1/(z_i - z_j),
+//   z_i <- z_i - p(z_i) / (p'(z_i) - p(z_i) S_i),
+// (the usual w/(1 - w S) with w = p/p', written with one complex division).
+// The iteration converges cubically: after a step of length e the error
+// left in z_i is about e^3 / s_i^2, s_i the distance to the nearest other
+// root.  Returns 1 when, for every root, e^3 / (s_i^2 max(1,|z_i|)) <= tau or
+// e <= 1e-13 max(1,|z_i|) (a step at the rounding level, which also ends the
+// slow approach of a double root).  *emax receives max_i e_i^2 / max(1,|z_i|^2).
 template <typename T>
 __device__ __forceinline__ bool aberth_sweep(const cx<T> c[6], cx<T> z[5],
-                                             bool deg4, T tol2) {
-  cx<T> w[5];
+                                             bool deg4, T tau, T* emax) {
+  cx<T> p[5], dp[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) horner(c, z[i], p[i], dp[i]);
+  cx<T> S[5];
+  T rmax[5];  // 1 / (distance to the nearest other root)^2
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
-    cx<T> p, dp;
-    horner(c, z[i], p, dp);
-    const T r = rcp_fast(c_norm(dp));
-    w[i] = {fma(p.re, dp.re, p.im * dp.im) * r,
-            fma(p.im, dp.re, -p.re * dp.im) * r};
+    S[i] = {(T)0, (T)0};
+    rmax[i] = (T)0;
   }
-  cx<T> S[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) S[i] = {(T)0, (T)0};
 #pragma unroll
   for (int i = 0; i < 5; ++i)
 #pragma unroll
     for (int j = i + 1; j < 5; ++j) {
       const cx<T> dz = c_sub(z[i], z[j]);
-      const T r = rcp_fast(c_norm(dz));
+      const T r = rcp_raw(c_norm(dz));
       const T ire = dz.re * r, iim = -dz.im * r;  // 1/(z_i - z_j)
       S[i].re += ire;
       S[i].im += iim;
       S[j].re -= ire;
       S[j].im -= iim;
+      rmax[i] = r > rmax[i] ? r : rmax[i];
+      rmax[j] = r > rmax[j] ? r : rmax[j];
     }
   bool conv = true;
+  T em = (T)0;
+  const T tau2 = tau * tau;
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
-    // den = 1 - w S
-    const cx<T> ws = c_mul(w[i], S[i]);
-    const cx<T> den = {(T)1 - ws.re, -ws.im};
+    // den = p' - p S ; dz = p / den
+    const cx<T> pS = c_mul(p[i], S[i]);
+    const cx<T> den = c_sub(dp[i], pS);
     const T r = rcp_fast(c_norm(den));
-    cx<T> dz = {fma(w[i].re, den.re, w[i].im * den.im) * r,
-                fma(w[i].im, den.re, -w[i].re * den.im) * r};
+    cx<T> dz = {fma(p[i].re, den.re, p[i].im * den.im) * r,
+                fma(p[i].im, den.re, -p[i].re * den.im) * r};
     if (i == 4 && deg4) dz = {(T)0, (T)0};
     z[i] = c_sub(z[i], dz);
     const T zn = c_norm(z[i]);
-    conv = conv && (c_norm(dz) <= tol2 * (zn > (T)1 ? zn : (T)1));
+    const T sc = zn > (T)1 ? zn : (T)1;
+    const T e2 = c_norm(dz);
+    // (e^2)^3 (1/s^2)^2 <= tau^2 |z|^2, or e^2 <= 1e-26 |z|^2
+    const bool ok = (e2 * e2 * e2 * (rmax[i] * rmax[i]) <= tau2 * sc) ||
+                    (e2 <= (T)1e-26 * sc);
+    conv = conv && (ok || (i == 4 && deg4));
+    const T er = e2 / sc;
+    em = er > em ? er : em;
   }
+  *emax = em;
   return conv;
 }
 
@@ -320,7 +340,7 @@ __device__ __forceinline__ double grp_shfl_down(double v, int off) {
 }
 
 struct LaneStats {
-  unsigned long long solves, iters, capped, fallback, deg4;
+  unsigned long long solves, iters, capped, fallback, deg4, wave_iters, iters32;
 };
 
 // Solve one polynomial from the roots in z (warm) or from a cold start.
@@ -331,9 +351,11 @@ __device__ __forceinline__ void solve_roots(const cx<double> c[6], bool deg4,
                                             cx<double> z[5], LaneStats& st,
                                             bool& ok) {
   constexpr int MAXIT64 = 60, MAXIT32 = 30;
-  const double tol64 = 1e-9 * 1e-9;
+  // estimated relative error left after the last step
+  const double tau64 = 1e-16;
+  const float tau32 = 1e-7f;
   if (!warm && active) cold_start<double>(c, deg4, z);
-  int it_lane = 0, it32_lane = 0;
+  int it_lane = 0, it32_lane = 0, it_wave = 0;
   bool done = !active;
   if (MODE == SBLM_MIXED) {
     cx<float> cf[6];
@@ -342,12 +364,21 @@ __device__ __forceinline__ void solve_roots(const cx<double> c[6], bool deg4,
     cx<float> zf[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) zf[i] = {(float)z[i].re, (float)z[i].im};
-    // degree-4 polynomials skip the FP32 phase (parked root out of range)
-    bool done32 = done || deg4;
+    // The FP32 phase runs the solves that start cold (the long part of the
+    // iteration); a warm start is already closer to the roots than FP32 can
+    // resolve, so those solves and degree-4 polynomials (parked root out of
+    // FP32 range) go straight to FP64.  The FP32 phase also ends when its
+    // steps stop shrinking: the roots are then at the FP32 rounding floor.
+    bool done32 = done || deg4 || warm;
+    float prev = INFINITY;
     for (int it = 0; it < MAXIT32; ++it) {
       if (__all(done32)) break;
+      ++it_wave;
       if (!done32) {
-        done32 = aberth_sweep<float>(cf, zf, false, 1e-4f * 1e-4f);
+        float em;
+        done32 = aberth_sweep<float>(cf, zf, false, tau32, &em);
+        done32 = done32 || (em > 0.25f * prev);  // |dz| shrank by < 2x
+        prev = em;
         ++it32_lane;
       }
     }
@@ -358,8 +389,10 @@ __device__ __forceinline__ void solve_roots(const cx<double> c[6], bool deg4,
   }
   for (int it = 0; it < MAXIT64; ++it) {
     if (__all(done)) break;
+    ++it_wave;
     if (!done) {
-      done = aberth_sweep<double>(c, z, deg4, tol64);
+      double em;
+      done = aberth_sweep<double>(c, z, deg4, tau64, &em);
       ++it_lane;
     }
   }
@@ -373,12 +406,19 @@ __device__ __forceinline__ void solve_roots(const cx<double> c[6], bool deg4,
     st.iters += it_lane + it32_lane;
     st.capped += done ? 0 : 1;
     st.deg4 += deg4 ? 1 : 0;
-    if (MODE == SBLM_MIXED) st.fallback += (it_lane > 2) ? 1 : 0;
+    // MIXED: a cold solve whose FP32 result needed more than two FP64 sweeps
+    if (MODE == SBLM_MIXED) st.fallback += (!warm && it_lane > 2) ? 1 : 0;
+    st.wave_iters += it_wave;
+    st.iters32 += it32_lane;
   }
 }
 
+#ifndef SBLM_MIN_WAVES_PER_EU
+#define SBLM_MIN_WAVES_PER_EU 1
+#endif
+
 template <int MODE, bool CHI2, int G>
-__global__ __launch_bounds__(256) void fitness_kernel(FitArgs a) {
+__global__ __launch_bounds__(256, SBLM_MIN_WAVES_PER_EU) void fitness_kernel(FitArgs a) {
   constexpr int GPW = 64 / G;  // individuals per wave
   const int lane = threadIdx.x & 63;
   const int gl = lane & (G - 1);  // lane within the group
@@ -424,12 +464,16 @@ __global__ __launch_bounds__(256) void fitness_kernel(FitArgs a) {
   const int64_t k0 = e0 + gl * Cg;
   const int64_t k1 = (k0 + Cg < e1) ? k0 + Cg : e1;
 
-  LaneStats st = {0, 0, 0, 0, 0};
+  LaneStats st = {0, 0, 0, 0, 0, 0, 0};
   Lsq ls = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   cx<double> z[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i) z[i] = {0.0, 0.0};
-  bool have_prev = false, prev_deg4 = false;
+  cx<double> zp[5];  // roots of the epoch before the previous one
+#pragma unroll
+  for (int i = 0; i < 5; ++i) zp[i] = {0.0, 0.0};
+  bool have_prev = false, prev_deg4 = false, have_prev2 = false;
+  double t1 = 0.0, t2 = 0.0;  // epochs of z and zp
 
   for (int64_t s = 0; s < C; ++s) {
     const int64_t k = k0 + s;
@@ -446,8 +490,26 @@ __global__ __launch_bounds__(256) void fitness_kernel(FitArgs a) {
     const bool deg4 = c_norm(c[5]) <= 1e-24 * cmax;
     if (deg4) c[5] = {0.0, 0.0};
     const bool warm = have_prev && !deg4 && !prev_deg4;
+    // Linear extrapolation of every root from the two previous epochs,
+    // scaled by the ratio of epoch spacings (clamped to [0, 4]).
+    cx<double> zs[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) zs[i] = z[i];
+    if (warm && have_prev2) {
+      const double gap = t1 - t2;
+      double r = gap != 0.0 ? (t - t1) / gap : 0.0;
+      r = fmin(fmax(r, 0.0), 4.0);
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+        z[i] = {fma(r, z[i].re - zp[i].re, z[i].re), fma(r, z[i].im - zp[i].im, z[i].im)};
+    }
     bool ok;
     solve_roots<MODE>(c, deg4, warm, active, z, st, ok);
+    have_prev2 = warm && ok;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) zp[i] = zs[i];
+    t2 = t1;
+    t1 = t;
     have_prev = ok;
     prev_deg4 = deg4;
     if (active) {
@@ -487,7 +549,6 @@ __global__ __launch_bounds__(256) void fitness_kernel(FitArgs a) {
         fs = 0.0;
         fb = ls.t1;
         c2 = fma(ls.d2 * ls.t2, ls.t2, ls.sse);
-        st.solves += 0;
       } else {
         fs = ls.t2;
         fb = fma(-ls.r12, fs, ls.t1);
@@ -509,6 +570,8 @@ __global__ __launch_bounds__(256) void fitness_kernel(FitArgs a) {
       st.capped += __shfl_down(st.capped, off, 64);
       st.fallback += __shfl_down(st.fallback, off, 64);
       st.deg4 += __shfl_down(st.deg4, off, 64);
+      st.wave_iters += __shfl_down(st.wave_iters, off, 64);
+      st.iters32 += __shfl_down(st.iters32, off, 64);
     }
     if (lane == 0 && st.solves) {
       atomicAdd(&a.stats->n_solves, st.solves);
@@ -516,6 +579,8 @@ __global__ __launch_bounds__(256) void fitness_kernel(FitArgs a) {
       if (st.capped) atomicAdd(&a.stats->n_capped, st.capped);
       if (st.fallback) atomicAdd(&a.stats->n_fallback, st.fallback);
       if (st.deg4) atomicAdd(&a.stats->n_degree4, st.deg4);
+      atomicAdd(&a.stats->n_wave_iter, st.wave_iters);
+      if (st.iters32) atomicAdd(&a.stats->n_iter_fp32, st.iters32);
     }
   }
 }

@@ -11,7 +11,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsblm.so")
+# SBLM_LIB selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("SBLM_LIB", os.path.join(_HERE, "libsblm.so"))
 NPAR = 6
 FP64, MIXED = 0, 1
 
@@ -44,7 +45,8 @@ class ea_lc_summary(ctypes.Structure):
                 ("gen", ctypes.c_int64), ("gen_restart", ctypes.c_int64)]
 
 
-STATS_FIELDS = ("n_solves", "n_iter", "n_capped", "n_fallback", "n_degree4", "n_degenerate")
+STATS_FIELDS = ("n_solves", "n_iter", "n_capped", "n_fallback", "n_degree4", "n_degenerate",
+                "n_wave_iter", "n_iter_fp32")
 
 _SIGS = {
     "sblm_magnify": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
@@ -117,7 +119,7 @@ def _ptr(x):
 
 
 def new_stats(device="cuda"):
-    """Zeroed sblm_stats block (6 x uint64) as an int64 device tensor."""
+    """Zeroed sblm_stats block (8 x uint64) as an int64 device tensor."""
     return torch.zeros(len(STATS_FIELDS), dtype=torch.int64, device=device)
 
 
