@@ -52,6 +52,10 @@ def parse():
                     help="target wall time of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=10)
+    ap.add_argument("--ragged-lc", type=int, default=4096,
+                    help="lightcurves of the ragged workload (0 = skip it)")
+    ap.add_argument("--ragged-steps", type=int, default=30)
+    ap.add_argument("--no-autotune", action="store_true")
     return ap.parse_args()
 
 
@@ -59,35 +63,39 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_batch(sblm, torch, n_lc, L, seed=2):
-    """Synthetic batch; observations from the library's own forward model."""
-    from paper_1208_4830_amd import inputs
-    wl = inputs.uniform_workload(seed, n_lc, L)
+def make_batch(sblm, torch, wl):
+    """Device lightcurves; observations from the library's own forward model."""
     dev = "cuda"
     t = torch.as_tensor(wl.t, device=dev)
     A = torch.empty(wl.t.size, dtype=torch.float64, device=dev)
-    for k in range(n_lc):  # each lightcurve has its own epochs
+    for k in range(wl.n_lc):  # each lightcurve has its own epochs
         a, b = int(wl.off[k]), int(wl.off[k + 1])
         A[a:b] = sblm.sblm_magnify(torch.as_tensor(wl.theta[:, k:k + 1].copy(), device=dev),
                                    t[a:b].contiguous())[0]
     A = A.cpu().numpy()
-    F = wl.Fs.repeat(L) * A + wl.Fb.repeat(L)
+    L = np.diff(wl.off)
+    F = np.repeat(wl.Fs, L) * A + np.repeat(wl.Fb, L)
     sig = wl.sfrac * F
     y = F + sig * wl.noise
     w = 1.0 / sig ** 2
     lcs = sblm.Lightcurves(torch.as_tensor(wl.off, device=dev), t,
                            torch.as_tensor(y, device=dev), torch.as_tensor(w, device=dev))
-    return wl, y, w, lcs
+    return y, w, lcs
 
 
-def run_form(sblm, torch, lcs, wl, chi2_true, args, mode):
-    n_lc, L, pop = args.n_lc, args.epochs, args.pop
-    mags_per_gen = n_lc * pop * L
+def run_form(sblm, torch, lcs, wl, chi2_true, pop, steps, args, mode, tune=True):
+    n_lc = wl.n_lc
+    mags_per_gen = pop * int(wl.off[-1])
     cfg = sblm.ea_default_config()
     cfg.pop = pop
     cfg.mode = mode
-    # warm-up on a scratch state (same shapes, graph already captured)
+    # warm-up and schedule choice on a scratch state (same shapes)
     scratch = sblm.EAState(cfg, lcs, 999)
+    report = ""
+    if tune and not args.no_autotune:
+        report = scratch.autotune()
+        log("bench: autotune\n" + report.strip())
+    sched = scratch.schedule()
     scratch.fit(args.warmup)
     torch.cuda.synchronize()
     # sweeps per solve (lane level) for the algorithmic FLOP count
@@ -108,11 +116,12 @@ def run_form(sblm, torch, lcs, wl, chi2_true, args, mode):
     k_ms = e0.elapsed_time(e1) / args.kernel_reps
     scratch.close()
 
-    # the timed fit: fresh state, `steps` generations
+    # the timed fit: fresh state with the chosen schedule, `steps` generations
     state = sblm.EAState(cfg, lcs, 1)
+    state.set_schedule(*sched)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    state.fit(args.steps)
+    state.fit(steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     summ = state.summary()
@@ -126,17 +135,18 @@ def run_form(sblm, torch, lcs, wl, chi2_true, args, mode):
         n32 = s["n_iter_fp32"] / max(s["n_solves"], 1)
         flop = FLOP_COEF + n32 * FLOP_SWEEP32 + (sweeps - n32) * FLOP_SWEEP64 \
             + FLOP_IMAGES + FLOP_LSQ
-    ms_step = dt * 1e3 / args.steps
+    ms_step = dt * 1e3 / steps
     return dict(
-        mags_per_s=mags_per_gen * args.steps / dt,
+        mags_per_s=mags_per_gen * steps / dt,
         ms_per_step=ms_step,
         fits_per_hour=n_lc * 3600.0 / (N_GEN_FIT * ms_step / 1e3),
-        success=success, generations=args.steps,
+        success=success, generations=steps,
         kernel_ms=k_ms, kernel_mags_per_s=mags_per_gen / (k_ms / 1e3),
         sweeps_per_solve=sweeps, flop_per_mag=flop,
         kernel_tflops=flop * mags_per_gen / (k_ms / 1e3) / 1e12,
         capped=s["n_capped"], fallback=s["n_fallback"],
-        wave_sweeps_per_solve=s["n_wave_iter"] / max(s["n_solves"], 1))
+        wave_sweeps_per_solve=s["n_wave_iter"] / max(s["n_solves"], 1),
+        schedule=dict(zip(("lanes", "waves_per_block", "persistent"), sched)))
 
 
 def cpu_baseline(wl, y, w, pop, target_s):
@@ -177,10 +187,12 @@ def main():
     from paper_1208_4830_amd import sblm
     sblm.load()
     assert torch.cuda.is_available()
+    from paper_1208_4830_amd import inputs
     log(f"bench: {args.n_lc} lightcurves x {args.epochs} epochs, pop {args.pop}, "
         f"{args.steps} generations")
-    wl, y, w, lcs = make_batch(sblm, torch, args.n_lc, args.epochs)
-    th_true = torch.as_tensor(np.repeat(wl.theta, 1, axis=1).copy(), device="cuda")
+    wl = inputs.uniform_workload(2, args.n_lc, args.epochs)
+    y, w, lcs = make_batch(sblm, torch, wl)
+    th_true = torch.as_tensor(wl.theta.copy(), device="cuda")
     c_true, _, _ = sblm.sblm_chi2(lcs, th_true, 1)
     chi2_true = c_true.cpu().numpy()
 
@@ -188,9 +200,22 @@ def main():
     for name in args.forms.split(","):
         mode = sblm.FP64 if name == "fp64" else sblm.MIXED
         log(f"bench: form {name}")
-        forms[name] = run_form(sblm, torch, lcs, wl, chi2_true, args, mode)
+        forms[name] = run_form(sblm, torch, lcs, wl, chi2_true, args.pop, args.steps, args, mode)
         log(f"bench: {name}: {json.dumps(forms[name])}")
     main_form = forms.get("fp64") or next(iter(forms.values()))
+
+    ragged = None
+    if args.ragged_lc > 0:
+        log(f"bench: ragged workload, {args.ragged_lc} lightcurves of 200-5000 epochs, pop 128")
+        wr = inputs.ragged_workload(4, args.ragged_lc)
+        yr, wr_w, lcs_r = make_batch(sblm, torch, wr)
+        c_true_r, _, _ = sblm.sblm_chi2(lcs_r, torch.as_tensor(wr.theta.copy(), device="cuda"), 1)
+        ragged = run_form(sblm, torch, lcs_r, wr, c_true_r.cpu().numpy(), 128,
+                          args.ragged_steps, args, sblm.FP64)
+        ragged["workload"] = (f"{args.ragged_lc} lightcurves, L ~ U{{200..5000}} "
+                              f"(total {int(wr.off[-1])} epochs), nightly cadence, pop 128")
+        log(f"bench: ragged: {json.dumps(ragged)}")
+        del lcs_r
 
     cpu = None
     if not args.no_cpu:
@@ -213,6 +238,7 @@ def main():
         "fits_per_hour": main_form["fits_per_hour"],
         "success_rate": main_form["success"],
         "forms": forms,
+        "ragged": ragged,
         "roofline": {"bound": "alu", "achieved": main_form["kernel_tflops"],
                      "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": main_form["kernel_tflops"] / PEAK_VALU_TFLOPS, "traffic": None,

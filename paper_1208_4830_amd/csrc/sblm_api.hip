@@ -44,7 +44,7 @@ static int waves_per_block() {
   const char* env = getenv("SBLM_WAVES_PER_BLOCK");
   if (env) {
     int w = atoi(env);
-    if (w >= 1 && w <= 16) return w;
+    if (w == 1 || w == 2 || w == 4) return w;  // blocks of <= 256 threads
   }
   return 4;
 }

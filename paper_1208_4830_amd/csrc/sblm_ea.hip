@@ -315,8 +315,16 @@ struct EaStateImpl {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipGraphExec_t graph = nullptr;
   sblm_stats* graph_stats = nullptr;
-  int lanes = 64;
+  // fitness schedule (chosen by ea_autotune): lanes per individual, waves
+  // per block, persistent launch with a work counter
+  int lanes = 16;
+  int wpb = 4;
+  int persistent = 1;
+  int32_t* order = nullptr;    // item -> individual, longest lightcurves first
+  unsigned int* queue = nullptr;
 };
+
+__global__ void queue_reset_kernel(unsigned int* q) { *q = 0u; }
 
 static size_t gen_smem(int pop) {
   return (size_t)pop * (SBLM_NPAR * sizeof(double) + sizeof(double) + sizeof(int));
@@ -358,7 +366,14 @@ static hipError_t enqueue_evaluate(EaStateImpl* s, sblm_stats* stats,
   a.Fb = s->Fb;
   a.stats = stats;
   a.lanes_per_ind = s->lanes;
-  return launch_fitness(a, s->cfg.mode, true, st, 4);
+  a.order = s->order;
+  if (s->persistent) {
+    a.queue = s->queue;
+    hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(1), 0, st, s->queue);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return launch_fitness(a, s->cfg.mode, true, st, s->wpb);
 }
 
 }  // namespace sblm
@@ -432,6 +447,8 @@ extern "C" void ea_destroy(ea_state* st) {
   (void)hipFree(s.Fs);
   (void)hipFree(s.Fb);
   (void)hipFree(s.lc);
+  (void)hipFree(s.order);
+  (void)hipFree(s.queue);
   (void)hipSetDevice(prev);
   st->~ea_state();
   free(st);
@@ -472,9 +489,62 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
   s.lanes = 16;
   if (env && (atoi(env) == 16 || atoi(env) == 32 || atoi(env) == 64)) s.lanes = atoi(env);
   const size_t nb = (size_t)p.n_ind * sizeof(double);
+  // longest-processing-time order of the work items: lightcurves by length,
+  // longest first (stable), the individuals of each lightcurve together
+  int64_t* off_h = (int64_t*)malloc((size_t)(p.n_lc + 1) * sizeof(int64_t));
+  int32_t* order_h = (int32_t*)malloc((size_t)p.n_ind * sizeof(int32_t));
+  int32_t* lcs_sorted = (int32_t*)malloc((size_t)p.n_lc * sizeof(int32_t));
+  if (!off_h || !order_h || !lcs_sorted) {
+    free(off_h);
+    free(order_h);
+    free(lcs_sorted);
+    ea_destroy(st);
+    return set_error(SBLM_ENOMEM, "ea_create: host allocation");
+  }
+  rc = check_hip(hipMemcpy(off_h, lcs->off, (size_t)(p.n_lc + 1) * sizeof(int64_t),
+                           hipMemcpyDeviceToHost),
+                 "ea_create offsets");
+  if (!rc)
+    for (int k = 0; k < p.n_lc; ++k)
+      if (off_h[k + 1] < off_h[k] || off_h[0] != 0) {
+        rc = set_error(SBLM_EINVAL, "ea_create: offsets not non-decreasing from 0");
+        break;
+      }
+  if (!rc) {
+    for (int k = 0; k < p.n_lc; ++k) lcs_sorted[k] = k;
+    // stable bottom-up merge sort, longest first
+    int32_t* tmp = (int32_t*)malloc((size_t)p.n_lc * sizeof(int32_t));
+    for (int w = 1; tmp && w < p.n_lc; w *= 2)
+      for (int lo = 0; lo < p.n_lc; lo += 2 * w) {
+        int mid = lo + w < p.n_lc ? lo + w : p.n_lc;
+        int hi = lo + 2 * w < p.n_lc ? lo + 2 * w : p.n_lc;
+        int i = lo, j = mid, o = lo;
+        while (i < mid && j < hi) {
+          const int64_t li = off_h[lcs_sorted[i] + 1] - off_h[lcs_sorted[i]];
+          const int64_t lj = off_h[lcs_sorted[j] + 1] - off_h[lcs_sorted[j]];
+          tmp[o++] = (lj > li) ? lcs_sorted[j++] : lcs_sorted[i++];
+        }
+        while (i < mid) tmp[o++] = lcs_sorted[i++];
+        while (j < hi) tmp[o++] = lcs_sorted[j++];
+        for (int k = lo; k < hi; ++k) lcs_sorted[k] = tmp[k];
+      }
+    free(tmp);
+    for (int64_t it = 0; it < p.n_ind; ++it)
+      order_h[it] = lcs_sorted[it / p.pop] * p.pop + (int32_t)(it % p.pop);
+  }
+  free(off_h);
+  free(lcs_sorted);
+  if (rc) {
+    free(order_h);
+    ea_destroy(st);
+    return rc;
+  }
   if (hipMalloc(&s.P, SBLM_NPAR * nb) != hipSuccess || hipMalloc(&s.chi2, nb) != hipSuccess ||
       hipMalloc(&s.Fs, nb) != hipSuccess || hipMalloc(&s.Fb, nb) != hipSuccess ||
-      hipMalloc(&s.lc, (size_t)p.n_lc * sizeof(EaLc)) != hipSuccess) {
+      hipMalloc(&s.lc, (size_t)p.n_lc * sizeof(EaLc)) != hipSuccess ||
+      hipMalloc(&s.order, (size_t)p.n_ind * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&s.queue, sizeof(unsigned int)) != hipSuccess) {
+    free(order_h);
     ea_destroy(st);
     return set_error(SBLM_ENOMEM, "ea_create: device allocation of %zu bytes failed",
                      (9 * nb + (size_t)p.n_lc * sizeof(EaLc)));
@@ -483,6 +553,14 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
                       "ea_create stream")) ||
       (rc = check_hip(hipEventCreateWithFlags(&s.ev_in, hipEventDisableTiming), "event")) ||
       (rc = check_hip(hipEventCreateWithFlags(&s.ev_out, hipEventDisableTiming), "event"))) {
+    ea_destroy(st);
+    return rc;
+  }
+  rc = check_hip(hipMemcpy(s.order, order_h, (size_t)p.n_ind * sizeof(int32_t),
+                           hipMemcpyHostToDevice),
+                 "ea_create order");
+  free(order_h);
+  if (rc) {
     ea_destroy(st);
     return rc;
   }
@@ -577,6 +655,105 @@ extern "C" int ea_fit(ea_state* st, int32_t n_gen, sblm_stats* stats, void* stre
       (rc = check_hip(hipStreamWaitEvent(caller, s.ev_out, 0), "ea_fit wait")))
     return rc;
   return SBLM_OK;
+}
+
+extern "C" int ea_get_schedule(ea_state* st, int32_t* sched) {
+  if (!st || !sched) return set_error(SBLM_EINVAL, "ea_get_schedule: null argument");
+  sched[0] = st->impl.lanes;
+  sched[1] = st->impl.wpb;
+  sched[2] = st->impl.persistent;
+  return SBLM_OK;
+}
+
+extern "C" int ea_set_schedule(ea_state* st, const int32_t* sched) {
+  if (!st || !sched) return set_error(SBLM_EINVAL, "ea_set_schedule: null argument");
+  if ((sched[0] != 16 && sched[0] != 32 && sched[0] != 64) ||
+      (sched[1] != 1 && sched[1] != 2 && sched[1] != 4) || (sched[2] != 0 && sched[2] != 1))
+    return set_error(SBLM_EINVAL, "ea_set_schedule: bad schedule (%d, %d, %d)", sched[0],
+                     sched[1], sched[2]);
+  EaStateImpl& s = st->impl;
+  s.lanes = sched[0];
+  s.wpb = sched[1];
+  s.persistent = sched[2];
+  return capture_graph(s, s.graph_stats);
+}
+
+// Times one evaluation of the state's population with the current schedule
+// (one untimed launch, then the mean of `reps`), on the work stream.
+static int time_evaluate(EaStateImpl& s, hipEvent_t e0, hipEvent_t e1, int reps, float* ms) {
+  int rc;
+  if ((rc = check_hip(enqueue_evaluate(&s, nullptr, s.work), "ea_autotune launch"))) return rc;
+  if ((rc = check_hip(hipEventRecord(e0, s.work), "ea_autotune event"))) return rc;
+  for (int r = 0; r < reps; ++r)
+    if ((rc = check_hip(enqueue_evaluate(&s, nullptr, s.work), "ea_autotune launch"))) return rc;
+  if ((rc = check_hip(hipEventRecord(e1, s.work), "ea_autotune event")) ||
+      (rc = check_hip(hipEventSynchronize(e1), "ea_autotune sync")) ||
+      (rc = check_hip(hipEventElapsedTime(ms, e0, e1), "ea_autotune time")))
+    return rc;
+  *ms /= (float)reps;
+  return SBLM_OK;
+}
+
+extern "C" int ea_autotune(ea_state* st, char* report, size_t report_len, void* stream) {
+  if (!st) return set_error(SBLM_ESTATE, "ea_autotune: null state");
+  EaStateImpl& s = st->impl;
+  int rc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if ((rc = check_hip(hipEventRecord(s.ev_in, (hipStream_t)stream), "ea_autotune event")) ||
+      (rc = check_hip(hipStreamWaitEvent(s.work, s.ev_in, 0), "ea_autotune wait")) ||
+      (rc = check_hip(hipEventCreate(&e0), "ea_autotune event")) ||
+      (rc = check_hip(hipEventCreate(&e1), "ea_autotune event"))) {
+    if (e0) (void)hipEventDestroy(e0);
+    return rc;
+  }
+  char buf[2048];
+  int len = 0;
+  buf[0] = 0;
+  // coordinate descent: lanes per individual, then waves per block, then
+  // persistent vs one-shot grid
+  int best[3] = {s.lanes, s.wpb, s.persistent};
+  float best_ms = INFINITY;
+  const int lanes_c[3] = {16, 32, 64}, wpb_c[3] = {1, 2, 4}, pers_c[2] = {1, 0};
+  for (int stage = 0; stage < 3 && !rc; ++stage) {
+    const int nc = stage == 2 ? 2 : 3;
+    for (int k = 0; k < nc && !rc; ++k) {
+      int cand[3] = {best[0], best[1], best[2]};
+      if (stage == 0) cand[0] = lanes_c[k];
+      if (stage == 1) cand[1] = wpb_c[k];
+      if (stage == 2) cand[2] = pers_c[k];
+      s.lanes = cand[0];
+      s.wpb = cand[1];
+      s.persistent = cand[2];
+      float ms = 0.0f;
+      rc = time_evaluate(s, e0, e1, 2, &ms);
+      if (rc) break;
+      if (len < (int)sizeof(buf) - 80)
+        len += snprintf(buf + len, sizeof(buf) - len, "lanes=%d wpb=%d persistent=%d: %.3f ms\n",
+                        cand[0], cand[1], cand[2], ms);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best[0] = cand[0];
+        best[1] = cand[1];
+        best[2] = cand[2];
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  s.lanes = best[0];
+  s.wpb = best[1];
+  s.persistent = best[2];
+  if (!rc) rc = capture_graph(s, s.graph_stats);
+  if (!rc && len < (int)sizeof(buf) - 80)
+    snprintf(buf + len, sizeof(buf) - len, "chosen: lanes=%d wpb=%d persistent=%d (%.3f ms)\n",
+             best[0], best[1], best[2], best_ms);
+  if (report && report_len) {
+    strncpy(report, buf, report_len - 1);
+    report[report_len - 1] = 0;
+  }
+  if (!rc) rc = check_hip(hipEventRecord(s.ev_out, s.work), "ea_autotune event");
+  if (!rc) rc = check_hip(hipStreamWaitEvent((hipStream_t)stream, s.ev_out, 0), "ea_autotune wait");
+  return rc;
 }
 
 extern "C" int ea_buffers(ea_state* st, double** P, double** chi2, double** Fs,

@@ -193,9 +193,8 @@ __device__ __forceinline__ void cold_start(const cx<T> c[6], bool deg4,
 template <typename T>
 __device__ __forceinline__ bool aberth_sweep(const cx<T> c[6], cx<T> z[5],
                                              bool deg4, T tau, T* emax) {
-  cx<T> p[5], dp[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) horner(c, z[i], p[i], dp[i]);
+  // pairwise terms from the current roots first, so that each root's p, p'
+  // is used as soon as it is computed (fewer live registers)
   cx<T> S[5];
   T rmax[5];  // 1 / (distance to the nearest other root)^2
 #pragma unroll
@@ -222,12 +221,13 @@ __device__ __forceinline__ bool aberth_sweep(const cx<T> c[6], cx<T> z[5],
   const T tau2 = tau * tau;
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
+    cx<T> p, dp;
+    horner(c, z[i], p, dp);
     // den = p' - p S ; dz = p / den
-    const cx<T> pS = c_mul(p[i], S[i]);
-    const cx<T> den = c_sub(dp[i], pS);
+    const cx<T> pS = c_mul(p, S[i]);
+    const cx<T> den = c_sub(dp, pS);
     const T r = rcp_fast(c_norm(den));
-    cx<T> dz = {fma(p[i].re, den.re, p[i].im * den.im) * r,
-                fma(p[i].im, den.re, -p[i].re * den.im) * r};
+    cx<T> dz = {fma(p.re, den.re, p.im * den.im) * r, fma(p.im, den.re, -p.re * den.im) * r};
     if (i == 4 && deg4) dz = {(T)0, (T)0};
     z[i] = c_sub(z[i], dz);
     const T zn = c_norm(z[i]);
@@ -417,18 +417,13 @@ __device__ __forceinline__ void solve_roots(const cx<double> c[6], bool deg4,
 #define SBLM_MIN_WAVES_PER_EU 1
 #endif
 
+// One wave's share of the work: 64/G individuals (items wave_item*64/G ...).
 template <int MODE, bool CHI2, int G>
-__global__ __launch_bounds__(256, SBLM_MIN_WAVES_PER_EU) void fitness_kernel(FitArgs a) {
-  constexpr int GPW = 64 / G;  // individuals per wave
+__device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
+                                         LaneStats& st) {
   const int lane = threadIdx.x & 63;
   const int gl = lane & (G - 1);  // lane within the group
-  // XCD-aware block order: consecutive logical blocks on one XCD
-  const int nb = gridDim.x, b = blockIdx.x;
-  const int per = nb / 8, rem = nb % 8, xcd = b % 8, idx = b / 8;
-  const int lb = (xcd < rem) ? xcd * (per + 1) + idx
-                             : rem * (per + 1) + (xcd - rem) * per + idx;
-  const int wave = lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int64_t item = (int64_t)wave * GPW + (lane / G);
+  const int64_t item = wave_item * (64 / G) + (lane / G);
   const bool valid = item < a.n_ind;
   const int64_t ind = valid ? (a.order ? (int64_t)a.order[item] : item) : 0;
 
@@ -464,7 +459,6 @@ __global__ __launch_bounds__(256, SBLM_MIN_WAVES_PER_EU) void fitness_kernel(Fit
   const int64_t k0 = e0 + gl * Cg;
   const int64_t k1 = (k0 + Cg < e1) ? k0 + Cg : e1;
 
-  LaneStats st = {0, 0, 0, 0, 0, 0, 0};
   Lsq ls = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   cx<double> z[5];
 #pragma unroll
@@ -562,6 +556,40 @@ __global__ __launch_bounds__(256, SBLM_MIN_WAVES_PER_EU) void fitness_kernel(Fit
     }
   }
 
+}
+
+// PERSIST = 0: one-shot grid.  PERSIST = 1: persistent grid fed by a work
+// counter; its loop keeps the kernel arguments live, so it is compiled for
+// two waves per SIMD (a few bytes of spill) instead of letting scalar-register
+// spills push it to one.
+template <int MODE, bool CHI2, int G, int PERSIST>
+__global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitness_kernel(
+    FitArgs a) {
+  // (blocks of at most 256 threads: launch_gg refuses larger ones)
+  constexpr int GPW = 64 / G;  // individuals per wave
+  const int lane = threadIdx.x & 63;
+  LaneStats st = {0, 0, 0, 0, 0, 0, 0};
+  // One-shot grid: wave w takes wave item w (blocks remapped so that
+  // consecutive logical blocks sit on one XCD).  Persistent grid: waves take
+  // items from a shared counter until it runs past the last one, so every
+  // wave reaches the exit.  One call site keeps one inlined copy of the body.
+  const int64_t n_wave_items = (a.n_ind + GPW - 1) / GPW;
+  if (PERSIST) {
+    for (;;) {
+      unsigned int v = 0;
+      if (lane == 0) v = atomicAdd(a.queue, 1u);
+      const int64_t wi = (int64_t)__shfl(v, 0, 64);
+      if (wi >= n_wave_items) break;
+      fit_wave<MODE, CHI2, G>(a, wi, st);
+    }
+  } else {
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int per = nb / 8, rem = nb % 8, xcd = b % 8, idx = b / 8;
+    const int lb = (xcd < rem) ? xcd * (per + 1) + idx
+                               : rem * (per + 1) + (xcd - rem) * per + idx;
+    const int64_t wi = (int64_t)lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    fit_wave<MODE, CHI2, G>(a, wi, st);
+  }
   if (a.stats) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -585,20 +613,35 @@ __global__ __launch_bounds__(256, SBLM_MIN_WAVES_PER_EU) void fitness_kernel(Fit
   }
 }
 
+// The kernels are compiled for blocks of at most this many threads.
+#define SBLM_FIT_MAX_THREADS 256
+
+template <int MODE, bool CHI2, int G>
+static hipError_t launch_gg(const FitArgs& a, hipStream_t s, int wpb) {
+  if (wpb < 1 || 64 * wpb > SBLM_FIT_MAX_THREADS) return hipErrorInvalidConfiguration;
+  const int64_t groups_per_block = (int64_t)wpb * (64 / G);
+  int64_t nblk = (a.n_ind + groups_per_block - 1) / groups_per_block;
+  if (nblk <= 0) return hipSuccess;
+  auto kern = a.queue ? fitness_kernel<MODE, CHI2, G, 1> : fitness_kernel<MODE, CHI2, G, 0>;
+  if (a.queue) {  // persistent grid: as many blocks as can be resident
+    int dev = 0, ncu = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wpb, 0);
+    if (e != hipSuccess) return e;
+    const int64_t resident = (int64_t)(per_cu > 0 ? per_cu : 1) * ncu;
+    nblk = nblk < resident ? nblk : resident;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(64 * wpb), 0, s, a);
+  return hipGetLastError();
+}
+
 template <int MODE, bool CHI2>
 static hipError_t launch_g(const FitArgs& a, hipStream_t s, int wpb) {
-  const int G = a.lanes_per_ind;
-  const int64_t groups_per_block = (int64_t)wpb * (64 / G);
-  const int64_t nblk = (a.n_ind + groups_per_block - 1) / groups_per_block;
-  if (nblk <= 0) return hipSuccess;
-  dim3 grid((unsigned)nblk), block(64 * wpb);
-  if (G == 64)
-    hipLaunchKernelGGL((fitness_kernel<MODE, CHI2, 64>), grid, block, 0, s, a);
-  else if (G == 32)
-    hipLaunchKernelGGL((fitness_kernel<MODE, CHI2, 32>), grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL((fitness_kernel<MODE, CHI2, 16>), grid, block, 0, s, a);
-  return hipGetLastError();
+  if (a.lanes_per_ind == 64) return launch_gg<MODE, CHI2, 64>(a, s, wpb);
+  if (a.lanes_per_ind == 32) return launch_gg<MODE, CHI2, 32>(a, s, wpb);
+  return launch_gg<MODE, CHI2, 16>(a, s, wpb);
 }
 
 hipError_t launch_fitness(const FitArgs& a, int mode, bool chi2,

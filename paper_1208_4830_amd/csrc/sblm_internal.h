@@ -38,6 +38,8 @@ struct FitArgs {
   // schedule
   const int32_t* order;  // nullable: item -> individual permutation
   int32_t lanes_per_ind;  // 64 or 32 or 16 (a power of two dividing 64)
+  unsigned int* queue;    // nullable: persistent launch, shared work counter
+                          // (must read 0 when the kernel starts)
 };
 
 // Launch the FP64 or mixed fitness kernel; chi2 = false writes A/n_img.

@@ -68,6 +68,9 @@ _SIGS = {
                 ctypes.c_void_p],
     "ea_load": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "ea_destroy": [ctypes.c_void_p],
+    "ea_autotune": [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t, ctypes.c_void_p],
+    "ea_get_schedule": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)],
+    "ea_set_schedule": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)],
     "ea_draws": [ctypes.c_uint64] * 6 + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
     "ea_generation_traced": [ctypes.c_void_p] * 6,
     "sblm_last_error": [],
@@ -116,6 +119,16 @@ def _dev(x, dtype=torch.float64):
 
 def _ptr(x):
     return ctypes.c_void_p(x.data_ptr()) if x is not None else None
+
+
+class _CudaArray:
+    def __init__(self, ptr, shape, typestr):
+        self.__cuda_array_interface__ = {"shape": shape, "typestr": typestr,
+                                         "data": (ptr, False), "version": 2, "strides": None}
+
+
+def _device_view(ptr, shape, typestr="<f8"):
+    return torch.as_tensor(_CudaArray(ptr, tuple(shape), typestr), device="cuda")
 
 
 def new_stats(device="cuda"):
@@ -219,6 +232,13 @@ class EAState:
     def ptr(self, name):
         return self._ptrs[name]
 
+    def view(self, name):
+        """Zero-copy torch view of a state buffer ('P' [6][n], 'chi2', 'Fs',
+        'Fb' [n]); valid until close()."""
+        n = self.lcs.n_lc * self.cfg.pop
+        shape = (NPAR, n) if name == "P" else (n,)
+        return _device_view(self._ptrs[name], shape)
+
     def generation(self, chi2, Fs, Fb, stream=None):
         _check(load().ea_generation(self.h, _ptr(_dev(chi2)), _ptr(_dev(Fs)), _ptr(_dev(Fb)),
                                     _stream(stream)))
@@ -233,6 +253,20 @@ class EAState:
 
     def fit(self, n_gen, stats=None, stream=None):
         _check(load().ea_fit(self.h, n_gen, _ptr(stats), _stream(stream)))
+
+    def autotune(self, stream=None):
+        """Time the candidate schedules; returns the report text."""
+        buf = ctypes.create_string_buffer(4096)
+        _check(load().ea_autotune(self.h, buf, len(buf), _stream(stream)))
+        return buf.value.decode()
+
+    def schedule(self):
+        out = (ctypes.c_int32 * 3)()
+        _check(load().ea_get_schedule(self.h, out))
+        return tuple(out)
+
+    def set_schedule(self, lanes, wpb, persistent):
+        _check(load().ea_set_schedule(self.h, (ctypes.c_int32 * 3)(lanes, wpb, persistent)))
 
     def summary(self, stream=None):
         out = (ea_lc_summary * self.lcs.n_lc)()

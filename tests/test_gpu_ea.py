@@ -170,3 +170,78 @@ def test_fit_improves_and_best_is_monotone(hip, mode):
     A, _ = O.magnify(wl.theta[:, :1], wl.t)
     chi2_true, _, _ = O.lsq_chi2(A[0], y, w)
     assert best[-1] < best[0] and np.isfinite(best[-1]) and chi2_true > 0
+
+
+def test_schedules_agree_and_autotune(hip):
+    # the waves per block and the launch form (persistent work counter or a
+    # one-shot grid) do not change any result bit; lanes per individual only
+    # change the warm-start chunks (roots at the rounding level)
+    wl = csr_workload(9, [0, 5, 64, 201, 777, 1500, 3000])
+    pop = 32
+    blobs = {}
+    for sched in [(16, 4, 1), (16, 2, 0), (16, 1, 1), (32, 4, 1), (64, 2, 0)]:
+        st, y, w = _make_state(hip, wl, pop, seed=21)
+        st.set_schedule(*sched)
+        assert st.schedule() == sched
+        st.fit(6)
+        blobs[sched] = st.save()
+        st.evaluate()
+        c = st.view("chi2").cpu().numpy().copy()
+        P = st.view("P").cpu().numpy()
+        theta = O.decode(P, np.array(st.cfg.lo[:]), np.array(st.cfg.hi[:]))
+        co, _, _ = O.chi2(wl.off, wl.t, y, w, theta, pop)
+        scale = np.array([np.sum(w[wl.off[k]:wl.off[k + 1]] * y[wl.off[k]:wl.off[k + 1]] ** 2)
+                          for k in range(wl.n_lc)]).repeat(pop)
+        assert np.all(np.abs(c - co) <= 1e-8 * co + 1e-14 * scale)
+        st.close()
+    ref = blobs[(16, 4, 1)]
+    assert blobs[(16, 2, 0)] == ref and blobs[(16, 1, 1)] == ref
+    st, _, _ = _make_state(hip, wl, pop, seed=21)
+    rep = st.autotune()
+    assert "chosen:" in rep and len(rep.splitlines()) == 9
+    lanes, wpb, pers = st.schedule()
+    assert lanes in (16, 32, 64) and wpb in (1, 2, 4) and pers in (0, 1)
+    with pytest.raises(hip.SblmError):  # blocks beyond the kernels' bound
+        st.set_schedule(16, 8, 1)
+    st.fit(6)
+    if lanes == 16:
+        assert st.save() == ref
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_ragged_full_size_sampled(hip, mode):
+    # 4096 lightcurves of 200-5000 epochs with survey-like cadence and
+    # 0.5-3% errors, population 128: the persistent longest-first schedule
+    # of ea_evaluate on the full batch, sampled individuals vs the oracle
+    wl = inputs.ragged_workload(4, 4096)
+    rng = np.random.default_rng(8)
+    pick = rng.choice(4096, 24, replace=False)
+    # observations of the sampled lightcurves from the oracle; the rest are
+    # filled with the same recipe so the batch has its full shape
+    y = np.ones_like(wl.t)
+    w = np.ones_like(wl.t)
+    for k in pick:
+        sl = slice(wl.off[k], wl.off[k + 1])
+        A, _ = O.magnify(wl.theta[:, k:k + 1], wl.t[sl])
+        F = wl.Fs[k] * A[0] + wl.Fb[k]
+        y[sl] = F + wl.sfrac[sl] * F * wl.noise[sl]
+        w[sl] = 1 / (wl.sfrac[sl] * F) ** 2
+    lcs = hip.Lightcurves(_cuda(wl.off, torch.int64), _cuda(wl.t), _cuda(y), _cuda(w))
+    cfg = hip.ea_default_config()
+    cfg.pop = 128
+    cfg.mode = mode
+    st = hip.EAState(cfg, lcs, 3)
+    assert st.schedule()[2] == 1
+    st.evaluate()
+    c = st.view("chi2").cpu().numpy()
+    P = st.view("P").cpu().numpy()
+    lo, hi = np.array(cfg.lo[:]), np.array(cfg.hi[:])
+    for k in pick:
+        for i in rng.choice(128, 2, replace=False):
+            col = k * 128 + i
+            th = O.decode(P[:, col:col + 1], lo, hi)
+            sl = slice(wl.off[k], wl.off[k + 1])
+            A, _ = O.magnify(th, wl.t[sl])
+            co, _, _ = O.lsq_chi2(A[0], y[sl], w[sl])
+            assert rel_err(c[col], co) < 1e-8, (k, i, c[col], co)
+    st.close()
