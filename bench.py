@@ -33,6 +33,9 @@ FLOP_SWEEP64 = 760
 FLOP_SWEEP32 = 680
 FLOP_IMAGES = 345
 FLOP_LSQ = 50
+# per image refined on the lens equation: one residual/g evaluation at the
+# root, one Newton step, one evaluation at the new point
+FLOP_POLISH = 150
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (fma) x 2.4 GHz, the same
 # for FP64 and for unpacked FP32 (packed FP32 is not used)
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -56,6 +59,8 @@ def parse():
                     help="lightcurves of the ragged workload (0 = skip it)")
     ap.add_argument("--ragged-steps", type=int, default=30)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--success-max-gen", type=int, default=3000,
+                    help="generation cap of the time-to-90%%-success run (0 = skip it)")
     return ap.parse_args()
 
 
@@ -129,12 +134,14 @@ def run_form(sblm, torch, lcs, wl, chi2_true, pop, steps, args, mode, tune=True)
     success = float(np.mean(best <= chi2_true + 10.0))
     state.close()
 
+    polished = s["n_polished"] / max(s["n_solves"], 1)
     if mode == sblm.FP64:
         flop = FLOP_COEF + sweeps * FLOP_SWEEP64 + FLOP_IMAGES + FLOP_LSQ
     else:  # FP32 sweeps, then FP64 sweeps
         n32 = s["n_iter_fp32"] / max(s["n_solves"], 1)
         flop = FLOP_COEF + n32 * FLOP_SWEEP32 + (sweeps - n32) * FLOP_SWEEP64 \
             + FLOP_IMAGES + FLOP_LSQ
+    flop += polished * FLOP_POLISH
     ms_step = dt * 1e3 / steps
     return dict(
         mags_per_s=mags_per_gen * steps / dt,
@@ -146,7 +153,39 @@ def run_form(sblm, torch, lcs, wl, chi2_true, pop, steps, args, mode, tune=True)
         kernel_tflops=flop * mags_per_gen / (k_ms / 1e3) / 1e12,
         capped=s["n_capped"], fallback=s["n_fallback"],
         wave_sweeps_per_solve=s["n_wave_iter"] / max(s["n_solves"], 1),
+        polished_per_solve=s["n_polished"] / max(s["n_solves"], 1),
         schedule=dict(zip(("lanes", "waves_per_block", "persistent"), sched)))
+
+
+def time_to_success(sblm, torch, lcs, chi2_true, pop, mode, sched, target=0.9, chunk=50,
+                    max_gen=3000):
+    """Generations and GPU seconds until `target` of the lightcurves meet the
+    success criterion (best chi^2 <= chi^2 of the true parameters + 10)."""
+    cfg = sblm.ea_default_config()
+    cfg.pop = pop
+    cfg.mode = mode
+    state = sblm.EAState(cfg, lcs, 7)
+    state.set_schedule(*sched)
+    n_lc = len(chi2_true)
+    gens, secs, curve = 0, 0.0, []
+    frac = 0.0
+    while gens < max_gen:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        state.fit(chunk)
+        torch.cuda.synchronize()
+        secs += time.perf_counter() - t0
+        gens += chunk
+        summ = state.summary()
+        best = np.array([summ[k].best_chi2 for k in range(n_lc)])
+        frac = float(np.mean(best <= chi2_true + 10.0))
+        curve.append((gens, round(frac, 4)))
+        if frac >= target:
+            break
+    state.close()
+    return dict(target=target, reached=frac >= target, generations=gens, gpu_seconds=secs,
+                success=frac, fits_per_hour=n_lc * 3600.0 / secs if frac >= target else None,
+                curve=curve[::max(1, len(curve) // 12)])
 
 
 def cpu_baseline(wl, y, w, pop, target_s):
@@ -203,6 +242,13 @@ def main():
         forms[name] = run_form(sblm, torch, lcs, wl, chi2_true, args.pop, args.steps, args, mode)
         log(f"bench: {name}: {json.dumps(forms[name])}")
     main_form = forms.get("fp64") or next(iter(forms.values()))
+    tts = None
+    if args.success_max_gen > 0:
+        log("bench: time to 90% success (plain FP64 EA)")
+        sched = tuple(main_form["schedule"].values())
+        tts = time_to_success(sblm, torch, lcs, chi2_true, args.pop, sblm.FP64, sched,
+                              max_gen=args.success_max_gen)
+        log(f"bench: success: {json.dumps(tts)}")
 
     ragged = None
     if args.ragged_lc > 0:
@@ -236,6 +282,8 @@ def main():
                    "n_lc": args.n_lc, "epochs": args.epochs, "pop": args.pop,
                    "parallelism": "single GPU"},
         "fits_per_hour": main_form["fits_per_hour"],
+        "fits_per_hour_at_90pct": tts["fits_per_hour"] if tts else None,
+        "time_to_90pct_success": tts,
         "success_rate": main_form["success"],
         "forms": forms,
         "ragged": ragged,

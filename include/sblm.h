@@ -83,6 +83,7 @@ typedef struct {
                                       over the solves of its lanes (lockstep
                                       cost; n_iter is the lanes' own need)    */
   unsigned long long n_iter_fp32;  /* MIXED: the FP32 part of n_iter          */
+  unsigned long long n_polished;   /* images refined on the lens equation     */
 } sblm_stats;
 
 /* Ragged batch of lightcurves in CSR form.  Lightcurve k owns epochs

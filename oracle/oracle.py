@@ -74,6 +74,12 @@ def _load():
     return lib
 
 
+def default_threads():
+    """Host threads for the oracle: the CPUs this process may use, at most 16
+    (one GPU's share of a shared host)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
@@ -136,7 +142,7 @@ def magnify(theta, t, nthreads=None):
     A = np.zeros((n, n_t))
     ni = np.zeros((n, n_t), dtype=np.int8)
     lib.orc_magnify(_p(theta), n, _p(t), n_t, _p(A), _p(ni, _i8p),
-                    nthreads or os.cpu_count() or 1)
+                    nthreads or default_threads())
     return A, ni
 
 
@@ -160,7 +166,7 @@ def chi2(off, t, y, w, theta, pop, nthreads=None):
     assert theta.shape == (6, n)
     c, fs, fb = np.zeros(n), np.zeros(n), np.zeros(n)
     lib.orc_chi2(_p(off, _i64p), n_lc, _p(t), _p(y), _p(w), _p(theta), pop,
-                 _p(c), _p(fs), _p(fb), nthreads or os.cpu_count() or 1)
+                 _p(c), _p(fs), _p(fb), nthreads or default_threads())
     return c, fs, fb
 
 

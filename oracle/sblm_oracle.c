@@ -35,6 +35,12 @@
  *   R4  chi^2 is written in flux with unconstrained Fs, Fb; a 2x2 system with
  *       sum w (A - Abar)^2 <= 1e-14 sum w A^2 is degenerate and falls back to
  *       Fs = 0, Fb = weighted mean of y.
+ *   R5  The images are the solutions of the lens equation; the polynomial's
+ *       roots only start them.  Each accepted root is refined by Newton's
+ *       method on Eq. (lensing) itself (a step is kept only while it lowers
+ *       the residual), because next to a caustic two roots of the quintic
+ *       nearly coincide and its roots lose accuracy that the lens equation
+ *       does not.
  */
 #include <complex.h>
 #include <math.h>
@@ -227,6 +233,30 @@ static int cmp_root(const void* a, const void* b) {
 
 #define ORC_IMAGE_TOL 1e-6
 
+/*
+ * Newton's method on the lens equation at an image z: with
+ * r = zeta - (z - 1/conj(z) + q/(d - conj(z))) and g = dzeta/dconj(z),
+ * the step dz solves dz + g conj(dz) = r, i.e. dz = (r - g conj(r)) / (1 - |g|^2).
+ * Steps are taken while they lower |r| and exceed 1e-16 |z|, at most 8.
+ */
+static cplx polish_image(cplx zeta, cplx z, double d, double q) {
+  double rn = lens_residual(zeta, z, d, q);
+  for (int it = 0; it < 8; ++it) {
+    cplx zb = conj(z);
+    cplx r = zeta - (z - 1.0 / zb + q / (d - zb));
+    cplx g = 1.0 / (zb * zb) + q / ((d - zb) * (d - zb));
+    double ag = cabs(g);
+    cplx dz = (r - g * conj(r)) / (1.0 - ag * ag);
+    cplx zn = z + dz;
+    double rnn = lens_residual(zeta, zn, d, q);
+    if (!(rnn < rn)) break;
+    z = zn;
+    rn = rnn;
+    if (cabs(dz) <= 1e-16 * cabs(z)) break;
+  }
+  return z;
+}
+
 int orc_images(double zr, double zi, double d, double q, double* img_r,
                double* img_i, double* detj, double* resid_sorted) {
   cplx zeta = zr + I * zi;
@@ -262,7 +292,7 @@ int orc_images(double zr, double zi, double d, double q, double* img_r,
   for (int k = 0; k < deg; ++k) below += (res[k] < ORC_IMAGE_TOL);
   int n = (deg == 5 && below >= 4) ? 5 : 3;
   for (int k = 0; k < n; ++k) {
-    cplx z = roots[order[k]];
+    cplx z = polish_image(zeta, roots[order[k]], d, q);
     if (img_r) img_r[k] = creal(z);
     if (img_i) img_i[k] = cimag(z);
     if (detj) detj[k] = det_jacobian(z, d, q);

@@ -247,44 +247,119 @@ __device__ __forceinline__ bool aberth_sweep(const cx<T> c[6], cx<T> z[5],
 // ---------------------------------------------------------------- images
 
 #define SBLM_IMAGE_TOL2 1e-12 /* residual threshold 1e-6, squared */
+#define SBLM_POLISH_DETJ 0.01 /* images with |det J| below this are refined */
+#define SBLM_POLISH_EST2 1e-24 /* ... and those whose residual could move A by
+                                  more than 1e-12 relative (squared) */
 
-// Images, det J and the magnification from five FP64 roots.
+// Lens-equation quantities at a trial image z: the residual
+// r = zeta - z + 1/conj(z) - q/(d - conj(z)) of Eq. (lensing) and
+// g = dzeta/dconj(z) = 1/conj(z)^2 + q/(d - conj(z))^2; returns |r|^2.
+// *iz2, *ie2 receive |1/z|^2 and |1/(d - z)|^2.
+__device__ __forceinline__ double image_eval(cx<double> z, cx<double> zeta, double d,
+                                             double q, cx<double>& res, cx<double>& g,
+                                             double* iz2, double* ie2) {
+  const double x = z.re, y = z.im;
+  // a = 1/conj(z) = z / |z|^2 ; b = 1/(d - conj(z))
+  const double n2 = fma(x, x, y * y);
+  const double iz = rcp_acc(n2);
+  const cx<double> a = {x * iz, y * iz};
+  const double ex = d - x;
+  const double e2 = fma(ex, ex, y * y);
+  const double ie = rcp_acc(e2);
+  const cx<double> b = {ex * ie, -y * ie};
+  res = {fma(-q, b.re, (zeta.re - x) + a.re), fma(-q, b.im, (zeta.im - y) + a.im)};
+  const cx<double> b2 = c_mul(b, b);
+  g = c_fma(a, a, cx<double>{q * b2.re, q * b2.im});
+  *iz2 = iz;
+  *ie2 = ie;
+  return c_norm(res);
+}
+
+// Images, det J and the magnification from five FP64 roots.  The image
+// count and the choice of images use the roots' residuals.  An accepted
+// image is then refined by up to two Newton steps on the lens equation
+// itself, dz = (r - g conj(r))/(1 - |g|^2), each kept only if it lowers the
+// residual, when it lies very close to a critical curve (|det J| < 0.01) or
+// when its residual r could move A by more than 1e-12 relative: the image moves
+// by about (1 + |g|) |r| / |det J|, det J by 2 |g| |h| times that
+// (h = dg/dconj(z), |h| <= 2|1/z|^3 + 2q|1/(d-z)|^3) and A_i by A_i^2 times
+// that, with A >= 1.  There the quintic's roots lose accuracy (near-coincident
+// roots next to a caustic, or the root cluster around the secondary lens at
+// small q) while the lens equation does not.
 __device__ __forceinline__ double magnification(const cx<double> z[5],
                                                 cx<double> zeta, double d,
                                                 double q, bool deg4,
-                                                int& nimg) {
+                                                int& nimg, int& npolish) {
   double r2[5], adet[5];
+  bool refine[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
-    const double x = z[i].re, y = z[i].im;
-    // a = 1/conj(z) = z / |z|^2 ; b = 1/(d - conj(z))
-    const double iz = rcp_acc(fma(x, x, y * y));
-    const cx<double> a = {x * iz, y * iz};
-    const double ex = d - x;
-    const double ie = rcp_acc(fma(ex, ex, y * y));
-    const cx<double> b = {ex * ie, -y * ie};
-    // residual of Eq. (lensing): zeta - z + 1/conj(z) - q/(d - conj(z))
-    const cx<double> res = {fma(-q, b.re, (zeta.re - x) + a.re),
-                            fma(-q, b.im, (zeta.im - y) + a.im)};
-    r2[i] = c_norm(res);
-    // g = 1/conj(z)^2 + q/(d - conj(z))^2 = a^2 + q b^2
-    const cx<double> b2 = c_mul(b, b);
-    const cx<double> g = c_fma(a, a, cx<double>{q * b2.re, q * b2.im});
-    adet[i] = fabs(1.0 - c_norm(g));
+    cx<double> res, g;
+    double iz2, ie2;
+    r2[i] = image_eval(z[i], zeta, d, q, res, g, &iz2, &ie2);
+    const double gn = c_norm(g);
+    adet[i] = fabs(1.0 - gn);
+    // (dA/A)^2 <= 64 |g|^2 (1 + |g|^2) (|1/z|^6 + q^2 |1/(d-z)|^6) |r|^2 / |det J|^6;
+    // refine when that exceeds SBLM_POLISH_EST2 (compared without dividing)
+    const double a3 = adet[i] * adet[i] * adet[i];
+    const double num =
+        64.0 * gn * (1.0 + gn) * fma(q * q * ie2, ie2 * ie2, iz2 * iz2 * iz2) * r2[i];
+    refine[i] = !(num <= SBLM_POLISH_EST2 * (a3 * a3)) || adet[i] < SBLM_POLISH_DETJ;
   }
   if (deg4) r2[4] = INFINITY;
   int below = 0;
 #pragma unroll
   for (int i = 0; i < 5; ++i) below += (r2[i] < SBLM_IMAGE_TOL2) ? 1 : 0;
   const bool five = !deg4 && below >= 4;
+  // accepted images: sum those that need no refinement, list the others
   double A = 0.0;
+  unsigned int todo = 0u;
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
     int rank = 0;
 #pragma unroll
     for (int j = 0; j < 5; ++j)
       rank += (r2[j] < r2[i] || (r2[j] == r2[i] && j < i)) ? 1 : 0;
-    if (five || rank < 3) A += rcp_acc(adet[i]);
+    const bool acc = five || rank < 3;
+    if (acc && refine[i])
+      todo |= 1u << i;
+    else if (acc)
+      A += rcp_acc(adet[i]);
+  }
+  // refinement: one image per lane per pass, so the wavefront runs as many
+  // passes as the lane with the most images to refine
+  while (__any(todo != 0u)) {
+    if (todo) {
+      const int i = __builtin_ctz(todo);
+      todo &= todo - 1u;
+      cx<double> zi = z[0];
+#pragma unroll
+      for (int k = 1; k < 5; ++k)
+        if (i == k) zi = z[k];
+      cx<double> res, g;
+      double iz2, ie2;
+      double rn = image_eval(zi, zeta, d, q, res, g, &iz2, &ie2);
+      ++npolish;
+      for (int step = 0; step < 2; ++step) {
+        const double det = 1.0 - c_norm(g);
+        const double idet = rcp_acc(det);
+        // dz = (r - g conj(r)) / det
+        const cx<double> gr = c_mul(g, cx<double>{res.re, -res.im});
+        const cx<double> dz = {(res.re - gr.re) * idet, (res.im - gr.im) * idet};
+        const cx<double> zn = {zi.re + dz.re, zi.im + dz.im};
+        cx<double> resn, gn2;
+        const double rnn = image_eval(zn, zeta, d, q, resn, gn2, &iz2, &ie2);
+        if (!(rnn < rn)) break;
+        zi = zn;
+        res = resn;
+        g = gn2;
+        rn = rnn;
+        // Newton converges quadratically: after a step of 1e-10 |z| the next
+        // one would be at the rounding level
+        if (c_norm(dz) <= 1e-20 * c_norm(zi)) break;
+      }
+      A += rcp_acc(fabs(1.0 - c_norm(g)));
+    }
   }
   nimg = five ? 5 : 3;
   return A;
@@ -340,7 +415,7 @@ __device__ __forceinline__ double grp_shfl_down(double v, int off) {
 }
 
 struct LaneStats {
-  unsigned long long solves, iters, capped, fallback, deg4, wave_iters, iters32;
+  unsigned long long solves, iters, capped, fallback, deg4, wave_iters, iters32, polished;
 };
 
 // Solve one polynomial from the roots in z (warm) or from a cold start.
@@ -507,8 +582,9 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
     have_prev = ok;
     prev_deg4 = deg4;
     if (active) {
-      int nimg;
-      const double A = magnification(z, zeta, d, q, deg4, nimg);
+      int nimg, npol = 0;
+      const double A = magnification(z, zeta, d, q, deg4, nimg, npol);
+      st.polished += npol;
       if (CHI2) {
         lsq_include(ls, a.w[k], 1.0, A, a.y[k]);
       } else {
@@ -568,7 +644,7 @@ __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitn
   // (blocks of at most 256 threads: launch_gg refuses larger ones)
   constexpr int GPW = 64 / G;  // individuals per wave
   const int lane = threadIdx.x & 63;
-  LaneStats st = {0, 0, 0, 0, 0, 0, 0};
+  LaneStats st = {0, 0, 0, 0, 0, 0, 0, 0};
   // One-shot grid: wave w takes wave item w (blocks remapped so that
   // consecutive logical blocks sit on one XCD).  Persistent grid: waves take
   // items from a shared counter until it runs past the last one, so every
@@ -600,6 +676,7 @@ __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitn
       st.deg4 += __shfl_down(st.deg4, off, 64);
       st.wave_iters += __shfl_down(st.wave_iters, off, 64);
       st.iters32 += __shfl_down(st.iters32, off, 64);
+      st.polished += __shfl_down(st.polished, off, 64);
     }
     if (lane == 0 && st.solves) {
       atomicAdd(&a.stats->n_solves, st.solves);
@@ -609,6 +686,7 @@ __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitn
       if (st.deg4) atomicAdd(&a.stats->n_degree4, st.deg4);
       atomicAdd(&a.stats->n_wave_iter, st.wave_iters);
       if (st.iters32) atomicAdd(&a.stats->n_iter_fp32, st.iters32);
+      if (st.polished) atomicAdd(&a.stats->n_polished, st.polished);
     }
   }
 }

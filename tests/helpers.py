@@ -39,33 +39,31 @@ def magnification_condition(zeta, d, q, tau=0.0, u0=0.0):
     """First-order bound on the relative error of A that rounding alone can
     cause in a correct FP64 evaluation, for a comparison of two of them.
 
-    Two sources, per accepted image z_i with g = 1/conj(z)^2 + q/(d-conj(z))^2,
-    h = dg/dconj(z) = -2/conj(z)^3 + 2q/(d-conj(z))^3, det J = 1 - |g|^2:
-    (a) coefficient rounding: a root moves by |dp(z_i)|/|p'(z_i)| with
-        |dp| <= e sum_j |c_j| |z_i|^j, e = 128 eps (each coefficient is formed
-        by ~20 rounded operations, some with cancellation, on each side);
-    (b) input rounding: the source position (tau, sin, cos) and 10^log10q are
-        each good to a few ulps; from d zeta = dz + g d conj(z), an image moves
-        by |dz| <= (1 + |g|) |d zeta| / |det J| with
-        |d zeta| = 16 eps (|tau| + u0 + 1) + 4 eps q / |d - conj(z)|.
+    Both implementations refine accepted images on the lens equation (the
+    oracle every one, the kernel every one whose residual could move A by
+    more than 1e-12 relative, and every one with |det J| < 0.01), so an image
+    is determined by the lens equation, not by the quintic.  Per accepted
+    image z_i, with g = 1/conj(z)^2 + q/(d-conj(z))^2,
+    h = dg/dconj(z) = -2/conj(z)^3 + 2q/(d-conj(z))^3, det J = 1 - |g|^2 and
+    s = |zeta| + |z| + 1/|z| + q/|d-z|, the image moves by at most
+    (1 + |g|) (|d zeta| + 16 eps s) / |det J|: |d zeta| = 16 eps (|tau| + u0
+    + 1) + 4 eps q / |d - conj(z)| is the rounding of the source position
+    (tau, sin, cos) and of 10^log10q, 16 eps s that of the lens-equation
+    residual the refinement drives to zero (from d zeta = dz + g d conj(z)).
     det J then moves by 2 |g| |h| |dz| and A_i = 1/|det J_i| by A_i^2 times
-    that.  Returns sum_i dA_i / A."""
+    that.  Returns sum_i dA_i / A + 5e-12 (the kernel's unrefined images)."""
     imgs, dj, _ = O.images(zeta, d, q)
-    c = O.lens_poly(zeta, d, q)
-    dc = c[1:] * np.arange(1, 6)
     A = np.sum(1.0 / np.abs(dj))
     tot = 0.0
     for z, det in zip(imgs, dj):
-        mag = np.sum(np.abs(c) * np.abs(z) ** np.arange(6))
-        dp = abs(np.polyval(dc[::-1], z))
         zb = np.conj(z)
         g = 1 / zb ** 2 + q / (d - zb) ** 2
         h = -2 / zb ** 3 + 2 * q / (d - zb) ** 3
-        dz_coef = 128 * EPS * mag / max(dp, 1e-300)
         dzeta = 16 * EPS * (abs(tau) + u0 + 1) + 4 * EPS * q / abs(d - zb)
-        dz_in = (1 + abs(g)) * dzeta / abs(det)
-        tot += (1.0 / det) ** 2 * 2 * abs(g) * abs(h) * (dz_coef + dz_in)
-    return tot / A
+        s = abs(zeta) + abs(z) + 1 / abs(z) + q / abs(d - z)
+        dz = (1 + abs(g)) * (dzeta + 16 * EPS * s) / abs(det)
+        tot += (1.0 / det) ** 2 * 2 * abs(g) * abs(h) * dz
+    return tot / A + 5e-12
 
 
 def ambiguous_count(zeta, d, q, lo=1e-9, hi=1e-3):
@@ -92,3 +90,47 @@ def csr_workload(seed, lengths, sigma_frac=0.01):
     t = np.concatenate(ts) if sum(lengths) else np.zeros(0)
     return inputs.Workload(theta, Fs, Fb, off, t, np.full(t.size, sigma_frac),
                            rng.standard_normal(t.size))
+
+
+def near_caustic_pairs(rng, n, r_max=0.01):
+    """n (theta, t) pairs whose source lies within r_max theta_E of a caustic.
+
+    Per pair: (log10 q, d) from the priors; a point of the critical curve from
+    the quartic e^{i phi} z^2 (z-d)^2 - (z-d)^2 - q z^2 = 0 (phi uniform, one of
+    its four roots at random, via batched companion-matrix eigenvalues),
+    mapped through the lens equation to the caustic; an offset r e^{i psi}
+    with r ~ U(0, r_max]; then a trajectory through that source position:
+    alpha ~ U[0, 2 pi), u0 = Re(zeta e^{-i alpha}) (alpha += pi if negative),
+    tau = -Im(zeta e^{-i alpha}), tE, t0 from the priors, t = t0 + tau tE."""
+    lq = rng.uniform(-3, 0, n)
+    d = rng.uniform(0.5, 2, n)
+    q = 10 ** lq
+    e = np.exp(1j * rng.uniform(0, 2 * np.pi, n))
+    # monic quartic z^4 + a3 z^3 + a2 z^2 + a1 z + a0 (divide by e)
+    a3 = -2 * d + 0j
+    a2 = (e * d * d - 1 - q) / e
+    a1 = 2 * d / e
+    a0 = -d * d / e
+    comp = np.zeros((n, 4, 4), dtype=complex)
+    comp[:, 0, :] = -np.stack([a3, a2, a1, a0], 1)
+    comp[:, 1, 0] = comp[:, 2, 1] = comp[:, 3, 2] = 1
+    roots = np.linalg.eigvals(comp)
+    z = roots[np.arange(n), rng.integers(0, 4, n)]
+    zb = np.conj(z)
+    zc = z - 1 / zb + q / (d - zb)
+    zeta = zc + rng.uniform(0, r_max, n) * np.exp(1j * rng.uniform(0, 2 * np.pi, n))
+    al = rng.uniform(0, 2 * np.pi, n)
+    rot = zeta * np.exp(-1j * al)
+    flip = rot.real < 0
+    al = np.where(flip, al + np.pi, al)
+    rot = np.where(flip, -rot, rot)
+    u0, tau = rot.real, -rot.imag
+    tE, t0 = rng.uniform(10, 100, n), rng.uniform(-10, 10, n)
+    theta = np.stack([lq, d, u0, al, tE, t0])
+    return theta, t0 + tau * tE
+
+
+def generic_pairs(rng, n):
+    """n (theta, t) pairs from the priors with tau ~ U[-2, 2]."""
+    theta = inputs.draw_theta(rng, n)
+    return theta, theta[5] + rng.uniform(-2, 2, n) * theta[4]
