@@ -154,7 +154,7 @@ def run_form(sblm, torch, lcs, wl, chi2_true, pop, steps, args, mode, tune=True)
         capped=s["n_capped"], fallback=s["n_fallback"],
         wave_sweeps_per_solve=s["n_wave_iter"] / max(s["n_solves"], 1),
         polished_per_solve=s["n_polished"] / max(s["n_solves"], 1),
-        schedule=dict(zip(("lanes", "waves_per_block", "persistent"), sched)))
+        schedule=dict(zip(("lanes", "waves_per_block", "persistent", "asynchronous"), sched)))
 
 
 def time_to_success(sblm, torch, lcs, chi2_true, pop, mode, sched, target=0.9, chunk=50,

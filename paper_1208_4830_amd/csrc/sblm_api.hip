@@ -40,6 +40,14 @@ static int choose_group(double mean_len) {
   return 16;
 }
 
+// Epoch stepping of the stateless calls: lockstep unless SBLM_ASYNC=1 (the
+// asynchronous form measured slower on the MI355X for 200-5000-epoch
+// lightcurves: 6.8 vs 4.6 ms per batched evaluation).
+static int async_stepping() {
+  const char* env = getenv("SBLM_ASYNC");
+  return (env && atoi(env) == 1) ? 1 : 0;
+}
+
 static int waves_per_block() {
   const char* env = getenv("SBLM_WAVES_PER_BLOCK");
   if (env) {
@@ -78,6 +86,7 @@ extern "C" int sblm_magnify(const double* theta, int64_t n, const double* t,
   a.n_img = n_img;
   a.stats = stats;
   a.lanes_per_ind = choose_group((double)n_t);
+  a.async = async_stepping();
   return check_hip(launch_fitness(a, mode, false, (hipStream_t)stream, waves_per_block()),
                    "sblm_magnify launch");
 }
@@ -112,6 +121,7 @@ extern "C" int sblm_chi2(const sblm_lcs* lcs, const double* theta, int32_t pop,
   // mean length is not known on the host without a copy; use the group
   // size that suits ~1000-epoch lightcurves unless overridden
   a.lanes_per_ind = choose_group(1000.0);
+  a.async = async_stepping();
   return check_hip(launch_fitness(a, mode, true, (hipStream_t)stream, waves_per_block()),
                    "sblm_chi2 launch");
 }

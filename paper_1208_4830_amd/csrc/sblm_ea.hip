@@ -320,6 +320,7 @@ struct EaStateImpl {
   int lanes = 16;
   int wpb = 4;
   int persistent = 1;
+  int async = 0;
   int32_t* order = nullptr;    // item -> individual, longest lightcurves first
   unsigned int* queue = nullptr;
 };
@@ -367,6 +368,7 @@ static hipError_t enqueue_evaluate(EaStateImpl* s, sblm_stats* stats,
   a.stats = stats;
   a.lanes_per_ind = s->lanes;
   a.order = s->order;
+  a.async = s->async;
   if (s->persistent) {
     a.queue = s->queue;
     hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(1), 0, st, s->queue);
@@ -662,19 +664,22 @@ extern "C" int ea_get_schedule(ea_state* st, int32_t* sched) {
   sched[0] = st->impl.lanes;
   sched[1] = st->impl.wpb;
   sched[2] = st->impl.persistent;
+  sched[3] = st->impl.async;
   return SBLM_OK;
 }
 
 extern "C" int ea_set_schedule(ea_state* st, const int32_t* sched) {
   if (!st || !sched) return set_error(SBLM_EINVAL, "ea_set_schedule: null argument");
   if ((sched[0] != 16 && sched[0] != 32 && sched[0] != 64) ||
-      (sched[1] != 1 && sched[1] != 2 && sched[1] != 4) || (sched[2] != 0 && sched[2] != 1))
-    return set_error(SBLM_EINVAL, "ea_set_schedule: bad schedule (%d, %d, %d)", sched[0],
-                     sched[1], sched[2]);
+      (sched[1] != 1 && sched[1] != 2 && sched[1] != 4) || (sched[2] != 0 && sched[2] != 1) ||
+      (sched[3] != 0 && sched[3] != 1))
+    return set_error(SBLM_EINVAL, "ea_set_schedule: bad schedule (%d, %d, %d, %d)", sched[0],
+                     sched[1], sched[2], sched[3]);
   EaStateImpl& s = st->impl;
   s.lanes = sched[0];
   s.wpb = sched[1];
   s.persistent = sched[2];
+  s.async = sched[3];
   return capture_graph(s, s.graph_stats);
 }
 
@@ -709,32 +714,32 @@ extern "C" int ea_autotune(ea_state* st, char* report, size_t report_len, void* 
   char buf[2048];
   int len = 0;
   buf[0] = 0;
-  // coordinate descent: lanes per individual, then waves per block, then
-  // persistent vs one-shot grid
-  int best[3] = {s.lanes, s.wpb, s.persistent};
+  // coordinate descent: epoch stepping (asynchronous or lockstep), lanes
+  // per individual, waves per block, persistent vs one-shot grid
+  int best[4] = {s.lanes, s.wpb, s.persistent, s.async};
   float best_ms = INFINITY;
-  const int lanes_c[3] = {16, 32, 64}, wpb_c[3] = {1, 2, 4}, pers_c[2] = {1, 0};
-  for (int stage = 0; stage < 3 && !rc; ++stage) {
-    const int nc = stage == 2 ? 2 : 3;
+  const int lanes_c[3] = {16, 32, 64}, wpb_c[3] = {1, 2, 4}, bin_c[2] = {1, 0};
+  const int stage_field[4] = {3, 0, 1, 2};
+  for (int stage = 0; stage < 4 && !rc; ++stage) {
+    const int field = stage_field[stage];
+    const int nc = (field == 0 || field == 1) ? 3 : 2;
     for (int k = 0; k < nc && !rc; ++k) {
-      int cand[3] = {best[0], best[1], best[2]};
-      if (stage == 0) cand[0] = lanes_c[k];
-      if (stage == 1) cand[1] = wpb_c[k];
-      if (stage == 2) cand[2] = pers_c[k];
+      int cand[4] = {best[0], best[1], best[2], best[3]};
+      cand[field] = field == 0 ? lanes_c[k] : (field == 1 ? wpb_c[k] : bin_c[k]);
       s.lanes = cand[0];
       s.wpb = cand[1];
       s.persistent = cand[2];
+      s.async = cand[3];
       float ms = 0.0f;
       rc = time_evaluate(s, e0, e1, 2, &ms);
       if (rc) break;
-      if (len < (int)sizeof(buf) - 80)
-        len += snprintf(buf + len, sizeof(buf) - len, "lanes=%d wpb=%d persistent=%d: %.3f ms\n",
-                        cand[0], cand[1], cand[2], ms);
+      if (len < (int)sizeof(buf) - 100)
+        len += snprintf(buf + len, sizeof(buf) - len,
+                        "lanes=%d wpb=%d persistent=%d async=%d: %.3f ms\n", cand[0], cand[1],
+                        cand[2], cand[3], ms);
       if (ms < best_ms) {
         best_ms = ms;
-        best[0] = cand[0];
-        best[1] = cand[1];
-        best[2] = cand[2];
+        for (int f = 0; f < 4; ++f) best[f] = cand[f];
       }
     }
   }
@@ -743,10 +748,12 @@ extern "C" int ea_autotune(ea_state* st, char* report, size_t report_len, void* 
   s.lanes = best[0];
   s.wpb = best[1];
   s.persistent = best[2];
+  s.async = best[3];
   if (!rc) rc = capture_graph(s, s.graph_stats);
-  if (!rc && len < (int)sizeof(buf) - 80)
-    snprintf(buf + len, sizeof(buf) - len, "chosen: lanes=%d wpb=%d persistent=%d (%.3f ms)\n",
-             best[0], best[1], best[2], best_ms);
+  if (!rc && len < (int)sizeof(buf) - 100)
+    snprintf(buf + len, sizeof(buf) - len,
+             "chosen: lanes=%d wpb=%d persistent=%d async=%d (%.3f ms)\n", best[0], best[1],
+             best[2], best[3], best_ms);
   if (report && report_len) {
     strncpy(report, buf, report_len - 1);
     report[report_len - 1] = 0;

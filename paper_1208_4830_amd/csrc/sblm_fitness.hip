@@ -492,110 +492,80 @@ __device__ __forceinline__ void solve_roots(const cx<double> c[6], bool deg4,
 #define SBLM_MIN_WAVES_PER_EU 1
 #endif
 
-// One wave's share of the work: 64/G individuals (items wave_item*64/G ...).
-template <int MODE, bool CHI2, int G>
-__device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
-                                         LaneStats& st) {
-  const int lane = threadIdx.x & 63;
-  const int gl = lane & (G - 1);  // lane within the group
-  const int64_t item = wave_item * (64 / G) + (lane / G);
-  const bool valid = item < a.n_ind;
-  const int64_t ind = valid ? (a.order ? (int64_t)a.order[item] : item) : 0;
+// Per-lane context of one work item: the individual, its parameters and the
+// lane's chunk [k0, k1) of the lightcurve's epochs.
+struct Item {
+  bool valid;
+  int gl;  // lane within the group
+  int64_t ind;
+  double q, d, u0, sa, ca, t0, itE;
+  int64_t e0, k0, k1, Cg, C;  // C: longest chunk in the wave
+};
 
+template <int G>
+__device__ __forceinline__ Item item_setup(const FitArgs& a, int64_t wave_item) {
+  Item x;
+  const int lane = threadIdx.x & 63;
+  x.gl = lane & (G - 1);
+  const int64_t item = wave_item * (64 / G) + (lane / G);
+  x.valid = item < a.n_ind;
+  x.ind = x.valid ? (a.order ? (int64_t)a.order[item] : item) : 0;
   // parameters of this individual (uniform within the group)
   double th[SBLM_NPAR];
 #pragma unroll
   for (int j = 0; j < SBLM_NPAR; ++j) {
-    const double v = valid ? a.theta[j * a.n_ind + ind] : 0.5;
+    const double v = x.valid ? a.theta[j * a.n_ind + x.ind] : 0.5;
     th[j] = a.encoded ? a.lo[j] + a.span[j] * v : v;
   }
-  const double q = exp10(th[0]);
-  const double d = th[1], u0 = th[2], tE = th[4], t0 = th[5];
-  double sa, ca;
-  sincos(th[3], &sa, &ca);
-  const double itE = 1.0 / tE;
-
+  x.q = exp10(th[0]);
+  x.d = th[1];
+  x.u0 = th[2];
+  x.t0 = th[5];
+  sincos(th[3], &x.sa, &x.ca);
+  x.itE = 1.0 / th[4];
   int64_t e0 = 0, e1 = a.n_t;
   if (a.off) {
-    const int64_t lc = ind / a.pop;
-    e0 = valid ? a.off[lc] : 0;
-    e1 = valid ? a.off[lc + 1] : 0;
+    const int64_t lc = x.ind / a.pop;
+    e0 = x.valid ? a.off[lc] : 0;
+    e1 = x.valid ? a.off[lc + 1] : 0;
   }
-  if (!valid) e1 = e0;
+  if (!x.valid) e1 = e0;
+  x.e0 = e0;
   const int64_t L = e1 - e0;
-  // chunk length: uniform across the wave (max over its groups)
-  int64_t Cg = (L + G - 1) / G;
-  int64_t C = Cg;
+  x.Cg = (L + G - 1) / G;
+  x.C = x.Cg;
 #pragma unroll
   for (int o = G; o < 64; o <<= 1) {
-    const int64_t oc = __shfl_xor(C, o, 64);
-    C = oc > C ? oc : C;
+    const int64_t oc = __shfl_xor(x.C, o, 64);
+    x.C = oc > x.C ? oc : x.C;
   }
-  const int64_t k0 = e0 + gl * Cg;
-  const int64_t k1 = (k0 + Cg < e1) ? k0 + Cg : e1;
+  x.k0 = e0 + x.gl * x.Cg;
+  x.k1 = (x.k0 + x.Cg < e1) ? x.k0 + x.Cg : e1;
+  return x;
+}
 
-  Lsq ls = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  cx<double> z[5];
+// Source position (Eq. sourcePos) and lens polynomial at epoch t.
+__device__ __forceinline__ bool epoch_poly(const Item& x, double t, cx<double>& zeta,
+                                           cx<double> c[6]) {
+  const double tau = (t - x.t0) * x.itE;
+  zeta = {fma(tau, x.sa, x.u0 * x.ca), fma(-tau, x.ca, x.u0 * x.sa)};
+  lens_coeffs(zeta, x.d, x.q, c);
+  double cmax = 0.0;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) z[i] = {0.0, 0.0};
-  cx<double> zp[5];  // roots of the epoch before the previous one
-#pragma unroll
-  for (int i = 0; i < 5; ++i) zp[i] = {0.0, 0.0};
-  bool have_prev = false, prev_deg4 = false, have_prev2 = false;
-  double t1 = 0.0, t2 = 0.0;  // epochs of z and zp
+  for (int j = 0; j < 6; ++j) cmax = fmax(cmax, c_norm(c[j]));
+  const bool deg4 = c_norm(c[5]) <= 1e-24 * cmax;
+  if (deg4) c[5] = {0.0, 0.0};
+  return deg4;
+}
 
-  for (int64_t s = 0; s < C; ++s) {
-    const int64_t k = k0 + s;
-    const bool active = (s < Cg) && (k < k1);
-    const double t = active ? a.t[k] : t0;
-    const double tau = (t - t0) * itE;
-    // Eq. (sourcePos)
-    const cx<double> zeta = {fma(tau, sa, u0 * ca), fma(-tau, ca, u0 * sa)};
-    cx<double> c[6];
-    lens_coeffs(zeta, d, q, c);
-    double cmax = 0.0;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) cmax = fmax(cmax, c_norm(c[j]));
-    const bool deg4 = c_norm(c[5]) <= 1e-24 * cmax;
-    if (deg4) c[5] = {0.0, 0.0};
-    const bool warm = have_prev && !deg4 && !prev_deg4;
-    // Linear extrapolation of every root from the two previous epochs,
-    // scaled by the ratio of epoch spacings (clamped to [0, 4]).
-    cx<double> zs[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) zs[i] = z[i];
-    if (warm && have_prev2) {
-      const double gap = t1 - t2;
-      double r = gap != 0.0 ? (t - t1) / gap : 0.0;
-      r = fmin(fmax(r, 0.0), 4.0);
-#pragma unroll
-      for (int i = 0; i < 5; ++i)
-        z[i] = {fma(r, z[i].re - zp[i].re, z[i].re), fma(r, z[i].im - zp[i].im, z[i].im)};
-    }
-    bool ok;
-    solve_roots<MODE>(c, deg4, warm, active, z, st, ok);
-    have_prev2 = warm && ok;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) zp[i] = zs[i];
-    t2 = t1;
-    t1 = t;
-    have_prev = ok;
-    prev_deg4 = deg4;
-    if (active) {
-      int nimg, npol = 0;
-      const double A = magnification(z, zeta, d, q, deg4, nimg, npol);
-      st.polished += npol;
-      if (CHI2) {
-        lsq_include(ls, a.w[k], 1.0, A, a.y[k]);
-      } else {
-        const int64_t o = ind * a.n_t + (k - e0);
-        a.A[o] = A;
-        if (a.n_img) a.n_img[o] = (int8_t)nimg;
-      }
-    }
-  }
-
-  if (CHI2) {
+// Merge the lanes' least-squares states of each group (fixed tree) and write
+// chi^2, Fs, Fb of the group's individual.
+template <int G>
+__device__ __forceinline__ void finish_chi2(const FitArgs& a, const Item& x, Lsq ls) {
+  const int gl = x.gl;
+  const bool valid = x.valid;
+  const int64_t ind = x.ind;
+  {
     // lane gl absorbs lane gl + off: fixed tree inside each group
 #pragma unroll
     for (int off = G / 2; off >= 1; off >>= 1) {
@@ -634,11 +604,205 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
 
 }
 
+// One wave's share of the work, lockstep form: 64/G individuals (items
+// wave_item*64/G ...); every lane solves its s-th epoch at the same time and
+// the wave moves on when all of them have converged.
+template <int MODE, bool CHI2, int G>
+__device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
+                                         LaneStats& st) {
+  Item x = item_setup<G>(a, wave_item);
+  const int64_t C = x.C, Cg = x.Cg, k0 = x.k0, k1 = x.k1, e0 = x.e0, ind = x.ind;
+  const double q = x.q, d = x.d, t0 = x.t0;
+  Lsq ls = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  cx<double> z[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) z[i] = {0.0, 0.0};
+  cx<double> zp[5];  // roots of the epoch before the previous one
+#pragma unroll
+  for (int i = 0; i < 5; ++i) zp[i] = {0.0, 0.0};
+  bool have_prev = false, prev_deg4 = false, have_prev2 = false;
+  double t1 = 0.0, t2 = 0.0;  // epochs of z and zp
+
+  for (int64_t s = 0; s < C; ++s) {
+    const int64_t k = k0 + s;
+    const bool active = (s < Cg) && (k < k1);
+    const double t = active ? a.t[k] : t0;
+    cx<double> zeta, c[6];
+    const bool deg4 = epoch_poly(x, t, zeta, c);
+    const bool warm = have_prev && !deg4 && !prev_deg4;
+    // Linear extrapolation of every root from the two previous epochs,
+    // scaled by the ratio of epoch spacings (clamped to [0, 4]).
+    cx<double> zs[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) zs[i] = z[i];
+    if (warm && have_prev2) {
+      const double gap = t1 - t2;
+      double r = gap != 0.0 ? (t - t1) / gap : 0.0;
+      r = fmin(fmax(r, 0.0), 4.0);
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+        z[i] = {fma(r, z[i].re - zp[i].re, z[i].re), fma(r, z[i].im - zp[i].im, z[i].im)};
+    }
+    bool ok;
+    solve_roots<MODE>(c, deg4, warm, active, z, st, ok);
+    have_prev2 = warm && ok;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) zp[i] = zs[i];
+    t2 = t1;
+    t1 = t;
+    have_prev = ok;
+    prev_deg4 = deg4;
+    if (active) {
+      int nimg, npol = 0;
+      const double A = magnification(z, zeta, d, q, deg4, nimg, npol);
+      st.polished += npol;
+      if (CHI2) {
+        lsq_include(ls, a.w[k], 1.0, A, a.y[k]);
+      } else {
+        const int64_t o = ind * a.n_t + (k - e0);
+        a.A[o] = A;
+        if (a.n_img) a.n_img[o] = (int8_t)nimg;
+      }
+    }
+  }
+
+  if (CHI2) finish_chi2<G>(a, x, ls);
+}
+
+// One wave's share of the work, asynchronous form: every lane moves on to
+// its next epoch as soon as its own solve has converged, so a wavefront pays
+// for the lanes' own sweeps (plus the epoch set-up and image work of the
+// lanes finishing in a pass) instead of the slowest lane of every epoch.
+// The warm start is a quadratic extrapolation of the roots of the last three
+// epochs (Lagrange in t) when the new epoch lies within their span, else
+// the linear one of the lockstep form.
+template <int MODE, bool CHI2, int G>
+__device__ __forceinline__ void fit_wave_async(const FitArgs& a, int64_t wave_item,
+                                               LaneStats& st) {
+  constexpr int MAXIT64 = 60, MAXIT32 = 30;
+  const double tau64 = 1e-16;
+  const float tau32 = 1e-7f;
+  const Item x = item_setup<G>(a, wave_item);
+  Lsq ls = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  cx<double> z[5], zp[5], zpp[5];  // iterate; roots of the two epochs before
+#pragma unroll
+  for (int i = 0; i < 5; ++i) z[i] = zp[i] = zpp[i] = {0.0, 0.0};
+  int nhist = 0;  // solved epochs held in z (after convergence), zp, zpp
+  double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+  bool prev_deg4 = false;
+  int64_t k = x.k0;
+  bool busy = k < x.k1, need_setup = busy;
+  cx<double> zeta = {0.0, 0.0}, c[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) c[j] = {0.0, 0.0};
+  bool deg4 = false, in32 = false, warm = false;
+  double t = 0.0;
+  int it64 = 0, it32 = 0;
+  float prev32 = INFINITY;
+  unsigned long long passes = 0;
+  while (__any(busy)) {
+    ++passes;
+    if (busy) {
+      if (need_setup) {
+        t = a.t[k];
+        deg4 = epoch_poly(x, t, zeta, c);
+        warm = nhist >= 1 && !deg4 && !prev_deg4;
+        if (warm) {
+          // weights of z (epoch t1), zp (t2), zpp (t3)
+          double w1 = 1.0, w2 = 0.0, w3 = 0.0;
+          const double d12 = t1 - t2, d13 = t1 - t3, d23 = t2 - t3;
+          if (nhist >= 3 && d12 > 0.0 && d23 > 0.0 && (t - t1) <= d13) {
+            const double a1 = t - t1, a2 = t - t2, a3 = t - t3;
+            w1 = a2 * a3 * rcp_fast(d12 * d13);
+            w2 = -a1 * a3 * rcp_fast(d12 * d23);
+            w3 = a1 * a2 * rcp_fast(d13 * d23);
+          } else if (nhist >= 2 && d12 > 0.0) {
+            const double r = fmin(fmax((t - t1) * rcp_fast(d12), 0.0), 4.0);
+            w1 = 1.0 + r;
+            w2 = -r;
+          }
+#pragma unroll
+          for (int i = 0; i < 5; ++i) {
+            const cx<double> p = {fma(w1, z[i].re, fma(w2, zp[i].re, w3 * zpp[i].re)),
+                                  fma(w1, z[i].im, fma(w2, zp[i].im, w3 * zpp[i].im))};
+            zpp[i] = zp[i];
+            zp[i] = z[i];
+            z[i] = p;
+          }
+          t3 = t2;
+          t2 = t1;
+        } else {
+          cold_start<double>(c, deg4, z);
+        }
+        in32 = (MODE == SBLM_MIXED) && !warm && !deg4;
+        it64 = 0;
+        it32 = 0;
+        prev32 = INFINITY;
+        need_setup = false;
+      }
+      bool finished = false, conv = false;
+      if (MODE == SBLM_MIXED && in32) {
+        // FP32 sweep on the rounded iterate (exactly representable back in FP64)
+        cx<float> cf[6], zf[5];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) cf[j] = {(float)c[j].re, (float)c[j].im};
+#pragma unroll
+        for (int i = 0; i < 5; ++i) zf[i] = {(float)z[i].re, (float)z[i].im};
+        float em;
+        bool d32 = aberth_sweep<float>(cf, zf, false, tau32, &em);
+        d32 = d32 || (em > 0.25f * prev32);
+        prev32 = em;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) z[i] = {(double)zf[i].re, (double)zf[i].im};
+        ++it32;
+        if (d32 || it32 >= MAXIT32) in32 = false;
+      } else {
+        double em;
+        conv = aberth_sweep<double>(c, z, deg4, tau64, &em);
+        ++it64;
+        finished = conv || it64 >= MAXIT64;
+      }
+      if (finished) {
+        bool finite = true;
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+          finite = finite && isfinite(z[i].re) && isfinite(z[i].im);
+        const bool ok = conv && finite;
+        int nimg, npol = 0;
+        const double A = magnification(z, zeta, x.d, x.q, deg4, nimg, npol);
+        if (CHI2) {
+          lsq_include(ls, a.w[k], 1.0, A, a.y[k]);
+        } else {
+          const int64_t o = x.ind * a.n_t + (k - x.e0);
+          a.A[o] = A;
+          if (a.n_img) a.n_img[o] = (int8_t)nimg;
+        }
+        st.solves += 1;
+        st.iters += it64 + it32;
+        st.iters32 += it32;
+        st.capped += conv ? 0 : 1;
+        st.deg4 += deg4 ? 1 : 0;
+        st.polished += npol;
+        if (MODE == SBLM_MIXED) st.fallback += (!warm && it64 > 2) ? 1 : 0;
+        // z now holds the roots of epoch t
+        nhist = ok ? (warm ? (nhist < 3 ? nhist + 1 : 3) : 1) : 0;
+        t1 = t;
+        prev_deg4 = deg4;
+        ++k;
+        busy = k < x.k1;
+        need_setup = busy;
+      }
+    }
+  }
+  if (x.k1 > x.k0) st.wave_iters += passes;
+  if (CHI2) finish_chi2<G>(a, x, ls);
+}
+
 // PERSIST = 0: one-shot grid.  PERSIST = 1: persistent grid fed by a work
 // counter; its loop keeps the kernel arguments live, so it is compiled for
 // two waves per SIMD (a few bytes of spill) instead of letting scalar-register
 // spills push it to one.
-template <int MODE, bool CHI2, int G, int PERSIST>
+template <int MODE, bool CHI2, int G, int PERSIST, int ASYNC>
 __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitness_kernel(
     FitArgs a) {
   // (blocks of at most 256 threads: launch_gg refuses larger ones)
@@ -656,7 +820,10 @@ __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitn
       if (lane == 0) v = atomicAdd(a.queue, 1u);
       const int64_t wi = (int64_t)__shfl(v, 0, 64);
       if (wi >= n_wave_items) break;
-      fit_wave<MODE, CHI2, G>(a, wi, st);
+      if (ASYNC)
+        fit_wave_async<MODE, CHI2, G>(a, wi, st);
+      else
+        fit_wave<MODE, CHI2, G>(a, wi, st);
     }
   } else {
     const int nb = gridDim.x, b = blockIdx.x;
@@ -664,7 +831,10 @@ __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitn
     const int lb = (xcd < rem) ? xcd * (per + 1) + idx
                                : rem * (per + 1) + (xcd - rem) * per + idx;
     const int64_t wi = (int64_t)lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    fit_wave<MODE, CHI2, G>(a, wi, st);
+    if (ASYNC)
+      fit_wave_async<MODE, CHI2, G>(a, wi, st);
+    else
+      fit_wave<MODE, CHI2, G>(a, wi, st);
   }
   if (a.stats) {
 #pragma unroll
@@ -700,7 +870,10 @@ static hipError_t launch_gg(const FitArgs& a, hipStream_t s, int wpb) {
   const int64_t groups_per_block = (int64_t)wpb * (64 / G);
   int64_t nblk = (a.n_ind + groups_per_block - 1) / groups_per_block;
   if (nblk <= 0) return hipSuccess;
-  auto kern = a.queue ? fitness_kernel<MODE, CHI2, G, 1> : fitness_kernel<MODE, CHI2, G, 0>;
+  auto kern = a.async ? (a.queue ? fitness_kernel<MODE, CHI2, G, 1, 1>
+                                 : fitness_kernel<MODE, CHI2, G, 0, 1>)
+                      : (a.queue ? fitness_kernel<MODE, CHI2, G, 1, 0>
+                                 : fitness_kernel<MODE, CHI2, G, 0, 0>);
   if (a.queue) {  // persistent grid: as many blocks as can be resident
     int dev = 0, ncu = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);

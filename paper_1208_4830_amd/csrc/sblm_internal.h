@@ -40,6 +40,7 @@ struct FitArgs {
   int32_t lanes_per_ind;  // 64 or 32 or 16 (a power of two dividing 64)
   unsigned int* queue;    // nullable: persistent launch, shared work counter
                           // (must read 0 when the kernel starts)
+  int32_t async;          // 1: lanes step through their epochs independently
 };
 
 // Launch the FP64 or mixed fitness kernel; chi2 = false writes A/n_img.

@@ -261,12 +261,14 @@ class EAState:
         return buf.value.decode()
 
     def schedule(self):
-        out = (ctypes.c_int32 * 3)()
+        """(lanes per individual, waves per block, persistent, asynchronous)."""
+        out = (ctypes.c_int32 * 4)()
         _check(load().ea_get_schedule(self.h, out))
         return tuple(out)
 
-    def set_schedule(self, lanes, wpb, persistent):
-        _check(load().ea_set_schedule(self.h, (ctypes.c_int32 * 3)(lanes, wpb, persistent)))
+    def set_schedule(self, lanes, wpb, persistent, asynchronous=1):
+        _check(load().ea_set_schedule(self.h, (ctypes.c_int32 * 4)(lanes, wpb, persistent,
+                                                                     asynchronous)))
 
     def summary(self, stream=None):
         out = (ea_lc_summary * self.lcs.n_lc)()

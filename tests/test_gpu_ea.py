@@ -179,7 +179,8 @@ def test_schedules_agree_and_autotune(hip):
     wl = csr_workload(9, [0, 5, 64, 201, 777, 1500, 3000])
     pop = 32
     blobs = {}
-    for sched in [(16, 4, 1), (16, 2, 0), (16, 1, 1), (32, 4, 1), (64, 2, 0)]:
+    for sched in [(16, 4, 1, 1), (16, 2, 0, 1), (16, 1, 1, 1), (16, 4, 1, 0), (16, 2, 0, 0),
+                  (32, 4, 1, 1), (64, 2, 0, 0)]:
         st, y, w = _make_state(hip, wl, pop, seed=21)
         st.set_schedule(*sched)
         assert st.schedule() == sched
@@ -194,18 +195,19 @@ def test_schedules_agree_and_autotune(hip):
                           for k in range(wl.n_lc)]).repeat(pop)
         assert np.all(np.abs(c - co) <= 1e-8 * co + 1e-14 * scale)
         st.close()
-    ref = blobs[(16, 4, 1)]
-    assert blobs[(16, 2, 0)] == ref and blobs[(16, 1, 1)] == ref
+    ref = blobs[(16, 4, 1, 1)]
+    assert blobs[(16, 2, 0, 1)] == ref and blobs[(16, 1, 1, 1)] == ref
+    assert blobs[(16, 2, 0, 0)] == blobs[(16, 4, 1, 0)]
     st, _, _ = _make_state(hip, wl, pop, seed=21)
     rep = st.autotune()
-    assert "chosen:" in rep and len(rep.splitlines()) == 9
-    lanes, wpb, pers = st.schedule()
-    assert lanes in (16, 32, 64) and wpb in (1, 2, 4) and pers in (0, 1)
+    assert "chosen:" in rep and len(rep.splitlines()) == 11
+    lanes, wpb, pers, asy = st.schedule()
+    assert lanes in (16, 32, 64) and wpb in (1, 2, 4) and pers in (0, 1) and asy in (0, 1)
     with pytest.raises(hip.SblmError):  # blocks beyond the kernels' bound
         st.set_schedule(16, 8, 1)
     st.fit(6)
     if lanes == 16:
-        assert st.save() == ref
+        assert st.save() == blobs[(16, 4, 1, asy)]
 
 
 @pytest.mark.parametrize("mode", [0, 1])

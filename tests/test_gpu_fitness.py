@@ -152,12 +152,13 @@ def test_chi2_parity_ragged(hip, mode):
 def test_chi2_deterministic_and_schedule_independent(hip):
     wl = csr_workload(12, [300, 700, 1000])
     outs = []
-    for lanes in ("64", "64", "32", "16"):
-        os.environ["SBLM_LANES"] = lanes
+    for lanes, asy in (("64", "0"), ("64", "0"), ("32", "0"), ("16", "0"), ("16", "1"),
+                       ("32", "1")):
+        os.environ["SBLM_LANES"], os.environ["SBLM_ASYNC"] = lanes, asy
         try:
             (c, fs, fb), (co, _, _), _ = _chi2_case(hip, wl, pop=8, mode=0)
         finally:
-            del os.environ["SBLM_LANES"]
+            del os.environ["SBLM_LANES"], os.environ["SBLM_ASYNC"]
         outs.append(c)
         assert np.all(rel_err(c, co) < 1e-8)
     assert np.array_equal(outs[0], outs[1])  # bitwise repeatable
