@@ -162,6 +162,7 @@ int sblm_chi2(const sblm_lcs* lcs, const double* theta, int32_t pop, int mode,
 #define EA_PURPOSE_MODE 3
 #define EA_PURPOSE_CREEP 4
 #define EA_PURPOSE_JUMP 5
+#define EA_PURPOSE_SEED 6 /* ea_seed: row = seeded row, j = draw (see there) */
 
 typedef struct {
   int32_t pop;           /* N_pop, 2 <= pop <= 1024                        */
@@ -282,6 +283,149 @@ int ea_load(ea_state* st, const void* buf, size_t len, void* stream);
 void ea_destroy(ea_state* st);
 
 /* ---------------------------------------------------------------------- */
+/* Learned proposal network                                                */
+/* ---------------------------------------------------------------------- */
+/*
+ * Not part of the paper's method: its neural-network approach (Sec. 1) is a
+ * competing fitter, whereas this network only proposes starting points for
+ * part of the initial population; the EA's chi^2 (Sec. 4.1, 4.4) judges them
+ * like any other individual and the uniform rows (Sec. A.1) remain.
+ *
+ * Input: a lightcurve resampled to MLP_NBINS normalised bins (sblm_resample),
+ * stored as BF16 (uint16 bit patterns, row-major [rows][256]).
+ * Network: 256 -> 512 (ReLU) -> 512 (ReLU) -> 120, BF16 weights and
+ * activations with FP32 accumulation on the matrix cores, FP32 master
+ * weights.  Output row (FP32, padded to MLP_NOUT_PAD = 128 columns):
+ *   [0, 8)     mixture logits of the K = 8 components,
+ *   [8, 64)    means, component k, target d at 8 + 7k + d,
+ *   [64, 120)  log standard deviations at 64 + 7k + d,
+ *   [120, 128) zero.
+ * Targets (the "target map", float [rows][7]):
+ *   0 (log10 q + 3)/3, 1 (d - 0.5)/1.5, 2 u0/0.5, 3 alpha/(2 pi) (periodic
+ *   on [0, 1)), 4 (t0 - t_first)/span, 5 tE/span, 6 Fs/(Fs + Fb),
+ * with t_first and span the first epoch and the time covered by the
+ * lightcurve.  Loss: the negative log-likelihood of the targets under the
+ * mixture averaged over the rows, the residual of target 3 wrapped into
+ * [-1/2, 1/2).
+ * Canonical parameter order (host arrays of MLP_NPARAMS floats): W1
+ * [256][512] (input-major), b1 [512], W2 [512][512], b2 [512], W3 [512][120],
+ * b3 [120].
+ */
+#define MLP_NBINS 256
+#define MLP_HIDDEN 512
+#define MLP_K 8
+#define MLP_D 7
+#define MLP_PERIODIC 3
+#define MLP_NOUT 120
+#define MLP_NOUT_PAD 128
+#define MLP_NPARAMS 455800
+
+typedef struct mlp_net mlp_net; /* opaque */
+
+/*
+ * sblm_resample -- every lightcurve of a ragged batch to 256 normalised
+ * bins over its observed span (epochs ascending within each lightcurve):
+ * epoch e of a lightcurve with first/last epochs t_a, t_b falls in bin
+ * min(floor((t_e - t_a)/(t_b - t_a) * 256), 255) (bin 0 if t_b = t_a); a bin
+ * holds the w-weighted mean flux of its epochs; bins without weight take the
+ * linear interpolation of the nearest filled bins (the nearest filled value
+ * beyond the first/last); then v -> (v - median)/max(max - median, 1e-12),
+ * the median being the mean of the 128th and 129th smallest values.  A
+ * lightcurve without weight gives zeros.
+ *   lcs   ragged lightcurves (device CSR), 1 <= n_lc <= 2^24
+ *   xf    [n_lc][256] FP32 out (nullable)
+ *   xb    [n_lc][256] BF16 out, round-to-nearest-even (nullable; not both)
+ */
+int sblm_resample(const sblm_lcs* lcs, float* xf, uint16_t* xb, void* stream);
+
+/*
+ * mlp_make_data -- training samples first .. first+n-1 of the stream keyed
+ * by `seed`: parameters uniform over the default EA domain, Fs = 1,
+ * Fb ~ U[0, 0.5], observed through nightly windows over t0 +- 2 tE with a
+ * Poisson epoch count per bin and Gaussian flux noise, magnified by the
+ * forward model of Sec. 2.2 (FP64) at the bin centres, then binned and
+ * normalised as by sblm_resample.  Sample s depends only on (seed, s).
+ *   xb [n][256] BF16 and/or xf [n][256] FP32 (one may be NULL), y [n][7]
+ *   targets (the target map above).  Device pointers.
+ * Allocates and frees temporary device memory; synchronises `stream`.
+ * Errors: SBLM_EINVAL, SBLM_ERANGE (n > 2^26), SBLM_ENOMEM, SBLM_EDEVICE.
+ */
+int mlp_make_data(uint64_t seed, int64_t first, int64_t n, uint16_t* xb,
+                  float* xf, float* y, void* stream);
+
+/*
+ * mlp_create -- a network with He-normal hidden weights (std sqrt(2/fan_in)),
+ * output weights of std 0.01 and zero biases (Philox, key (seed, 0)), Adam
+ * moments zero, and activation buffers for batch_max rows.
+ *   batch_max  positive multiple of 64, at most 2^20
+ * Allocates device memory on the current device.  Errors: SBLM_EINVAL,
+ * SBLM_ERANGE, SBLM_ENOMEM, SBLM_EDEVICE.
+ */
+int mlp_create(int32_t batch_max, uint64_t seed, mlp_net** out);
+void mlp_destroy(mlp_net* net);
+
+/* Host copies of the FP32 master parameters (canonical order above).
+ * mlp_set_params also refreshes the BF16 shadow and zeroes the Adam moments
+ * and step count.  Both synchronise the device. */
+int mlp_set_params(mlp_net* net, const float* params);
+int mlp_get_params(mlp_net* net, float* params);
+
+/*
+ * mlp_forward -- network output for `rows` inputs.
+ *   x    [rows][256] BF16, device;   out  [rows][128] FP32, device
+ * Any rows >= 0; processed in chunks of batch_max through the network's own
+ * buffers (so calls on one network must not overlap).
+ */
+int mlp_forward(mlp_net* net, const uint16_t* x, int64_t rows, float* out,
+                void* stream);
+
+/*
+ * mlp_loss_grad -- forward pass, loss and gradient of the loss with respect
+ * to every parameter (kept in the network; mlp_get_grad copies it out).
+ *   x [rows][256] BF16, y [rows][7] FP32 targets, device;
+ *   rows a multiple of 64 in [64, batch_max];
+ *   loss (nullable) device float receiving the mean loss.
+ * The backward GEMMs take BF16 copies of the output gradient and of the
+ * hidden-layer gradients; bias gradients are FP32 column sums.
+ */
+int mlp_loss_grad(mlp_net* net, const uint16_t* x, const float* y, int32_t rows,
+                  float* loss, void* stream);
+int mlp_get_grad(mlp_net* net, float* grad);
+
+/* One Adam step (Kingma & Ba 2015: beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias-corrected as p -= lr (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps)) with
+ * the last gradient; t counts the steps since creation or mlp_set_params. */
+int mlp_adam_step(mlp_net* net, float lr, void* stream);
+
+/*
+ * mlp_train -- epochs x floor(rows/batch) steps of mlp_loss_grad + Adam
+ * over consecutive batches of (x, y), the learning rate following a cosine
+ * from lr0 (first step) to lr1 (last step).  loss (nullable, device float
+ * [epochs*floor(rows/batch)]) receives the loss of every step.
+ */
+int mlp_train(mlp_net* net, const uint16_t* x, const float* y, int64_t rows,
+              int32_t batch, int32_t epochs, float lr0, float lr1, float* loss,
+              void* stream);
+
+/*
+ * ea_seed -- overwrite rows 0 .. n_seed-1 of every lightcurve's current
+ * population with draws from the network's proposal mixture.
+ *   out     [n_lc][ld_out] FP32 device, network output for each lightcurve
+ *           (mlp_forward of its sblm_resample bins), ld_out >= 120
+ *   n_seed  0 <= n_seed <= pop
+ * Row r of lightcurve l draws key (seed, l), counter (0, EA_PURPOSE_SEED, r,
+ * j/4): word 0 -> u, component = the first k with u * sum(e) < e_0 + ... +
+ * e_k, e_k = exp(logit_k - max logit); words 1..8 -> four Box-Muller pairs
+ * (sqrt(-2 ln u1) cos(2 pi u2), sqrt(-2 ln u1) sin(2 pi u2)) giving z_0..z_6;
+ * x_d = mean_kd + exp(logstd_kd) z_d, x_3 reduced mod 1; decoded through the
+ * target map with t_first/span of lightcurve l; re-encoded into the state's
+ * domain (Eq. EMMA-encoding) and clamped to [0, 1].  Lightcurves without
+ * epochs are left alone.  Run before ea_fit (which evaluates first).
+ */
+int ea_seed(ea_state* st, const float* out, int32_t ld_out, int32_t n_seed,
+            void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Diagnostics (used by the parity tests)                                  */
 /* ---------------------------------------------------------------------- */
 
@@ -298,6 +442,11 @@ int ea_draws(uint64_t seed, uint64_t lc, uint64_t gen, uint64_t purpose,
  * parents[l*2*floor(pop/2) + 2k] (first parent) and [... + 2k + 1]. */
 int ea_generation_traced(ea_state* st, const double* chi2, const double* Fs,
                          const double* Fb, int32_t* parents, void* stream);
+
+/* mlp_set_grad -- replace the network's gradient buffer with host values
+ * (canonical order, MLP_NPARAMS floats), so that mlp_adam_step can be
+ * checked on a given gradient.  Synchronises the device. */
+int mlp_set_grad(mlp_net* net, const float* grad);
 
 /* Thread-local description of the last error of this thread. */
 const char* sblm_last_error(void);

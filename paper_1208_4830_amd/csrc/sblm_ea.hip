@@ -50,7 +50,7 @@ __device__ __forceinline__ double clamp01(double x) {
 
 enum { P_INIT = EA_PURPOSE_INIT, P_TOURN = EA_PURPOSE_TOURN,
        P_MODE = EA_PURPOSE_MODE, P_CREEP = EA_PURPOSE_CREEP,
-       P_JUMP = EA_PURPOSE_JUMP };
+       P_JUMP = EA_PURPOSE_JUMP, P_SEED = EA_PURPOSE_SEED };
 
 #define EA_HIST 64
 
@@ -255,6 +255,70 @@ __global__ void ea_draws_kernel(uint64_t seed, uint64_t lc, uint64_t gen,
   if (k >= n) return;
   const Stream rs = {seed, lc, gen};
   out[k] = rs.draw(purpose, row, j0 + (uint64_t)k);
+}
+
+// Proposal seeding: row `row` < n_seed of lightcurve lc becomes a draw from
+// the mixture that the proposal network output O[lc][0..119] describes (8
+// logits, 8x7 means, 8x7 log standard deviations over the network's target
+// map), decoded to physical parameters on the lightcurve's observed span
+// and re-encoded (clamped) into the EA's domain.  Draws: key (seed, lc),
+// counter (0, EA_PURPOSE_SEED, row, j / 4); word 0 picks the component by
+// inversion of the softmax weights, words 1..8 give four Box-Muller pairs.
+struct SeedDomain {
+  double lo[SBLM_NPAR], span[SBLM_NPAR];
+};
+
+__global__ void ea_seed_kernel(EaParams p, double* P, const int64_t* off,
+                               const double* t, const float* O, int32_t ldo,
+                               int32_t n_seed, SeedDomain dom) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)p.n_lc * n_seed) return;
+  const int64_t lc = idx / n_seed;
+  const int row = (int)(idx % n_seed);
+  const int64_t o0 = off[lc], o1 = off[lc + 1];
+  if (o1 <= o0) return;
+  const double t_first = t[o0], tspan = t[o1 - 1] - t_first;
+  const Stream rs = {p.seed, (uint64_t)lc, 0};
+  const float* o = O + lc * (int64_t)ldo;
+  const int K = MLP_K, D = MLP_D;
+  double lmax = (double)o[0];
+  for (int k = 1; k < K; ++k) lmax = fmax(lmax, (double)o[k]);
+  double S = 0.0;
+  for (int k = 0; k < K; ++k) S += exp((double)o[k] - lmax);
+  const double u = u01(rs.draw(P_SEED, (uint64_t)row, 0));
+  int comp = K - 1;
+  double acc = 0.0;
+  for (int k = 0; k < K; ++k) {
+    acc += exp((double)o[k] - lmax);
+    if (u * S < acc) {
+      comp = k;
+      break;
+    }
+  }
+  double z[8];
+  for (int i = 0; i < 4; ++i) {
+    const double u1 = u01(rs.draw(P_SEED, (uint64_t)row, (uint64_t)(1 + 2 * i)));
+    const double u2 = u01(rs.draw(P_SEED, (uint64_t)row, (uint64_t)(2 + 2 * i)));
+    const double rad = sqrt(-2.0 * log(u1));
+    z[2 * i] = rad * cos(2.0 * M_PI * u2);
+    z[2 * i + 1] = rad * sin(2.0 * M_PI * u2);
+  }
+  double x[MLP_D];
+  for (int d = 0; d < D; ++d)
+    x[d] = (double)o[K + comp * D + d] + exp((double)o[K + K * D + comp * D + d]) * z[d];
+  x[MLP_PERIODIC] -= floor(x[MLP_PERIODIC]);
+  double th[SBLM_NPAR];
+  th[0] = -3.0 + 3.0 * x[0];
+  th[1] = 0.5 + 1.5 * x[1];
+  th[2] = 0.5 * x[2];
+  th[3] = 2.0 * M_PI * x[3];
+  th[4] = tspan * x[5];
+  th[5] = t_first + tspan * x[4];
+  const int64_t col = lc * p.pop + row;
+  for (int g = 0; g < SBLM_NPAR; ++g) {
+    const double e = (th[g] - dom.lo[g]) / dom.span[g];
+    P[g * p.n_ind + col] = fmin(fmax(e, 0.0), 1.0);
+  }
 }
 
 // ---------------------------------------------------------------- host side
@@ -564,6 +628,29 @@ extern "C" int ea_draws(uint64_t seed, uint64_t lc, uint64_t gen, uint64_t purpo
   hipLaunchKernelGGL(ea_draws_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                      (hipStream_t)stream, seed, lc, gen, purpose, row, j0, n, out);
   return check_hip(hipGetLastError(), "ea_draws launch");
+}
+
+extern "C" int ea_seed(ea_state* st, const float* out, int32_t ld_out, int32_t n_seed,
+                       void* stream) {
+  if (!st) return set_error(SBLM_ESTATE, "ea_seed: null state");
+  EaStateImpl& s = st->impl;
+  if (!out) return set_error(SBLM_EINVAL, "ea_seed: null network output");
+  if (ld_out < MLP_NOUT)
+    return set_error(SBLM_EINVAL, "ea_seed: ld_out = %d < %d", ld_out, MLP_NOUT);
+  if (n_seed < 0 || n_seed > s.prm.pop)
+    return set_error(SBLM_EINVAL, "ea_seed: n_seed = %d outside [0, pop = %d]", n_seed,
+                     s.prm.pop);
+  if (n_seed == 0) return SBLM_OK;
+  SeedDomain dom;
+  for (int g = 0; g < SBLM_NPAR; ++g) {
+    dom.lo[g] = s.cfg.lo[g];
+    dom.span[g] = s.cfg.hi[g] - s.cfg.lo[g];
+  }
+  const int64_t n = (int64_t)s.prm.n_lc * n_seed;
+  hipLaunchKernelGGL(ea_seed_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, s.prm, s.P, s.lcs.off, s.lcs.t, out, ld_out,
+                     n_seed, dom);
+  return check_hip(hipGetLastError(), "ea_seed launch");
 }
 
 extern "C" int ea_evaluate(ea_state* st, sblm_stats* stats, void* stream) {

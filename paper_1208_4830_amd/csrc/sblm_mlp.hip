@@ -1,0 +1,926 @@
+// sblm_mlp.hip -- learned proposal network for seeding the EA population.
+//
+// Not part of the paper's method (its neural network is a competing fitter,
+// Sec. 1); the network only proposes starting points, and the EA's chi^2
+// (Sec. 4.1, 4.4) stays the judge.  Contents:
+//   * sblm_resample: a lightcurve -> 256 normalised bins;
+//   * mlp_make_data: training lightcurves drawn from the EA's parameter
+//     domain and observed at bin level through the forward model (Sec. 2.2);
+//   * the network 256 -> 512 -> 512 -> 120 (ReLU hidden layers) whose output
+//     is a K = 8 mixture of diagonal Gaussians over 7 targets, trained by its
+//     own BF16 MFMA forward and backward GEMMs, an FP64 mixture-likelihood
+//     kernel, deterministic column sums and Adam on FP32 master weights.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "sblm_internal.h"
+#include "sblm_rng.h"
+
+namespace sblm {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int NB = MLP_NBINS;      // 256 input bins
+constexpr int NH = MLP_HIDDEN;     // 512 hidden units
+constexpr int NO = MLP_NOUT;       // 120 outputs
+constexpr int NOP = MLP_NOUT_PAD;  // 128 (padded output width)
+constexpr int KM = MLP_K, DM = MLP_D;
+
+// Device parameter layout (FP32 master copy, BF16 shadow and Adam moments):
+// W1 [256][512], b1 [512], W2 [512][512], b2 [512], W3 [512][128], b3 [128];
+// the 8 pad columns of W3 and b3 hold zeros and receive zero gradient.
+constexpr int64_t OFF_W1 = 0;
+constexpr int64_t OFF_B1 = OFF_W1 + (int64_t)NB * NH;
+constexpr int64_t OFF_W2 = OFF_B1 + NH;
+constexpr int64_t OFF_B2 = OFF_W2 + (int64_t)NH * NH;
+constexpr int64_t OFF_W3 = OFF_B2 + NH;
+constexpr int64_t OFF_B3 = OFF_W3 + (int64_t)NH * NOP;
+constexpr int64_t NP_DEV = OFF_B3 + NOP;
+
+constexpr uint64_t P_MLP_INIT = 32;  // Philox purposes of this file (key
+constexpr uint64_t P_DATA = 33;      // word 1 = sample index or 0)
+
+// ------------------------------------------------------------------ BF16
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0;  // NaN
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);      // RNE
+}
+
+// ------------------------------------------------------------------ GEMM
+//
+// C[M][N] = A[M][K] * B[K][N] on BF16 operands with FP32 accumulation in
+// the 32x32x16 matrix-core instruction.  A workgroup of four waves owns a
+// 64x64 tile of C (2x2 waves of 32x32); K advances in stages of 32 staged
+// through LDS (double-buffered, one barrier per stage), each stage two MFMA
+// per wave.  Operands are read from either layout:
+//   AK: A[m*lda + k] (k contiguous)   else A[k*lda + m]
+//   BK: B[n*ldb + k] (k contiguous)   else B[k*ldb + n]
+// LDS holds both tiles as [row = m or n][32 k] so every lane fetches its 8
+// consecutive k values with one 16-byte read (row stride padded to 40).
+// Epilogue: + bias[n], then * (mask[m][n] > 0), then ReLU, written as FP32
+// and/or BF16.  Requires M % 64 == 0, N % 64 == 0, K % 32 == 0.
+struct GemmArgs {
+  const uint16_t* A;
+  int64_t lda;
+  const uint16_t* B;
+  int64_t ldb;
+  int M, N, K;
+  const float* bias;     // [N] or null
+  const uint16_t* mask;  // [M][ldm] BF16 or null
+  int64_t ldm;
+  float* Cf;             // [M][ldc] or null
+  uint16_t* Cb;          // [M][ldc] or null
+  int64_t ldc;
+  int relu;
+};
+
+constexpr int TM = 64, TK = 32, LDS_STRIDE = 40;
+
+template <bool KC>
+__device__ __forceinline__ void load_tile(const uint16_t* X, int64_t ld, int r0,
+                                          int k0, uint4& v) {
+  const int t = threadIdx.x;
+  if (KC) {
+    v = *(const uint4*)(X + (int64_t)(r0 + (t >> 2)) * ld + k0 + (t & 3) * 8);
+  } else {
+    v = *(const uint4*)(X + (int64_t)(k0 + (t >> 3)) * ld + r0 + (t & 7) * 8);
+  }
+}
+
+template <bool KC>
+__device__ __forceinline__ void store_tile(uint16_t* S, const uint4& v) {
+  const int t = threadIdx.x;
+  if (KC) {
+    *(uint4*)(S + (t >> 2) * LDS_STRIDE + (t & 3) * 8) = v;
+  } else {
+    const int k = t >> 3, r = (t & 7) * 8;
+    const uint16_t* e = (const uint16_t*)&v;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) S[(r + i) * LDS_STRIDE + k] = e[i];
+  }
+}
+
+template <bool AK, bool BK>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t sA[2][TM * LDS_STRIDE];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[2][TM * LDS_STRIDE];
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TM;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int nst = g.K / TK;
+
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+
+  uint4 ra, rb;
+  load_tile<AK>(g.A, g.lda, m0, 0, ra);
+  load_tile<BK>(g.B, g.ldb, n0, 0, rb);
+  store_tile<AK>(sA[0], ra);
+  store_tile<BK>(sB[0], rb);
+  __syncthreads();
+  for (int s = 0; s < nst; ++s) {
+    const int cur = s & 1;
+    if (s + 1 < nst) {
+      load_tile<AK>(g.A, g.lda, m0, (s + 1) * TK, ra);
+      load_tile<BK>(g.B, g.ldb, n0, (s + 1) * TK, rb);
+    }
+    const uint16_t* pa = sA[cur] + (wm + (lane & 31)) * LDS_STRIDE + 8 * (lane >> 5);
+    const uint16_t* pb = sB[cur] + (wn + (lane & 31)) * LDS_STRIDE + 8 * (lane >> 5);
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 16) {
+      const bf16x8 a = *(const bf16x8*)(pa + kk);
+      const bf16x8 b = *(const bf16x8*)(pb + kk);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    if (s + 1 < nst) {
+      store_tile<AK>(sA[cur ^ 1], ra);
+      store_tile<BK>(sB[cur ^ 1], rb);
+    }
+    __syncthreads();
+  }
+
+  // lane l, register r holds C[(r%4) + 8(r/4) + 4(l/32)][l%32] of the wave
+  const int n = n0 + wn + (lane & 31);
+  const float bias = g.bias ? g.bias[n] : 0.0f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int m = m0 + wm + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
+    float v = acc[r] + bias;
+    if (g.mask) {
+      const uint16_t h = g.mask[(int64_t)m * g.ldm + n];
+      if (h == 0 || (h & 0x8000u)) v = 0.0f;
+    }
+    if (g.relu) v = fmaxf(v, 0.0f);
+    if (g.Cf) g.Cf[(int64_t)m * g.ldc + n] = v;
+    if (g.Cb) g.Cb[(int64_t)m * g.ldc + n] = f2bf(v);
+  }
+}
+
+hipError_t gemm(const GemmArgs& g, bool ak, bool bk, hipStream_t st) {
+  const dim3 grid(g.N / TM, g.M / TM);
+  if (ak && !bk)
+    hipLaunchKernelGGL((gemm_bf16_kernel<true, false>), grid, dim3(256), 0, st, g);
+  else if (ak && bk)
+    hipLaunchKernelGGL((gemm_bf16_kernel<true, true>), grid, dim3(256), 0, st, g);
+  else if (!ak && !bk)
+    hipLaunchKernelGGL((gemm_bf16_kernel<false, false>), grid, dim3(256), 0, st, g);
+  else
+    hipLaunchKernelGGL((gemm_bf16_kernel<false, true>), grid, dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------- mixture likelihood
+//
+// One thread per sample.  Output row O = (8 logits, 8x7 means, 8x7 log
+// standard deviations, 8 pad); target row y[7], target 3 periodic on [0, 1).
+// loss_row = -log p(y)/n and dO = d loss / dO (pad entries 0), in FP64:
+//   log pi_k = logit_k - logsumexp(logit),  r_kd = y_d - mu_kd (wrapped),
+//   a_k = log pi_k + sum_d [-r^2/(2 s^2) - log s - log(2 pi)/2],
+//   gamma_k = exp(a_k - logsumexp(a)),
+//   dlogit_k = (pi_k - gamma_k)/n, dmu = -gamma r/s^2/n,
+//   dlog s = -gamma (r^2/s^2 - 1)/n.
+__global__ void mlp_nll_kernel(const float* O, const float* y, int n, float* dOf,
+                               uint16_t* dOb, float* loss_row) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  const float* o = O + (int64_t)b * NOP;
+  const double inv_n = 1.0 / (double)n;
+  const double HALF_LOG_2PI = 0.91893853320467274178;
+  double yv[DM];
+  for (int d = 0; d < DM; ++d) yv[d] = (double)y[(int64_t)b * DM + d];
+  double lmax = (double)o[0];
+  for (int k = 1; k < KM; ++k) lmax = fmax(lmax, (double)o[k]);
+  double se = 0.0;
+  for (int k = 0; k < KM; ++k) se += exp((double)o[k] - lmax);
+  const double lse = lmax + log(se);
+  double a[KM];
+  double amax = -INFINITY;
+  for (int k = 0; k < KM; ++k) {
+    double s = (double)o[k] - lse;
+    for (int d = 0; d < DM; ++d) {
+      double r = yv[d] - (double)o[KM + k * DM + d];
+      if (d == MLP_PERIODIC) r -= floor(r + 0.5);
+      const double ls = (double)o[KM + KM * DM + k * DM + d];
+      const double s2 = exp(2.0 * ls);
+      s += -0.5 * r * r / s2 - ls - HALF_LOG_2PI;
+    }
+    a[k] = s;
+    amax = fmax(amax, s);
+  }
+  double sa = 0.0;
+  for (int k = 0; k < KM; ++k) sa += exp(a[k] - amax);
+  const double lp = amax + log(sa);
+  loss_row[b] = (float)(-lp * inv_n);
+  float* gf = dOf + (int64_t)b * NOP;
+  uint16_t* gb = dOb + (int64_t)b * NOP;
+  for (int k = 0; k < KM; ++k) {
+    const double gam = exp(a[k] - lp);
+    const double pi = exp((double)o[k] - lse);
+    const float gl = (float)((pi - gam) * inv_n);
+    gf[k] = gl;
+    gb[k] = f2bf(gl);
+    for (int d = 0; d < DM; ++d) {
+      double r = yv[d] - (double)o[KM + k * DM + d];
+      if (d == MLP_PERIODIC) r -= floor(r + 0.5);
+      const double ls = (double)o[KM + KM * DM + k * DM + d];
+      const double is2 = exp(-2.0 * ls);
+      const float gm = (float)(-gam * r * is2 * inv_n);
+      const float gs = (float)(-gam * (r * r * is2 - 1.0) * inv_n);
+      gf[KM + k * DM + d] = gm;
+      gb[KM + k * DM + d] = f2bf(gm);
+      gf[KM + KM * DM + k * DM + d] = gs;
+      gb[KM + KM * DM + k * DM + d] = f2bf(gs);
+    }
+  }
+  for (int c = NO; c < NOP; ++c) {
+    gf[c] = 0.0f;
+    gb[c] = 0;
+  }
+}
+
+// Column sums out[c] = sum_r X[r][c] for c < ncol, r < nrow: 32 columns by
+// 8 row chunks per block, chunks combined in a fixed order (deterministic).
+__global__ void colsum_kernel(const float* X, int64_t ld, int nrow, int ncol,
+                              float* out) {
+  __shared__ float part[8][32];
+  const int c = blockIdx.x * 32 + (threadIdx.x & 31);
+  const int chunk = threadIdx.x >> 5;
+  const int per = (nrow + 7) / 8;
+  float s = 0.0f;
+  if (c < ncol) {
+    const int r1 = min(nrow, (chunk + 1) * per);
+    for (int r = chunk * per; r < r1; ++r) s += X[(int64_t)r * ld + c];
+  }
+  part[chunk][threadIdx.x & 31] = s;
+  __syncthreads();
+  if (chunk == 0 && c < ncol) {
+    float t = part[0][threadIdx.x];
+    for (int j = 1; j < 8; ++j) t += part[j][threadIdx.x];
+    out[c] = t;
+  }
+}
+
+hipError_t colsum(const float* X, int64_t ld, int nrow, int ncol, float* out,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(colsum_kernel, dim3((ncol + 31) / 32), dim3(256), 0, st, X, ld,
+                     nrow, ncol, out);
+  return hipGetLastError();
+}
+
+// Adam (Kingma & Ba 2015) with bias correction factors c1 = 1/(1 - b1^t),
+// c2 = 1/(1 - b2^t):  p -= lr * (m c1) / (sqrt(v c2) + eps); also refreshes
+// the BF16 shadow of the weights.  1 - b1 and 1 - b2 come from the host in
+// double (1.0f - 0.999f would carry a 1e-5 relative error into v).
+__global__ void adam_kernel(float* p, const float* g, float* m, float* v,
+                            uint16_t* pb, int64_t n, float lr, float b1, float b2,
+                            float omb1, float omb2, float eps, float c1, float c2) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + omb1 * gi;
+    const float vi = b2 * v[i] + omb2 * (gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    p[i] = pi;
+    pb[i] = f2bf(pi);
+  }
+}
+
+__global__ void to_bf16_kernel(const float* p, uint16_t* pb, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    pb[i] = f2bf(p[i]);
+}
+
+__global__ void fill_u16_kernel(uint16_t* x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0;
+}
+
+// He-normal weights (std sqrt(2/fan_in); output layer std 0.01), zero
+// biases.  Normal deviates by the Box-Muller transform of two Philox words.
+__global__ void mlp_init_kernel(float* p, uint16_t* pb, uint64_t seed) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < NP_DEV;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float val = 0.0f;
+    double sd = 0.0;
+    if (i < OFF_B1) sd = sqrt(2.0 / NB);
+    else if (i >= OFF_W2 && i < OFF_B2) sd = sqrt(2.0 / NH);
+    else if (i >= OFF_W3 && i < OFF_B3 && (i - OFF_W3) % NOP < NO) sd = 0.01;
+    if (sd > 0.0) {
+      const u64x4 w = philox4x64_10(0, P_MLP_INIT, (uint64_t)i, 0, seed, 0);
+      const double u1 = u01(w.v[0]), u2 = u01(w.v[1]);
+      val = (float)(sd * sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2));
+    }
+    p[i] = val;
+    pb[i] = f2bf(val);
+  }
+}
+
+// ------------------------------------------------------------ resampling
+//
+// Shared by sblm_resample and mlp_make_data; 256 threads, thread j owns
+// bin j.  On entry val[j] holds the bin value and filled[j] its flag.
+// Empty bins take the linear interpolation of the nearest filled bins on
+// either side, evaluated as v_l + (v_h - v_l)(j - l)/(h - l) (the nearest
+// filled value beyond the last filled bin at either end); then the bins are
+// normalised as (v - median)/max(max - median, 1e-12), the median of 256
+// values being the mean of the two central order statistics.
+__device__ void finish_bins(double* val, int* filled, double* srt, int any_filled,
+                            float* xf, uint16_t* xb) {
+  const int j = threadIdx.x;
+  if (!any_filled) {
+    if (xf) xf[j] = 0.0f;
+    if (xb) xb[j] = 0;
+    return;
+  }
+  double v = val[j];
+  if (!filled[j]) {
+    int l = j - 1, h = j + 1;
+    while (l >= 0 && !filled[l]) --l;
+    while (h < NB && !filled[h]) ++h;
+    if (l >= 0 && h < NB)
+      v = val[l] + (val[h] - val[l]) * (double)(j - l) / (double)(h - l);
+    else
+      v = (l >= 0) ? val[l] : val[h];
+  }
+  srt[j] = v;
+  __syncthreads();
+  // bitonic sort of srt[0..255], ascending
+  for (int k = 2; k <= NB; k <<= 1) {
+    for (int s = k >> 1; s > 0; s >>= 1) {
+      const int p = j ^ s;
+      if (p > j) {
+        const double x = srt[j], y = srt[p];
+        const bool up = (j & k) == 0;
+        if ((x > y) == up) {
+          srt[j] = y;
+          srt[p] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const double med = (srt[NB / 2 - 1] + srt[NB / 2]) / 2.0;
+  const double div = fmax(srt[NB - 1] - med, 1e-12);
+  const double r = (v - med) / div;
+  if (xf) xf[j] = (float)r;
+  if (xb) xb[j] = f2bf((float)r);
+}
+
+__device__ __forceinline__ int bin_of(double t, double t_a, double span) {
+  if (span <= 0.0) return 0;
+  const double u = (t - t_a) / span * (double)NB;
+  return (int)fmin(u, (double)(NB - 1));
+}
+
+// One block of 256 threads per lightcurve (t ascending within each).
+__global__ __launch_bounds__(256) void resample_kernel(const int64_t* off,
+                                                       const double* t,
+                                                       const double* y,
+                                                       const double* w, float* xf,
+                                                       uint16_t* xb) {
+  __shared__ double val[NB], srt[NB];
+  __shared__ int filled[NB];
+  __shared__ int any;
+  const int lc = blockIdx.x, j = threadIdx.x;
+  const int64_t o0 = off[lc], o1 = off[lc + 1];
+  float* xfl = xf ? xf + (int64_t)lc * NB : nullptr;
+  uint16_t* xbl = xb ? xb + (int64_t)lc * NB : nullptr;
+  if (j == 0) any = 0;
+  __syncthreads();
+  double sw = 0.0, swy = 0.0;
+  if (o1 > o0) {
+    const double t_a = t[o0], span = t[o1 - 1] - t_a;
+    // first epoch of bin >= j and of bin >= j + 1 (bins non-decreasing)
+    int64_t lo = o0, hi = o1;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (bin_of(t[mid], t_a, span) < j) lo = mid + 1; else hi = mid;
+    }
+    int64_t e1 = lo, hi2 = o1;
+    while (e1 < hi2) {
+      const int64_t mid = e1 + (hi2 - e1) / 2;
+      if (bin_of(t[mid], t_a, span) <= j) e1 = mid + 1; else hi2 = mid;
+    }
+    for (int64_t e = lo; e < e1; ++e) {
+      const double we = w[e];
+      sw += we;
+      swy += we * y[e];
+    }
+  }
+  filled[j] = sw > 0.0;
+  val[j] = sw > 0.0 ? swy / sw : 0.0;
+  if (sw > 0.0) any = 1;
+  __syncthreads();
+  finish_bins(val, filled, srt, any, xfl, xbl);
+}
+
+// ------------------------------------------------------- training data
+//
+// Sample s uses Philox key (seed, s), counter (0, P_DATA, row, j / 4):
+//   row 0: words 0..5 the parameters (uniform over the domain below, in the
+//          library's plane order), word 6 Fb ~ U[0, 0.5] (Fs = 1), word 7
+//          the noise fraction s ~ U[0.005, 0.03], word 8 the epoch count
+//          L ~ U{200..5000};
+//   row 1 + j: words 0..3 for bin j (Poisson count, two normal deviates).
+// The observing window is t0 +- 2 tE seen through nightly windows
+// [n + 0.1, n + 0.1 + 1/3] days; t_first, t_last are its first and last
+// observable instants and span = t_last - t_first.  Bin j covers
+// [t_first + span j/256, t_first + span (j+1)/256]; its expected epoch count
+// is c_j = n_sched o_j / sum(o) + n_dense d_j / (0.2 tE), with o_j its
+// overlap with the nightly windows, d_j its overlap with t0 +- 0.1 tE,
+// n_dense = round(L/10), n_sched = L - n_dense; the count is Poisson(c_j)
+// (inversion for c_j <= 64, else the rounded normal approximation).  A
+// counted bin holds F = Fs A(t_j) + Fb plus N(0, (s F)^2 / count) noise, A
+// from the forward model at the bin centre; then empty bins and
+// normalisation as for sblm_resample.
+//
+// Targets: (log10 q + 3)/3, (d - 0.5)/1.5, u0/0.5, alpha/(2 pi),
+// (t0 - t_first)/span, tE/span, Fs/(Fs + Fb).
+constexpr double NIGHT0 = 0.1, NIGHT_LEN = 1.0 / 3.0;
+
+__device__ void data_window(double t0, double tE, double& t_first, double& t_last) {
+  const double ta = t0 - 2.0 * tE, tb = t0 + 2.0 * tE;
+  const double na = floor(ta - NIGHT0);
+  t_first = (ta <= na + NIGHT0 + NIGHT_LEN) ? ta : na + 1.0 + NIGHT0;
+  const double nb = floor(tb - NIGHT0);
+  t_last = (tb <= nb + NIGHT0 + NIGHT_LEN) ? tb : nb + NIGHT0 + NIGHT_LEN;
+}
+
+// aux row per sample: t_first, span, t0, tE, Fb, s, L
+constexpr int NAUX = 8;
+
+__global__ void data_draw_kernel(uint64_t seed, int64_t first, int n, double* theta,
+                                 double* aux, float* y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double DLO[6] = {-3.0, 0.5, 0.0, 0.0, 10.0, -10.0};
+  const double DHI[6] = {0.0, 2.0, 0.5, 2.0 * M_PI, 100.0, 10.0};
+  const uint64_t s = (uint64_t)(first + i);
+  const u64x4 w0 = philox4x64_10(0, P_DATA, 0, 0, seed, s);
+  const u64x4 w1 = philox4x64_10(0, P_DATA, 0, 1, seed, s);
+  const u64x4 w2 = philox4x64_10(0, P_DATA, 0, 2, seed, s);
+  const uint64_t wd[9] = {w0.v[0], w0.v[1], w0.v[2], w0.v[3], w1.v[0],
+                          w1.v[1], w1.v[2], w1.v[3], w2.v[0]};
+  double th[6];
+  for (int g = 0; g < 6; ++g) th[g] = DLO[g] + (DHI[g] - DLO[g]) * u01(wd[g]);
+  const double Fb = 0.5 * u01(wd[6]);
+  const double sn = 0.005 + 0.025 * u01(wd[7]);
+  const double L = (double)(200u + below(wd[8], 4801u));
+  double t_first, t_last;
+  data_window(th[5], th[4], t_first, t_last);
+  const double span = t_last - t_first;
+  for (int g = 0; g < 4; ++g) theta[(int64_t)g * n + i] = th[g];
+  theta[(int64_t)4 * n + i] = th[4] / span;
+  theta[(int64_t)5 * n + i] = (th[5] - t_first) / span;
+  double* a = aux + (int64_t)i * NAUX;
+  a[0] = t_first;
+  a[1] = span;
+  a[2] = th[5];
+  a[3] = th[4];
+  a[4] = Fb;
+  a[5] = sn;
+  a[6] = L;
+  a[7] = 0.0;
+  float* yy = y + (int64_t)i * DM;
+  yy[0] = (float)((th[0] + 3.0) / 3.0);
+  yy[1] = (float)((th[1] - 0.5) / 1.5);
+  yy[2] = (float)(th[2] / 0.5);
+  yy[3] = (float)(th[3] / (2.0 * M_PI));
+  yy[4] = (float)((th[5] - t_first) / span);
+  yy[5] = (float)(th[4] / span);
+  yy[6] = (float)(1.0 / (1.0 + Fb));
+}
+
+__device__ __forceinline__ double overlap(double a0, double a1, double b0, double b1) {
+  return fmax(0.0, fmin(a1, b1) - fmax(a0, b0));
+}
+
+__global__ __launch_bounds__(256) void data_finish_kernel(uint64_t seed, int64_t first,
+                                                          const double* aux,
+                                                          const double* A, float* xf,
+                                                          uint16_t* xb) {
+  __shared__ double val[NB], srt[NB], red[NB];
+  __shared__ int filled[NB];
+  __shared__ int any;
+  const int i = blockIdx.x, j = threadIdx.x;
+  const uint64_t s = (uint64_t)(first + i);
+  const double* a = aux + (int64_t)i * NAUX;
+  const double t_first = a[0], span = a[1], t0 = a[2], tE = a[3], Fb = a[4],
+               sn = a[5], L = a[6];
+  const double b0 = t_first + span * (double)j / NB;
+  const double b1 = t_first + span * (double)(j + 1) / NB;
+  double o = 0.0;
+  for (double nt = floor(b0) - 1.0; nt <= floor(b1); nt += 1.0)
+    o += overlap(b0, b1, nt + NIGHT0, nt + NIGHT0 + NIGHT_LEN);
+  const double dj = overlap(b0, b1, t0 - 0.1 * tE, t0 + 0.1 * tE);
+  red[j] = o;
+  if (j == 0) any = 0;
+  __syncthreads();
+  for (int h = NB / 2; h > 0; h >>= 1) {  // fixed-order tree sum
+    if (j < h) red[j] += red[j + h];
+    __syncthreads();
+  }
+  const double osum = red[0];
+  const double n_dense = floor(0.1 * L + 0.5), n_sched = L - n_dense;
+  const double c = (osum > 0.0 ? n_sched * o / osum : 0.0) + n_dense * dj / (0.2 * tE);
+  const u64x4 wb = philox4x64_10(0, P_DATA, 1 + (uint64_t)j, 0, seed, s);
+  const double r1 = u01(wb.v[1]), r2 = u01(wb.v[2]);
+  const double rad = sqrt(-2.0 * log(r1));
+  const double z1 = rad * cos(2.0 * M_PI * r2), z2 = rad * sin(2.0 * M_PI * r2);
+  double cnt;
+  if (c <= 64.0) {
+    const double u = u01(wb.v[0]);
+    double p = exp(-c), F = p;
+    cnt = 0.0;
+    while (u > F && cnt < 1000.0) {
+      cnt += 1.0;
+      p = p * c / cnt;
+      F += p;
+    }
+  } else {
+    cnt = fmax(0.0, floor(c + sqrt(c) * z2 + 0.5));
+  }
+  const double flux = A[(int64_t)i * NB + j] + Fb;
+  filled[j] = cnt > 0.0;
+  val[j] = cnt > 0.0 ? flux + sn * flux / sqrt(cnt) * z1 : 0.0;
+  if (cnt > 0.0) any = 1;
+  __syncthreads();
+  finish_bins(val, filled, srt, any, xf ? xf + (int64_t)i * NB : nullptr,
+              xb ? xb + (int64_t)i * NB : nullptr);
+}
+
+__global__ void bin_centres_kernel(double* u) {
+  u[threadIdx.x] = ((double)threadIdx.x + 0.5) / NB;
+}
+
+}  // namespace
+}  // namespace sblm
+
+using namespace sblm;
+
+// ------------------------------------------------------------- network
+
+struct mlp_net {
+  int device = 0;
+  int batch_max = 0;
+  int64_t step = 0;
+  float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+  uint16_t* pb = nullptr;
+  uint16_t* xbuf = nullptr;   // [batch_max][256]
+  uint16_t *h1 = nullptr, *h2 = nullptr;  // [batch_max][512] post-ReLU
+  float* o = nullptr;         // [batch_max][128]
+  float* dof = nullptr;       // [batch_max][128]
+  uint16_t* dob = nullptr;
+  float *dz2f = nullptr, *dz1f = nullptr;  // [batch_max][512]
+  uint16_t *dz2b = nullptr, *dz1b = nullptr;
+  float* lrow = nullptr;      // [batch_max]
+};
+
+static void net_free(mlp_net* n) {
+  void* ptrs[] = {n->p, n->g, n->m, n->v, n->pb, n->xbuf, n->h1, n->h2, n->o,
+                  n->dof, n->dob, n->dz2f, n->dz1f, n->dz2b, n->dz1b, n->lrow};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+}
+
+static int grid_for(int64_t n) {
+  return (int)std::min<int64_t>((n + 255) / 256, 4096);
+}
+
+extern "C" int mlp_create(int32_t batch_max, uint64_t seed, mlp_net** out) {
+  if (!out) return set_error(SBLM_EINVAL, "mlp_create: null out");
+  *out = nullptr;
+  if (batch_max < 64 || batch_max % 64 != 0)
+    return set_error(SBLM_EINVAL, "mlp_create: batch_max = %d is not a positive multiple of 64",
+                     batch_max);
+  if (batch_max > (1 << 20))
+    return set_error(SBLM_ERANGE, "mlp_create: batch_max = %d beyond 2^20", batch_max);
+  mlp_net* n = new (std::nothrow) mlp_net();
+  if (!n) return set_error(SBLM_ENOMEM, "mlp_create: host allocation");
+  n->batch_max = batch_max;
+  if (hipGetDevice(&n->device) != hipSuccess) {
+    delete n;
+    return set_error(SBLM_EDEVICE, "mlp_create: hipGetDevice");
+  }
+  const size_t B = (size_t)batch_max;
+  bool ok = hipMalloc(&n->p, NP_DEV * 4) == hipSuccess &&
+            hipMalloc(&n->g, NP_DEV * 4) == hipSuccess &&
+            hipMalloc(&n->m, NP_DEV * 4) == hipSuccess &&
+            hipMalloc(&n->v, NP_DEV * 4) == hipSuccess &&
+            hipMalloc(&n->pb, NP_DEV * 2) == hipSuccess &&
+            hipMalloc(&n->xbuf, B * NB * 2) == hipSuccess &&
+            hipMalloc(&n->h1, B * NH * 2) == hipSuccess &&
+            hipMalloc(&n->h2, B * NH * 2) == hipSuccess &&
+            hipMalloc(&n->o, B * NOP * 4) == hipSuccess &&
+            hipMalloc(&n->dof, B * NOP * 4) == hipSuccess &&
+            hipMalloc(&n->dob, B * NOP * 2) == hipSuccess &&
+            hipMalloc(&n->dz2f, B * NH * 4) == hipSuccess &&
+            hipMalloc(&n->dz1f, B * NH * 4) == hipSuccess &&
+            hipMalloc(&n->dz2b, B * NH * 2) == hipSuccess &&
+            hipMalloc(&n->dz1b, B * NH * 2) == hipSuccess &&
+            hipMalloc(&n->lrow, B * 4) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    net_free(n);
+    delete n;
+    return set_error(SBLM_ENOMEM, "mlp_create: device allocation");
+  }
+  hipLaunchKernelGGL(mlp_init_kernel, dim3(grid_for(NP_DEV)), dim3(256), 0, nullptr, n->p,
+                     n->pb, seed);
+  int rc = check_hip(hipGetLastError(), "mlp_create: init launch");
+  if (rc == SBLM_OK)
+    rc = check_hip(hipMemset(n->g, 0, NP_DEV * 4), "mlp_create: memset");
+  if (rc == SBLM_OK)
+    rc = check_hip(hipMemset(n->m, 0, NP_DEV * 4), "mlp_create: memset");
+  if (rc == SBLM_OK)
+    rc = check_hip(hipMemset(n->v, 0, NP_DEV * 4), "mlp_create: memset");
+  if (rc == SBLM_OK) rc = check_hip(hipDeviceSynchronize(), "mlp_create: init");
+  if (rc != SBLM_OK) {
+    net_free(n);
+    delete n;
+    return rc;
+  }
+  *out = n;
+  return SBLM_OK;
+}
+
+extern "C" void mlp_destroy(mlp_net* n) {
+  if (!n) return;
+  (void)hipDeviceSynchronize();
+  net_free(n);
+  delete n;
+}
+
+// canonical (host) order: W1 [256][512], b1, W2 [512][512], b2, W3 [512][120], b3 [120]
+static void canon_map(int64_t* dst_of_src) {
+  int64_t k = 0;
+  for (int64_t i = 0; i < OFF_W3; ++i) dst_of_src[k++] = i;
+  for (int r = 0; r < NH; ++r)
+    for (int c = 0; c < NO; ++c) dst_of_src[k++] = OFF_W3 + (int64_t)r * NOP + c;
+  for (int c = 0; c < NO; ++c) dst_of_src[k++] = OFF_B3 + c;
+}
+
+static int copy_canonical(mlp_net* n, float* dev, float* host, bool to_host,
+                          const char* who) {
+  float* tmp = (float*)calloc(NP_DEV, sizeof(float));
+  int64_t* map = (int64_t*)malloc(MLP_NPARAMS * sizeof(int64_t));
+  if (!tmp || !map) {
+    free(tmp);
+    free(map);
+    return set_error(SBLM_ENOMEM, "%s: host allocation", who);
+  }
+  canon_map(map);
+  int rc = SBLM_OK;
+  if (to_host) {
+    rc = check_hip(hipMemcpy(tmp, dev, NP_DEV * 4, hipMemcpyDeviceToHost), who);
+    if (rc == SBLM_OK)
+      for (int64_t i = 0; i < MLP_NPARAMS; ++i) host[i] = tmp[map[i]];
+  } else {
+    for (int64_t i = 0; i < MLP_NPARAMS; ++i) tmp[map[i]] = host[i];
+    rc = check_hip(hipMemcpy(dev, tmp, NP_DEV * 4, hipMemcpyHostToDevice), who);
+  }
+  free(tmp);
+  free(map);
+  (void)n;
+  return rc;
+}
+
+extern "C" int mlp_set_params(mlp_net* n, const float* params) {
+  if (!n || !params) return set_error(SBLM_EINVAL, "mlp_set_params: null argument");
+  int rc = copy_canonical(n, n->p, (float*)params, false, "mlp_set_params");
+  if (rc != SBLM_OK) return rc;
+  hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(NP_DEV)), dim3(256), 0, nullptr, n->p,
+                     n->pb, NP_DEV);
+  rc = check_hip(hipGetLastError(), "mlp_set_params: launch");
+  if (rc == SBLM_OK) rc = check_hip(hipMemset(n->m, 0, NP_DEV * 4), "mlp_set_params");
+  if (rc == SBLM_OK) rc = check_hip(hipMemset(n->v, 0, NP_DEV * 4), "mlp_set_params");
+  if (rc == SBLM_OK) rc = check_hip(hipDeviceSynchronize(), "mlp_set_params");
+  n->step = 0;
+  return rc;
+}
+
+extern "C" int mlp_get_params(mlp_net* n, float* params) {
+  if (!n || !params) return set_error(SBLM_EINVAL, "mlp_get_params: null argument");
+  int rc = check_hip(hipDeviceSynchronize(), "mlp_get_params");
+  if (rc != SBLM_OK) return rc;
+  return copy_canonical(n, n->p, params, true, "mlp_get_params");
+}
+
+extern "C" int mlp_get_grad(mlp_net* n, float* grad) {
+  if (!n || !grad) return set_error(SBLM_EINVAL, "mlp_get_grad: null argument");
+  int rc = check_hip(hipDeviceSynchronize(), "mlp_get_grad");
+  if (rc != SBLM_OK) return rc;
+  return copy_canonical(n, n->g, grad, true, "mlp_get_grad");
+}
+
+extern "C" int mlp_set_grad(mlp_net* n, const float* grad) {
+  if (!n || !grad) return set_error(SBLM_EINVAL, "mlp_set_grad: null argument");
+  int rc = check_hip(hipDeviceSynchronize(), "mlp_set_grad");
+  if (rc != SBLM_OK) return rc;
+  return copy_canonical(n, n->g, (float*)grad, false, "mlp_set_grad");
+}
+
+// Forward pass of rows [0, nb) of X (nb % 64 == 0) into n->o.
+static hipError_t forward_rows(mlp_net* n, const uint16_t* X, int nb, hipStream_t st) {
+  GemmArgs g;
+  memset(&g, 0, sizeof(g));
+  g.A = X; g.lda = NB; g.B = n->pb + OFF_W1; g.ldb = NH;
+  g.M = nb; g.N = NH; g.K = NB; g.bias = n->p + OFF_B1; g.Cb = n->h1; g.ldc = NH;
+  g.relu = 1;
+  hipError_t e = gemm(g, true, false, st);
+  if (e != hipSuccess) return e;
+  g.A = n->h1; g.lda = NH; g.B = n->pb + OFF_W2; g.ldb = NH; g.K = NH;
+  g.bias = n->p + OFF_B2; g.Cb = n->h2;
+  e = gemm(g, true, false, st);
+  if (e != hipSuccess) return e;
+  g.A = n->h2; g.B = n->pb + OFF_W3; g.ldb = NOP; g.N = NOP; g.bias = n->p + OFF_B3;
+  g.Cb = nullptr; g.Cf = n->o; g.ldc = NOP; g.relu = 0;
+  return gemm(g, true, false, st);
+}
+
+extern "C" int mlp_forward(mlp_net* n, const uint16_t* x, int64_t rows, float* out,
+                           void* stream) {
+  if (!n) return set_error(SBLM_ESTATE, "mlp_forward: null network");
+  if (rows < 0) return set_error(SBLM_EINVAL, "mlp_forward: rows < 0");
+  if (rows == 0) return SBLM_OK;
+  if (!x || !out) return set_error(SBLM_EINVAL, "mlp_forward: null x or out");
+  hipStream_t st = (hipStream_t)stream;
+  for (int64_t r0 = 0; r0 < rows; r0 += n->batch_max) {
+    const int nr = (int)std::min<int64_t>(n->batch_max, rows - r0);
+    const int nb = (nr + 63) / 64 * 64;
+    hipError_t e = hipMemcpyAsync(n->xbuf, x + r0 * NB, (size_t)nr * NB * 2,
+                                  hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && nb > nr) {
+      hipLaunchKernelGGL(fill_u16_kernel, dim3(grid_for((int64_t)(nb - nr) * NB)), dim3(256),
+                         0, st, n->xbuf + (int64_t)nr * NB, (int64_t)(nb - nr) * NB);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = forward_rows(n, n->xbuf, nb, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(out + r0 * NOP, n->o, (size_t)nr * NOP * 4,
+                         hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return check_hip(e, "mlp_forward");
+  }
+  return SBLM_OK;
+}
+
+static hipError_t loss_grad(mlp_net* n, const uint16_t* x, const float* y, int rows,
+                            float* loss, hipStream_t st) {
+  hipError_t e = forward_rows(n, x, rows, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mlp_nll_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, n->o, y,
+                     rows, n->dof, n->dob, n->lrow);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  GemmArgs g;
+  memset(&g, 0, sizeof(g));
+  // dZ2 = (dO W3^T) * [H2 > 0]
+  g.A = n->dob; g.lda = NOP; g.B = n->pb + OFF_W3; g.ldb = NOP;
+  g.M = rows; g.N = NH; g.K = NOP; g.mask = n->h2; g.ldm = NH;
+  g.Cf = n->dz2f; g.Cb = n->dz2b; g.ldc = NH;
+  if ((e = gemm(g, true, true, st)) != hipSuccess) return e;
+  // dZ1 = (dZ2 W2^T) * [H1 > 0]
+  g.A = n->dz2b; g.lda = NH; g.B = n->pb + OFF_W2; g.ldb = NH; g.K = NH;
+  g.mask = n->h1; g.Cf = n->dz1f; g.Cb = n->dz1b;
+  if ((e = gemm(g, true, true, st)) != hipSuccess) return e;
+  // weight gradients: gW = (layer input)^T dZ, contraction over the batch
+  memset(&g, 0, sizeof(g));
+  g.A = n->h2; g.lda = NH; g.B = n->dob; g.ldb = NOP;
+  g.M = NH; g.N = NOP; g.K = rows; g.Cf = n->g + OFF_W3; g.ldc = NOP;
+  if ((e = gemm(g, false, false, st)) != hipSuccess) return e;
+  g.A = n->h1; g.lda = NH; g.B = n->dz2b; g.ldb = NH; g.N = NH;
+  g.Cf = n->g + OFF_W2; g.ldc = NH;
+  if ((e = gemm(g, false, false, st)) != hipSuccess) return e;
+  g.A = x; g.lda = NB; g.B = n->dz1b; g.M = NB; g.Cf = n->g + OFF_W1;
+  if ((e = gemm(g, false, false, st)) != hipSuccess) return e;
+  if ((e = colsum(n->dof, NOP, rows, NOP, n->g + OFF_B3, st)) != hipSuccess) return e;
+  if ((e = colsum(n->dz2f, NH, rows, NH, n->g + OFF_B2, st)) != hipSuccess) return e;
+  if ((e = colsum(n->dz1f, NH, rows, NH, n->g + OFF_B1, st)) != hipSuccess) return e;
+  if (loss) e = colsum(n->lrow, 1, rows, 1, loss, st);
+  return e;
+}
+
+extern "C" int mlp_loss_grad(mlp_net* n, const uint16_t* x, const float* y, int32_t rows,
+                             float* loss, void* stream) {
+  if (!n) return set_error(SBLM_ESTATE, "mlp_loss_grad: null network");
+  if (!x || !y) return set_error(SBLM_EINVAL, "mlp_loss_grad: null x or y");
+  if (rows < 64 || rows % 64 != 0 || rows > n->batch_max)
+    return set_error(SBLM_EINVAL,
+                     "mlp_loss_grad: rows = %d must be a multiple of 64 in [64, %d]", rows,
+                     n->batch_max);
+  return check_hip(loss_grad(n, x, y, rows, loss, (hipStream_t)stream), "mlp_loss_grad");
+}
+
+static hipError_t adam(mlp_net* n, float lr, hipStream_t st) {
+  const double b1 = 0.9, b2 = 0.999;
+  n->step += 1;
+  const double c1 = 1.0 / (1.0 - pow(b1, (double)n->step));
+  const double c2 = 1.0 / (1.0 - pow(b2, (double)n->step));
+  hipLaunchKernelGGL(adam_kernel, dim3(grid_for(NP_DEV)), dim3(256), 0, st, n->p, n->g,
+                     n->m, n->v, n->pb, NP_DEV, lr, (float)b1, (float)b2,
+                     (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f, (float)c1, (float)c2);
+  return hipGetLastError();
+}
+
+extern "C" int mlp_adam_step(mlp_net* n, float lr, void* stream) {
+  if (!n) return set_error(SBLM_ESTATE, "mlp_adam_step: null network");
+  if (!(lr >= 0.0f)) return set_error(SBLM_EINVAL, "mlp_adam_step: lr must be >= 0");
+  return check_hip(adam(n, lr, (hipStream_t)stream), "mlp_adam_step");
+}
+
+extern "C" int mlp_train(mlp_net* n, const uint16_t* x, const float* y, int64_t rows,
+                         int32_t batch, int32_t epochs, float lr0, float lr1,
+                         float* loss, void* stream) {
+  if (!n) return set_error(SBLM_ESTATE, "mlp_train: null network");
+  if (!x || !y) return set_error(SBLM_EINVAL, "mlp_train: null x or y");
+  if (batch < 64 || batch % 64 != 0 || batch > n->batch_max)
+    return set_error(SBLM_EINVAL, "mlp_train: batch = %d must be a multiple of 64 in [64, %d]",
+                     batch, n->batch_max);
+  if (epochs < 0 || rows < batch)
+    return set_error(SBLM_EINVAL, "mlp_train: epochs = %d, rows = %lld (< batch?)", epochs,
+                     (long long)rows);
+  if (!(lr0 >= 0.0f) || !(lr1 >= 0.0f))
+    return set_error(SBLM_EINVAL, "mlp_train: learning rates must be >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t per = rows / batch;
+  const int64_t total = per * epochs;
+  for (int64_t k = 0; k < total; ++k) {
+    const int64_t r0 = (k % per) * batch;
+    const double fr = total > 1 ? (double)k / (double)(total - 1) : 0.0;
+    const float lr = (float)(lr1 + 0.5 * (lr0 - lr1) * (1.0 + cos(M_PI * fr)));
+    hipError_t e = loss_grad(n, x + r0 * NB, y + r0 * DM, batch, loss ? loss + k : nullptr,
+                             st);
+    if (e == hipSuccess) e = adam(n, lr, st);
+    if (e != hipSuccess) return check_hip(e, "mlp_train");
+  }
+  return SBLM_OK;
+}
+
+// ---------------------------------------------------------- resampling
+
+extern "C" int sblm_resample(const sblm_lcs* lcs, float* xf, uint16_t* xb, void* stream) {
+  if (!lcs || !lcs->off || !lcs->t || !lcs->y || !lcs->w)
+    return set_error(SBLM_EINVAL, "sblm_resample: null lightcurve descriptor or array");
+  if (lcs->n_lc < 1) return set_error(SBLM_EINVAL, "sblm_resample: n_lc < 1");
+  if (lcs->n_lc > (1 << 24)) return set_error(SBLM_ERANGE, "sblm_resample: n_lc beyond 2^24");
+  if (!xf && !xb) return set_error(SBLM_EINVAL, "sblm_resample: no output");
+  hipLaunchKernelGGL(resample_kernel, dim3(lcs->n_lc), dim3(NB), 0, (hipStream_t)stream,
+                     lcs->off, lcs->t, lcs->y, lcs->w, xf, xb);
+  return check_hip(hipGetLastError(), "sblm_resample launch");
+}
+
+extern "C" int mlp_make_data(uint64_t seed, int64_t first, int64_t n, uint16_t* xb,
+                             float* xf, float* y, void* stream) {
+  if (n < 0 || first < 0) return set_error(SBLM_EINVAL, "mlp_make_data: negative range");
+  if (n == 0) return SBLM_OK;
+  if (!y || (!xb && !xf)) return set_error(SBLM_EINVAL, "mlp_make_data: null output");
+  if (n > (1LL << 26)) return set_error(SBLM_ERANGE, "mlp_make_data: n beyond 2^26");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t chunk = std::min<int64_t>(n, 1 << 16);
+  double *theta = nullptr, *aux = nullptr, *A = nullptr, *u = nullptr;
+  bool ok = hipMalloc(&theta, (size_t)chunk * 6 * 8) == hipSuccess &&
+            hipMalloc(&aux, (size_t)chunk * NAUX * 8) == hipSuccess &&
+            hipMalloc(&A, (size_t)chunk * NB * 8) == hipSuccess &&
+            hipMalloc(&u, NB * 8) == hipSuccess;
+  int rc = SBLM_OK;
+  if (!ok) {
+    (void)hipGetLastError();
+    rc = set_error(SBLM_ENOMEM, "mlp_make_data: device allocation");
+  }
+  if (rc == SBLM_OK) {
+    hipLaunchKernelGGL(bin_centres_kernel, dim3(1), dim3(NB), 0, st, u);
+    rc = check_hip(hipGetLastError(), "mlp_make_data: launch");
+  }
+  for (int64_t s0 = 0; rc == SBLM_OK && s0 < n; s0 += chunk) {
+    const int nc = (int)std::min<int64_t>(chunk, n - s0);
+    hipLaunchKernelGGL(data_draw_kernel, dim3((nc + 255) / 256), dim3(256), 0, st, seed,
+                       first + s0, nc, theta, aux, y + s0 * DM);
+    rc = check_hip(hipGetLastError(), "mlp_make_data: draw launch");
+    if (rc == SBLM_OK) rc = sblm_magnify(theta, nc, u, NB, SBLM_FP64, A, nullptr, nullptr, st);
+    if (rc == SBLM_OK) {
+      hipLaunchKernelGGL(data_finish_kernel, dim3(nc), dim3(NB), 0, st, seed, first + s0,
+                         aux, A, xf ? xf + s0 * NB : nullptr, xb ? xb + s0 * NB : nullptr);
+      rc = check_hip(hipGetLastError(), "mlp_make_data: finish launch");
+    }
+  }
+  // the temporaries are released once the queued work has used them
+  if (hipStreamSynchronize(st) != hipSuccess && rc == SBLM_OK)
+    rc = check_hip(hipGetLastError(), "mlp_make_data: synchronise");
+  if (theta) (void)hipFree(theta);
+  if (aux) (void)hipFree(aux);
+  if (A) (void)hipFree(A);
+  if (u) (void)hipFree(u);
+  return rc;
+}

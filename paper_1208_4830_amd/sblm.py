@@ -15,6 +15,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("SBLM_LIB", os.path.join(_HERE, "libsblm.so"))
 NPAR = 6
 FP64, MIXED = 0, 1
+# proposal network sizes (include/sblm.h)
+NBINS, NOUT, NOUT_PAD, NTARGET, NPARAMS = 256, 120, 128, 7, 455800
 
 _lib = None
 
@@ -74,6 +76,26 @@ _SIGS = {
     "ea_draws": [ctypes.c_uint64] * 6 + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
     "ea_generation_traced": [ctypes.c_void_p] * 6,
     "sblm_last_error": [],
+    "sblm_resample": [ctypes.POINTER(sblm_lcs), ctypes.c_void_p, ctypes.c_void_p,
+                      ctypes.c_void_p],
+    "mlp_make_data": [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "mlp_create": [ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p)],
+    "mlp_destroy": [ctypes.c_void_p],
+    "mlp_set_params": [ctypes.c_void_p, ctypes.c_void_p],
+    "mlp_get_params": [ctypes.c_void_p, ctypes.c_void_p],
+    "mlp_forward": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                    ctypes.c_void_p],
+    "mlp_loss_grad": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                      ctypes.c_void_p, ctypes.c_void_p],
+    "mlp_get_grad": [ctypes.c_void_p, ctypes.c_void_p],
+    "mlp_set_grad": [ctypes.c_void_p, ctypes.c_void_p],
+    "mlp_adam_step": [ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p],
+    "mlp_train": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                  ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                  ctypes.c_void_p, ctypes.c_void_p],
+    "ea_seed": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                ctypes.c_void_p],
 }
 EXPORTS = tuple(_SIGS)
 
@@ -93,6 +115,7 @@ def load():
     lib.sblm_last_error.restype = ctypes.c_char_p
     lib.ea_default_config.restype = None
     lib.ea_destroy.restype = None
+    lib.mlp_destroy.restype = None
     _lib = lib
     return lib
 
@@ -286,9 +309,108 @@ class EAState:
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(load().ea_load(self.h, buf, len(blob), _stream(stream)))
 
+    def seed(self, out, n_seed, stream=None):
+        """Overwrite rows [0, n_seed) of every lightcurve's population with
+        draws from the proposal mixture out[n_lc][>=120] (float32)."""
+        out = _dev(out, torch.float32)
+        _check(load().ea_seed(self.h, _ptr(out), out.shape[1], n_seed, _stream(stream)))
+
     def close(self):
         if self.h:
             load().ea_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- proposal network
+
+def sblm_resample(lcs, want_f32=False, want_bf16=True, stream=None):
+    """(xb [n_lc][256] bfloat16 or None, xf [n_lc][256] float32 or None)."""
+    dev = lcs.t.device
+    xb = torch.empty((lcs.n_lc, NBINS), dtype=torch.bfloat16, device=dev) if want_bf16 else None
+    xf = torch.empty((lcs.n_lc, NBINS), dtype=torch.float32, device=dev) if want_f32 else None
+    _check(load().sblm_resample(ctypes.byref(lcs.desc), _ptr(xf), _ptr(xb), _stream(stream)))
+    return xb, xf
+
+
+def mlp_make_data(seed, first, n, want_f32=False, device="cuda", stream=None):
+    """Training samples first..first+n-1: (xb bfloat16 [n][256], xf float32
+    [n][256] or None, y float32 [n][7])."""
+    xb = torch.empty((n, NBINS), dtype=torch.bfloat16, device=device)
+    xf = torch.empty((n, NBINS), dtype=torch.float32, device=device) if want_f32 else None
+    y = torch.empty((n, NTARGET), dtype=torch.float32, device=device)
+    _check(load().mlp_make_data(seed, first, n, _ptr(xb), _ptr(xf), _ptr(y), _stream(stream)))
+    return xb, xf, y
+
+
+class MLP:
+    """Owner of an mlp_net* (weights, Adam moments and activation buffers)."""
+
+    def __init__(self, batch_max=1024, seed=0):
+        h = ctypes.c_void_p()
+        _check(load().mlp_create(batch_max, seed, ctypes.byref(h)))
+        self.h = h
+        self.batch_max = batch_max
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == NPARAMS
+        _check(load().mlp_set_params(self.h, p.ctypes.data_as(ctypes.c_void_p)))
+
+    def get_params(self):
+        import numpy as np
+        p = np.empty(NPARAMS, dtype=np.float32)
+        _check(load().mlp_get_params(self.h, p.ctypes.data_as(ctypes.c_void_p)))
+        return p
+
+    def grad(self):
+        import numpy as np
+        g = np.empty(NPARAMS, dtype=np.float32)
+        _check(load().mlp_get_grad(self.h, g.ctypes.data_as(ctypes.c_void_p)))
+        return g
+
+    def set_grad(self, grad):
+        import numpy as np
+        g = np.ascontiguousarray(grad, dtype=np.float32)
+        assert g.size == NPARAMS
+        _check(load().mlp_set_grad(self.h, g.ctypes.data_as(ctypes.c_void_p)))
+
+    def forward(self, xb, out=None, stream=None):
+        xb = _dev(xb, torch.bfloat16)
+        if out is None:
+            out = torch.empty((xb.shape[0], NOUT_PAD), dtype=torch.float32, device=xb.device)
+        _check(load().mlp_forward(self.h, _ptr(xb), xb.shape[0], _ptr(_dev(out, torch.float32)),
+                                  _stream(stream)))
+        return out
+
+    def loss_grad(self, xb, y, stream=None):
+        xb, y = _dev(xb, torch.bfloat16), _dev(y, torch.float32)
+        loss = torch.zeros(1, dtype=torch.float32, device=xb.device)
+        _check(load().mlp_loss_grad(self.h, _ptr(xb), _ptr(y), xb.shape[0], _ptr(loss),
+                                    _stream(stream)))
+        return loss
+
+    def adam_step(self, lr, stream=None):
+        _check(load().mlp_adam_step(self.h, lr, _stream(stream)))
+
+    def train(self, xb, y, batch=1024, epochs=1, lr0=1e-3, lr1=1e-5, stream=None):
+        """Returns the per-step losses (float32 device tensor)."""
+        xb, y = _dev(xb, torch.bfloat16), _dev(y, torch.float32)
+        steps = epochs * (xb.shape[0] // batch)
+        loss = torch.zeros(max(steps, 1), dtype=torch.float32, device=xb.device)
+        _check(load().mlp_train(self.h, _ptr(xb), _ptr(y), xb.shape[0], batch, epochs, lr0,
+                                lr1, _ptr(loss), _stream(stream)))
+        return loss[:steps]
+
+    def close(self):
+        if self.h:
+            load().mlp_destroy(self.h)
             self.h = None
 
     def __del__(self):

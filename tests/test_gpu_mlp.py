@@ -1,0 +1,215 @@
+"""GPU parity of the learned proposal path against the FP64 oracle:
+resampling, training samples, the network's forward pass, gradients and
+Adam step, and the seeding draws; training is deterministic and lowers the
+loss."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp_oracle as M
+from paper_1208_4830_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+def canon(p):
+    return np.concatenate([np.asarray(p[k], np.float64).ravel() for k in NAMES])
+
+
+def uncanon(v):
+    out, o = {}, 0
+    shapes = {"W1": (256, 512), "b1": (512,), "W2": (512, 512), "b2": (512,),
+              "W3": (512, 120), "b3": (120,)}
+    for k in NAMES:
+        n = int(np.prod(shapes[k]))
+        out[k] = np.asarray(v[o:o + n], np.float64).reshape(shapes[k])
+        o += n
+    return out
+
+
+def bf16(a):
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    t = torch.from_numpy(np.asarray(a, np.float32).copy()).to(torch.bfloat16)
+    return t.to(torch.float64).numpy()
+
+
+def gpu_params(p):
+    """The values the network computes with: BF16 weights, FP32 biases."""
+    q = {}
+    for k in NAMES:
+        v = np.asarray(p[k], np.float32).astype(np.float64)
+        q[k] = bf16(v) if k.startswith("W") else v
+    return q
+
+
+def make_lcs(hip, lengths, seed, special=True):
+    """CSR lightcurves with uniform cadence, random fluxes and weights."""
+    rng = np.random.default_rng(seed)
+    ts, ys, ws = [], [], []
+    for k, L in enumerate(lengths):
+        t = np.sort(rng.uniform(-50, 50, L))
+        y = 1.0 + 0.2 * rng.random(L)
+        w = rng.uniform(0.5, 2.0, L)
+        ts.append(t), ys.append(y), ws.append(w)
+    if special:
+        # epochs crowded into the first bins plus one at the end, some with
+        # zero weight; a lightcurve with no weight at all; a constant one
+        t = np.concatenate([np.linspace(0, 0.3, 40), [100.0]])
+        w = np.ones(41)
+        w[::3] = 0.0
+        ts.append(t), ys.append(np.cos(t)), ws.append(w)
+        ts.append(np.linspace(0, 1, 9)), ys.append(np.ones(9)), ws.append(np.zeros(9))
+        ts.append(np.linspace(0, 1, 33)), ys.append(np.full(33, 2.5)), ws.append(np.ones(33))
+    off = np.zeros(len(ts) + 1, np.int64)
+    off[1:] = np.cumsum([len(t) for t in ts])
+    cat = [np.concatenate(a) if len(a) else np.zeros(0) for a in (ts, ys, ws)]
+    dev = lambda a, dt=torch.float64: torch.tensor(a, dtype=dt, device="cuda")
+    lcs = hip.Lightcurves(dev(off, torch.int64), dev(cat[0]), dev(cat[1]), dev(cat[2]))
+    return lcs, off, cat
+
+
+def test_resample_matches_oracle(hip):
+    # empty, single-epoch and two-epoch lightcurves, sizes across many bins
+    lengths = [0, 1, 2, 17, 255, 256, 257, 1000, 4999]
+    lcs, off, (t, y, w) = make_lcs(hip, lengths, seed=3)
+    xb, xf = hip.sblm_resample(lcs, want_f32=True, want_bf16=True)
+    torch.cuda.synchronize()
+    xf = xf.cpu().numpy().astype(np.float64)
+    for k in range(len(off) - 1):
+        sl = slice(off[k], off[k + 1])
+        ref = M.resample(t[sl], y[sl], w[sl])
+        err = np.abs(xf[k] - ref)
+        assert np.all(err <= 1.2e-7 * np.abs(ref) + 1e-30), (k, err.max())
+    # the BF16 output is the round-to-nearest-even of the FP32 one
+    assert torch.equal(xb.cpu(), torch.from_numpy(xf.astype(np.float32)).to(torch.bfloat16))
+
+
+def test_training_samples_match_oracle(hip):
+    seed, first, n = 1234, 50, 12
+    xb, xf, y = hip.mlp_make_data(seed, first, n, want_f32=True)
+    torch.cuda.synchronize()
+    xf, y = xf.cpu().numpy().astype(np.float64), y.cpu().numpy().astype(np.float64)
+    for i in range(n):
+        x_ref, y_ref = M.make_sample(seed, first + i)
+        assert np.max(np.abs(xf[i] - x_ref)) < 1e-6, (i, np.max(np.abs(xf[i] - x_ref)))
+        assert np.allclose(y[i], y_ref, rtol=2e-7, atol=1e-7), i
+    # sample s depends only on (seed, s): a shifted range reproduces the rows
+    xb2, _, y2 = hip.mlp_make_data(seed, first + 5, 4)
+    assert torch.equal(xb2, xb[5:9]) and np.array_equal(y2.cpu().numpy(), y[5:9].astype(np.float32))
+
+
+@pytest.mark.parametrize("rows", [192, 150])
+def test_forward_matches_oracle(hip, rows):
+    rng = np.random.default_rng(7)
+    p = M.init_params(rng, scale_out=0.3)
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.normal(scale=0.1, size=p[k].shape)
+    net = hip.MLP(batch_max=128, seed=1)  # rows span two chunks
+    net.set_params(canon(p).astype(np.float32))
+    x = bf16(rng.normal(size=(rows, 256)))
+    out = net.forward(torch.tensor(x, dtype=torch.bfloat16, device="cuda"))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.all(got[:, 120:] == 0)
+    q = gpu_params(p)
+    ref, _ = M.forward(q, x)
+    rel = np.linalg.norm(got[:, :120] - ref) / np.linalg.norm(ref)
+    # the kernels round the hidden activations to BF16; with that rounding
+    # emulated only the FP32 accumulation order differs
+    h1 = bf16(np.maximum(x @ q["W1"] + q["b1"], 0))
+    h2 = bf16(np.maximum(h1 @ q["W2"] + q["b2"], 0))
+    emu = h2 @ q["W3"] + q["b3"]
+    scale = np.abs(h2) @ np.abs(q["W3"]) + np.abs(q["b3"])
+    e_emu = np.abs(got[:, :120] - emu) / scale
+    print(f"forward rows={rows}: rel vs FP64 {rel:.2e}, emulated max {e_emu.max():.2e}, "
+          f"median {np.median(e_emu):.2e}")
+    assert rel < 1e-2
+    assert np.median(e_emu) < 1e-5 and e_emu.max() < 1e-2
+    net.close()
+
+
+def test_gradients_match_oracle(hip):
+    rng = np.random.default_rng(8)
+    p = M.init_params(rng, scale_out=0.3)
+    net = hip.MLP(batch_max=256, seed=1)
+    net.set_params(canon(p).astype(np.float32))
+    x = bf16(rng.normal(size=(256, 256)))
+    y = rng.uniform(0, 1, (256, 7)).astype(np.float32)
+    loss = net.loss_grad(torch.tensor(x, dtype=torch.bfloat16, device="cuda"),
+                         torch.tensor(y, device="cuda"))
+    g = uncanon(net.grad())
+    L_ref, g_ref = M.loss_and_grad(gpu_params(p), x, y.astype(np.float64))
+    L = float(loss.cpu())
+    print(f"loss gpu {L:.6f} oracle {L_ref:.6f}")
+    assert abs(L - L_ref) <= 1e-2 * abs(L_ref)
+    for k in NAMES:
+        a, b = g[k].ravel(), g_ref[k].ravel()
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+        print(f"  {k}: rel {rel:.2e} cos {cos:.6f}")
+        assert rel < 3e-2 and cos > 0.999, k
+    net.close()
+
+
+def test_adam_steps_match_oracle(hip):
+    rng = np.random.default_rng(9)
+    p = {"w": (rng.normal(size=455800) * 0.05).astype(np.float32).astype(np.float64)}
+    net = hip.MLP(batch_max=64, seed=1)
+    net.set_params(p["w"].astype(np.float32))
+    st = {}
+    for t, lr in ((1, 1e-3), (2, 5e-4), (3, 2e-3)):
+        g = (rng.normal(size=455800) * 10.0 ** rng.uniform(-9, 0, 455800)).astype(np.float32)
+        g[::1000] = 0.0
+        net.set_grad(g)
+        net.adam_step(lr)
+        M.adam_step(p, {"w": g.astype(np.float64)}, st, lr=lr, t=t)
+        got = net.get_params().astype(np.float64)
+        err = np.abs(got - p["w"])
+        assert np.all(err <= 2.4e-7 * np.abs(p["w"]) + 1e-9 * lr / 1e-3), (t, err.max())
+    net.close()
+
+
+def test_training_is_deterministic_and_lowers_the_loss(hip):
+    xb, _, y = hip.mlp_make_data(3, 0, 8192)
+    nets = [hip.MLP(batch_max=512, seed=5) for _ in range(2)]
+    curves = [n.train(xb, y, batch=512, epochs=3, lr0=1e-3, lr1=1e-4) for n in nets]
+    torch.cuda.synchronize()
+    c = curves[0].cpu().numpy()
+    print(f"training loss: first {c[:4].mean():.3f} last {c[-4:].mean():.3f}")
+    assert np.all(np.isfinite(c)) and c[-4:].mean() < c[:4].mean() - 1.0
+    assert torch.equal(curves[0], curves[1])
+    assert np.array_equal(nets[0].get_params(), nets[1].get_params())
+    for n in nets:
+        n.close()
+
+
+def test_seeding_matches_oracle(hip):
+    lengths = [40, 0, 300, 1, 1200]
+    lcs, off, (t, y, w) = make_lcs(hip, lengths, seed=4, special=False)
+    cfg = hip.ea_default_config()
+    cfg.pop = 16
+    st = hip.EAState(cfg, lcs, 77)
+    P0 = st.view("P").clone()
+    rng = np.random.default_rng(5)
+    out = np.zeros((len(lengths), 128), np.float32)
+    out[:, :8] = rng.normal(size=(len(lengths), 8))
+    out[:, 8:64] = rng.uniform(-0.2, 1.2, (len(lengths), 56))
+    out[:, 64:120] = rng.uniform(-4, -0.5, (len(lengths), 56))
+    st.seed(torch.tensor(out, device="cuda"), 9)
+    torch.cuda.synchronize()
+    P = st.view("P").cpu().numpy()
+    P0 = P0.cpu().numpy()
+    lo, hi = np.array(cfg.lo[:]), np.array(cfg.hi[:])
+    for k, L in enumerate(lengths):
+        cols = k * 16 + np.arange(16)
+        if L == 0:
+            assert np.array_equal(P[:, cols], P0[:, cols])
+            continue
+        tf = t[off[k]]
+        span = t[off[k + 1] - 1] - tf
+        ref = M.seed_rows(out[k].astype(np.float64), tf, span, lo, hi, 77, k, 9)
+        assert np.allclose(P[:, cols[:9]].T, ref, rtol=0, atol=1e-12), k
+        assert np.array_equal(P[:, cols[9:]], P0[:, cols[9:]])
+    st.close()

@@ -4,6 +4,7 @@ import numpy as np
 from scipy import stats
 
 from oracle import mlp_oracle as M
+from oracle import oracle as O
 
 
 def test_resample_closed_forms():
@@ -91,3 +92,115 @@ def test_training_reduces_loss():
         L, g = M.loss_and_grad(p, X, Y)
         M.adam_step(p, g, st, lr=1e-3, t=t)
     assert L < L0 - 1.0
+
+
+# ------------------------------------------------- training-sample pins
+
+def test_poisson_count_is_the_poisson_quantile_function():
+    rng = np.random.default_rng(3)
+    n_checked = 0
+    for _ in range(400):
+        c = rng.uniform(0.01, 64.0)
+        u = rng.uniform()
+        k = M.poisson_count(c, u, 0.0)
+        # skip draws that sit on a CDF step to rounding precision
+        if min(abs(stats.poisson.cdf(k, c) - u), abs(stats.poisson.cdf(k - 1, c) - u)) < 1e-12:
+            continue
+        assert k == stats.poisson.ppf(u, c), (c, u)
+        n_checked += 1
+    assert n_checked > 390
+    # large means: the rounded normal approximation, never negative
+    assert M.poisson_count(100.0, 0.5, 1.5) == np.floor(100 + 10 * 1.5 + 0.5)
+    assert M.poisson_count(100.0, 0.5, -50.0) == 0.0
+
+
+def test_data_window_lies_in_nights_and_in_the_event_window():
+    rng = np.random.default_rng(4)
+    for _ in range(500):
+        t0, tE = rng.uniform(-10, 10), rng.uniform(10, 100)
+        tf, tl = M.data_window(t0, tE)
+        ta, tb = t0 - 2 * tE, t0 + 2 * tE
+        assert ta <= tf < ta + 1.0 and tb - 1.0 < tl <= tb
+        for x in (tf, tl):
+            ph = x - np.floor(x)
+            assert 0.1 - 1e-9 <= ph <= 0.1 + 1 / 3 + 1e-9
+        # an endpoint already inside a night is kept
+        pa = ta - np.floor(ta)
+        if 0.1 <= pa <= 0.1 + 1 / 3:
+            assert tf == ta
+
+
+def test_expected_counts_add_up_to_the_epoch_count():
+    for s in range(6):
+        th, Fb, sn, L = M.sample_params(11, s)
+        c, tf, span = M.expected_counts(th, L)
+        assert np.all(c >= 0)
+        # the dense window t0 +- 0.1 tE lies inside the observed span
+        assert abs(c.sum() - L) <= 1e-9 * L
+        assert 200 <= L <= 5000 and 0 <= Fb <= 0.5 and 0.005 <= sn <= 0.03
+
+
+def test_observed_bins_are_the_forward_model_at_the_bin_centres():
+    # noise-free limit: bin j holds Fs*A + Fb with A evaluated on the
+    # physical time of its centre, t_first + span (j + 1/2)/256 (days); this
+    # checks the window and the rescaled t0, tE that the sampler feeds the
+    # forward model
+    th = np.array([-1.3, 1.1, 0.15, 2.2, 35.0, -4.0])
+    vals, filled, y, tf, span = M.observe(5, 0, th, 0.2, 1e-13, 3000)
+    j = np.flatnonzero(filled)
+    assert j.size > 50
+    t = tf + span * (j + 0.5) / 256
+    A = O.magnify(th[:, None], t)[0][0]
+    assert np.allclose(vals[j], A + 0.2, rtol=1e-9)
+    assert np.allclose(y, [1.7 / 3, 0.6 / 1.5, 0.3, 2.2 / (2 * np.pi), (-4.0 - tf) / span,
+                           35.0 / span, 1 / 1.2], rtol=1e-14)
+
+
+def test_make_sample_is_normalised():
+    for s in range(4):
+        x, y = M.make_sample(2, s)
+        assert abs(np.median(x)) < 1e-12 and abs(x.max() - 1) < 1e-12
+        assert np.all((y >= 0) & (y <= 1))
+        assert 0.45 < y[4] < 0.55 and 0.24 < y[5] < 0.27
+
+
+# ------------------------------------------------------ seeding pins
+
+def _mixture(logits, mu, ls):
+    o = np.zeros(128)
+    o[:8] = logits
+    o[8:64] = np.asarray(mu, float).ravel()
+    o[64:120] = np.asarray(ls, float).ravel()
+    return o
+
+
+LO = np.array([-3.0, 0.5, 0.0, 0.0, 10.0, -10.0])
+HI = np.array([0.0, 2.0, 0.5, 2 * np.pi, 100.0, 10.0])
+
+
+def test_seed_rows_point_mass_decodes_the_mean():
+    mu = np.tile([0.2, 0.4, 0.6, 1.3, 0.5, 0.1, 0.7], (8, 1))
+    o = _mixture([50] + [-50] * 7, mu, np.full((8, 7), -40.0))
+    rows = M.seed_rows(o, 2.0, 200.0, LO, HI, seed=9, lc=4, n_seed=5)
+    th = np.array([-3 + 0.6, 0.5 + 0.6, 0.3, 2 * np.pi * 0.3, 20.0, 2.0 + 100.0])
+    ref = np.clip((th - LO) / (HI - LO), 0, 1)   # t0 = 102 clamps to 1
+    assert np.allclose(rows, ref[None, :], atol=1e-12)
+    assert rows[0, 5] == 1.0
+
+
+def test_seed_rows_component_frequencies_and_gaussian_draws():
+    pi = np.array([0.05, 0.1, 0.15, 0.2, 0.25, 0.1, 0.1, 0.05])
+    mu = np.zeros((8, 7)) + 0.5
+    mu[:, 1] = np.arange(8) / 10 + 0.1       # component k puts d at 0.1 k + 0.1
+    ls = np.full((8, 7), -40.0)
+    ls[:, 0] = np.log(0.05)                  # log10 q dimension ~ N(0.5, 0.05^2)
+    o = _mixture(np.log(pi) + 3.0, mu, ls)
+    n = 3000
+    rows = M.seed_rows(o, 0.0, 100.0, LO, HI, seed=1, lc=0, n_seed=n)
+    x1 = (rows[:, 1] * (HI[1] - LO[1]) + LO[1] - 0.5) / 1.5
+    comp = np.rint((x1 - 0.1) * 10).astype(int)
+    counts = np.bincount(comp, minlength=8)
+    chi = ((counts - n * pi) ** 2 / (n * pi)).sum()
+    assert chi < stats.chi2.ppf(0.999, 7)
+    z = ((rows[:, 0] * 3 - 3 + 3) / 3 - 0.5) / 0.05
+    assert stats.kstest(z, "norm").pvalue > 1e-3
