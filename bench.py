@@ -9,6 +9,11 @@ from one HIP graph.  The default run times a full fit (500 generations) in
 the plain FP64 form and in the mixed-precision form, reports the success rate
 (best chi^2 <= chi^2 of the true parameters + 10) and fits/hour, the fitness
 kernel's roofline fraction, and the CPU oracle timed on a bounded sample.
+Then the ragged batching workload (4096 lightcurves of 200-5000 irregular
+epochs, population 128) is timed per generation, and on the same lightcurves
+the plain EA is compared with the learned form: a proposal network trained
+on generated lightcurves seeds half of every population (at the start and at
+each restart) and the EA's chi^2 judges.
 
 Prints ONE JSON line.
 """
@@ -61,6 +66,11 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--success-max-gen", type=int, default=3000,
                     help="generation cap of the time-to-90%%-success run (0 = skip it)")
+    ap.add_argument("--learned-gens", type=int, default=300,
+                    help="generations of the plain-vs-learned comparison on the ragged "
+                         "workload (0 = skip it)")
+    ap.add_argument("--mlp-samples", type=int, default=1 << 20)
+    ap.add_argument("--mlp-epochs", type=int, default=16)
     return ap.parse_args()
 
 
@@ -188,6 +198,93 @@ def time_to_success(sblm, torch, lcs, chi2_true, pop, mode, sched, target=0.9, c
                 curve=curve[::max(1, len(curve) // 12)])
 
 
+# Matrix-core FLOPs of one training step per sample: forward 2 P, backward
+# 4 P (data and weight gradients), P = 256*512 + 512*512 + 512*128 weights
+# as the kernels multiply them (output layer padded to 128 columns)
+MLP_GEMM_WEIGHTS = 256 * 512 + 512 * 512 + 512 * 128
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def learned_form(sblm, torch, lcs, chi2_true, pop, sched, args, chunk=50):
+    """Plain EA vs the EA whose population is half seeded (and re-seeded at
+    every restart) by the proposal network; the network is trained first on
+    generated lightcurves.  Success = best chi^2 <= chi^2 of the true
+    parameters + 10."""
+    n_lc = len(chi2_true)
+    sync = torch.cuda.synchronize
+    sync()
+    t0 = time.perf_counter()
+    xb, _, yt = sblm.mlp_make_data(11, 0, args.mlp_samples)
+    sync()
+    t_data = time.perf_counter() - t0
+    net = sblm.MLP(batch_max=1024, seed=2)
+    batch = 1024
+    steps = args.mlp_epochs * (args.mlp_samples // batch)
+    t0 = time.perf_counter()
+    loss = net.train(xb, yt, batch=batch, epochs=args.mlp_epochs, lr0=2e-3, lr1=1e-5)
+    sync()
+    t_train = time.perf_counter() - t0
+    lc = loss.cpu().numpy()
+    step_s = t_train / max(steps, 1)
+    mfma_tflops = 6.0 * batch * MLP_GEMM_WEIGHTS / step_s / 1e12
+    del xb, yt
+    cfg = sblm.ea_default_config()
+    cfg.pop = pop
+    runs = {}
+    for form in ("plain", "learned"):
+        state = sblm.EAState(cfg, lcs, 7)
+        state.set_schedule(*sched)
+        sync()
+        t0 = time.perf_counter()
+        if form == "learned":  # resample, infer and seed: part of the fit's GPU time
+            xr, _ = sblm.sblm_resample(lcs)
+            out = net.forward(xr)
+            state.seed(out, pop // 2, at_restarts=True)
+        sync()
+        secs = time.perf_counter() - t0
+        t_seed = secs
+        gens, curve = 0, []
+        while gens < args.learned_gens:
+            sync()
+            t0 = time.perf_counter()
+            state.fit(chunk)
+            sync()
+            secs += time.perf_counter() - t0
+            gens += chunk
+            summ = state.summary()
+            best = np.array([summ[k].best_chi2 for k in range(n_lc)])
+            curve.append((gens, round(float(np.mean(best <= chi2_true + 10.0)), 4),
+                          round(secs, 3)))
+        state.close()
+        runs[form] = dict(curve=curve, success=curve[-1][1], gpu_seconds=secs,
+                          seed_seconds=t_seed if form == "learned" else 0.0)
+    net.close()
+    # GPU time for the learned form to match the plain EA's final success
+    target = runs["plain"]["success"]
+    hit = next((c for c in runs["learned"]["curve"] if c[1] >= target), None)
+    p90 = {f: next((c for c in r["curve"] if c[1] >= 0.9), None) for f, r in runs.items()}
+    return dict(
+        workload=f"{n_lc} ragged lightcurves, pop {pop}, {pop // 2} rows seeded at the start "
+                 f"and at every restart",
+        training=dict(samples=args.mlp_samples, epochs=args.mlp_epochs, batch=batch,
+                      steps=steps, data_seconds=t_data, train_seconds=t_train,
+                      us_per_step=step_s * 1e6, loss_first=float(lc[:16].mean()),
+                      loss_last=float(lc[-16:].mean()),
+                      mfma_tflops=mfma_tflops, mfma_frac=mfma_tflops / PEAK_BF16_TFLOPS),
+        plain=runs["plain"], learned=runs["learned"],
+        learned_matches_plain_final=dict(
+            plain_success=target, plain_gpu_seconds=runs["plain"]["gpu_seconds"],
+            learned_generations=hit[0] if hit else None,
+            learned_gpu_seconds=hit[2] if hit else None,
+            speedup=(runs["plain"]["gpu_seconds"] / hit[2]) if hit else None),
+        gpu_seconds_per_fit=dict(
+            plain=runs["plain"]["gpu_seconds"] / n_lc,
+            learned=runs["learned"]["gpu_seconds"] / n_lc,
+            learned_with_training=(runs["learned"]["gpu_seconds"] + t_data + t_train) / n_lc),
+        reached_90pct={f: (v is not None) for f, v in p90.items()},
+        fits_per_hour_at_90pct={f: (n_lc * 3600.0 / v[2] if v else None) for f, v in p90.items()})
+
+
 def cpu_baseline(wl, y, w, pop, target_s):
     """The CPU oracle's chi^2 on a sample of the same workload."""
     import oracle as O
@@ -251,6 +348,7 @@ def main():
         log(f"bench: success: {json.dumps(tts)}")
 
     ragged = None
+    learned = None
     if args.ragged_lc > 0:
         log(f"bench: ragged workload, {args.ragged_lc} lightcurves of 200-5000 epochs, pop 128")
         wr = inputs.ragged_workload(4, args.ragged_lc)
@@ -261,6 +359,11 @@ def main():
         ragged["workload"] = (f"{args.ragged_lc} lightcurves, L ~ U{{200..5000}} "
                               f"(total {int(wr.off[-1])} epochs), nightly cadence, pop 128")
         log(f"bench: ragged: {json.dumps(ragged)}")
+        if args.learned_gens > 0:
+            log("bench: learned form (proposal network) vs plain EA on the ragged workload")
+            learned = learned_form(sblm, torch, lcs_r, c_true_r.cpu().numpy(), 128,
+                                   tuple(ragged["schedule"].values()), args)
+            log(f"bench: learned: {json.dumps(learned)}")
         del lcs_r
 
     cpu = None
@@ -287,6 +390,7 @@ def main():
         "success_rate": main_form["success"],
         "forms": forms,
         "ragged": ragged,
+        "learned": learned,
         "roofline": {"bound": "alu", "achieved": main_form["kernel_tflops"],
                      "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": main_form["kernel_tflops"] / PEAK_VALU_TFLOPS, "traffic": None,

@@ -413,17 +413,26 @@ int mlp_train(mlp_net* net, const uint16_t* x, const float* y, int64_t rows,
  *   out     [n_lc][ld_out] FP32 device, network output for each lightcurve
  *           (mlp_forward of its sblm_resample bins), ld_out >= 120
  *   n_seed  0 <= n_seed <= pop
- * Row r of lightcurve l draws key (seed, l), counter (0, EA_PURPOSE_SEED, r,
- * j/4): word 0 -> u, component = the first k with u * sum(e) < e_0 + ... +
- * e_k, e_k = exp(logit_k - max logit); words 1..8 -> four Box-Muller pairs
- * (sqrt(-2 ln u1) cos(2 pi u2), sqrt(-2 ln u1) sin(2 pi u2)) giving z_0..z_6;
- * x_d = mean_kd + exp(logstd_kd) z_d, x_3 reduced mod 1; decoded through the
- * target map with t_first/span of lightcurve l; re-encoded into the state's
- * domain (Eq. EMMA-encoding) and clamped to [0, 1].  Lightcurves without
- * epochs are left alone.  Run before ea_fit (which evaluates first).
+ *   flags   0, or EA_SEED_AT_RESTARTS: keep `out` attached so that every
+ *           later restart (Sec. A.7; the fresh population of Sec. A.1) also
+ *           re-draws rows 0 .. n_seed-1 from the mixture.  The caller keeps
+ *           `out` alive and unchanged while it is attached; a call with
+ *           flags 0 or n_seed 0 detaches it.  Attaching or detaching
+ *           re-captures the generation graph (synchronises the state).
+ * Row r of lightcurve l at generation g (the lightcurve's current generation
+ * here, the first generation of the new sequence at a restart) draws key
+ * (seed, l), counter (g, EA_PURPOSE_SEED, r, j/4): word 0 -> u, component =
+ * the first k with u * sum(e) < e_0 + ... + e_k, e_k = exp(logit_k - max
+ * logit); words 1..8 -> four Box-Muller pairs (sqrt(-2 ln u1) cos(2 pi u2),
+ * sqrt(-2 ln u1) sin(2 pi u2)) giving z_0..z_6; x_d = mean_kd + exp(logstd_kd)
+ * z_d, x_3 reduced mod 1; decoded through the target map with t_first/span
+ * of lightcurve l; re-encoded into the state's domain (Eq. EMMA-encoding) and
+ * clamped to [0, 1].  Lightcurves without epochs are left alone.  Seeding
+ * before ea_fit takes effect at once (ea_fit evaluates first).
  */
+#define EA_SEED_AT_RESTARTS 1
 int ea_seed(ea_state* st, const float* out, int32_t ld_out, int32_t n_seed,
-            void* stream);
+            int32_t flags, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Diagnostics (used by the parity tests)                                  */

@@ -273,8 +273,9 @@ def make_sample(seed, s, nbins=256):
 
 # --------------------------------------------------------------- seeding
 
-def seed_rows(o, t_first, span, lo, hi, seed, lc, n_seed):
-    """Encoded population rows [n_seed][6] drawn from the mixture o[>=120]."""
+def seed_rows(o, t_first, span, lo, hi, seed, lc, n_seed, gen=0):
+    """Encoded population rows [n_seed][6] drawn from the mixture o[>=120]
+    with the counters of generation `gen`."""
     o = np.asarray(o, dtype=float)
     lmax = max(o[:K])
     e = [math.exp(o[k] - lmax) for k in range(K)]
@@ -286,7 +287,7 @@ def seed_rows(o, t_first, span, lo, hi, seed, lc, n_seed):
     lo, hi = np.asarray(lo, float), np.asarray(hi, float)
     rows = np.zeros((n_seed, 6))
     for r in range(n_seed):
-        u = O.u01(O.draw(seed, lc, 0, P_SEED, r, 0))
+        u = O.u01(O.draw(seed, lc, gen, P_SEED, r, 0))
         comp, acc = K - 1, 0.0
         for k in range(K):
             acc += e[k]
@@ -295,8 +296,8 @@ def seed_rows(o, t_first, span, lo, hi, seed, lc, n_seed):
                 break
         z = []
         for i in range(4):
-            u1 = O.u01(O.draw(seed, lc, 0, P_SEED, r, 1 + 2 * i))
-            u2 = O.u01(O.draw(seed, lc, 0, P_SEED, r, 2 + 2 * i))
+            u1 = O.u01(O.draw(seed, lc, gen, P_SEED, r, 1 + 2 * i))
+            u2 = O.u01(O.draw(seed, lc, gen, P_SEED, r, 2 + 2 * i))
             rad = math.sqrt(-2.0 * math.log(u1))
             z += [rad * math.cos(2.0 * math.pi * u2), rad * math.sin(2.0 * math.pi * u2)]
         x = np.array([mu[comp, d] + math.exp(ls[comp, d]) * z[d] for d in range(D)])

@@ -113,10 +113,84 @@ __device__ __forceinline__ double rank_key(double c) {
   return isnan(c) ? INFINITY : c;
 }
 
+// Proposal seeding: row `row` < n_seed of lightcurve lc becomes a draw from
+// the mixture that the proposal network output O[lc][0..119] describes (8
+// logits, 8x7 means, 8x7 log standard deviations over the network's target
+// map), decoded to physical parameters on the lightcurve's observed span
+// and re-encoded (clamped) into the EA's domain.  Draws: key (seed, lc),
+// counter (gen, EA_PURPOSE_SEED, row, j / 4); word 0 picks the component by
+// inversion of the softmax weights, words 1..8 give four Box-Muller pairs.
+struct Proposals {
+  const float* O;  // [n_lc][ld] network outputs, or null (no seeding)
+  int32_t ld;
+  int32_t n_seed;
+  const int64_t* off;
+  const double* t;
+  double lo[SBLM_NPAR], span[SBLM_NPAR];
+};
+
+__device__ void seed_row(const EaParams& p, double* P, const Proposals& pr,
+                         int64_t lc, int row, int64_t gen) {
+  const int64_t o0 = pr.off[lc], o1 = pr.off[lc + 1];
+  if (o1 <= o0) return;
+  const double t_first = pr.t[o0], tspan = pr.t[o1 - 1] - t_first;
+  const Stream rs = {p.seed, (uint64_t)lc, (uint64_t)gen};
+  const float* o = pr.O + lc * (int64_t)pr.ld;
+  const int K = MLP_K, D = MLP_D;
+  double lmax = (double)o[0];
+  for (int k = 1; k < K; ++k) lmax = fmax(lmax, (double)o[k]);
+  double S = 0.0;
+  for (int k = 0; k < K; ++k) S += exp((double)o[k] - lmax);
+  const double u = u01(rs.draw(P_SEED, (uint64_t)row, 0));
+  int comp = K - 1;
+  double acc = 0.0;
+  for (int k = 0; k < K; ++k) {
+    acc += exp((double)o[k] - lmax);
+    if (u * S < acc) {
+      comp = k;
+      break;
+    }
+  }
+  double z[8];
+  for (int i = 0; i < 4; ++i) {
+    const double u1 = u01(rs.draw(P_SEED, (uint64_t)row, (uint64_t)(1 + 2 * i)));
+    const double u2 = u01(rs.draw(P_SEED, (uint64_t)row, (uint64_t)(2 + 2 * i)));
+    const double rad = sqrt(-2.0 * log(u1));
+    z[2 * i] = rad * cos(2.0 * M_PI * u2);
+    z[2 * i + 1] = rad * sin(2.0 * M_PI * u2);
+  }
+  double x[MLP_D];
+  for (int d = 0; d < D; ++d)
+    x[d] = (double)o[K + comp * D + d] + exp((double)o[K + K * D + comp * D + d]) * z[d];
+  x[MLP_PERIODIC] -= floor(x[MLP_PERIODIC]);
+  double th[SBLM_NPAR];
+  th[0] = -3.0 + 3.0 * x[0];
+  th[1] = 0.5 + 1.5 * x[1];
+  th[2] = 0.5 * x[2];
+  th[3] = 2.0 * M_PI * x[3];
+  th[4] = tspan * x[5];
+  th[5] = t_first + tspan * x[4];
+  const int64_t col = lc * p.pop + row;
+  for (int g = 0; g < SBLM_NPAR; ++g) {
+    const double e = (th[g] - pr.lo[g]) / pr.span[g];
+    P[g * p.n_ind + col] = fmin(fmax(e, 0.0), 1.0);
+  }
+}
+
+// One thread per (lightcurve, seeded row); keyed by each lightcurve's
+// current generation.
+__global__ void ea_seed_kernel(EaParams p, double* P, const EaLc* lcs, Proposals pr) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)p.n_lc * pr.n_seed) return;
+  const int64_t lc = idx / pr.n_seed;
+  seed_row(p, P, pr, lc, (int)(idx % pr.n_seed), lcs[lc].gen);
+}
+
 // One generation (Sec. A.3-A.7) for lightcurve blockIdx.x.
 __global__ void ea_generation_kernel(EaParams p, double* P, EaLc* lcs,
                                      const double* chi2, const double* Fs,
-                                     const double* Fb, int32_t* parents_out) {
+                                     const double* Fb, int32_t* parents_out,
+                                     Proposals pr) {
   extern __shared__ double smem[];
   const int N = p.pop;
   double* sP = smem;                         // [6][N] old population
@@ -189,6 +263,10 @@ __global__ void ea_generation_kernel(EaParams p, double* P, EaLc* lcs,
 
   if (s_restart) {  // fresh population keyed by the next generation
     init_rows(p, P, lc, gen + 1);
+    if (pr.O) {  // attached proposals re-seed their rows
+      __syncthreads();
+      for (int r = threadIdx.x; r < pr.n_seed; r += blockDim.x) seed_row(p, P, pr, lc, r, gen + 1);
+    }
     return;
   }
   const double pm = s_pmut;
@@ -257,70 +335,6 @@ __global__ void ea_draws_kernel(uint64_t seed, uint64_t lc, uint64_t gen,
   out[k] = rs.draw(purpose, row, j0 + (uint64_t)k);
 }
 
-// Proposal seeding: row `row` < n_seed of lightcurve lc becomes a draw from
-// the mixture that the proposal network output O[lc][0..119] describes (8
-// logits, 8x7 means, 8x7 log standard deviations over the network's target
-// map), decoded to physical parameters on the lightcurve's observed span
-// and re-encoded (clamped) into the EA's domain.  Draws: key (seed, lc),
-// counter (0, EA_PURPOSE_SEED, row, j / 4); word 0 picks the component by
-// inversion of the softmax weights, words 1..8 give four Box-Muller pairs.
-struct SeedDomain {
-  double lo[SBLM_NPAR], span[SBLM_NPAR];
-};
-
-__global__ void ea_seed_kernel(EaParams p, double* P, const int64_t* off,
-                               const double* t, const float* O, int32_t ldo,
-                               int32_t n_seed, SeedDomain dom) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)p.n_lc * n_seed) return;
-  const int64_t lc = idx / n_seed;
-  const int row = (int)(idx % n_seed);
-  const int64_t o0 = off[lc], o1 = off[lc + 1];
-  if (o1 <= o0) return;
-  const double t_first = t[o0], tspan = t[o1 - 1] - t_first;
-  const Stream rs = {p.seed, (uint64_t)lc, 0};
-  const float* o = O + lc * (int64_t)ldo;
-  const int K = MLP_K, D = MLP_D;
-  double lmax = (double)o[0];
-  for (int k = 1; k < K; ++k) lmax = fmax(lmax, (double)o[k]);
-  double S = 0.0;
-  for (int k = 0; k < K; ++k) S += exp((double)o[k] - lmax);
-  const double u = u01(rs.draw(P_SEED, (uint64_t)row, 0));
-  int comp = K - 1;
-  double acc = 0.0;
-  for (int k = 0; k < K; ++k) {
-    acc += exp((double)o[k] - lmax);
-    if (u * S < acc) {
-      comp = k;
-      break;
-    }
-  }
-  double z[8];
-  for (int i = 0; i < 4; ++i) {
-    const double u1 = u01(rs.draw(P_SEED, (uint64_t)row, (uint64_t)(1 + 2 * i)));
-    const double u2 = u01(rs.draw(P_SEED, (uint64_t)row, (uint64_t)(2 + 2 * i)));
-    const double rad = sqrt(-2.0 * log(u1));
-    z[2 * i] = rad * cos(2.0 * M_PI * u2);
-    z[2 * i + 1] = rad * sin(2.0 * M_PI * u2);
-  }
-  double x[MLP_D];
-  for (int d = 0; d < D; ++d)
-    x[d] = (double)o[K + comp * D + d] + exp((double)o[K + K * D + comp * D + d]) * z[d];
-  x[MLP_PERIODIC] -= floor(x[MLP_PERIODIC]);
-  double th[SBLM_NPAR];
-  th[0] = -3.0 + 3.0 * x[0];
-  th[1] = 0.5 + 1.5 * x[1];
-  th[2] = 0.5 * x[2];
-  th[3] = 2.0 * M_PI * x[3];
-  th[4] = tspan * x[5];
-  th[5] = t_first + tspan * x[4];
-  const int64_t col = lc * p.pop + row;
-  for (int g = 0; g < SBLM_NPAR; ++g) {
-    const double e = (th[g] - dom.lo[g]) / dom.span[g];
-    P[g * p.n_ind + col] = fmin(fmax(e, 0.0), 1.0);
-  }
-}
-
 // ---------------------------------------------------------------- host side
 
 struct EaStateImpl {
@@ -345,6 +359,7 @@ struct EaStateImpl {
   int async = 0;
   int32_t* order = nullptr;    // item -> individual, longest lightcurves first
   unsigned int* queue = nullptr;
+  Proposals prop = {};         // attached by ea_seed(..., EA_SEED_AT_RESTARTS)
 };
 
 __global__ void queue_reset_kernel(unsigned int* q) { *q = 0u; }
@@ -364,7 +379,7 @@ static hipError_t enqueue_generation(EaStateImpl* s, const double* chi2,
                                      int32_t* parents, hipStream_t st) {
   hipLaunchKernelGGL(ea_generation_kernel, dim3(s->prm.n_lc),
                      dim3(gen_block(s->prm.pop)), gen_smem(s->prm.pop), st, s->prm,
-                     s->P, s->lc, chi2, Fs, Fb, parents);
+                     s->P, s->lc, chi2, Fs, Fb, parents, s->prop);
   return hipGetLastError();
 }
 
@@ -630,27 +645,41 @@ extern "C" int ea_draws(uint64_t seed, uint64_t lc, uint64_t gen, uint64_t purpo
   return check_hip(hipGetLastError(), "ea_draws launch");
 }
 
+static int capture_graph(EaStateImpl& s, sblm_stats* stats);
+
 extern "C" int ea_seed(ea_state* st, const float* out, int32_t ld_out, int32_t n_seed,
-                       void* stream) {
+                       int32_t flags, void* stream) {
   if (!st) return set_error(SBLM_ESTATE, "ea_seed: null state");
   EaStateImpl& s = st->impl;
-  if (!out) return set_error(SBLM_EINVAL, "ea_seed: null network output");
-  if (ld_out < MLP_NOUT)
-    return set_error(SBLM_EINVAL, "ea_seed: ld_out = %d < %d", ld_out, MLP_NOUT);
+  if (flags & ~EA_SEED_AT_RESTARTS) return set_error(SBLM_EINVAL, "ea_seed: unknown flags");
   if (n_seed < 0 || n_seed > s.prm.pop)
     return set_error(SBLM_EINVAL, "ea_seed: n_seed = %d outside [0, pop = %d]", n_seed,
                      s.prm.pop);
-  if (n_seed == 0) return SBLM_OK;
-  SeedDomain dom;
+  if (n_seed > 0 && !out) return set_error(SBLM_EINVAL, "ea_seed: null network output");
+  if (n_seed > 0 && ld_out < MLP_NOUT)
+    return set_error(SBLM_EINVAL, "ea_seed: ld_out = %d < %d", ld_out, MLP_NOUT);
+  Proposals pr = {};
+  pr.O = n_seed > 0 ? out : nullptr;
+  pr.ld = ld_out;
+  pr.n_seed = n_seed;
+  pr.off = s.lcs.off;
+  pr.t = s.lcs.t;
   for (int g = 0; g < SBLM_NPAR; ++g) {
-    dom.lo[g] = s.cfg.lo[g];
-    dom.span[g] = s.cfg.hi[g] - s.cfg.lo[g];
+    pr.lo[g] = s.cfg.lo[g];
+    pr.span[g] = s.cfg.hi[g] - s.cfg.lo[g];
   }
-  const int64_t n = (int64_t)s.prm.n_lc * n_seed;
-  hipLaunchKernelGGL(ea_seed_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                     (hipStream_t)stream, s.prm, s.P, s.lcs.off, s.lcs.t, out, ld_out,
-                     n_seed, dom);
-  return check_hip(hipGetLastError(), "ea_seed launch");
+  if (n_seed > 0) {
+    const int64_t n = (int64_t)s.prm.n_lc * n_seed;
+    hipLaunchKernelGGL(ea_seed_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, s.prm, s.P, s.lc, pr);
+    int rc = check_hip(hipGetLastError(), "ea_seed launch");
+    if (rc) return rc;
+  }
+  const bool attach = (flags & EA_SEED_AT_RESTARTS) && n_seed > 0;
+  const bool was = s.prop.O != nullptr;
+  s.prop = attach ? pr : Proposals{};
+  if ((attach || was) && s.graph) return capture_graph(s, s.graph_stats);
+  return SBLM_OK;
 }
 
 extern "C" int ea_evaluate(ea_state* st, sblm_stats* stats, void* stream) {
@@ -663,6 +692,8 @@ extern "C" int ea_evaluate(ea_state* st, sblm_stats* stats, void* stream) {
 // work stream) into an executable graph bound to `stats`.
 static int capture_graph(EaStateImpl& s, sblm_stats* stats) {
   if (s.graph) {
+    int rc0 = check_hip(hipStreamSynchronize(s.work), "ea graph re-capture");
+    if (rc0) return rc0;
     (void)hipGraphExecDestroy(s.graph);
     s.graph = nullptr;
   }

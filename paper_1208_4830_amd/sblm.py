@@ -17,6 +17,7 @@ NPAR = 6
 FP64, MIXED = 0, 1
 # proposal network sizes (include/sblm.h)
 NBINS, NOUT, NOUT_PAD, NTARGET, NPARAMS = 256, 120, 128, 7, 455800
+SEED_AT_RESTARTS = 1
 
 _lib = None
 
@@ -95,7 +96,7 @@ _SIGS = {
                   ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                   ctypes.c_void_p, ctypes.c_void_p],
     "ea_seed": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
-                ctypes.c_void_p],
+                ctypes.c_int32, ctypes.c_void_p],
 }
 EXPORTS = tuple(_SIGS)
 
@@ -309,11 +310,15 @@ class EAState:
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(load().ea_load(self.h, buf, len(blob), _stream(stream)))
 
-    def seed(self, out, n_seed, stream=None):
+    def seed(self, out, n_seed, at_restarts=False, stream=None):
         """Overwrite rows [0, n_seed) of every lightcurve's population with
-        draws from the proposal mixture out[n_lc][>=120] (float32)."""
+        draws from the proposal mixture out[n_lc][>=120] (float32); with
+        at_restarts, every later restart re-draws them (out is kept alive
+        here while attached)."""
         out = _dev(out, torch.float32)
-        _check(load().ea_seed(self.h, _ptr(out), out.shape[1], n_seed, _stream(stream)))
+        _check(load().ea_seed(self.h, _ptr(out), out.shape[1], n_seed,
+                              SEED_AT_RESTARTS if at_restarts else 0, _stream(stream)))
+        self._proposals = out if (at_restarts and n_seed > 0) else None
 
     def close(self):
         if self.h:

@@ -213,3 +213,86 @@ def test_seeding_matches_oracle(hip):
         assert np.allclose(P[:, cols[:9]].T, ref, rtol=0, atol=1e-12), k
         assert np.array_equal(P[:, cols[9:]], P0[:, cols[9:]])
     st.close()
+
+
+def test_restarts_reseed_attached_proposals(hip):
+    from oracle import oracle as O
+    lengths = [60, 200, 0, 90]
+    lcs, off, (t, y, w) = make_lcs(hip, lengths, seed=6, special=False)
+    cfg = hip.ea_default_config()
+    cfg.pop = 16
+    cfg.stag_window, cfg.restart_after, cfg.stag_frac = 1, 1, 0.99  # restart often
+    seed = 31
+    st = hip.EAState(cfg, lcs, seed)
+    rng = np.random.default_rng(6)
+    out = np.zeros((len(lengths), 128), np.float32)
+    out[:, :8] = rng.normal(size=(len(lengths), 8))
+    out[:, 8:64] = rng.uniform(0, 1, (len(lengths), 56))
+    out[:, 64:120] = rng.uniform(-3, -1, (len(lengths), 56))
+    st.seed(torch.tensor(out, device="cuda"), 5, at_restarts=True)
+    lo, hi = np.array(cfg.lo[:]), np.array(cfg.hi[:])
+    prev = [s.n_restarts for s in st.summary()]
+    checked = 0
+    for _ in range(12):
+        st.evaluate()
+        st.generation(st.view("chi2"), st.view("Fs"), st.view("Fb"))
+        summ = st.summary()
+        P = st.view("P").cpu().numpy()
+        for k, L in enumerate(lengths):
+            if L == 0 or summ[k].n_restarts == prev[k]:
+                continue
+            g = summ[k].gen_restart
+            cols = k * 16 + np.arange(16)
+            tf, span = t[off[k]], t[off[k + 1] - 1] - t[off[k]]
+            ref = M.seed_rows(out[k].astype(np.float64), tf, span, lo, hi, seed, k, 5, gen=g)
+            assert np.allclose(P[:, cols[:5]].T, ref, rtol=0, atol=1e-12), (k, g)
+            # the other rows are the fresh population of Sec. A.1 (antithetic pairs)
+            for r in range(5, 16):
+                i = r if r < 8 else r - 8
+                u = np.array([O.u01(O.draw(seed, k, g, 1, i, j)) for j in range(6)])
+                assert np.array_equal(P[:, cols[r]], u if r < 8 else 1.0 - u), (k, g, r)
+            checked += 1
+        prev = [s.n_restarts for s in summ]
+    assert checked >= 3
+    # detaching: a later restart draws the plain population again
+    st.seed(torch.tensor(out, device="cuda"), 0)
+    st.close()
+
+
+def test_trained_network_improves_the_ea(hip):
+    # a network trained on generated lightcurves seeds half of the population
+    # at the start and at every restart; against the plain EA on the same
+    # ragged lightcurves, EA seed and generation count
+    xb, _, yt = hip.mlp_make_data(11, 0, 1 << 18)
+    net = hip.MLP(batch_max=1024, seed=2)
+    net.train(xb, yt, batch=1024, epochs=4, lr0=2e-3, lr1=1e-5)
+    wl = inputs.ragged_workload(21, 256)
+    t = torch.tensor(wl.t, device="cuda")
+    A = torch.empty_like(t)
+    for k in range(wl.n_lc):
+        a, b = int(wl.off[k]), int(wl.off[k + 1])
+        A[a:b] = hip.sblm_magnify(torch.tensor(wl.theta[:, k:k + 1].copy(), device="cuda"),
+                                  t[a:b].contiguous())[0]
+    L = np.diff(wl.off)
+    F = np.repeat(wl.Fs, L) * A.cpu().numpy() + np.repeat(wl.Fb, L)
+    sig = wl.sfrac * F
+    lcs = hip.Lightcurves(torch.tensor(wl.off, device="cuda"), t,
+                          torch.tensor(F + sig * wl.noise, device="cuda"),
+                          torch.tensor(1.0 / sig ** 2, device="cuda"))
+    c_true = hip.sblm_chi2(lcs, torch.tensor(wl.theta.copy(), device="cuda"), 1)[0].cpu().numpy()
+    xr, _ = hip.sblm_resample(lcs)
+    out = net.forward(xr)
+    success = {}
+    for form in ("plain", "learned"):
+        cfg = hip.ea_default_config()
+        cfg.pop = 128
+        st = hip.EAState(cfg, lcs, 7)
+        if form == "learned":
+            st.seed(out, 64, at_restarts=True)
+        st.fit(150)
+        best = np.array([s.best_chi2 for s in st.summary()])
+        success[form] = float(np.mean(best <= c_true + 10.0))
+        st.close()
+    print(f"success after 150 generations: {success}")
+    assert success["learned"] >= success["plain"] + 0.05
+    net.close()
