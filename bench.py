@@ -9,7 +9,9 @@ from one HIP graph.  The default run times a full fit (500 generations) in
 the plain FP64 form and in the mixed-precision form, reports the success rate
 (best chi^2 <= chi^2 of the true parameters + 10) and fits/hour, the fitness
 kernel's roofline fraction, and the CPU oracle timed on a bounded sample.
-Then the ragged batching workload (4096 lightcurves of 200-5000 irregular
+Time to 90% success is measured for the plain EA and for the learned form
+(proposal seeding), each with the paper's simplex fine-tuning of the
+fittest solution at every checkpoint.  Then the ragged batching workload (4096 lightcurves of 200-5000 irregular
 epochs, population 128) is timed per generation, and on the same lightcurves
 the plain EA is compared with the learned form: a proposal network trained
 on generated lightcurves seeds half of every population (at the start and at
@@ -64,11 +66,13 @@ def parse():
                     help="lightcurves of the ragged workload (0 = skip it)")
     ap.add_argument("--ragged-steps", type=int, default=30)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--success-max-gen", type=int, default=3000,
-                    help="generation cap of the time-to-90%%-success run (0 = skip it)")
+    ap.add_argument("--success-max-gen", type=int, default=1600,
+                    help="generation cap of the time-to-90%%-success runs (0 = skip them)")
+    ap.add_argument("--success-every", type=int, default=100)
     ap.add_argument("--learned-gens", type=int, default=300,
                     help="generations of the plain-vs-learned comparison on the ragged "
                          "workload (0 = skip it)")
+    ap.add_argument("--learned-every", type=int, default=100)
     ap.add_argument("--mlp-samples", type=int, default=1 << 20)
     ap.add_argument("--mlp-epochs", type=int, default=16)
     return ap.parse_args()
@@ -167,50 +171,71 @@ def run_form(sblm, torch, lcs, wl, chi2_true, pop, steps, args, mode, tune=True)
         schedule=dict(zip(("lanes", "waves_per_block", "persistent", "asynchronous"), sched)))
 
 
-def time_to_success(sblm, torch, lcs, chi2_true, pop, mode, sched, target=0.9, chunk=50,
-                    max_gen=3000):
-    """Generations and GPU seconds until `target` of the lightcurves meet the
-    success criterion (best chi^2 <= chi^2 of the true parameters + 10)."""
+def success_run(sblm, torch, lcs, chi2_true, pop, mode, sched, lo, hi, proposals=None,
+                max_gen=1600, every=100, target=0.9, seed=7):
+    """EA with optional proposal seeding; at every checkpoint the fittest
+    solution of each lightcurve is fine-tuned by two simplex passes (on a
+    copy: the EA continues untouched), as the paper's "EA with amoeba".
+    Success = chi^2 <= chi^2 of the true parameters + 10.  GPU time of a
+    checkpoint = EA time so far + that checkpoint's simplex time."""
     cfg = sblm.ea_default_config()
     cfg.pop = pop
     cfg.mode = mode
-    state = sblm.EAState(cfg, lcs, 7)
+    state = sblm.EAState(cfg, lcs, seed)
     state.set_schedule(*sched)
     n_lc = len(chi2_true)
-    gens, secs, curve = 0, 0.0, []
-    frac = 0.0
-    while gens < max_gen:
-        torch.cuda.synchronize()
+    sync = torch.cuda.synchronize
+    ea_s = 0.0
+    if proposals is not None:  # resampling + inference done by the caller
+        sync()
         t0 = time.perf_counter()
-        state.fit(chunk)
-        torch.cuda.synchronize()
-        secs += time.perf_counter() - t0
-        gens += chunk
-        summ = state.summary()
-        best = np.array([summ[k].best_chi2 for k in range(n_lc)])
-        frac = float(np.mean(best <= chi2_true + 10.0))
-        curve.append((gens, round(frac, 4)))
-        if frac >= target:
+        state.seed(proposals, pop // 2, at_restarts=True)
+        sync()
+        ea_s += time.perf_counter() - t0
+    nm_cfg = sblm.nm_default_config()
+    nm_cfg.mode = mode
+    gens, curve, hit_ea, hit_nm = 0, [], None, None
+    while gens < max_gen:
+        sync()
+        t0 = time.perf_counter()
+        state.fit(every)
+        sync()
+        ea_s += time.perf_counter() - t0
+        gens += every
+        x0, c0 = state.best()
+        sync()
+        t0 = time.perf_counter()
+        x1, c1, _, _, _ = sblm.nm_refine(lcs, lo, hi, x0, nm_cfg)
+        _, c2, _, _, _ = sblm.nm_refine(lcs, lo, hi, x1, nm_cfg)
+        sync()
+        nm_s = time.perf_counter() - t0
+        c0 = c0.cpu().numpy()
+        c2 = np.minimum(np.minimum(c1.cpu().numpy(), c2.cpu().numpy()), c0)
+        s_ea = float(np.mean(c0 <= chi2_true + 10.0))
+        s_nm = float(np.mean(c2 <= chi2_true + 10.0))
+        curve.append(dict(gen=gens, ea=round(s_ea, 4), ea_amoeba=round(s_nm, 4),
+                          ea_seconds=round(ea_s, 3), amoeba_seconds=round(nm_s, 3)))
+        if hit_ea is None and s_ea >= target:
+            hit_ea = (gens, ea_s)
+        if hit_nm is None and s_nm >= target:
+            hit_nm = (gens, ea_s + nm_s)
+        if hit_nm is not None:
             break
     state.close()
-    return dict(target=target, reached=frac >= target, generations=gens, gpu_seconds=secs,
-                success=frac, fits_per_hour=n_lc * 3600.0 / secs if frac >= target else None,
-                curve=curve[::max(1, len(curve) // 12)])
+    per_hour = lambda h: n_lc * 3600.0 / h[1] if h else None
+    return dict(target=target, curve=curve,
+                ea_amoeba=dict(reached=hit_nm is not None,
+                               generations=hit_nm[0] if hit_nm else None,
+                               gpu_seconds=hit_nm[1] if hit_nm else None,
+                               fits_per_hour=per_hour(hit_nm)),
+                ea_alone=dict(reached=hit_ea is not None,
+                              generations=hit_ea[0] if hit_ea else None,
+                              gpu_seconds=hit_ea[1] if hit_ea else None,
+                              fits_per_hour=per_hour(hit_ea)))
 
 
-# Matrix-core FLOPs of one training step per sample: forward 2 P, backward
-# 4 P (data and weight gradients), P = 256*512 + 512*512 + 512*128 weights
-# as the kernels multiply them (output layer padded to 128 columns)
-MLP_GEMM_WEIGHTS = 256 * 512 + 512 * 512 + 512 * 128
-PEAK_BF16_TFLOPS = 2500.0
-
-
-def learned_form(sblm, torch, lcs, chi2_true, pop, sched, args, chunk=50):
-    """Plain EA vs the EA whose population is half seeded (and re-seeded at
-    every restart) by the proposal network; the network is trained first on
-    generated lightcurves.  Success = best chi^2 <= chi^2 of the true
-    parameters + 10."""
-    n_lc = len(chi2_true)
+def train_proposals(sblm, torch, args):
+    """Proposal network trained on generated lightcurves (timed)."""
     sync = torch.cuda.synchronize
     sync()
     t0 = time.perf_counter()
@@ -227,62 +252,59 @@ def learned_form(sblm, torch, lcs, chi2_true, pop, sched, args, chunk=50):
     lc = loss.cpu().numpy()
     step_s = t_train / max(steps, 1)
     mfma_tflops = 6.0 * batch * MLP_GEMM_WEIGHTS / step_s / 1e12
-    del xb, yt
-    cfg = sblm.ea_default_config()
-    cfg.pop = pop
-    runs = {}
-    for form in ("plain", "learned"):
-        state = sblm.EAState(cfg, lcs, 7)
-        state.set_schedule(*sched)
-        sync()
-        t0 = time.perf_counter()
-        if form == "learned":  # resample, infer and seed: part of the fit's GPU time
-            xr, _ = sblm.sblm_resample(lcs)
-            out = net.forward(xr)
-            state.seed(out, pop // 2, at_restarts=True)
-        sync()
-        secs = time.perf_counter() - t0
-        t_seed = secs
-        gens, curve = 0, []
-        while gens < args.learned_gens:
-            sync()
-            t0 = time.perf_counter()
-            state.fit(chunk)
-            sync()
-            secs += time.perf_counter() - t0
-            gens += chunk
-            summ = state.summary()
-            best = np.array([summ[k].best_chi2 for k in range(n_lc)])
-            curve.append((gens, round(float(np.mean(best <= chi2_true + 10.0)), 4),
-                          round(secs, 3)))
-        state.close()
-        runs[form] = dict(curve=curve, success=curve[-1][1], gpu_seconds=secs,
-                          seed_seconds=t_seed if form == "learned" else 0.0)
-    net.close()
-    # GPU time for the learned form to match the plain EA's final success
-    target = runs["plain"]["success"]
-    hit = next((c for c in runs["learned"]["curve"] if c[1] >= target), None)
-    p90 = {f: next((c for c in r["curve"] if c[1] >= 0.9), None) for f, r in runs.items()}
+    info = dict(samples=args.mlp_samples, epochs=args.mlp_epochs, batch=batch, steps=steps,
+                data_seconds=t_data, train_seconds=t_train, us_per_step=step_s * 1e6,
+                loss_first=float(lc[:16].mean()), loss_last=float(lc[-16:].mean()),
+                mfma_tflops=mfma_tflops, mfma_frac=mfma_tflops / PEAK_BF16_TFLOPS)
+    return net, info
+
+
+def propose(sblm, torch, net, lcs):
+    """Resampling + network forward pass for every lightcurve (timed)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xr, _ = sblm.sblm_resample(lcs)
+    out = net.forward(xr)
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+# Matrix-core FLOPs of one training step per sample: forward 2 P, backward
+# 4 P (data and weight gradients), P = 256*512 + 512*512 + 512*128 weights
+# as the kernels multiply them (output layer padded to 128 columns)
+MLP_GEMM_WEIGHTS = 256 * 512 + 512 * 512 + 512 * 128
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def learned_form(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, net, train_info, args):
+    """Plain EA vs the EA whose population is half seeded (and re-seeded at
+    every restart) by the proposal network, both with the simplex
+    fine-tuning at every checkpoint."""
+    out, t_inf = propose(sblm, torch, net, lcs)
+    plain = success_run(sblm, torch, lcs, chi2_true, pop, sblm.FP64, sched, lo, hi,
+                        max_gen=args.learned_gens, every=args.learned_every)
+    learned = success_run(sblm, torch, lcs, chi2_true, pop, sblm.FP64, sched, lo, hi,
+                          proposals=out, max_gen=args.learned_gens, every=args.learned_every)
+    n_lc = len(chi2_true)
+    last_p, last_l = plain["curve"][-1], learned["curve"][-1]
+    # GPU time for the learned form to match the plain form's last success
+    hit = next((c for c in learned["curve"] if c["ea_amoeba"] >= last_p["ea_amoeba"]), None)
     return dict(
-        workload=f"{n_lc} ragged lightcurves, pop {pop}, {pop // 2} rows seeded at the start "
-                 f"and at every restart",
-        training=dict(samples=args.mlp_samples, epochs=args.mlp_epochs, batch=batch,
-                      steps=steps, data_seconds=t_data, train_seconds=t_train,
-                      us_per_step=step_s * 1e6, loss_first=float(lc[:16].mean()),
-                      loss_last=float(lc[-16:].mean()),
-                      mfma_tflops=mfma_tflops, mfma_frac=mfma_tflops / PEAK_BF16_TFLOPS),
-        plain=runs["plain"], learned=runs["learned"],
-        learned_matches_plain_final=dict(
-            plain_success=target, plain_gpu_seconds=runs["plain"]["gpu_seconds"],
-            learned_generations=hit[0] if hit else None,
-            learned_gpu_seconds=hit[2] if hit else None,
-            speedup=(runs["plain"]["gpu_seconds"] / hit[2]) if hit else None),
-        gpu_seconds_per_fit=dict(
-            plain=runs["plain"]["gpu_seconds"] / n_lc,
-            learned=runs["learned"]["gpu_seconds"] / n_lc,
-            learned_with_training=(runs["learned"]["gpu_seconds"] + t_data + t_train) / n_lc),
-        reached_90pct={f: (v is not None) for f, v in p90.items()},
-        fits_per_hour_at_90pct={f: (n_lc * 3600.0 / v[2] if v else None) for f, v in p90.items()})
+        workload=f"{n_lc} lightcurves, pop {pop}, {pop // 2} rows seeded at the start and at "
+                 f"every restart; EA + two simplex passes from the fittest solution",
+        training=train_info, inference_seconds=t_inf, plain=plain, learned=learned,
+        learned_matches_plain_last=dict(
+            plain_success=last_p["ea_amoeba"],
+            plain_gpu_seconds=last_p["ea_seconds"] + last_p["amoeba_seconds"],
+            learned_generations=hit["gen"] if hit else None,
+            learned_gpu_seconds=(hit["ea_seconds"] + hit["amoeba_seconds"] + t_inf)
+            if hit else None),
+        gpu_seconds_per_fit_last=dict(
+            plain=(last_p["ea_seconds"] + last_p["amoeba_seconds"]) / n_lc,
+            learned=(last_l["ea_seconds"] + last_l["amoeba_seconds"] + t_inf) / n_lc,
+            learned_with_training=(last_l["ea_seconds"] + last_l["amoeba_seconds"] + t_inf
+                                   + train_info["data_seconds"] + train_info["train_seconds"])
+            / n_lc))
 
 
 def cpu_baseline(wl, y, w, pop, target_s):
@@ -339,13 +361,29 @@ def main():
         forms[name] = run_form(sblm, torch, lcs, wl, chi2_true, args.pop, args.steps, args, mode)
         log(f"bench: {name}: {json.dumps(forms[name])}")
     main_form = forms.get("fp64") or next(iter(forms.values()))
-    tts = None
+    lo, hi = inputs.PRIOR_LO, inputs.PRIOR_HI  # the default EA domain
+    sched = tuple(main_form["schedule"].values())
+    net = train_info = None
+    if args.success_max_gen > 0 or args.learned_gens > 0:
+        log("bench: training the proposal network on generated lightcurves")
+        net, train_info = train_proposals(sblm, torch, args)
+        log(f"bench: training: {json.dumps(train_info)}")
+    success = None
     if args.success_max_gen > 0:
-        log("bench: time to 90% success (plain FP64 EA)")
-        sched = tuple(main_form["schedule"].values())
-        tts = time_to_success(sblm, torch, lcs, chi2_true, args.pop, sblm.FP64, sched,
-                              max_gen=args.success_max_gen)
-        log(f"bench: success: {json.dumps(tts)}")
+        log("bench: time to 90% success, plain and learned, EA + simplex fine-tuning")
+        out_p, t_inf = propose(sblm, torch, net, lcs)
+        success = dict(
+            plain=success_run(sblm, torch, lcs, chi2_true, args.pop, sblm.FP64, sched, lo, hi,
+                              max_gen=args.success_max_gen, every=args.success_every),
+            learned=success_run(sblm, torch, lcs, chi2_true, args.pop, sblm.FP64, sched, lo,
+                                hi, proposals=out_p, max_gen=args.success_max_gen,
+                                every=args.success_every),
+            inference_seconds=t_inf)
+        lrn = success["learned"]["ea_amoeba"]
+        if lrn["gpu_seconds"] is not None:  # proposals are part of the learned fit's GPU time
+            lrn["gpu_seconds"] += t_inf
+            lrn["fits_per_hour"] = args.n_lc * 3600.0 / lrn["gpu_seconds"]
+        log(f"bench: success: {json.dumps(success)}")
 
     ragged = None
     learned = None
@@ -362,9 +400,12 @@ def main():
         if args.learned_gens > 0:
             log("bench: learned form (proposal network) vs plain EA on the ragged workload")
             learned = learned_form(sblm, torch, lcs_r, c_true_r.cpu().numpy(), 128,
-                                   tuple(ragged["schedule"].values()), args)
+                                   tuple(ragged["schedule"].values()), lo, hi, net,
+                                   train_info, args)
             log(f"bench: learned: {json.dumps(learned)}")
         del lcs_r
+    if net is not None:
+        net.close()
 
     cpu = None
     if not args.no_cpu:
@@ -385,8 +426,9 @@ def main():
                    "n_lc": args.n_lc, "epochs": args.epochs, "pop": args.pop,
                    "parallelism": "single GPU"},
         "fits_per_hour": main_form["fits_per_hour"],
-        "fits_per_hour_at_90pct": tts["fits_per_hour"] if tts else None,
-        "time_to_90pct_success": tts,
+        "fits_per_hour_at_90pct": ({f: success[f]["ea_amoeba"]["fits_per_hour"]
+                                    for f in ("plain", "learned")} if success else None),
+        "time_to_90pct_success": success,
         "success_rate": main_form["success"],
         "forms": forms,
         "ragged": ragged,

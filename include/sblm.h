@@ -283,6 +283,65 @@ int ea_load(ea_state* st, const void* buf, size_t len, void* stream);
 void ea_destroy(ea_state* st);
 
 /* ---------------------------------------------------------------------- */
+/* Simplex fine-tuning ("EA with amoeba", Sec. 3.1, Tables 2-3)            */
+/* ---------------------------------------------------------------------- */
+/*
+ * The downhill simplex of Nelder & Mead (1965) in the form of Lagarias,
+ * Reeds, Wright & Wright (1998), which the paper applies to the fittest
+ * solution of the EA.  One simplex per lightcurve, in the EA's encoded domain
+ * [0, 1]^6 (Eq. EMMA-encoding), chi^2 as in sblm_chi2:
+ *   - coefficients: reflection 1, expansion 2, contraction 1/2, shrink 1/2;
+ *   - initial simplex: x0 (clipped) and, for k = 0..5, x0 with coordinate k
+ *     multiplied by 1.05 (set to 0.00025 where it is 0), a value above 1
+ *     reflected to 2 - value, then clipped to [0, 1];
+ *   - every trial point (reflection, expansion, contractions, shrunk
+ *     vertices) is clipped to [0, 1];
+ *   - vertices are kept in ascending chi^2, equal values in their previous
+ *     order (a new vertex after older equal ones); NaN counts as +inf;
+ *   - before each step the run stops if every vertex lies within tol_x of
+ *     the best in every coordinate and within tol_f of its chi^2, or after
+ *     max_iter steps (a shrink counts as one step).
+ */
+typedef struct {
+  double tol_x;     /* encoded units, default 1e-4                        */
+  double tol_f;     /* chi^2 units, default 1e-4                          */
+  int32_t max_iter; /* simplex steps, default 200 x 6 = 1200; <= 10^6     */
+  int32_t mode;     /* sblm_mode of the fitness evaluations, default FP64 */
+} nm_config;
+
+void nm_default_config(nm_config* cfg);
+
+/*
+ * nm_refine -- refine one start point per lightcurve.
+ *   lcs     ragged lightcurves (device CSR), 1 <= n_lc <= 2^24
+ *   lo, hi  HOST double[6], the domain of the encoding (lo < hi)
+ *   x0      [6][n_lc] device, encoded start points
+ *   x       [6][n_lc] device out, best vertex (may alias x0)
+ *   chi2, Fs, Fb  [n_lc] device out (nullable), its chi^2 and fluxes
+ *   n_iter  [n_lc] device int32 out (nullable), simplex steps taken
+ *   stats   (nullable) fitness counters
+ * Allocates and frees a workspace of ~1 KB per lightcurve; synchronises
+ * `stream`.  Errors: SBLM_EINVAL, SBLM_ERANGE, SBLM_ENOMEM, SBLM_EDEVICE.
+ */
+int nm_refine(const sblm_lcs* lcs, const double* lo, const double* hi,
+              const double* x0, const nm_config* cfg, double* x, double* chi2,
+              double* Fs, double* Fb, int32_t* n_iter, sblm_stats* stats,
+              void* stream);
+
+/* ea_best -- the fittest solution seen so far by every lightcurve's EA:
+ * x [6][n_lc] device (encoded), chi2 [n_lc] device (nullable). */
+int ea_best(ea_state* st, double* x, double* chi2, void* stream);
+
+/*
+ * ea_refine -- nm_refine from every lightcurve's fittest solution (ea_best),
+ * in the state's domain; where the simplex finds a lower chi^2 the record
+ * (best chi^2, parameters, fluxes, generation) is replaced.  The population
+ * is not touched.  n_iter as in nm_refine.  Synchronises `stream`.
+ */
+int ea_refine(ea_state* st, const nm_config* cfg, int32_t* n_iter, sblm_stats* stats,
+              void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Learned proposal network                                                */
 /* ---------------------------------------------------------------------- */
 /*

@@ -335,6 +335,29 @@ __global__ void ea_draws_kernel(uint64_t seed, uint64_t lc, uint64_t gen,
   out[k] = rs.draw(purpose, row, j0 + (uint64_t)k);
 }
 
+// The record's fittest solution as a [6][n_lc] encoded array.
+__global__ void ea_best_kernel(const EaLc* lcs, int32_t n_lc, double* x, double* chi2) {
+  const int lc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lc >= n_lc) return;
+  for (int g = 0; g < SBLM_NPAR; ++g) x[(int64_t)g * n_lc + lc] = lcs[lc].best_p[g];
+  if (chi2) chi2[lc] = lcs[lc].best_chi2;
+}
+
+// Replaces a record whose refined solution is fitter.
+__global__ void ea_improve_kernel(EaLc* lcs, int32_t n_lc, const double* x, const double* chi2,
+                                  const double* Fs, const double* Fb) {
+  const int lc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lc >= n_lc) return;
+  EaLc& r = lcs[lc];
+  if (chi2[lc] < r.best_chi2) {
+    r.best_chi2 = chi2[lc];
+    r.best_Fs = Fs[lc];
+    r.best_Fb = Fb[lc];
+    for (int g = 0; g < SBLM_NPAR; ++g) r.best_p[g] = x[(int64_t)g * n_lc + lc];
+    r.best_gen = r.gen;
+  }
+}
+
 // ---------------------------------------------------------------- host side
 
 struct EaStateImpl {
@@ -680,6 +703,53 @@ extern "C" int ea_seed(ea_state* st, const float* out, int32_t ld_out, int32_t n
   s.prop = attach ? pr : Proposals{};
   if ((attach || was) && s.graph) return capture_graph(s, s.graph_stats);
   return SBLM_OK;
+}
+
+extern "C" int ea_best(ea_state* st, double* x, double* chi2, void* stream) {
+  if (!st) return set_error(SBLM_ESTATE, "ea_best: null state");
+  if (!x) return set_error(SBLM_EINVAL, "ea_best: null x");
+  EaStateImpl& s = st->impl;
+  hipLaunchKernelGGL(ea_best_kernel, dim3((s.prm.n_lc + 255) / 256), dim3(256), 0,
+                     (hipStream_t)stream, s.lc, s.prm.n_lc, x, chi2);
+  return check_hip(hipGetLastError(), "ea_best launch");
+}
+
+extern "C" int ea_refine(ea_state* st, const nm_config* cfg, int32_t* n_iter,
+                         sblm_stats* stats, void* stream) {
+  if (!st) return set_error(SBLM_ESTATE, "ea_refine: null state");
+  int rc = nm_check(cfg, "ea_refine");
+  if (rc) return rc;
+  EaStateImpl& s = st->impl;
+  const int n = s.prm.n_lc;
+  hipStream_t hs = (hipStream_t)stream;
+  double *x0 = nullptr, *x = nullptr, *c = nullptr, *fs = nullptr, *fb = nullptr;
+  const size_t nn = (size_t)n;
+  if (hipMalloc(&x0, nn * SBLM_NPAR * 8) != hipSuccess ||
+      hipMalloc(&x, nn * SBLM_NPAR * 8) != hipSuccess || hipMalloc(&c, nn * 8) != hipSuccess ||
+      hipMalloc(&fs, nn * 8) != hipSuccess || hipMalloc(&fb, nn * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    rc = set_error(SBLM_ENOMEM, "ea_refine: device allocation");
+  }
+  if (rc == SBLM_OK) {
+    hipLaunchKernelGGL(ea_best_kernel, dim3((n + 255) / 256), dim3(256), 0, hs, s.lc, n, x0,
+                       nullptr);
+    rc = check_hip(hipGetLastError(), "ea_refine: launch");
+  }
+  double span[SBLM_NPAR];
+  for (int g = 0; g < SBLM_NPAR; ++g) span[g] = s.cfg.hi[g] - s.cfg.lo[g];
+  if (rc == SBLM_OK)
+    rc = nm_run(s.lcs, s.cfg.lo, span, x0, *cfg, x, c, fs, fb, n_iter, stats, hs);
+  if (rc == SBLM_OK) {
+    hipLaunchKernelGGL(ea_improve_kernel, dim3((n + 255) / 256), dim3(256), 0, hs, s.lc, n, x,
+                       c, fs, fb);
+    rc = check_hip(hipGetLastError(), "ea_refine: launch");
+  }
+  if (hipStreamSynchronize(hs) != hipSuccess && rc == SBLM_OK)
+    rc = check_hip(hipGetLastError(), "ea_refine: synchronise");
+  double* bufs[] = {x0, x, c, fs, fb};
+  for (double* b : bufs)
+    if (b) (void)hipFree(b);
+  return rc;
 }
 
 extern "C" int ea_evaluate(ea_state* st, sblm_stats* stats, void* stream) {

@@ -1,0 +1,395 @@
+// sblm_nm.hip -- batched downhill-simplex refinement, one simplex per
+// lightcurve (the amoeba fine-tuning of the EA's fittest solution, Sec. 3.1
+// and the "EA with amoeba" rows of Tables 2-3; method of Nelder & Mead 1965
+// in the form of Lagarias, Reeds, Wright & Wright 1998).
+//
+// The simplex lives in the EA's encoded domain [0, 1]^6 (Eq. EMMA-encoding):
+// reflection 1, expansion 2, contraction 1/2, shrink 1/2; the initial
+// simplex is x0 plus x0 with coordinate k scaled by 1.05 (0.00025 where it
+// is 0), reflected below 1 and clipped; every trial point is clipped to the
+// domain; vertices stay in ascending chi^2 order with ties kept in their
+// previous order (NaN counts as +inf); the run stops before a step once
+// every vertex is within tol_x of the best in every coordinate and within
+// tol_f in chi^2, or after max_iter steps.
+//
+// Device form: each round evaluates four trial points per lightcurve in one
+// launch of the fitness kernel -- the reflection and, speculatively, the
+// expansion and both contractions, since all four depend only on the current
+// simplex -- so one round is one simplex step whatever branch it takes.  The
+// six vertices of a shrink are evaluated over the next two rounds, and the
+// seven initial vertices over the first two.  The sequence of simplices is
+// that of the sequential algorithm.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "sblm_internal.h"
+
+namespace sblm {
+namespace {
+
+constexpr int NP = SBLM_NPAR;  // 6 coordinates
+constexpr int NV = NP + 1;     // 7 vertices
+constexpr int NS = 4;          // trial slots per lightcurve and round
+
+enum : int32_t { PH_INIT1 = 0, PH_INIT2, PH_STEP, PH_SHRINK1, PH_SHRINK2, PH_DONE };
+
+struct NmWork {
+  int32_t n;       // lightcurves
+  double* V;       // [NV][NP][n] vertices
+  double* F;       // [NV][n] chi^2 of the vertices
+  double* FsV;     // [NV][n]
+  double* FbV;     // [NV][n]
+  double* T;       // [NP][n * NS] trial points, individual lc * NS + slot
+  double* cT;      // [n * NS] trial chi^2
+  double* fsT;
+  double* fbT;
+  int32_t* phase;  // [n]
+  int32_t* steps;  // [n]
+  int32_t* done;   // [n] 1 once finished: its trial slots are not evaluated
+  unsigned int* active;
+};
+
+__device__ __forceinline__ double clip01(double x) { return fmin(fmax(x, 0.0), 1.0); }
+__device__ __forceinline__ double finite_or_inf(double x) { return isnan(x) ? INFINITY : x; }
+
+__device__ __forceinline__ double& vtx(const NmWork& w, int v, int g, int lc) {
+  return w.V[((int64_t)v * NP + g) * w.n + lc];
+}
+__device__ __forceinline__ void put_trial(const NmWork& w, int lc, int slot, const double* x) {
+  for (int g = 0; g < NP; ++g) w.T[(int64_t)g * w.n * NS + (int64_t)lc * NS + slot] = x[g];
+}
+__device__ __forceinline__ void get_trial(const NmWork& w, int lc, int slot, double* x) {
+  for (int g = 0; g < NP; ++g) x[g] = w.T[(int64_t)g * w.n * NS + (int64_t)lc * NS + slot];
+}
+
+__global__ void nm_start_kernel(NmWork w, const double* x0) {
+  const int lc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lc >= w.n) return;
+  double x[NP];
+  for (int g = 0; g < NP; ++g) x[g] = clip01(x0[(int64_t)g * w.n + lc]);
+  for (int v = 0; v < NV; ++v)
+    for (int g = 0; g < NP; ++g) {
+      double y = x[g];
+      if (v == g + 1) y = (y != 0.0) ? (1.0 + 0.05) * y : 0.00025;
+      if (y > 1.0) y = 2.0 * 1.0 - y;
+      vtx(w, v, g, lc) = clip01(y);
+    }
+  w.phase[lc] = PH_INIT1;
+  w.steps[lc] = 0;
+  w.done[lc] = 0;
+}
+
+__global__ void nm_reset_kernel(unsigned int* active) { *active = 0u; }
+
+// Trial points of this round.
+__global__ void nm_propose_kernel(NmWork w, double tol_x, double tol_f, int32_t max_iter) {
+  const int lc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lc >= w.n) return;
+  int ph = w.phase[lc];
+  double x[NP];
+  if (ph == PH_STEP) {
+    double dx = 0.0, df = 0.0;
+    bool undefined = false;  // inf - inf: never converged
+    const double f0 = w.F[lc];
+    for (int v = 1; v < NV; ++v) {
+      const double d = fabs(f0 - w.F[(int64_t)v * w.n + lc]);
+      undefined |= isnan(d);
+      df = fmax(df, d);
+      for (int g = 0; g < NP; ++g) dx = fmax(dx, fabs(vtx(w, v, g, lc) - vtx(w, 0, g, lc)));
+    }
+    if ((!undefined && dx <= tol_x && df <= tol_f) || w.steps[lc] >= max_iter) {
+      ph = PH_DONE;
+      w.phase[lc] = PH_DONE;
+      w.done[lc] = 1;
+    }
+  }
+  switch (ph) {
+    case PH_INIT1:
+    case PH_SHRINK1:
+      for (int s = 0; s < NS; ++s) {
+        const int v = (ph == PH_INIT1) ? s : 1 + s;
+        for (int g = 0; g < NP; ++g) x[g] = vtx(w, v, g, lc);
+        put_trial(w, lc, s, x);
+      }
+      break;
+    case PH_INIT2:
+    case PH_SHRINK2:
+      for (int s = 0; s < NS; ++s) {
+        const int v = (ph == PH_INIT2) ? (s < 3 ? 4 + s : 6) : (s < 2 ? 5 + s : 6);
+        for (int g = 0; g < NP; ++g) x[g] = vtx(w, v, g, lc);
+        put_trial(w, lc, s, x);
+      }
+      break;
+    case PH_STEP: {
+      double xbar[NP], xw[NP];
+      for (int g = 0; g < NP; ++g) {
+        double sum = vtx(w, 0, g, lc);
+        for (int v = 1; v < NV - 1; ++v) sum += vtx(w, v, g, lc);
+        xbar[g] = sum / NP;
+        xw[g] = vtx(w, NV - 1, g, lc);
+      }
+      // reflection, expansion, outside and inside contraction
+      const double rho = 1.0, chi = 2.0, psi = 0.5;
+      for (int g = 0; g < NP; ++g) x[g] = clip01((1 + rho) * xbar[g] - rho * xw[g]);
+      put_trial(w, lc, 0, x);
+      for (int g = 0; g < NP; ++g) x[g] = clip01((1 + rho * chi) * xbar[g] - rho * chi * xw[g]);
+      put_trial(w, lc, 1, x);
+      for (int g = 0; g < NP; ++g) x[g] = clip01((1 + psi * rho) * xbar[g] - psi * rho * xw[g]);
+      put_trial(w, lc, 2, x);
+      for (int g = 0; g < NP; ++g) x[g] = clip01((1 - psi) * xbar[g] + psi * xw[g]);
+      put_trial(w, lc, 3, x);
+      break;
+    }
+    default:  // done: the best vertex, so that the slots stay valid inputs
+      for (int g = 0; g < NP; ++g) x[g] = vtx(w, 0, g, lc);
+      for (int s = 0; s < NS; ++s) put_trial(w, lc, s, x);
+      break;
+  }
+}
+
+struct Vertex {
+  double x[NP];
+  double f, fs, fb;
+};
+
+__device__ void load_simplex(const NmWork& w, int lc, Vertex* s) {
+  for (int v = 0; v < NV; ++v) {
+    for (int g = 0; g < NP; ++g) s[v].x[g] = vtx(w, v, g, lc);
+    s[v].f = w.F[(int64_t)v * w.n + lc];
+    s[v].fs = w.FsV[(int64_t)v * w.n + lc];
+    s[v].fb = w.FbV[(int64_t)v * w.n + lc];
+  }
+}
+
+__device__ void store_simplex(const NmWork& w, int lc, const Vertex* s) {
+  for (int v = 0; v < NV; ++v) {
+    for (int g = 0; g < NP; ++g) vtx(w, v, g, lc) = s[v].x[g];
+    w.F[(int64_t)v * w.n + lc] = s[v].f;
+    w.FsV[(int64_t)v * w.n + lc] = s[v].fs;
+    w.FbV[(int64_t)v * w.n + lc] = s[v].fb;
+  }
+}
+
+// stable insertion sort by f (equal values keep their order)
+__device__ void sort_simplex(Vertex* s) {
+  for (int i = 1; i < NV; ++i) {
+    const Vertex key = s[i];
+    int j = i - 1;
+    while (j >= 0 && s[j].f > key.f) {
+      s[j + 1] = s[j];
+      --j;
+    }
+    s[j + 1] = key;
+  }
+}
+
+__device__ void take_trial(const NmWork& w, int lc, int slot, Vertex& v) {
+  const int64_t i = (int64_t)lc * NS + slot;
+  get_trial(w, lc, slot, v.x);
+  v.f = finite_or_inf(w.cT[i]);
+  v.fs = w.fsT[i];
+  v.fb = w.fbT[i];
+}
+
+__global__ void nm_update_kernel(NmWork w) {
+  const int lc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lc >= w.n) return;
+  const int ph = w.phase[lc];
+  if (ph == PH_DONE) return;
+  Vertex s[NV];
+  load_simplex(w, lc, s);
+  int next = ph;
+  switch (ph) {
+    case PH_INIT1:
+      for (int k = 0; k < NS; ++k) take_trial(w, lc, k, s[k]);
+      next = PH_INIT2;
+      break;
+    case PH_INIT2:
+      for (int k = 0; k < 3; ++k) take_trial(w, lc, k, s[4 + k]);
+      sort_simplex(s);
+      next = PH_STEP;
+      break;
+    case PH_SHRINK1:
+      for (int k = 0; k < NS; ++k) take_trial(w, lc, k, s[1 + k]);
+      next = PH_SHRINK2;
+      break;
+    case PH_SHRINK2:
+      for (int k = 0; k < 2; ++k) take_trial(w, lc, k, s[5 + k]);
+      sort_simplex(s);
+      next = PH_STEP;
+      break;
+    case PH_STEP: {
+      Vertex r, e, oc, ic;
+      take_trial(w, lc, 0, r);
+      take_trial(w, lc, 1, e);
+      take_trial(w, lc, 2, oc);
+      take_trial(w, lc, 3, ic);
+      int accept = -1;  // 0 r, 1 e, 2 oc, 3 ic; -1 shrink
+      if (r.f < s[0].f) accept = (e.f < r.f) ? 1 : 0;
+      else if (r.f < s[NV - 2].f) accept = 0;
+      else if (r.f < s[NV - 1].f) accept = (oc.f <= r.f) ? 2 : -1;
+      else accept = (ic.f < s[NV - 1].f) ? 3 : -1;
+      if (accept >= 0) {
+        s[NV - 1] = accept == 0 ? r : accept == 1 ? e : accept == 2 ? oc : ic;
+        sort_simplex(s);
+        next = PH_STEP;
+      } else {
+        const double sigma = 0.5;
+        for (int v = 1; v < NV; ++v)
+          for (int g = 0; g < NP; ++g)
+            s[v].x[g] = clip01(s[0].x[g] + sigma * (s[v].x[g] - s[0].x[g]));
+        next = PH_SHRINK1;
+      }
+      w.steps[lc] += 1;
+      break;
+    }
+  }
+  store_simplex(w, lc, s);
+  w.phase[lc] = next;
+  atomicAdd(w.active, 1u);
+}
+
+__global__ void nm_finish_kernel(NmWork w, double* x, double* chi2, double* Fs, double* Fb,
+                                 int32_t* n_iter) {
+  const int lc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lc >= w.n) return;
+  for (int g = 0; g < NP; ++g) x[(int64_t)g * w.n + lc] = vtx(w, 0, g, lc);
+  if (chi2) chi2[lc] = w.F[lc];
+  if (Fs) Fs[lc] = w.FsV[lc];
+  if (Fb) Fb[lc] = w.FbV[lc];
+  if (n_iter) n_iter[lc] = w.steps[lc];
+}
+
+}  // namespace
+
+int nm_check(const nm_config* cfg, const char* who) {
+  if (!cfg) return set_error(SBLM_EINVAL, "%s: null config", who);
+  if (!(cfg->tol_x >= 0.0) || !(cfg->tol_f >= 0.0))
+    return set_error(SBLM_EINVAL, "%s: negative tolerance", who);
+  if (cfg->max_iter < 0 || cfg->max_iter > 1000000)
+    return set_error(SBLM_EINVAL, "%s: max_iter = %d outside [0, 10^6]", who, cfg->max_iter);
+  if (cfg->mode != SBLM_FP64 && cfg->mode != SBLM_MIXED)
+    return set_error(SBLM_EINVAL, "%s: unknown mode %d", who, cfg->mode);
+  return SBLM_OK;
+}
+
+int nm_run(const sblm_lcs& lcs, const double* lo, const double* span, const double* x0,
+           const nm_config& cfg, double* x, double* chi2, double* Fs, double* Fb,
+           int32_t* n_iter, sblm_stats* stats, hipStream_t st) {
+  const int n = lcs.n_lc;
+  NmWork w;
+  memset(&w, 0, sizeof(w));
+  w.n = n;
+  const size_t nn = (size_t)n;
+  bool ok = hipMalloc(&w.V, nn * NV * NP * 8) == hipSuccess &&
+            hipMalloc(&w.F, nn * NV * 8) == hipSuccess &&
+            hipMalloc(&w.FsV, nn * NV * 8) == hipSuccess &&
+            hipMalloc(&w.FbV, nn * NV * 8) == hipSuccess &&
+            hipMalloc(&w.T, nn * NS * NP * 8) == hipSuccess &&
+            hipMalloc(&w.cT, nn * NS * 8) == hipSuccess &&
+            hipMalloc(&w.fsT, nn * NS * 8) == hipSuccess &&
+            hipMalloc(&w.fbT, nn * NS * 8) == hipSuccess &&
+            hipMalloc(&w.phase, nn * 4) == hipSuccess &&
+            hipMalloc(&w.steps, nn * 4) == hipSuccess &&
+            hipMalloc(&w.done, nn * 4) == hipSuccess &&
+            hipMalloc(&w.active, 4) == hipSuccess;
+  int rc = SBLM_OK;
+  if (!ok) {
+    (void)hipGetLastError();
+    rc = set_error(SBLM_ENOMEM, "nm_refine: device allocation");
+  }
+  FitArgs a;
+  memset(&a, 0, sizeof(a));
+  a.theta = w.T;
+  a.n_ind = (int64_t)n * NS;
+  a.encoded = 1;
+  for (int g = 0; g < NP; ++g) {
+    a.lo[g] = lo[g];
+    a.span[g] = span[g];
+  }
+  a.off = lcs.off;
+  a.pop = NS;
+  a.t = lcs.t;
+  a.y = lcs.y;
+  a.w = lcs.w;
+  a.chi2 = w.cT;
+  a.Fs = w.fsT;
+  a.Fb = w.fbT;
+  a.stats = stats;
+  a.skip = w.done;
+  // a round is latency-bound unless the batch fills the GPU many times over:
+  // more lanes per individual shorten the longest lightcurve's chain
+  a.lanes_per_ind = ((int64_t)n * NS * 64 <= (int64_t)8 * 256 * 256) ? 64 : 16;
+  const dim3 grid((n + 255) / 256), blk(256);
+  if (rc == SBLM_OK) {
+    hipLaunchKernelGGL(nm_start_kernel, grid, blk, 0, st, w, x0);
+    rc = check_hip(hipGetLastError(), "nm_refine: start");
+  }
+  // rounds: 2 for the initial simplex, 1 per step, 2 more per shrink
+  const int64_t max_rounds = 4 + 3 * (int64_t)cfg.max_iter;
+  const int chunk = 16;
+  for (int64_t r = 0; rc == SBLM_OK && r < max_rounds; r += chunk) {
+    for (int k = 0; k < chunk && rc == SBLM_OK; ++k) {
+      hipLaunchKernelGGL(nm_reset_kernel, dim3(1), dim3(1), 0, st, w.active);
+      hipLaunchKernelGGL(nm_propose_kernel, grid, blk, 0, st, w, cfg.tol_x, cfg.tol_f,
+                         cfg.max_iter);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess) e = launch_fitness(a, cfg.mode, true, st, 4);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(nm_update_kernel, grid, blk, 0, st, w);
+        e = hipGetLastError();
+      }
+      rc = check_hip(e, "nm_refine: round");
+    }
+    unsigned int active = 1;
+    if (rc == SBLM_OK)
+      rc = check_hip(hipMemcpyAsync(&active, w.active, 4, hipMemcpyDeviceToHost, st),
+                     "nm_refine: copy");
+    if (rc == SBLM_OK) rc = check_hip(hipStreamSynchronize(st), "nm_refine: synchronise");
+    if (active == 0) break;
+  }
+  if (rc == SBLM_OK) {
+    hipLaunchKernelGGL(nm_finish_kernel, grid, blk, 0, st, w, x, chi2, Fs, Fb, n_iter);
+    rc = check_hip(hipGetLastError(), "nm_refine: finish");
+  }
+  if (hipStreamSynchronize(st) != hipSuccess && rc == SBLM_OK)
+    rc = check_hip(hipGetLastError(), "nm_refine: synchronise");
+  void* bufs[] = {w.V,     w.F,     w.FsV,  w.FbV,  w.T,      w.cT,
+                  w.fsT,   w.fbT,   w.phase, w.steps, w.done, w.active};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  return rc;
+}
+
+}  // namespace sblm
+
+using namespace sblm;
+
+extern "C" void nm_default_config(nm_config* cfg) {
+  if (!cfg) return;
+  cfg->tol_x = 1e-4;
+  cfg->tol_f = 1e-4;
+  cfg->max_iter = 200 * SBLM_NPAR;
+  cfg->mode = SBLM_FP64;
+}
+
+extern "C" int nm_refine(const sblm_lcs* lcs, const double* lo, const double* hi,
+                         const double* x0, const nm_config* cfg, double* x, double* chi2,
+                         double* Fs, double* Fb, int32_t* n_iter, sblm_stats* stats,
+                         void* stream) {
+  int rc = nm_check(cfg, "nm_refine");
+  if (rc) return rc;
+  if (!lcs || !lcs->off || !lcs->t || !lcs->y || !lcs->w)
+    return set_error(SBLM_EINVAL, "nm_refine: null lightcurve descriptor or array");
+  if (lcs->n_lc < 1) return set_error(SBLM_EINVAL, "nm_refine: n_lc < 1");
+  if (lcs->n_lc > (1 << 24)) return set_error(SBLM_ERANGE, "nm_refine: n_lc beyond 2^24");
+  if (!lo || !hi || !x0 || !x) return set_error(SBLM_EINVAL, "nm_refine: null lo, hi, x0 or x");
+  double span[SBLM_NPAR];
+  for (int g = 0; g < SBLM_NPAR; ++g) {
+    if (!(hi[g] > lo[g])) return set_error(SBLM_EINVAL, "nm_refine: hi[%d] <= lo[%d]", g, g);
+    span[g] = hi[g] - lo[g];
+  }
+  return nm_run(*lcs, lo, span, x0, *cfg, x, chi2, Fs, Fb, n_iter, stats,
+                (hipStream_t)stream);
+}

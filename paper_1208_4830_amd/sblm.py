@@ -40,6 +40,11 @@ class ea_config(ctypes.Structure):
                 ("mode", ctypes.c_int32)]
 
 
+class nm_config(ctypes.Structure):
+    _fields_ = [("tol_x", ctypes.c_double), ("tol_f", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("mode", ctypes.c_int32)]
+
+
 class ea_lc_summary(ctypes.Structure):
     _fields_ = [("best_chi2", ctypes.c_double), ("best_Fs", ctypes.c_double),
                 ("best_Fb", ctypes.c_double), ("best_theta", ctypes.c_double * NPAR),
@@ -95,6 +100,14 @@ _SIGS = {
     "mlp_train": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                   ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                   ctypes.c_void_p, ctypes.c_void_p],
+    "nm_default_config": [ctypes.POINTER(nm_config)],
+    "nm_refine": [ctypes.POINTER(sblm_lcs), ctypes.POINTER(ctypes.c_double),
+                  ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.POINTER(nm_config),
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "ea_best": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "ea_refine": [ctypes.c_void_p, ctypes.POINTER(nm_config), ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_void_p],
     "ea_seed": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                 ctypes.c_int32, ctypes.c_void_p],
 }
@@ -117,6 +130,7 @@ def load():
     lib.ea_default_config.restype = None
     lib.ea_destroy.restype = None
     lib.mlp_destroy.restype = None
+    lib.nm_default_config.restype = None
     _lib = lib
     return lib
 
@@ -320,6 +334,22 @@ class EAState:
                               SEED_AT_RESTARTS if at_restarts else 0, _stream(stream)))
         self._proposals = out if (at_restarts and n_seed > 0) else None
 
+    def best(self, stream=None):
+        """(x [6][n_lc] encoded, chi2 [n_lc]) of every lightcurve's record."""
+        n = self.lcs.n_lc
+        x = torch.empty((NPAR, n), dtype=torch.float64, device=self.lcs.t.device)
+        c = torch.empty(n, dtype=torch.float64, device=self.lcs.t.device)
+        _check(load().ea_best(self.h, _ptr(x), _ptr(c), _stream(stream)))
+        return x, c
+
+    def refine(self, cfg=None, stats=None, stream=None):
+        """Simplex fine-tuning of every record; returns the steps taken."""
+        cfg = cfg or nm_default_config()
+        it = torch.empty(self.lcs.n_lc, dtype=torch.int32, device=self.lcs.t.device)
+        _check(load().ea_refine(self.h, ctypes.byref(cfg), _ptr(it), _ptr(stats),
+                                _stream(stream)))
+        return it
+
     def close(self):
         if self.h:
             load().ea_destroy(self.h)
@@ -330,6 +360,32 @@ class EAState:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- simplex
+
+def nm_default_config():
+    cfg = nm_config()
+    load().nm_default_config(ctypes.byref(cfg))
+    return cfg
+
+
+def nm_refine(lcs, lo, hi, x0, cfg=None, stats=None, stream=None):
+    """(x [6][n_lc], chi2, Fs, Fb [n_lc], steps [n_lc] int32) from encoded
+    start points x0 [6][n_lc] in the domain [lo, hi]."""
+    cfg = cfg or nm_default_config()
+    x0 = _dev(x0)
+    n = lcs.n_lc
+    dev = x0.device
+    x = torch.empty_like(x0)
+    c, fs, fb = (torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
+    it = torch.empty(n, dtype=torch.int32, device=dev)
+    lo_ = (ctypes.c_double * NPAR)(*[float(v) for v in lo])
+    hi_ = (ctypes.c_double * NPAR)(*[float(v) for v in hi])
+    _check(load().nm_refine(ctypes.byref(lcs.desc), lo_, hi_, _ptr(x0), ctypes.byref(cfg),
+                            _ptr(x), _ptr(c), _ptr(fs), _ptr(fb), _ptr(it), _ptr(stats),
+                            _stream(stream)))
+    return x, c, fs, fb, it
 
 
 # ---------------------------------------------------------------- proposal network

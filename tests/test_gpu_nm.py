@@ -1,0 +1,101 @@
+"""GPU parity of the batched simplex refinement against the simplex oracle
+driven by the oracle's chi^2, and the EA-with-amoeba record update."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import nm_oracle as NM
+from oracle import oracle as O
+from paper_1208_4830_amd import inputs
+from tests.helpers import oracle_lightcurves
+
+pytestmark = pytest.mark.gpu
+
+LO, HI = inputs.PRIOR_LO, inputs.PRIOR_HI
+
+
+def oracle_f(t, y, w):
+    off = np.array([0, t.size], np.int64)
+
+    def f(x):
+        th = O.decode(np.asarray(x, float)[:, None], LO, HI)
+        return O.chi2(off, t, y, w, th, 1, nthreads=1)[0][0]
+    return f
+
+
+def device_lcs(hip, wl, y, w):
+    cu = lambda a, dt=torch.float64: torch.tensor(a, dtype=dt, device="cuda")
+    return hip.Lightcurves(cu(wl.off, torch.int64), cu(wl.t), cu(y), cu(w))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_simplex_matches_oracle(hip, mode):
+    # ragged lengths including an empty lightcurve; starts near the truth,
+    # one start on the domain's edges (0 and 1 coordinates)
+    lengths = [300, 0, 257, 64, 300, 120, 300, 33]
+    wl = inputs.uniform_workload(41, len(lengths), 300)
+    ts, off = [], [0]
+    for k, L in enumerate(lengths):
+        ts.append(wl.t[k * 300:k * 300 + L])
+        off.append(off[-1] + L)
+    wl.t, wl.off = np.concatenate(ts), np.array(off, np.int64)
+    wl.sfrac, wl.noise = wl.sfrac[:wl.t.size], wl.noise[:wl.t.size]
+    y, w = oracle_lightcurves(wl)
+    lcs = device_lcs(hip, wl, y, w)
+    rng = np.random.default_rng(3)
+    x0 = np.clip((wl.theta - LO[:, None]) / (HI - LO)[:, None]
+                 + rng.normal(scale=0.02, size=wl.theta.shape), 0, 1)
+    x0[:, 3] = [0.0, 1.0, 0.5, 1.0, 0.0, 0.4]
+    cfg = hip.nm_default_config()
+    cfg.max_iter, cfg.mode = 150, mode
+    x, c, fs, fb, it = hip.nm_refine(lcs, LO, HI, torch.tensor(x0, device="cuda"), cfg)
+    x, c, fs, fb, it = (a.cpu().numpy() for a in (x, c, fs, fb, it))
+    for k in range(len(lengths)):
+        sl = slice(off[k], off[k + 1])
+        xr, fr, steps, _, _ = NM.minimise(oracle_f(wl.t[sl], y[sl], w[sl]), x0[:, k],
+                                          cfg.tol_x, cfg.tol_f, cfg.max_iter)
+        # the simplices follow from the accept/shrink decisions alone: the
+        # same decisions give bit-identical vertices
+        assert it[k] == steps, (k, it[k], steps)
+        assert np.array_equal(x[:, k], xr), (k, x[:, k] - xr)
+        tol = 1e-8 if mode == 0 else 1e-6
+        assert abs(c[k] - fr) <= tol * max(abs(fr), 1e-300) + 1e-14 * np.sum(w[sl] * y[sl] ** 2)
+    assert np.all(c <= np.array([oracle_f(wl.t[off[k]:off[k + 1]], y[off[k]:off[k + 1]],
+                                          w[off[k]:off[k + 1]])(x0[:, k]) + 1e-9
+                                 for k in range(len(lengths))]))
+
+
+def test_ea_refine_improves_records_only(hip):
+    wl = inputs.uniform_workload(42, 32, 400)
+    y, w = oracle_lightcurves(wl)
+    lcs = device_lcs(hip, wl, y, w)
+    cfg = hip.ea_default_config()
+    cfg.pop = 48
+    st = hip.EAState(cfg, lcs, 5)
+    st.fit(30)
+    before = [(s.best_chi2, tuple(s.best_theta)) for s in st.summary()]
+    P0 = st.view("P").clone()
+    x0, c0 = st.best()
+    it = st.refine()
+    torch.cuda.synchronize()
+    after = st.summary()
+    assert torch.equal(P0, st.view("P"))  # the population is not touched
+    th = torch.tensor(np.array([s.best_theta[:] for s in after]).T.copy(), device="cuda")
+    c_new, fs_new, _ = hip.sblm_chi2(lcs, th, 1)
+    c_new = c_new.cpu().numpy()
+    n_better = 0
+    for k, s in enumerate(after):
+        assert s.best_chi2 <= before[k][0]
+        if s.best_chi2 < before[k][0]:
+            n_better += 1
+            # the record is consistent: its chi^2 is that of its parameters
+            assert abs(c_new[k] - s.best_chi2) <= 1e-9 * s.best_chi2
+        else:
+            assert tuple(s.best_theta) == before[k][1]
+    assert n_better >= 16 and int(it.max()) > 0
+    c_true = hip.sblm_chi2(lcs, torch.tensor(wl.theta.copy(), device="cuda"), 1)[0].cpu().numpy()
+    ok_before = np.mean(np.array([b[0] for b in before]) <= c_true + 10)
+    ok_after = np.mean(np.array([s.best_chi2 for s in after]) <= c_true + 10)
+    print(f"success before/after the simplex: {ok_before:.3f} / {ok_after:.3f}")
+    assert ok_after >= ok_before
+    st.close()
