@@ -47,6 +47,21 @@ FLOP_POLISH = 150
 # for FP64 and for unpacked FP32 (packed FP32 is not used)
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 N_GEN_FIT = 500
+# HBM traffic of one launch of the FP64 chi^2 fitness kernel on the default
+# workload and schedule, from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a
+# copy kernel of known size (profiles/fitness_kernel_fp64_256lc_1000ep_pop256_
+# traffic.md).  Valid only for the kernel source it was taken on.
+FITNESS_TRAFFIC = dict(source_sha256_16="00b8857656191977", bytes_per_launch=61.25e6,
+                       algorithmic_bytes_per_launch=10.86e6)
+
+
+def fitness_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1208_4830_amd", "csrc", "sblm_fitness.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    return FITNESS_TRAFFIC["bytes_per_launch"] if sha == FITNESS_TRAFFIC["source_sha256_16"] \
+        else None
 
 
 def parse():
@@ -73,6 +88,9 @@ def parse():
                     help="generations of the plain-vs-learned comparison on the ragged "
                          "workload (0 = skip it)")
     ap.add_argument("--learned-every", type=int, default=100)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device 4 times (a kernel of "
+                         "known traffic that scales the profiler's byte counters)")
     ap.add_argument("--mlp-samples", type=int, default=1 << 20)
     ap.add_argument("--mlp-epochs", type=int, default=16)
     return ap.parse_args()
@@ -346,6 +364,15 @@ def main():
     sblm.load()
     assert torch.cuda.is_available()
     from paper_1208_4830_amd import inputs
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib << 18  # float32 elements
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copied {args.copy_calibration_mib} MiB x 4 (counter calibration)")
+        del src, dst
     log(f"bench: {args.n_lc} lightcurves x {args.epochs} epochs, pop {args.pop}, "
         f"{args.steps} generations")
     wl = inputs.uniform_workload(2, args.n_lc, args.epochs)
@@ -435,7 +462,9 @@ def main():
         "learned": learned,
         "roofline": {"bound": "alu", "achieved": main_form["kernel_tflops"],
                      "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": main_form["kernel_tflops"] / PEAK_VALU_TFLOPS, "traffic": None,
+                     "frac": main_form["kernel_tflops"] / PEAK_VALU_TFLOPS,
+                     "traffic": fitness_traffic(), "traffic_unit": "B/launch",
+                     "algorithmic_bytes": FITNESS_TRAFFIC["algorithmic_bytes_per_launch"],
                      "kernel": "fitness_kernel (FP64)",
                      "flop_per_magnification": main_form["flop_per_mag"]},
         "cpu_baseline": cpu,
