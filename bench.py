@@ -51,7 +51,7 @@ N_GEN_FIT = 500
 # workload and schedule, from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a
 # copy kernel of known size (profiles/fitness_kernel_fp64_256lc_1000ep_pop256_
 # traffic.md).  Valid only for the kernel source it was taken on.
-FITNESS_TRAFFIC = dict(source_sha256_16="00b8857656191977", bytes_per_launch=61.25e6,
+FITNESS_TRAFFIC = dict(source_sha256_16="f4b28e4075215986", bytes_per_launch=63.04e6,
                        algorithmic_bytes_per_launch=10.86e6)
 
 
@@ -81,6 +81,8 @@ def parse():
                     help="lightcurves of the ragged workload (0 = skip it)")
     ap.add_argument("--ragged-steps", type=int, default=30)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-after", type=int, default=30,
+                    help="generations the scratch state evolves before the autotuner")
     ap.add_argument("--success-max-gen", type=int, default=1600,
                     help="generation cap of the time-to-90%%-success runs (0 = skip them)")
     ap.add_argument("--success-every", type=int, default=100)
@@ -126,15 +128,17 @@ def run_form(sblm, torch, lcs, wl, chi2_true, pop, steps, args, mode, tune=True)
     cfg = sblm.ea_default_config()
     cfg.pop = pop
     cfg.mode = mode
-    # warm-up and schedule choice on a scratch state (same shapes)
+    # warm-up and schedule choice on a scratch state (same shapes), tuned
+    # after some generations: the initial uniform population solves very
+    # differently from the evolved ones the fit spends its time on
     scratch = sblm.EAState(cfg, lcs, 999)
+    scratch.fit(max(args.warmup, args.tune_after))
+    torch.cuda.synchronize()
     report = ""
     if tune and not args.no_autotune:
         report = scratch.autotune()
         log("bench: autotune\n" + report.strip())
     sched = scratch.schedule()
-    scratch.fit(args.warmup)
-    torch.cuda.synchronize()
     # sweeps per solve (lane level) for the algorithmic FLOP count
     st = sblm.new_stats()
     scratch.evaluate(stats=st)
@@ -174,6 +178,10 @@ def run_form(sblm, torch, lcs, wl, chi2_true, pop, steps, args, mode, tune=True)
         flop = FLOP_COEF + n32 * FLOP_SWEEP32 + (sweeps - n32) * FLOP_SWEEP64 \
             + FLOP_IMAGES + FLOP_LSQ
     flop += polished * FLOP_POLISH
+    # what the wavefronts executed: lockstep sweeps (n_wave_iter) instead of
+    # the lanes' own need
+    wave = s["n_wave_iter"] / max(s["n_solves"], 1)
+    flop_exec = flop + (wave - sweeps) * FLOP_SWEEP64
     ms_step = dt * 1e3 / steps
     return dict(
         mags_per_s=mags_per_gen * steps / dt,
@@ -183,6 +191,7 @@ def run_form(sblm, torch, lcs, wl, chi2_true, pop, steps, args, mode, tune=True)
         kernel_ms=k_ms, kernel_mags_per_s=mags_per_gen / (k_ms / 1e3),
         sweeps_per_solve=sweeps, flop_per_mag=flop,
         kernel_tflops=flop * mags_per_gen / (k_ms / 1e3) / 1e12,
+        kernel_tflops_executed=flop_exec * mags_per_gen / (k_ms / 1e3) / 1e12,
         capped=s["n_capped"], fallback=s["n_fallback"],
         wave_sweeps_per_solve=s["n_wave_iter"] / max(s["n_solves"], 1),
         polished_per_solve=s["n_polished"] / max(s["n_solves"], 1),
@@ -465,6 +474,8 @@ def main():
                      "frac": main_form["kernel_tflops"] / PEAK_VALU_TFLOPS,
                      "traffic": fitness_traffic(), "traffic_unit": "B/launch",
                      "algorithmic_bytes": FITNESS_TRAFFIC["algorithmic_bytes_per_launch"],
+                     "executed_tflops": main_form["kernel_tflops_executed"],
+                     "executed_frac": main_form["kernel_tflops_executed"] / PEAK_VALU_TFLOPS,
                      "kernel": "fitness_kernel (FP64)",
                      "flop_per_magnification": main_form["flop_per_mag"]},
         "cpu_baseline": cpu,

@@ -37,6 +37,17 @@
 
 #include "sblm_internal.h"
 
+// Stopping tolerance of the FP64 root iteration: the estimated error left in
+// every root after the last step, relative to max(1, |z|).  The roots only
+// start the images: an accepted image whose residual on the lens equation
+// could move A by more than 1e-12 relative is refined on the lens equation
+// itself (see magnification), so this tolerance sets the work, not the
+// accuracy of A; 1e-11 keeps the measured magnification errors unchanged
+// against 1e-16 while most warm-started solves end after one sweep.
+#ifndef SBLM_ROOT_TAU
+#define SBLM_ROOT_TAU 1e-11
+#endif
+
 namespace sblm {
 
 // ---------------------------------------------------------------- complex
@@ -427,7 +438,7 @@ __device__ __forceinline__ void solve_roots(const cx<double> c[6], bool deg4,
                                             bool& ok) {
   constexpr int MAXIT64 = 60, MAXIT32 = 30;
   // estimated relative error left after the last step
-  const double tau64 = 1e-16;
+  const double tau64 = SBLM_ROOT_TAU;
   const float tau32 = 1e-7f;
   if (!warm && active) cold_start<double>(c, deg4, z);
   int it_lane = 0, it32_lane = 0, it_wave = 0;
@@ -605,6 +616,30 @@ __device__ __forceinline__ void finish_chi2(const FitArgs& a, const Item& x, Lsq
 
 }
 
+// Per-lane history of the roots of the two epochs before the current one,
+// kept in LDS (touched once per epoch, at the warm start; in registers it
+// would hold 40 VGPRs through the whole solve).  Dynamic shared memory of
+// ROOT_HIST_BYTES per thread; element [((slot*5 + i)*2 + part) * blockDim.x +
+// thread] holds root i of epoch slot (0: previous but one, 1: the one
+// before), real (part 0) or imaginary (part 1).
+constexpr size_t ROOT_HIST_BYTES = 2 * 5 * 2 * sizeof(double);
+
+struct RootHist {
+  double* h;
+  __device__ __forceinline__ cx<double> get(int slot, int i) const {
+    const int n = blockDim.x;
+    return {h[((slot * 5 + i) * 2) * n + threadIdx.x],
+            h[((slot * 5 + i) * 2 + 1) * n + threadIdx.x]};
+  }
+  __device__ __forceinline__ void set(int slot, int i, cx<double> v) const {
+    const int n = blockDim.x;
+    h[((slot * 5 + i) * 2) * n + threadIdx.x] = v.re;
+    h[((slot * 5 + i) * 2 + 1) * n + threadIdx.x] = v.im;
+  }
+};
+
+extern __shared__ double fit_dyn_smem[];
+
 // One wave's share of the work, lockstep form: 64/G individuals (items
 // wave_item*64/G ...); every lane solves its s-th epoch at the same time and
 // the wave moves on when all of them have converged.
@@ -618,11 +653,14 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
   cx<double> z[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i) z[i] = {0.0, 0.0};
-  cx<double> zp[5];  // roots of the epoch before the previous one
+  const RootHist hist = {fit_dyn_smem};  // zp (slot 0), zpp (slot 1)
 #pragma unroll
-  for (int i = 0; i < 5; ++i) zp[i] = {0.0, 0.0};
-  bool have_prev = false, prev_deg4 = false, have_prev2 = false;
-  double t1 = 0.0, t2 = 0.0;  // epochs of z and zp
+  for (int i = 0; i < 5; ++i) {
+    hist.set(0, i, {0.0, 0.0});
+    hist.set(1, i, {0.0, 0.0});
+  }
+  bool have_prev = false, prev_deg4 = false, have_prev2 = false, have_prev3 = false;
+  double t1 = 0.0, t2 = 0.0, t3 = 0.0;  // epochs of z, zp and zpp
 
   for (int64_t s = 0; s < C; ++s) {
     const int64_t k = k0 + s;
@@ -631,24 +669,38 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
     cx<double> zeta, c[6];
     const bool deg4 = epoch_poly(x, t, zeta, c);
     const bool warm = have_prev && !deg4 && !prev_deg4;
-    // Linear extrapolation of every root from the two previous epochs,
-    // scaled by the ratio of epoch spacings (clamped to [0, 4]).
-    cx<double> zs[5];
+    // Warm start: quadratic (Lagrange in t) extrapolation of every root from
+    // the three previous epochs when the new epoch lies within their span,
+    // else linear from two, scaled by the ratio of epoch spacings (clamped to
+    // [0, 4]); the history shifts as it is used.
+    {
+      const bool ex2 = warm && have_prev2;
+      const double d12 = t1 - t2, d23 = t2 - t3, d13 = t1 - t3;
+      double w1 = 1.0, w2 = 0.0, w3 = 0.0;
+      if (ex2 && have_prev3 && d12 > 0.0 && d23 > 0.0 && (t - t1) <= d13) {
+        const double a1 = t - t1, a2 = t - t2, a3 = t - t3;
+        w1 = a2 * a3 * rcp_fast(d12 * d13);
+        w2 = -a1 * a3 * rcp_fast(d12 * d23);
+        w3 = a1 * a2 * rcp_fast(d13 * d23);
+      } else if (ex2 && d12 != 0.0) {
+        const double r = fmin(fmax((t - t1) / d12, 0.0), 4.0);
+        w1 = 1.0 + r;
+        w2 = -r;
+      }
 #pragma unroll
-    for (int i = 0; i < 5; ++i) zs[i] = z[i];
-    if (warm && have_prev2) {
-      const double gap = t1 - t2;
-      double r = gap != 0.0 ? (t - t1) / gap : 0.0;
-      r = fmin(fmax(r, 0.0), 4.0);
-#pragma unroll
-      for (int i = 0; i < 5; ++i)
-        z[i] = {fma(r, z[i].re - zp[i].re, z[i].re), fma(r, z[i].im - zp[i].im, z[i].im)};
+      for (int i = 0; i < 5; ++i) {
+        const cx<double> old = z[i], zp = hist.get(0, i), zpp = hist.get(1, i);
+        z[i] = {fma(w1, old.re, fma(w2, zp.re, w3 * zpp.re)),
+                fma(w1, old.im, fma(w2, zp.im, w3 * zpp.im))};
+        hist.set(1, i, zp);
+        hist.set(0, i, old);
+      }
     }
     bool ok;
     solve_roots<MODE>(c, deg4, warm, active, z, st, ok);
+    have_prev3 = have_prev2 && warm && ok;
     have_prev2 = warm && ok;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) zp[i] = zs[i];
+    t3 = t2;
     t2 = t1;
     t1 = t;
     have_prev = ok;
@@ -681,13 +733,18 @@ template <int MODE, bool CHI2, int G>
 __device__ __forceinline__ void fit_wave_async(const FitArgs& a, int64_t wave_item,
                                                LaneStats& st) {
   constexpr int MAXIT64 = 60, MAXIT32 = 30;
-  const double tau64 = 1e-16;
+  const double tau64 = SBLM_ROOT_TAU;
   const float tau32 = 1e-7f;
   const Item x = item_setup<G>(a, wave_item);
   Lsq ls = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  cx<double> z[5], zp[5], zpp[5];  // iterate; roots of the two epochs before
+  cx<double> z[5];  // iterate; the roots of the two epochs before are in LDS
+  const RootHist hist = {fit_dyn_smem};  // zp (slot 0), zpp (slot 1)
 #pragma unroll
-  for (int i = 0; i < 5; ++i) z[i] = zp[i] = zpp[i] = {0.0, 0.0};
+  for (int i = 0; i < 5; ++i) {
+    z[i] = {0.0, 0.0};
+    hist.set(0, i, {0.0, 0.0});
+    hist.set(1, i, {0.0, 0.0});
+  }
   int nhist = 0;  // solved epochs held in z (after convergence), zp, zpp
   double t1 = 0.0, t2 = 0.0, t3 = 0.0;
   bool prev_deg4 = false;
@@ -724,10 +781,11 @@ __device__ __forceinline__ void fit_wave_async(const FitArgs& a, int64_t wave_it
           }
 #pragma unroll
           for (int i = 0; i < 5; ++i) {
-            const cx<double> p = {fma(w1, z[i].re, fma(w2, zp[i].re, w3 * zpp[i].re)),
-                                  fma(w1, z[i].im, fma(w2, zp[i].im, w3 * zpp[i].im))};
-            zpp[i] = zp[i];
-            zp[i] = z[i];
+            const cx<double> zp = hist.get(0, i), zpp = hist.get(1, i);
+            const cx<double> p = {fma(w1, z[i].re, fma(w2, zp.re, w3 * zpp.re)),
+                                  fma(w1, z[i].im, fma(w2, zp.im, w3 * zpp.im))};
+            hist.set(1, i, zp);
+            hist.set(0, i, z[i]);
             z[i] = p;
           }
           t3 = t2;
@@ -868,6 +926,7 @@ __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitn
 template <int MODE, bool CHI2, int G>
 static hipError_t launch_gg(const FitArgs& a, hipStream_t s, int wpb) {
   if (wpb < 1 || 64 * wpb > SBLM_FIT_MAX_THREADS) return hipErrorInvalidConfiguration;
+  const size_t smem = ROOT_HIST_BYTES * 64 * wpb;
   const int64_t groups_per_block = (int64_t)wpb * (64 / G);
   int64_t nblk = (a.n_ind + groups_per_block - 1) / groups_per_block;
   if (nblk <= 0) return hipSuccess;
@@ -880,12 +939,12 @@ static hipError_t launch_gg(const FitArgs& a, hipStream_t s, int wpb) {
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wpb, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wpb, smem);
     if (e != hipSuccess) return e;
     const int64_t resident = (int64_t)(per_cu > 0 ? per_cu : 1) * ncu;
     nblk = nblk < resident ? nblk : resident;
   }
-  hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(64 * wpb), 0, s, a);
+  hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(64 * wpb), smem, s, a);
   return hipGetLastError();
 }
 

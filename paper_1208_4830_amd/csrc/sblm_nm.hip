@@ -318,9 +318,10 @@ int nm_run(const sblm_lcs& lcs, const double* lo, const double* span, const doub
   a.Fb = w.fbT;
   a.stats = stats;
   a.skip = w.done;
-  // a round is latency-bound unless the batch fills the GPU many times over:
-  // more lanes per individual shorten the longest lightcurve's chain
-  a.lanes_per_ind = ((int64_t)n * NS * 64 <= (int64_t)8 * 256 * 256) ? 64 : 16;
+  // rounds are latency-bound (each waits for its longest lightcurve, and
+  // later rounds hold only the unfinished simplices): 64 lanes per
+  // individual give the shortest chain of epochs per lane
+  a.lanes_per_ind = 64;
   const dim3 grid((n + 255) / 256), blk(256);
   if (rc == SBLM_OK) {
     hipLaunchKernelGGL(nm_start_kernel, grid, blk, 0, st, w, x0);
