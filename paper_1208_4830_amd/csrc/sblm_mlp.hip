@@ -66,7 +66,10 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 // LDS holds both tiles as [row = m or n][32 k] so every lane fetches its 8
 // consecutive k values with one 16-byte read (row stride padded to 40).
 // Epilogue: + bias[n], then * (mask[m][n] > 0), then ReLU, written as FP32
-// and/or BF16.  Requires M % 64 == 0, N % 64 == 0, K % 32 == 0.
+// and/or BF16.  Requires M % 64 == 0, N % 64 == 0, K % (32 * ksplit) == 0.
+// With ksplit > 1 (the weight gradients, a contraction over the batch) each
+// K range writes its own FP32 partial (no bias, mask or ReLU) and
+// splitk_reduce_kernel adds them in order.
 struct GemmArgs {
   const uint16_t* A;
   int64_t lda;
@@ -76,10 +79,11 @@ struct GemmArgs {
   const float* bias;     // [N] or null
   const uint16_t* mask;  // [M][ldm] BF16 or null
   int64_t ldm;
-  float* Cf;             // [M][ldc] or null
+  float* Cf;             // [M][ldc] or null (with ksplit > 1: [ksplit][M][ldc])
   uint16_t* Cb;          // [M][ldc] or null
   int64_t ldc;
   int relu;
+  int ksplit;            // K is cut into ksplit equal ranges (blockIdx.z), 0/1: none
 };
 
 constexpr int TM = 64, TK = 32, LDS_STRIDE = 40;
@@ -115,23 +119,24 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TM;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const int nst = g.K / TK;
+  const int nst = g.K / TK / gridDim.z;  // stages of this K range
+  const int kb = blockIdx.z * nst * TK;   // its first k
 
   f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 
   uint4 ra, rb;
-  load_tile<AK>(g.A, g.lda, m0, 0, ra);
-  load_tile<BK>(g.B, g.ldb, n0, 0, rb);
+  load_tile<AK>(g.A, g.lda, m0, kb, ra);
+  load_tile<BK>(g.B, g.ldb, n0, kb, rb);
   store_tile<AK>(sA[0], ra);
   store_tile<BK>(sB[0], rb);
   __syncthreads();
   for (int s = 0; s < nst; ++s) {
     const int cur = s & 1;
     if (s + 1 < nst) {
-      load_tile<AK>(g.A, g.lda, m0, (s + 1) * TK, ra);
-      load_tile<BK>(g.B, g.ldb, n0, (s + 1) * TK, rb);
+      load_tile<AK>(g.A, g.lda, m0, kb + (s + 1) * TK, ra);
+      load_tile<BK>(g.B, g.ldb, n0, kb + (s + 1) * TK, rb);
     }
     const uint16_t* pa = sA[cur] + (wm + (lane & 31)) * LDS_STRIDE + 8 * (lane >> 5);
     const uint16_t* pb = sB[cur] + (wn + (lane & 31)) * LDS_STRIDE + 8 * (lane >> 5);
@@ -160,13 +165,13 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
       if (h == 0 || (h & 0x8000u)) v = 0.0f;
     }
     if (g.relu) v = fmaxf(v, 0.0f);
-    if (g.Cf) g.Cf[(int64_t)m * g.ldc + n] = v;
+    if (g.Cf) g.Cf[(int64_t)blockIdx.z * g.M * g.ldc + (int64_t)m * g.ldc + n] = v;
     if (g.Cb) g.Cb[(int64_t)m * g.ldc + n] = f2bf(v);
   }
 }
 
 hipError_t gemm(const GemmArgs& g, bool ak, bool bk, hipStream_t st) {
-  const dim3 grid(g.N / TM, g.M / TM);
+  const dim3 grid(g.N / TM, g.M / TM, g.ksplit > 1 ? g.ksplit : 1);
   if (ak && !bk)
     hipLaunchKernelGGL((gemm_bf16_kernel<true, false>), grid, dim3(256), 0, st, g);
   else if (ak && bk)
@@ -180,100 +185,155 @@ hipError_t gemm(const GemmArgs& g, bool ak, bool bk, hipStream_t st) {
 
 // --------------------------------------------------- mixture likelihood
 //
-// One thread per sample.  Output row O = (8 logits, 8x7 means, 8x7 log
-// standard deviations, 8 pad); target row y[7], target 3 periodic on [0, 1).
-// loss_row = -log p(y)/n and dO = d loss / dO (pad entries 0), in FP64:
+// Eight threads per sample, thread k owning mixture component k.  Output row
+// O = (8 logits, 8x7 means, 8x7 log standard deviations, 8 pad); target row
+// y[7], target 3 periodic on [0, 1).  loss_row = -log p(y)/n and dO = d loss
+// / dO (pad entries 0), in FP64:
 //   log pi_k = logit_k - logsumexp(logit),  r_kd = y_d - mu_kd (wrapped),
 //   a_k = log pi_k + sum_d [-r^2/(2 s^2) - log s - log(2 pi)/2],
 //   gamma_k = exp(a_k - logsumexp(a)),
 //   dlogit_k = (pi_k - gamma_k)/n, dmu = -gamma r/s^2/n,
 //   dlog s = -gamma (r^2/s^2 - 1)/n.
-__global__ void mlp_nll_kernel(const float* O, const float* y, int n, float* dOf,
-                               uint16_t* dOb, float* loss_row) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n) return;
-  const float* o = O + (int64_t)b * NOP;
+// The maxima and sums over the eight components are butterflies inside each
+// group of eight lanes (a fixed order, so the result is deterministic).
+__device__ __forceinline__ double grp8_max(double v) {
+#pragma unroll
+  for (int m = 1; m < 8; m <<= 1) v = fmax(v, __shfl_xor(v, m, 8));
+  return v;
+}
+__device__ __forceinline__ double grp8_sum(double v) {
+#pragma unroll
+  for (int m = 1; m < 8; m <<= 1) v += __shfl_xor(v, m, 8);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void mlp_nll_kernel(const float* O, const float* y, int n,
+                                                      float* dOf, uint16_t* dOb,
+                                                      float* loss_row) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = gid >> 3, k = gid & 7;  // n * 8 threads, a multiple of 64
+  const bool valid = b < n;
+  const int bb = valid ? b : 0;
+  const float* o = O + (int64_t)bb * NOP;
   const double inv_n = 1.0 / (double)n;
   const double HALF_LOG_2PI = 0.91893853320467274178;
-  double yv[DM];
-  for (int d = 0; d < DM; ++d) yv[d] = (double)y[(int64_t)b * DM + d];
-  double lmax = (double)o[0];
-  for (int k = 1; k < KM; ++k) lmax = fmax(lmax, (double)o[k]);
-  double se = 0.0;
-  for (int k = 0; k < KM; ++k) se += exp((double)o[k] - lmax);
-  const double lse = lmax + log(se);
-  double a[KM];
-  double amax = -INFINITY;
-  for (int k = 0; k < KM; ++k) {
-    double s = (double)o[k] - lse;
-    for (int d = 0; d < DM; ++d) {
-      double r = yv[d] - (double)o[KM + k * DM + d];
-      if (d == MLP_PERIODIC) r -= floor(r + 0.5);
-      const double ls = (double)o[KM + KM * DM + k * DM + d];
-      const double s2 = exp(2.0 * ls);
-      s += -0.5 * r * r / s2 - ls - HALF_LOG_2PI;
-    }
-    a[k] = s;
-    amax = fmax(amax, s);
+  const double logit = (double)o[k];
+  const double lse_l = [&] {
+    const double m = grp8_max(logit);
+    return m + log(grp8_sum(exp(logit - m)));
+  }();
+  double r[DM], is2[DM];
+  double a = logit - lse_l;
+#pragma unroll
+  for (int d = 0; d < DM; ++d) {
+    double rr = (double)y[(int64_t)bb * DM + d] - (double)o[KM + k * DM + d];
+    if (d == MLP_PERIODIC) rr -= floor(rr + 0.5);
+    const double ls = (double)o[KM + KM * DM + k * DM + d];
+    is2[d] = exp(-2.0 * ls);
+    r[d] = rr;
+    a += -0.5 * rr * rr * is2[d] - ls - HALF_LOG_2PI;
   }
-  double sa = 0.0;
-  for (int k = 0; k < KM; ++k) sa += exp(a[k] - amax);
-  const double lp = amax + log(sa);
-  loss_row[b] = (float)(-lp * inv_n);
+  const double amax = grp8_max(a);
+  const double lp = amax + log(grp8_sum(exp(a - amax)));
+  const double gam = exp(a - lp);
+  const double pi = exp(logit - lse_l);
+  if (!valid) return;
+  if (k == 0) loss_row[b] = (float)(-lp * inv_n);
   float* gf = dOf + (int64_t)b * NOP;
   uint16_t* gb = dOb + (int64_t)b * NOP;
-  for (int k = 0; k < KM; ++k) {
-    const double gam = exp(a[k] - lp);
-    const double pi = exp((double)o[k] - lse);
-    const float gl = (float)((pi - gam) * inv_n);
-    gf[k] = gl;
-    gb[k] = f2bf(gl);
-    for (int d = 0; d < DM; ++d) {
-      double r = yv[d] - (double)o[KM + k * DM + d];
-      if (d == MLP_PERIODIC) r -= floor(r + 0.5);
-      const double ls = (double)o[KM + KM * DM + k * DM + d];
-      const double is2 = exp(-2.0 * ls);
-      const float gm = (float)(-gam * r * is2 * inv_n);
-      const float gs = (float)(-gam * (r * r * is2 - 1.0) * inv_n);
-      gf[KM + k * DM + d] = gm;
-      gb[KM + k * DM + d] = f2bf(gm);
-      gf[KM + KM * DM + k * DM + d] = gs;
-      gb[KM + KM * DM + k * DM + d] = f2bf(gs);
-    }
+  const float gl = (float)((pi - gam) * inv_n);
+  gf[k] = gl;
+  gb[k] = f2bf(gl);
+#pragma unroll
+  for (int d = 0; d < DM; ++d) {
+    const float gm = (float)(-gam * r[d] * is2[d] * inv_n);
+    const float gs = (float)(-gam * (r[d] * r[d] * is2[d] - 1.0) * inv_n);
+    gf[KM + k * DM + d] = gm;
+    gb[KM + k * DM + d] = f2bf(gm);
+    gf[KM + KM * DM + k * DM + d] = gs;
+    gb[KM + KM * DM + k * DM + d] = f2bf(gs);
   }
-  for (int c = NO; c < NOP; ++c) {
-    gf[c] = 0.0f;
-    gb[c] = 0;
-  }
+  gf[NO + k] = 0.0f;  // the eight pad columns
+  gb[NO + k] = 0;
 }
 
-// Column sums out[c] = sum_r X[r][c] for c < ncol, r < nrow: 32 columns by
-// 8 row chunks per block, chunks combined in a fixed order (deterministic).
-__global__ void colsum_kernel(const float* X, int64_t ld, int nrow, int ncol,
-                              float* out) {
-  __shared__ float part[8][32];
-  const int c = blockIdx.x * 32 + (threadIdx.x & 31);
-  const int chunk = threadIdx.x >> 5;
-  const int per = (nrow + 7) / 8;
-  float s = 0.0f;
-  if (c < ncol) {
-    const int r1 = min(nrow, (chunk + 1) * per);
-    for (int r = chunk * per; r < r1; ++r) s += X[(int64_t)r * ld + c];
-  }
-  part[chunk][threadIdx.x & 31] = s;
+// Column sums out[c] = sum_r X[r][c] of up to four matrices in one pair of
+// launches (bias gradients and the loss).  Stage 1: block (column tile of
+// 64, row chunk rc) sums its rows in four interleaved groups combined in a
+// fixed order into part[rc][column]; stage 2 adds the RC chunks in order.
+// Deterministic.
+constexpr int CS_RC = 16;
+struct ColSeg {
+  const float* X;
+  int64_t ld;
+  int ncol;
+  float* out;
+};
+struct ColSegs {
+  ColSeg s[4];
+  int nseg;
+  int tile0[5];  // first 64-column tile of each segment
+  int col0[5];   // first column of each segment in the partial array
+  int nrow;
+};
+
+__global__ __launch_bounds__(256) void colsum_stage1(ColSegs cs, float* part, int ncol_all) {
+  __shared__ float red[4][64];
+  int sg = 0;
+  while (sg + 1 < cs.nseg && (int)blockIdx.x >= cs.tile0[sg + 1]) ++sg;
+  const ColSeg& g = cs.s[sg];
+  const int c = ((int)blockIdx.x - cs.tile0[sg]) * 64 + (threadIdx.x & 63);
+  const int grp = threadIdx.x >> 6;
+  const int per = (cs.nrow + CS_RC - 1) / CS_RC;
+  const int r0 = blockIdx.y * per, r1 = min(cs.nrow, r0 + per);
+  float acc = 0.0f;
+  if (c < g.ncol)
+    for (int r = r0 + grp; r < r1; r += 4) acc += g.X[(int64_t)r * g.ld + c];
+  red[grp][threadIdx.x & 63] = acc;
   __syncthreads();
-  if (chunk == 0 && c < ncol) {
-    float t = part[0][threadIdx.x];
-    for (int j = 1; j < 8; ++j) t += part[j][threadIdx.x];
-    out[c] = t;
+  if (grp == 0 && c < g.ncol) {
+    const int j = threadIdx.x;
+    part[(int64_t)blockIdx.y * ncol_all + cs.col0[sg] + c] =
+        ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
   }
 }
 
-hipError_t colsum(const float* X, int64_t ld, int nrow, int ncol, float* out,
-                  hipStream_t st) {
-  hipLaunchKernelGGL(colsum_kernel, dim3((ncol + 31) / 32), dim3(256), 0, st, X, ld,
-                     nrow, ncol, out);
+__global__ void colsum_stage2(ColSegs cs, const float* part, int ncol_all) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol_all) return;
+  int sg = 0;
+  while (sg + 1 < cs.nseg && c >= cs.col0[sg + 1]) ++sg;
+  float t = part[c];
+  for (int rc = 1; rc < CS_RC; ++rc) t += part[(int64_t)rc * ncol_all + c];
+  cs.s[sg].out[c - cs.col0[sg]] = t;
+}
+
+// part must hold CS_RC x (total columns) floats.
+hipError_t colsums(ColSegs cs, float* part, hipStream_t st) {
+  cs.tile0[0] = 0;
+  cs.col0[0] = 0;
+  for (int i = 0; i < cs.nseg; ++i) {
+    cs.tile0[i + 1] = cs.tile0[i] + (cs.s[i].ncol + 63) / 64;
+    cs.col0[i + 1] = cs.col0[i] + cs.s[i].ncol;
+  }
+  const int ncol_all = cs.col0[cs.nseg];
+  hipLaunchKernelGGL(colsum_stage1, dim3(cs.tile0[cs.nseg], CS_RC), dim3(256), 0, st, cs, part,
+                     ncol_all);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(colsum_stage2, dim3((ncol_all + 255) / 256), dim3(256), 0, st, cs, part,
+                     ncol_all);
   return hipGetLastError();
+}
+
+// Sum of ks partial matrices part[z][i], z in order (split-K reduction).
+__global__ void splitk_reduce_kernel(const float* part, int ks, int64_t n, float* out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float t = part[i];
+    for (int z = 1; z < ks; ++z) t += part[(int64_t)z * n + i];
+    out[i] = t;
+  }
 }
 
 // Adam (Kingma & Ba 2015) with bias correction factors c1 = 1/(1 - b1^t),
@@ -587,11 +647,17 @@ struct mlp_net {
   float *dz2f = nullptr, *dz1f = nullptr;  // [batch_max][512]
   uint16_t *dz2b = nullptr, *dz1b = nullptr;
   float* lrow = nullptr;      // [batch_max]
+  float* kpart = nullptr;     // split-K partials, [KSPLIT_MAX][512 * 512]
+  float* cpart = nullptr;     // column-sum partials, [CS_RC][COLS_ALL]
 };
 
+constexpr int KSPLIT_MAX = 8;
+constexpr int COLS_ALL = NOP + NH + NH + 1;  // b3, b2, b1 gradients and the loss
+
 static void net_free(mlp_net* n) {
-  void* ptrs[] = {n->p, n->g, n->m, n->v, n->pb, n->xbuf, n->h1, n->h2, n->o,
-                  n->dof, n->dob, n->dz2f, n->dz1f, n->dz2b, n->dz1b, n->lrow};
+  void* ptrs[] = {n->p,    n->g,    n->m,    n->v,    n->pb,   n->xbuf,
+                  n->h1,   n->h2,   n->o,    n->dof,  n->dob,  n->dz2f,
+                  n->dz1f, n->dz2b, n->dz1b, n->lrow, n->kpart, n->cpart};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -631,7 +697,9 @@ extern "C" int mlp_create(int32_t batch_max, uint64_t seed, mlp_net** out) {
             hipMalloc(&n->dz1f, B * NH * 4) == hipSuccess &&
             hipMalloc(&n->dz2b, B * NH * 2) == hipSuccess &&
             hipMalloc(&n->dz1b, B * NH * 2) == hipSuccess &&
-            hipMalloc(&n->lrow, B * 4) == hipSuccess;
+            hipMalloc(&n->lrow, B * 4) == hipSuccess &&
+            hipMalloc(&n->kpart, (size_t)KSPLIT_MAX * NH * NH * 4) == hipSuccess &&
+            hipMalloc(&n->cpart, (size_t)CS_RC * COLS_ALL * 4) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     net_free(n);
@@ -781,7 +849,7 @@ static hipError_t loss_grad(mlp_net* n, const uint16_t* x, const float* y, int r
                             float* loss, hipStream_t st) {
   hipError_t e = forward_rows(n, x, rows, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(mlp_nll_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, n->o, y,
+  hipLaunchKernelGGL(mlp_nll_kernel, dim3((rows * 8 + 255) / 256), dim3(256), 0, st, n->o, y,
                      rows, n->dof, n->dob, n->lrow);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   GemmArgs g;
@@ -795,21 +863,38 @@ static hipError_t loss_grad(mlp_net* n, const uint16_t* x, const float* y, int r
   g.A = n->dz2b; g.lda = NH; g.B = n->pb + OFF_W2; g.ldb = NH; g.K = NH;
   g.mask = n->h1; g.Cf = n->dz1f; g.Cb = n->dz1b;
   if ((e = gemm(g, true, true, st)) != hipSuccess) return e;
-  // weight gradients: gW = (layer input)^T dZ, contraction over the batch
-  memset(&g, 0, sizeof(g));
-  g.A = n->h2; g.lda = NH; g.B = n->dob; g.ldb = NOP;
-  g.M = NH; g.N = NOP; g.K = rows; g.Cf = n->g + OFF_W3; g.ldc = NOP;
-  if ((e = gemm(g, false, false, st)) != hipSuccess) return e;
-  g.A = n->h1; g.lda = NH; g.B = n->dz2b; g.ldb = NH; g.N = NH;
-  g.Cf = n->g + OFF_W2; g.ldc = NH;
-  if ((e = gemm(g, false, false, st)) != hipSuccess) return e;
-  g.A = x; g.lda = NB; g.B = n->dz1b; g.M = NB; g.Cf = n->g + OFF_W1;
-  if ((e = gemm(g, false, false, st)) != hipSuccess) return e;
-  if ((e = colsum(n->dof, NOP, rows, NOP, n->g + OFF_B3, st)) != hipSuccess) return e;
-  if ((e = colsum(n->dz2f, NH, rows, NH, n->g + OFF_B2, st)) != hipSuccess) return e;
-  if ((e = colsum(n->dz1f, NH, rows, NH, n->g + OFF_B1, st)) != hipSuccess) return e;
-  if (loss) e = colsum(n->lrow, 1, rows, 1, loss, st);
-  return e;
+  // weight gradients: gW = (layer input)^T dZ, a contraction over the batch,
+  // cut into K ranges of at least 128 rows (more workgroups, shorter chains)
+  int ks = 1;
+  while (ks < KSPLIT_MAX && rows % (64 * ks) == 0 && rows / (2 * ks) >= 128) ks *= 2;
+  struct { const uint16_t* A; int64_t lda; const uint16_t* B; int64_t ldb; int M, N;
+           float* out; } wg[3] = {
+      {n->h2, NH, n->dob, NOP, NH, NOP, n->g + OFF_W3},
+      {n->h1, NH, n->dz2b, NH, NH, NH, n->g + OFF_W2},
+      {x, NB, n->dz1b, NH, NB, NH, n->g + OFF_W1}};
+  for (int i = 0; i < 3; ++i) {
+    memset(&g, 0, sizeof(g));
+    g.A = wg[i].A; g.lda = wg[i].lda; g.B = wg[i].B; g.ldb = wg[i].ldb;
+    g.M = wg[i].M; g.N = wg[i].N; g.K = rows; g.ldc = wg[i].N; g.ksplit = ks;
+    g.Cf = ks > 1 ? n->kpart : wg[i].out;
+    if ((e = gemm(g, false, false, st)) != hipSuccess) return e;
+    if (ks > 1) {
+      const int64_t mn = (int64_t)g.M * g.N;
+      hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for(mn)), dim3(256), 0, st, n->kpart,
+                         ks, mn, wg[i].out);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  // bias gradients and the loss
+  ColSegs cs;
+  memset(&cs, 0, sizeof(cs));
+  cs.s[0] = {n->dof, NOP, NOP, n->g + OFF_B3};
+  cs.s[1] = {n->dz2f, NH, NH, n->g + OFF_B2};
+  cs.s[2] = {n->dz1f, NH, NH, n->g + OFF_B1};
+  cs.s[3] = {n->lrow, 1, 1, loss ? loss : n->cpart};  // unused slot when no loss
+  cs.nseg = loss ? 4 : 3;
+  cs.nrow = rows;
+  return colsums(cs, n->cpart, st);
 }
 
 extern "C" int mlp_loss_grad(mlp_net* n, const uint16_t* x, const float* y, int32_t rows,
