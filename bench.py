@@ -93,6 +93,8 @@ def parse():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device 4 times (a kernel of "
                          "known traffic that scales the profiler's byte counters)")
+    ap.add_argument("--train-network", action="store_true",
+                    help="train the proposal network even when no success run uses it")
     ap.add_argument("--mlp-samples", type=int, default=1 << 20)
     ap.add_argument("--mlp-epochs", type=int, default=16)
     return ap.parse_args()
@@ -356,9 +358,26 @@ def cpu_baseline(wl, y, w, pop, target_s):
     n_lcs = min(wl.n_lc, max(1, n_ind // pop))
     per = max(1, n_ind // n_lcs)
     dt, mags = run(per, n_lcs)
+    # one core on a smaller sample (about a fifth of the wall time)
+    n1 = max(1, int(0.2 * target_s * rate / nthreads / 1000))
+    t0 = time.perf_counter()
+    off1 = wl.off[:2]
+    th1 = inputs.draw_theta(rng, n1)
+    O.chi2(off1, wl.t[:int(off1[1])], y[:int(off1[1])], w[:int(off1[1])], th1, n1, nthreads=1)
+    dt1 = time.perf_counter() - t0
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=mags / dt, unit="magnifications/s", cores=nthreads, kind="oracle",
                 sample=f"{n_lcs} lightcurves x {per} individuals x {int(wl.off[1])} epochs "
-                       f"({mags} magnifications + chi^2, {dt:.1f} s)")
+                       f"({mags} magnifications + chi^2, {dt:.1f} s)",
+                one_core_value=n1 * int(off1[1]) / dt1,
+                one_core_sample=f"1 lightcurve x {n1} individuals x {int(off1[1])} epochs "
+                                f"({dt1:.1f} s)",
+                host_cpus=os.cpu_count(), cpu_model=cpu_model)
 
 
 def main():
@@ -400,7 +419,7 @@ def main():
     lo, hi = inputs.PRIOR_LO, inputs.PRIOR_HI  # the default EA domain
     sched = tuple(main_form["schedule"].values())
     net = train_info = None
-    if args.success_max_gen > 0 or args.learned_gens > 0:
+    if args.success_max_gen > 0 or args.learned_gens > 0 or args.train_network:
         log("bench: training the proposal network on generated lightcurves")
         net, train_info = train_proposals(sblm, torch, args)
         log(f"bench: training: {json.dumps(train_info)}")
