@@ -58,13 +58,14 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 //
 // C[M][N] = A[M][K] * B[K][N] on BF16 operands with FP32 accumulation in
 // the 32x32x16 matrix-core instruction.  A workgroup of four waves owns a
-// 64x64 tile of C (2x2 waves of 32x32); K advances in stages of 32 staged
-// through LDS (double-buffered, one barrier per stage), each stage two MFMA
-// per wave.  Operands are read from either layout:
+// 64x64 tile of C (2x2 waves of 32x32); K advances through LDS
+// (double-buffered, one barrier per stage) in stages of TKS = 128 (32 when
+// K per range is not a multiple of 128), TKS/16 MFMA per wave and stage.
+// Operands are read from either layout:
 //   AK: A[m*lda + k] (k contiguous)   else A[k*lda + m]
 //   BK: B[n*ldb + k] (k contiguous)   else B[k*ldb + n]
-// LDS holds both tiles as [row = m or n][32 k] so every lane fetches its 8
-// consecutive k values with one 16-byte read (row stride padded to 40).
+// LDS holds both tiles as [row = m or n][TKS k] so every lane fetches its 8
+// consecutive k values with one 16-byte read (row stride padded by 8).
 // Epilogue: + bias[n], then * (mask[m][n] > 0), then ReLU, written as FP32
 // and/or BF16.  Requires M % 64 == 0, N % 64 == 0, K % (32 * ksplit) == 0.
 // With ksplit > 1 (the weight gradients, a contraction over the batch) each
@@ -86,69 +87,83 @@ struct GemmArgs {
   int ksplit;            // K is cut into ksplit equal ranges (blockIdx.z), 0/1: none
 };
 
-constexpr int TM = 64, TK = 32, LDS_STRIDE = 40;
+constexpr int TM = 64;
 
-template <bool KC>
-__device__ __forceinline__ void load_tile(const uint16_t* X, int64_t ld, int r0,
-                                          int k0, uint4& v) {
+// One K stage of a 64-row operand tile: TKS k values per row, TKS/32 chunks
+// of 8 BF16 (16 bytes) per thread, all loads issued before any is used.
+template <bool KC, int TKS>
+__device__ __forceinline__ void load_tile(const uint16_t* X, int64_t ld, int r0, int k0,
+                                          uint4* v) {
   const int t = threadIdx.x;
-  if (KC) {
-    v = *(const uint4*)(X + (int64_t)(r0 + (t >> 2)) * ld + k0 + (t & 3) * 8);
-  } else {
-    v = *(const uint4*)(X + (int64_t)(k0 + (t >> 3)) * ld + r0 + (t & 7) * 8);
-  }
-}
-
-template <bool KC>
-__device__ __forceinline__ void store_tile(uint16_t* S, const uint4& v) {
-  const int t = threadIdx.x;
-  if (KC) {
-    *(uint4*)(S + (t >> 2) * LDS_STRIDE + (t & 3) * 8) = v;
-  } else {
-    const int k = t >> 3, r = (t & 7) * 8;
-    const uint16_t* e = (const uint16_t*)&v;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) S[(r + i) * LDS_STRIDE + k] = e[i];
+  for (int j = 0; j < TKS / 32; ++j) {
+    const int q = t + 256 * j;  // chunk index
+    if (KC) {  // row q / (TKS/8), k chunk q % (TKS/8)
+      v[j] = *(const uint4*)(X + (int64_t)(r0 + q / (TKS / 8)) * ld + k0 + (q % (TKS / 8)) * 8);
+    } else {   // k row q / 8, 8 consecutive rows from (q % 8) * 8
+      v[j] = *(const uint4*)(X + (int64_t)(k0 + q / 8) * ld + r0 + (q % 8) * 8);
+    }
   }
 }
 
-template <bool AK, bool BK>
+template <bool KC, int TKS>
+__device__ __forceinline__ void store_tile(uint16_t* S, const uint4* v) {
+  constexpr int STRIDE = TKS + 8;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < TKS / 32; ++j) {
+    const int q = t + 256 * j;
+    if (KC) {
+      *(uint4*)(S + (q / (TKS / 8)) * STRIDE + (q % (TKS / 8)) * 8) = v[j];
+    } else {
+      const int k = q / 8, r = (q % 8) * 8;
+      const uint16_t* e = (const uint16_t*)&v[j];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) S[(r + i) * STRIDE + k] = e[i];
+    }
+  }
+}
+
+// TKS: k values per LDS stage (32 or 128); deeper stages keep more loads in
+// flight per round trip, which is what bounds these small GEMMs.
+template <bool AK, bool BK, int TKS>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) uint16_t sA[2][TM * LDS_STRIDE];
-  __shared__ __attribute__((aligned(16))) uint16_t sB[2][TM * LDS_STRIDE];
+  constexpr int STRIDE = TKS + 8;  // padded LDS row (elements)
+  __shared__ __attribute__((aligned(16))) uint16_t sA[2][TM * STRIDE];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[2][TM * STRIDE];
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TM;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const int nst = g.K / TK / gridDim.z;  // stages of this K range
-  const int kb = blockIdx.z * nst * TK;   // its first k
+  const int nst = g.K / TKS / gridDim.z;  // stages of this K range
+  const int kb = blockIdx.z * nst * TKS;  // its first k
 
   f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 
-  uint4 ra, rb;
-  load_tile<AK>(g.A, g.lda, m0, kb, ra);
-  load_tile<BK>(g.B, g.ldb, n0, kb, rb);
-  store_tile<AK>(sA[0], ra);
-  store_tile<BK>(sB[0], rb);
+  uint4 ra[TKS / 32], rb[TKS / 32];
+  load_tile<AK, TKS>(g.A, g.lda, m0, kb, ra);
+  load_tile<BK, TKS>(g.B, g.ldb, n0, kb, rb);
+  store_tile<AK, TKS>(sA[0], ra);
+  store_tile<BK, TKS>(sB[0], rb);
   __syncthreads();
   for (int s = 0; s < nst; ++s) {
     const int cur = s & 1;
     if (s + 1 < nst) {
-      load_tile<AK>(g.A, g.lda, m0, kb + (s + 1) * TK, ra);
-      load_tile<BK>(g.B, g.ldb, n0, kb + (s + 1) * TK, rb);
+      load_tile<AK, TKS>(g.A, g.lda, m0, kb + (s + 1) * TKS, ra);
+      load_tile<BK, TKS>(g.B, g.ldb, n0, kb + (s + 1) * TKS, rb);
     }
-    const uint16_t* pa = sA[cur] + (wm + (lane & 31)) * LDS_STRIDE + 8 * (lane >> 5);
-    const uint16_t* pb = sB[cur] + (wn + (lane & 31)) * LDS_STRIDE + 8 * (lane >> 5);
+    const uint16_t* pa = sA[cur] + (wm + (lane & 31)) * STRIDE + 8 * (lane >> 5);
+    const uint16_t* pb = sB[cur] + (wn + (lane & 31)) * STRIDE + 8 * (lane >> 5);
 #pragma unroll
-    for (int kk = 0; kk < TK; kk += 16) {
+    for (int kk = 0; kk < TKS; kk += 16) {
       const bf16x8 a = *(const bf16x8*)(pa + kk);
       const bf16x8 b = *(const bf16x8*)(pb + kk);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
     if (s + 1 < nst) {
-      store_tile<AK>(sA[cur ^ 1], ra);
-      store_tile<BK>(sB[cur ^ 1], rb);
+      store_tile<AK, TKS>(sA[cur ^ 1], ra);
+      store_tile<BK, TKS>(sB[cur ^ 1], rb);
     }
     __syncthreads();
   }
@@ -170,17 +185,23 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
   }
 }
 
-hipError_t gemm(const GemmArgs& g, bool ak, bool bk, hipStream_t st) {
+template <int TKS>
+hipError_t gemm_t(const GemmArgs& g, bool ak, bool bk, hipStream_t st) {
   const dim3 grid(g.N / TM, g.M / TM, g.ksplit > 1 ? g.ksplit : 1);
   if (ak && !bk)
-    hipLaunchKernelGGL((gemm_bf16_kernel<true, false>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<true, false, TKS>), grid, dim3(256), 0, st, g);
   else if (ak && bk)
-    hipLaunchKernelGGL((gemm_bf16_kernel<true, true>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<true, true, TKS>), grid, dim3(256), 0, st, g);
   else if (!ak && !bk)
-    hipLaunchKernelGGL((gemm_bf16_kernel<false, false>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<false, false, TKS>), grid, dim3(256), 0, st, g);
   else
-    hipLaunchKernelGGL((gemm_bf16_kernel<false, true>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<false, true, TKS>), grid, dim3(256), 0, st, g);
   return hipGetLastError();
+}
+
+hipError_t gemm(const GemmArgs& g, bool ak, bool bk, hipStream_t st) {
+  const int ks = g.ksplit > 1 ? g.ksplit : 1;
+  return (g.K / ks) % 128 == 0 ? gemm_t<128>(g, ak, bk, st) : gemm_t<32>(g, ak, bk, st);
 }
 
 // --------------------------------------------------- mixture likelihood
