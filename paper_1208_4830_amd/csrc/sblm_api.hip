@@ -29,12 +29,12 @@ int check_hip(hipError_t e, const char* what) {
 // consecutive epochs, so a smaller share of its solves start cold; on the
 // MI355X 16 lanes per individual were fastest for 1000-epoch lightcurves
 // (17.9 vs 16.8 and 15.4 Gmag/s for 32 and 64).  Overridable with
-// SBLM_LANES (16, 32 or 64) for tuning runs.
+// SBLM_LANES (8, 16, 32 or 64) for tuning runs.
 static int choose_group(double mean_len) {
   const char* env = getenv("SBLM_LANES");
   if (env) {
     int g = atoi(env);
-    if (g == 16 || g == 32 || g == 64) return g;
+    if (g == 8 || g == 16 || g == 32 || g == 64) return g;
   }
   (void)mean_len;
   return 16;

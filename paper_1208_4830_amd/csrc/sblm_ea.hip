@@ -816,7 +816,7 @@ extern "C" int ea_get_schedule(ea_state* st, int32_t* sched) {
 
 extern "C" int ea_set_schedule(ea_state* st, const int32_t* sched) {
   if (!st || !sched) return set_error(SBLM_EINVAL, "ea_set_schedule: null argument");
-  if ((sched[0] != 16 && sched[0] != 32 && sched[0] != 64) ||
+  if ((sched[0] != 8 && sched[0] != 16 && sched[0] != 32 && sched[0] != 64) ||
       (sched[1] != 1 && sched[1] != 2 && sched[1] != 4) || (sched[2] != 0 && sched[2] != 1) ||
       (sched[3] != 0 && sched[3] != 1))
     return set_error(SBLM_EINVAL, "ea_set_schedule: bad schedule (%d, %d, %d, %d)", sched[0],
@@ -864,11 +864,11 @@ extern "C" int ea_autotune(ea_state* st, char* report, size_t report_len, void* 
   // per individual, waves per block, persistent vs one-shot grid
   int best[4] = {s.lanes, s.wpb, s.persistent, s.async};
   float best_ms = INFINITY;
-  const int lanes_c[3] = {16, 32, 64}, wpb_c[3] = {1, 2, 4}, bin_c[2] = {1, 0};
+  const int lanes_c[4] = {8, 16, 32, 64}, wpb_c[3] = {1, 2, 4}, bin_c[2] = {1, 0};
   const int stage_field[4] = {3, 0, 1, 2};
   for (int stage = 0; stage < 4 && !rc; ++stage) {
     const int field = stage_field[stage];
-    const int nc = (field == 0 || field == 1) ? 3 : 2;
+    const int nc = field == 0 ? 4 : (field == 1 ? 3 : 2);
     for (int k = 0; k < nc && !rc; ++k) {
       int cand[4] = {best[0], best[1], best[2], best[3]};
       cand[field] = field == 0 ? lanes_c[k] : (field == 1 ? wpb_c[k] : bin_c[k]);

@@ -952,6 +952,7 @@ template <int MODE, bool CHI2>
 static hipError_t launch_g(const FitArgs& a, hipStream_t s, int wpb) {
   if (a.lanes_per_ind == 64) return launch_gg<MODE, CHI2, 64>(a, s, wpb);
   if (a.lanes_per_ind == 32) return launch_gg<MODE, CHI2, 32>(a, s, wpb);
+  if (a.lanes_per_ind == 8) return launch_gg<MODE, CHI2, 8>(a, s, wpb);
   return launch_gg<MODE, CHI2, 16>(a, s, wpb);
 }
 

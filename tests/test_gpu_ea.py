@@ -180,7 +180,7 @@ def test_schedules_agree_and_autotune(hip):
     pop = 32
     blobs = {}
     for sched in [(16, 4, 1, 1), (16, 2, 0, 1), (16, 1, 1, 1), (16, 4, 1, 0), (16, 2, 0, 0),
-                  (32, 4, 1, 1), (64, 2, 0, 0)]:
+                  (32, 4, 1, 1), (64, 2, 0, 0), (8, 4, 1, 0), (8, 1, 0, 0), (8, 2, 1, 1)]:
         st, y, w = _make_state(hip, wl, pop, seed=21)
         st.set_schedule(*sched)
         assert st.schedule() == sched
@@ -198,11 +198,13 @@ def test_schedules_agree_and_autotune(hip):
     ref = blobs[(16, 4, 1, 1)]
     assert blobs[(16, 2, 0, 1)] == ref and blobs[(16, 1, 1, 1)] == ref
     assert blobs[(16, 2, 0, 0)] == blobs[(16, 4, 1, 0)]
+    assert blobs[(8, 1, 0, 0)] == blobs[(8, 4, 1, 0)]
     st, _, _ = _make_state(hip, wl, pop, seed=21)
     rep = st.autotune()
-    assert "chosen:" in rep and len(rep.splitlines()) == 11
+    # 2 stepping + 4 lanes + 3 waves-per-block + 2 launch-form candidates
+    assert "chosen:" in rep and len(rep.splitlines()) == 12
     lanes, wpb, pers, asy = st.schedule()
-    assert lanes in (16, 32, 64) and wpb in (1, 2, 4) and pers in (0, 1) and asy in (0, 1)
+    assert lanes in (8, 16, 32, 64) and wpb in (1, 2, 4) and pers in (0, 1) and asy in (0, 1)
     with pytest.raises(hip.SblmError):  # blocks beyond the kernels' bound
         st.set_schedule(16, 8, 1)
     st.fit(6)
