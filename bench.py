@@ -390,7 +390,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the fit shards by "
-                          "lightcurve and multi-GPU runs are not part of this build",
+                          "lightcurve, and no multi-GPU path is implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
