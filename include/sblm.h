@@ -283,7 +283,7 @@ int ea_load(ea_state* st, const void* buf, size_t len, void* stream);
 void ea_destroy(ea_state* st);
 
 /* ---------------------------------------------------------------------- */
-/* Simplex fine-tuning ("EA with amoeba", Sec. 3.1, Tables 2-3)            */
+/* Simplex fine-tuning ("EA with amoeba", Sec. 4.1, Tables 2-3)            */
 /* ---------------------------------------------------------------------- */
 /*
  * The downhill simplex of Nelder & Mead (1965) in the form of Lagarias,
@@ -345,7 +345,7 @@ int ea_refine(ea_state* st, const nm_config* cfg, int32_t* n_iter, sblm_stats* s
 /* Learned proposal network                                                */
 /* ---------------------------------------------------------------------- */
 /*
- * Not part of the paper's method: its neural-network approach (Sec. 1) is a
+ * Not part of the paper's method: its neural-network approach (Sec. 4.1) is a
  * competing fitter, whereas this network only proposes starting points for
  * part of the initial population; the EA's chi^2 (Sec. 4.1, 4.4) judges them
  * like any other individual and the uniform rows (Sec. A.1) remain.

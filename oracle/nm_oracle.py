@@ -3,7 +3,7 @@ Wright & Wright (1998) -- TEST INFRASTRUCTURE, the reference of the GPU
 simplex refinement.
 
 The paper fine-tunes the fittest solution of the EA with the amoeba method
-(its Sec. 3.1, "EA with amoeba" in Tables 2 and 3), using the Lagarias et
+(its Sec. 4.1, "EA with amoeba" in Tables 2 and 3), using the Lagarias et
 al. algorithm, without stating its settings.  Here it runs in the EA's
 encoded domain [0, 1]^6 (Eq. EMMA-encoding) with the customary settings of
 that algorithm:

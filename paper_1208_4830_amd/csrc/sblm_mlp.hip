@@ -1,7 +1,7 @@
 // sblm_mlp.hip -- learned proposal network for seeding the EA population.
 //
 // Not part of the paper's method (its neural network is a competing fitter,
-// Sec. 1); the network only proposes starting points, and the EA's chi^2
+// Sec. 4.1); the network only proposes starting points, and the EA's chi^2
 // (Sec. 4.1, 4.4) stays the judge.  Contents:
 //   * sblm_resample: a lightcurve -> 256 normalised bins;
 //   * mlp_make_data: training lightcurves drawn from the EA's parameter

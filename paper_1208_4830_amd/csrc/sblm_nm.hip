@@ -1,5 +1,5 @@
 // sblm_nm.hip -- batched downhill-simplex refinement, one simplex per
-// lightcurve (the amoeba fine-tuning of the EA's fittest solution, Sec. 3.1
+// lightcurve (the amoeba fine-tuning of the EA's fittest solution, Sec. 4.1
 // and the "EA with amoeba" rows of Tables 2-3; method of Nelder & Mead 1965
 // in the form of Lagarias, Reeds, Wright & Wright 1998).
 //
