@@ -386,6 +386,49 @@ def cpu_baseline(wl, y, w, pop, target_s):
                 host_cpus=os.cpu_count(), cpu_model=cpu_model)
 
 
+def single_fit(sblm, torch, nthreads):
+    """The single-lightcurve configuration in full (400 uniform epochs over
+    t0 +- 2 tE, sigma = 1% of the flux, population 48, 100 generations): on
+    the GPU (one graph per generation) and with the CPU oracle (its chi^2 on
+    `nthreads` threads and its EA generation), same seeds."""
+    import oracle as O
+    from paper_1208_4830_amd import inputs
+    wl = inputs.uniform_workload(1, 1, 400)
+    A, _ = O.magnify(wl.theta, wl.t)  # observations from the oracle's forward model
+    F = wl.Fs[0] * A[0] + wl.Fb[0]
+    sig = wl.sfrac * F
+    y, w = F + sig * wl.noise, 1.0 / sig ** 2
+    pop, gens, seed = 48, 100, 3
+    lo, hi = inputs.PRIOR_LO, inputs.PRIOR_HI
+    c_true = O.chi2(wl.off, wl.t, y, w, wl.theta, 1, nthreads=1)[0][0]
+    cu = lambda a, dt=torch.float64: torch.as_tensor(a, dtype=dt, device="cuda")
+    lcs = sblm.Lightcurves(cu(wl.off, torch.int64), cu(wl.t), cu(y), cu(w))
+    cfg = sblm.ea_default_config()
+    cfg.pop = pop
+    st = sblm.EAState(cfg, lcs, seed)
+    st.fit(2)  # warm-up (graph, code objects)
+    st.close()
+    st = sblm.EAState(cfg, lcs, seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.fit(gens)
+    torch.cuda.synchronize()
+    gpu_s = time.perf_counter() - t0
+    gpu_best = st.summary()[0].best_chi2
+    st.close()
+    ea = O.EA(pop, seed, 0)
+    t0 = time.perf_counter()
+    for _ in range(gens):
+        th = O.decode(ea.P.T.copy(), lo, hi)
+        c, fs, fb = O.chi2(wl.off, wl.t, y, w, th, pop, nthreads=nthreads)
+        ea.generation(c, fs, fb)
+    cpu_s = time.perf_counter() - t0
+    return dict(workload="1 lightcurve x 400 uniform epochs, pop 48, 100 generations",
+                gpu_seconds=gpu_s, cpu_seconds=cpu_s, cpu_threads=nthreads,
+                gpu_best_chi2=gpu_best, cpu_best_chi2=ea.summary()["best_chi2"],
+                chi2_true=c_true)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -472,6 +515,7 @@ def main():
     if not args.no_cpu:
         log("bench: CPU oracle sample")
         cpu = cpu_baseline(wl, y, w, args.pop, args.cpu_seconds)
+        cpu["single_fit"] = single_fit(sblm, torch, cpu["cores"])
         log(f"bench: cpu {json.dumps(cpu)}")
 
     out = {
