@@ -51,7 +51,7 @@ N_GEN_FIT = 500
 # workload and schedule, from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a
 # copy kernel of known size (profiles/fitness_kernel_fp64_256lc_1000ep_pop256_
 # traffic.md).  Valid only for the kernel source it was taken on.
-FITNESS_TRAFFIC = dict(source_sha256_16="d8795810461084dd", bytes_per_launch=63.05e6,
+FITNESS_TRAFFIC = dict(source_sha256_16="25e0af193c65df2f", bytes_per_launch=63.07e6,
                        algorithmic_bytes_per_launch=10.86e6)
 
 
@@ -90,6 +90,9 @@ def parse():
                     help="generations of the plain-vs-learned comparison on the ragged "
                          "workload (0 = skip it)")
     ap.add_argument("--learned-every", type=int, default=100)
+    ap.add_argument("--islands", default="8,50,2",
+                    help="island form for the success comparison: islands,migrate every,"
+                         "migrants (empty: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device 4 times (a kernel of "
                          "known traffic that scales the profiler's byte counters)")
@@ -201,7 +204,7 @@ def run_form(sblm, torch, lcs, wl, chi2_true, pop, steps, args, mode, tune=True)
 
 
 def success_run(sblm, torch, lcs, chi2_true, pop, mode, sched, lo, hi, proposals=None,
-                max_gen=1600, every=100, target=0.9, seed=7, passes=3):
+                max_gen=1600, every=100, target=0.9, seed=7, passes=3, islands=None):
     """EA with optional proposal seeding; at every checkpoint the fittest
     solution of each lightcurve is fine-tuned by `passes` simplex passes, each
     restarted from the last (on a copy: the EA continues untouched), as the
@@ -210,10 +213,17 @@ def success_run(sblm, torch, lcs, chi2_true, pop, mode, sched, lo, hi, proposals
     and with them the EA's path, so a fixed schedule makes these runs
     reproducible on any device.
     Success = chi^2 <= chi^2 of the true parameters + 10.  GPU time of a
-    checkpoint = EA time so far + that checkpoint's simplex time."""
+    checkpoint = EA time so far + that checkpoint's simplex time.
+    islands = (n_islands, migrate every, migrants): the island form with the
+    same total population (pop // n_islands rows per island); its simplex
+    passes start from every island's record (the best island record for
+    the EA alone)."""
     cfg = sblm.ea_default_config()
     cfg.pop = pop
     cfg.mode = mode
+    if islands:
+        cfg.n_islands, cfg.mig_every, cfg.n_migrants = islands
+        cfg.pop = pop // cfg.n_islands
     state = sblm.EAState(cfg, lcs, seed)
     state.set_schedule(*sched)
     n_lc = len(chi2_true)
@@ -222,7 +232,7 @@ def success_run(sblm, torch, lcs, chi2_true, pop, mode, sched, lo, hi, proposals
     if proposals is not None:  # resampling + inference done by the caller
         sync()
         t0 = time.perf_counter()
-        state.seed(proposals, pop // 2, at_restarts=True)
+        state.seed(proposals, cfg.pop // 2, at_restarts=True)
         sync()
         ea_s += time.perf_counter() - t0
     nm_cfg = sblm.nm_default_config()
@@ -235,13 +245,16 @@ def success_run(sblm, torch, lcs, chi2_true, pop, mode, sched, lo, hi, proposals
         sync()
         ea_s += time.perf_counter() - t0
         gens += every
-        x, c0 = state.best()
+        reps = cfg.n_islands
+        x, c0 = state.records() if reps > 1 else state.best()
         sync()
         t0 = time.perf_counter()
         c2 = c0.clone()
         for _ in range(passes):
-            x, c, _, _, _ = sblm.nm_refine(lcs, lo, hi, x, nm_cfg)
+            x, c, _, _, _ = sblm.nm_refine(lcs, lo, hi, x, nm_cfg, reps=reps)
             c2 = torch.minimum(c2, c)
+        c0 = c0.view(n_lc, reps).min(dim=1).values
+        c2 = c2.view(n_lc, reps).min(dim=1).values
         sync()
         nm_s = time.perf_counter() - t0
         c0 = c0.cpu().numpy()
@@ -484,6 +497,13 @@ def main():
                                 hi, proposals=out_p, max_gen=args.success_max_gen,
                                 every=args.success_every),
             inference_seconds=t_inf)
+        if args.islands:
+            isl = tuple(int(v) for v in args.islands.split(","))
+            success["islands"] = success_run(sblm, torch, lcs, chi2_true, args.pop, sblm.FP64,
+                                             sched, lo, hi, max_gen=args.success_max_gen,
+                                             every=args.success_every, islands=isl)
+            success["islands"]["config"] = dict(islands=isl[0], pop_per_island=args.pop // isl[0],
+                                                migrate_every=isl[1], migrants=isl[2])
         lrn = success["learned"]["ea_amoeba"]
         if lrn["gpu_seconds"] is not None:  # proposals are part of the learned fit's GPU time
             lrn["gpu_seconds"] += t_inf
@@ -532,7 +552,8 @@ def main():
                    "parallelism": "single GPU"},
         "fits_per_hour": main_form["fits_per_hour"],
         "fits_per_hour_at_90pct": ({f: success[f]["ea_amoeba"]["fits_per_hour"]
-                                    for f in ("plain", "learned")} if success else None),
+                                    for f in ("plain", "learned", "islands") if f in success}
+                                   if success else None),
         "time_to_90pct_success": success,
         "success_rate": main_form["success"],
         "forms": forms,

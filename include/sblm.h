@@ -176,18 +176,34 @@ typedef struct {
   double lo[SBLM_NPAR];  /* Omega_j = [lo_j, hi_j] (Sec. A.2)              */
   double hi[SBLM_NPAR];
   int32_t mode;          /* sblm_mode used by ea_fit's fitness evaluation  */
+  /* Island form (Sec. 5.3): every lightcurve has n_islands populations of
+   * pop rows that evolve independently and exchange their fittest rows.
+   * Island i of lightcurve k is an Appendix-A EA of its own whose draws use
+   * the lightcurve index k * n_islands + i (so n_islands = 1 is the plain
+   * EA).  Migration, in ea_fit, before the generation step of generation g
+   * (generations completed) when g > 0 and g % mig_every == 0: on a ring,
+   * island i sends its n_migrants fittest rows (stable ascending chi^2, NaN
+   * last) with their fitness to island (i + 1) % n_islands, where the r-th
+   * fittest replaces the row of rank pop - 1 - r; all islands send from the
+   * state before any receives.  The rows of lightcurve k are
+   * [k * n_islands * pop, (k + 1) * n_islands * pop), island-major. */
+  int32_t n_islands;     /* 1 <= n_islands <= 256                           */
+  int32_t mig_every;     /* >= 0; 0 = never                                */
+  int32_t n_migrants;    /* 0 <= n_migrants <= pop / 2; 0 = never           */
 } ea_config;
 
 /* Fills cfg with the defaults used by this library: pop 256, N_tourn =
  * ceil(pop/25), p_mut0 0.01, p_mut in [1e-4, 0.5], 1% over 10 generations,
  * restart after 10 consecutive flags, Omega = {log10 q in [-3,0], d in
  * [0.5,2], u0 in [0,0.5], alpha in [0,2pi], tE in [10,100], t0 in [-10,10]},
- * FP64 fitness.  Host pointer. */
+ * FP64 fitness, one island (no migration).  Host pointer. */
 void ea_default_config(ea_config* cfg);
 
 typedef struct ea_state ea_state; /* opaque */
 
-/* Per-lightcurve summary, host-side copy (ea_summary). */
+/* Per-lightcurve summary, host-side copy (ea_summary).  With islands, every
+ * field is that of the island holding the lightcurve's best chi^2 (the
+ * lowest island index among equals). */
 typedef struct {
   double best_chi2;      /* best chi^2 seen since ea_create (all restarts) */
   double best_Fs, best_Fb;
@@ -209,6 +225,8 @@ typedef struct {
  *          must stay alive and unchanged for the life of the state
  *   seed   64-bit seed (Philox key word 0)
  *   out    host pointer receiving the new state
+ * With islands every island is initialised so, from its own draws.
+ * n_lc * n_islands * pop <= 2^31 - 1.
  * The only entry point that allocates device memory.  Errors: SBLM_EINVAL,
  * SBLM_ERANGE, SBLM_ENOMEM, SBLM_EDEVICE.
  */
@@ -222,8 +240,10 @@ int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t seed,
  * pairs (row 0 keeps the fittest individual), apply creep then jump mutation
  * to every offspring gene, then the stagnation test, the p_mut update and a
  * restart when the flags have repeated restart_after times.
- *   chi2, Fs, Fb  [n_lc*pop] device, fitness of the current population in
- *          its current row order (as written by sblm_chi2 or ea_evaluate)
+ *   chi2, Fs, Fb  [n_lc*n_islands*pop] device, fitness of the current
+ *          population in its current row order (as written by sblm_chi2 with
+ *          n_islands*pop individuals per lightcurve, or by ea_evaluate)
+ * Every island takes its own generation; no migration (see ea_migrate).
  * Errors: SBLM_EINVAL, SBLM_ESTATE, SBLM_EDEVICE.
  */
 int ea_generation(ea_state* st, const double* chi2, const double* Fs,
@@ -235,8 +255,9 @@ int ea_generation(ea_state* st, const double* chi2, const double* Fs,
 int ea_evaluate(ea_state* st, sblm_stats* stats, void* stream);
 
 /*
- * ea_fit -- run n_gen generations, each = ea_evaluate + ea_generation on the
- * state's own buffers, replayed from one captured HIP graph.
+ * ea_fit -- run n_gen generations, each = ea_evaluate + (when due, the
+ * migration of ea_config) + ea_generation on the state's own buffers,
+ * replayed from one captured HIP graph.
  *   n_gen  >= 0
  * Errors: SBLM_EINVAL, SBLM_ESTATE, SBLM_EDEVICE.
  */
@@ -262,9 +283,21 @@ int ea_autotune(ea_state* st, char* report, size_t report_len, void* stream);
 int ea_get_schedule(ea_state* st, int32_t* sched);
 int ea_set_schedule(ea_state* st, const int32_t* sched);
 
+/*
+ * ea_migrate -- one ring migration among the islands of every lightcurve
+ * now, whatever the generation (the exchange that ea_fit makes when it is
+ * due, Sec. 5.3 and ea_config): rows of the population and the matching
+ * entries of chi2, Fs and Fb ([n_lc*n_islands*pop] device, modified in
+ * place) are overwritten.  NULL fitness pointers select the state's own
+ * buffers.  Errors: SBLM_ESTATE when the state has one island or no
+ * migrants; SBLM_EINVAL when only some of the pointers are NULL.
+ */
+int ea_migrate(ea_state* st, double* chi2, double* Fs, double* Fb, void* stream);
+
 /* Device pointers into the state (valid until ea_destroy):
- * P [6][n_lc*pop] encoded population, chi2/Fs/Fb [n_lc*pop] the buffers
- * ea_evaluate writes.  Any pointer argument may be NULL. */
+ * P [6][n_lc*n_islands*pop] encoded population, chi2/Fs/Fb
+ * [n_lc*n_islands*pop] the buffers ea_evaluate writes.  Any pointer argument
+ * may be NULL. */
 int ea_buffers(ea_state* st, double** P, double** chi2, double** Fs,
                double** Fb);
 
@@ -328,15 +361,35 @@ int nm_refine(const sblm_lcs* lcs, const double* lo, const double* hi,
               double* Fs, double* Fb, int32_t* n_iter, sblm_stats* stats,
               void* stream);
 
+/*
+ * nm_refine_multi -- as nm_refine with `reps` independent simplices per
+ * lightcurve (several start points: the fittest solution of every island,
+ * or the random starts of an iterated simplex).  Simplex j = k * reps + i
+ * works on lightcurve k; x0, x [6][n_lc * reps], chi2, Fs, Fb, n_iter
+ * [n_lc * reps].  1 <= reps, n_lc * reps <= 2^24.  nm_refine is reps = 1.
+ */
+int nm_refine_multi(const sblm_lcs* lcs, int32_t reps, const double* lo,
+                    const double* hi, const double* x0, const nm_config* cfg,
+                    double* x, double* chi2, double* Fs, double* Fb,
+                    int32_t* n_iter, sblm_stats* stats, void* stream);
+
 /* ea_best -- the fittest solution seen so far by every lightcurve's EA:
- * x [6][n_lc] device (encoded), chi2 [n_lc] device (nullable). */
+ * x [6][n_lc] device (encoded), chi2 [n_lc] device (nullable).  With
+ * islands: the best island record (the lowest island index among equals). */
 int ea_best(ea_state* st, double* x, double* chi2, void* stream);
 
+/* ea_records -- the record of every island: x [6][n_lc * n_islands] device
+ * (encoded), chi2 [n_lc * n_islands] device (nullable), island-major within
+ * each lightcurve.  Without islands the same as ea_best. */
+int ea_records(ea_state* st, double* x, double* chi2, void* stream);
+
 /*
- * ea_refine -- nm_refine from every lightcurve's fittest solution (ea_best),
- * in the state's domain; where the simplex finds a lower chi^2 the record
- * (best chi^2, parameters, fluxes, generation) is replaced.  The population
- * is not touched.  n_iter as in nm_refine.  Synchronises `stream`.
+ * ea_refine -- a simplex (as nm_refine) from every record (ea_records: one
+ * per lightcurve, or one per island), in the state's domain; where the
+ * simplex finds a lower chi^2 that record (best chi^2, parameters, fluxes,
+ * generation) is replaced.  The population is not touched.  n_iter
+ * [n_lc * n_islands] device (nullable), the steps of each simplex.
+ * Synchronises `stream`.
  */
 int ea_refine(ea_state* st, const nm_config* cfg, int32_t* n_iter, sblm_stats* stats,
               void* stream);
@@ -468,7 +521,9 @@ int mlp_train(mlp_net* net, const uint16_t* x, const float* y, int64_t rows,
 
 /*
  * ea_seed -- overwrite rows 0 .. n_seed-1 of every lightcurve's current
- * population with draws from the network's proposal mixture.
+ * population (of every island) with draws from the network's proposal
+ * mixture; island i of lightcurve k draws with lightcurve index
+ * k * n_islands + i and the network output and epochs of lightcurve k.
  *   out     [n_lc][ld_out] FP32 device, network output for each lightcurve
  *           (mlp_forward of its sblm_resample bins), ld_out >= 120
  *   n_seed  0 <= n_seed <= pop

@@ -64,11 +64,15 @@ struct EaLc {
   double hist[EA_HIST];  // best chi^2 of generation g at hist[g % (window+1)]
 };
 
+// One EA population per "virtual lightcurve": with islands (Sec. 5.3),
+// island i of lightcurve k is virtual lightcurve k * n_isl + i, and n_lc
+// counts virtual lightcurves.
 struct EaParams {
   int32_t n_lc, pop, n_tourn, window, restart_after;
+  int32_t n_isl;  // islands per lightcurve
   double p_mut0, p_mut_min, p_mut_max, stag_frac;
   uint64_t seed;
-  int64_t n_ind;  // n_lc * pop
+  int64_t n_ind;  // n_lc * pop (all islands)
 };
 
 // Sec. A.1: rows i < pop/2 uniform, row i + pop/2 = 1 - row i, odd last row
@@ -131,11 +135,12 @@ struct Proposals {
 
 __device__ void seed_row(const EaParams& p, double* P, const Proposals& pr,
                          int64_t lc, int row, int64_t gen) {
-  const int64_t o0 = pr.off[lc], o1 = pr.off[lc + 1];
+  const int64_t k = lc / p.n_isl;  // the lightcurve of this island
+  const int64_t o0 = pr.off[k], o1 = pr.off[k + 1];
   if (o1 <= o0) return;
   const double t_first = pr.t[o0], tspan = pr.t[o1 - 1] - t_first;
   const Stream rs = {p.seed, (uint64_t)lc, (uint64_t)gen};
-  const float* o = pr.O + lc * (int64_t)pr.ld;
+  const float* o = pr.O + k * (int64_t)pr.ld;
   const int K = MLP_K, D = MLP_D;
   double lmax = (double)o[0];
   for (int k = 1; k < K; ++k) lmax = fmax(lmax, (double)o[k]);
@@ -335,26 +340,102 @@ __global__ void ea_draws_kernel(uint64_t seed, uint64_t lc, uint64_t gen,
   out[k] = rs.draw(purpose, row, j0 + (uint64_t)k);
 }
 
-// The record's fittest solution as a [6][n_lc] encoded array.
-__global__ void ea_best_kernel(const EaLc* lcs, int32_t n_lc, double* x, double* chi2) {
-  const int lc = blockIdx.x * blockDim.x + threadIdx.x;
-  if (lc >= n_lc) return;
-  for (int g = 0; g < SBLM_NPAR; ++g) x[(int64_t)g * n_lc + lc] = lcs[lc].best_p[g];
-  if (chi2) chi2[lc] = lcs[lc].best_chi2;
+// Record of lightcurve k: that of its island with the lowest best chi^2,
+// the lowest island index among equals (records are never NaN).
+__device__ __forceinline__ int64_t best_island(const EaLc* lcs, int64_t k, int n_isl) {
+  int64_t v = k * n_isl;
+  for (int i = 1; i < n_isl; ++i)
+    if (lcs[k * n_isl + i].best_chi2 < lcs[v].best_chi2) v = k * n_isl + i;
+  return v;
 }
 
-// Replaces a record whose refined solution is fitter.
-__global__ void ea_improve_kernel(EaLc* lcs, int32_t n_lc, const double* x, const double* chi2,
-                                  const double* Fs, const double* Fb) {
+// The record's fittest solution as a [6][n_lc] encoded array (n_lc
+// lightcurves, not islands).
+__global__ void ea_best_kernel(const EaLc* lcs, int32_t n_lc, int32_t n_isl, double* x,
+                               double* chi2) {
   const int lc = blockIdx.x * blockDim.x + threadIdx.x;
   if (lc >= n_lc) return;
+  const EaLc& r = lcs[best_island(lcs, lc, n_isl)];
+  for (int g = 0; g < SBLM_NPAR; ++g) x[(int64_t)g * n_lc + lc] = r.best_p[g];
+  if (chi2) chi2[lc] = r.best_chi2;
+}
+
+// Replaces every record (one per island) whose refined solution is fitter.
+__global__ void ea_improve_kernel(EaLc* lcs, int32_t n_rec, const double* x, const double* chi2,
+                                  const double* Fs, const double* Fb) {
+  const int lc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lc >= n_rec) return;
   EaLc& r = lcs[lc];
   if (chi2[lc] < r.best_chi2) {
     r.best_chi2 = chi2[lc];
     r.best_Fs = Fs[lc];
     r.best_Fb = Fb[lc];
-    for (int g = 0; g < SBLM_NPAR; ++g) r.best_p[g] = x[(int64_t)g * n_lc + lc];
+    for (int g = 0; g < SBLM_NPAR; ++g) r.best_p[g] = x[(int64_t)g * n_rec + lc];
     r.best_gen = r.gen;
+  }
+}
+
+// Island migration (Sec. 5.3; timing, ring and replacement rule as stated
+// with ea_config).  Two launches so that every island sends from the state
+// before any receives: the first ranks each island (stable counting rank on
+// the rank key) and copies its m fittest rows, with their fitness, to slots
+// 0..m-1 of its own outbox and notes the rows of ranks pop-1 .. pop-m; the
+// second copies the outbox of the island before it on the ring over those
+// rows.  Every island of a state has the same generation count, so both
+// launches agree on whether the migration is due.
+struct MigArgs {
+  double* chi2;     // [n_ind] fitness of the current rows, updated in place
+  double* Fs;
+  double* Fb;
+  double* out;      // [n_lc][m][9] outbox: 6 genes, chi^2, Fs, Fb
+  int32_t* least;   // [n_lc][m] row of rank pop - 1 - r
+  int32_t m, every, force;
+};
+
+__device__ __forceinline__ bool migration_due(const MigArgs& a, int64_t gen) {
+  return a.force || (gen > 0 && gen % a.every == 0);
+}
+
+__global__ void ea_emigrate_kernel(EaParams p, const double* P, const EaLc* lcs, MigArgs a) {
+  extern __shared__ double skey[];  // [pop]
+  const int64_t v = blockIdx.x;
+  if (!migration_due(a, lcs[v].gen)) return;
+  const int N = p.pop;
+  const int64_t base = v * N;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) skey[i] = rank_key(a.chi2[base + i]);
+  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const double ki = skey[i];
+    int r = 0;
+    for (int j = 0; j < N; ++j) {
+      const double kj = skey[j];
+      r += (kj < ki || (kj == ki && j < i)) ? 1 : 0;
+    }
+    if (r < a.m) {
+      double* o = a.out + (v * a.m + r) * 9;
+      for (int g = 0; g < SBLM_NPAR; ++g) o[g] = P[g * p.n_ind + base + i];
+      o[6] = a.chi2[base + i];
+      o[7] = a.Fs[base + i];
+      o[8] = a.Fb[base + i];
+    }
+    if (r >= N - a.m) a.least[v * a.m + (N - 1 - r)] = i;
+  }
+}
+
+__global__ void ea_immigrate_kernel(EaParams p, double* P, const EaLc* lcs, MigArgs a) {
+  const int64_t v = blockIdx.x;
+  if (!migration_due(a, lcs[v].gen)) return;
+  const int64_t k = v / p.n_isl;
+  const int i = (int)(v - k * p.n_isl);
+  const int64_t src = k * p.n_isl + (i + p.n_isl - 1) % p.n_isl;
+  const int64_t base = v * p.pop;
+  for (int r = threadIdx.x; r < a.m; r += blockDim.x) {
+    const int row = a.least[v * a.m + r];
+    const double* o = a.out + (src * a.m + r) * 9;
+    for (int g = 0; g < SBLM_NPAR; ++g) P[g * p.n_ind + base + row] = o[g];
+    a.chi2[base + row] = o[6];
+    a.Fs[base + row] = o[7];
+    a.Fb[base + row] = o[8];
   }
 }
 
@@ -383,6 +464,10 @@ struct EaStateImpl {
   int32_t* order = nullptr;    // item -> individual, longest lightcurves first
   unsigned int* queue = nullptr;
   Proposals prop = {};         // attached by ea_seed(..., EA_SEED_AT_RESTARTS)
+  int n_phys = 0;              // lightcurves (prm.n_lc counts islands)
+  double* mig_out = nullptr;   // migration outboxes (islands with migrants)
+  int32_t* mig_least = nullptr;
+  bool mig_in_fit = false;     // ea_fit migrates when due
 };
 
 __global__ void queue_reset_kernel(unsigned int* q) { *q = 0u; }
@@ -406,6 +491,26 @@ static hipError_t enqueue_generation(EaStateImpl* s, const double* chi2,
   return hipGetLastError();
 }
 
+static hipError_t enqueue_migration(EaStateImpl* s, double* chi2, double* Fs, double* Fb,
+                                    int force, hipStream_t st) {
+  MigArgs a;
+  a.chi2 = chi2;
+  a.Fs = Fs;
+  a.Fb = Fb;
+  a.out = s->mig_out;
+  a.least = s->mig_least;
+  a.m = s->cfg.n_migrants;
+  a.every = s->cfg.mig_every > 0 ? s->cfg.mig_every : 1;
+  a.force = force;
+  hipLaunchKernelGGL(ea_emigrate_kernel, dim3(s->prm.n_lc), dim3(gen_block(s->prm.pop)),
+                     (size_t)s->prm.pop * sizeof(double), st, s->prm, s->P, s->lc, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(ea_immigrate_kernel, dim3(s->prm.n_lc), dim3(64), 0, st, s->prm, s->P,
+                     s->lc, a);
+  return hipGetLastError();
+}
+
 static hipError_t enqueue_evaluate(EaStateImpl* s, sblm_stats* stats,
                                    hipStream_t st) {
   FitArgs a;
@@ -418,7 +523,7 @@ static hipError_t enqueue_evaluate(EaStateImpl* s, sblm_stats* stats,
     a.span[j] = s->cfg.hi[j] - s->cfg.lo[j];
   }
   a.off = s->lcs.off;
-  a.pop = s->prm.pop;
+  a.pop = s->prm.pop * s->prm.n_isl;  // all islands of a lightcurve together
   a.t = s->lcs.t;
   a.y = s->lcs.y;
   a.w = s->lcs.w;
@@ -466,6 +571,7 @@ extern "C" void ea_default_config(ea_config* c) {
     c->hi[j] = hi[j];
   }
   c->mode = SBLM_FP64;
+  c->n_islands = 1;  // no islands, no migration
 }
 
 static int validate(const ea_config* c) {
@@ -490,6 +596,12 @@ static int validate(const ea_config* c) {
     return set_error(SBLM_EINVAL, "ea_config: tE domain must be positive");
   if (c->mode != SBLM_FP64 && c->mode != SBLM_MIXED)
     return set_error(SBLM_EINVAL, "ea_config: unknown mode %d", c->mode);
+  if (c->n_islands < 1 || c->n_islands > 256)
+    return set_error(SBLM_ERANGE, "ea_config: n_islands = %d outside [1, 256]", c->n_islands);
+  if (c->mig_every < 0) return set_error(SBLM_EINVAL, "ea_config: mig_every < 0");
+  if (c->n_migrants < 0 || 2 * c->n_migrants > c->pop)
+    return set_error(SBLM_EINVAL, "ea_config: n_migrants = %d outside [0, pop/2]",
+                     c->n_migrants);
   return SBLM_OK;
 }
 
@@ -511,6 +623,8 @@ extern "C" void ea_destroy(ea_state* st) {
   (void)hipFree(s.lc);
   (void)hipFree(s.order);
   (void)hipFree(s.queue);
+  (void)hipFree(s.mig_out);
+  (void)hipFree(s.mig_least);
   (void)hipSetDevice(prev);
   st->~ea_state();
   free(st);
@@ -526,8 +640,8 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
     return set_error(SBLM_EINVAL, "ea_create: null lightcurve array");
   if (lcs->n_lc < 1 || lcs->n_lc > (1 << 20))
     return set_error(SBLM_ERANGE, "ea_create: n_lc = %d", lcs->n_lc);
-  if ((int64_t)lcs->n_lc * cfg->pop > (1LL << 31) - 1)
-    return set_error(SBLM_ERANGE, "ea_create: n_lc * pop too large");
+  if ((int64_t)lcs->n_lc * cfg->n_islands * cfg->pop > (1LL << 31) - 1)
+    return set_error(SBLM_ERANGE, "ea_create: n_lc * n_islands * pop too large");
   void* mem = malloc(sizeof(ea_state));
   if (!mem) return set_error(SBLM_ENOMEM, "ea_create: host allocation");
   ea_state* st = new (mem) ea_state();
@@ -536,7 +650,9 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
   s.lcs = *lcs;
   (void)hipGetDevice(&s.device);
   EaParams& p = s.prm;
-  p.n_lc = lcs->n_lc;
+  s.n_phys = lcs->n_lc;
+  p.n_isl = cfg->n_islands;
+  p.n_lc = lcs->n_lc * cfg->n_islands;
   p.pop = cfg->pop;
   p.n_tourn = cfg->n_tourn > 0 ? cfg->n_tourn : (cfg->pop + 24) / 25;
   p.window = cfg->stag_window;
@@ -552,10 +668,13 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
   if (env && (atoi(env) == 16 || atoi(env) == 32 || atoi(env) == 64)) s.lanes = atoi(env);
   const size_t nb = (size_t)p.n_ind * sizeof(double);
   // longest-processing-time order of the work items: lightcurves by length,
-  // longest first (stable), the individuals of each lightcurve together
-  int64_t* off_h = (int64_t*)malloc((size_t)(p.n_lc + 1) * sizeof(int64_t));
+  // longest first (stable), the individuals of each lightcurve (all its
+  // islands) together
+  const int nl = s.n_phys;
+  const int popf = p.pop * p.n_isl;
+  int64_t* off_h = (int64_t*)malloc((size_t)(nl + 1) * sizeof(int64_t));
   int32_t* order_h = (int32_t*)malloc((size_t)p.n_ind * sizeof(int32_t));
-  int32_t* lcs_sorted = (int32_t*)malloc((size_t)p.n_lc * sizeof(int32_t));
+  int32_t* lcs_sorted = (int32_t*)malloc((size_t)nl * sizeof(int32_t));
   if (!off_h || !order_h || !lcs_sorted) {
     free(off_h);
     free(order_h);
@@ -563,23 +682,23 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
     ea_destroy(st);
     return set_error(SBLM_ENOMEM, "ea_create: host allocation");
   }
-  rc = check_hip(hipMemcpy(off_h, lcs->off, (size_t)(p.n_lc + 1) * sizeof(int64_t),
+  rc = check_hip(hipMemcpy(off_h, lcs->off, (size_t)(nl + 1) * sizeof(int64_t),
                            hipMemcpyDeviceToHost),
                  "ea_create offsets");
   if (!rc)
-    for (int k = 0; k < p.n_lc; ++k)
+    for (int k = 0; k < nl; ++k)
       if (off_h[k + 1] < off_h[k] || off_h[0] != 0) {
         rc = set_error(SBLM_EINVAL, "ea_create: offsets not non-decreasing from 0");
         break;
       }
   if (!rc) {
-    for (int k = 0; k < p.n_lc; ++k) lcs_sorted[k] = k;
+    for (int k = 0; k < nl; ++k) lcs_sorted[k] = k;
     // stable bottom-up merge sort, longest first
-    int32_t* tmp = (int32_t*)malloc((size_t)p.n_lc * sizeof(int32_t));
-    for (int w = 1; tmp && w < p.n_lc; w *= 2)
-      for (int lo = 0; lo < p.n_lc; lo += 2 * w) {
-        int mid = lo + w < p.n_lc ? lo + w : p.n_lc;
-        int hi = lo + 2 * w < p.n_lc ? lo + 2 * w : p.n_lc;
+    int32_t* tmp = (int32_t*)malloc((size_t)nl * sizeof(int32_t));
+    for (int w = 1; tmp && w < nl; w *= 2)
+      for (int lo = 0; lo < nl; lo += 2 * w) {
+        int mid = lo + w < nl ? lo + w : nl;
+        int hi = lo + 2 * w < nl ? lo + 2 * w : nl;
         int i = lo, j = mid, o = lo;
         while (i < mid && j < hi) {
           const int64_t li = off_h[lcs_sorted[i] + 1] - off_h[lcs_sorted[i]];
@@ -592,7 +711,7 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
       }
     free(tmp);
     for (int64_t it = 0; it < p.n_ind; ++it)
-      order_h[it] = lcs_sorted[it / p.pop] * p.pop + (int32_t)(it % p.pop);
+      order_h[it] = lcs_sorted[it / popf] * popf + (int32_t)(it % popf);
   }
   free(off_h);
   free(lcs_sorted);
@@ -605,7 +724,12 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
       hipMalloc(&s.Fs, nb) != hipSuccess || hipMalloc(&s.Fb, nb) != hipSuccess ||
       hipMalloc(&s.lc, (size_t)p.n_lc * sizeof(EaLc)) != hipSuccess ||
       hipMalloc(&s.order, (size_t)p.n_ind * sizeof(int32_t)) != hipSuccess ||
-      hipMalloc(&s.queue, sizeof(unsigned int)) != hipSuccess) {
+      hipMalloc(&s.queue, sizeof(unsigned int)) != hipSuccess ||
+      (p.n_isl > 1 && cfg->n_migrants > 0 &&
+       (hipMalloc(&s.mig_out, (size_t)p.n_lc * cfg->n_migrants * 9 * sizeof(double)) !=
+            hipSuccess ||
+        hipMalloc(&s.mig_least, (size_t)p.n_lc * cfg->n_migrants * sizeof(int32_t)) !=
+            hipSuccess))) {
     free(order_h);
     ea_destroy(st);
     return set_error(SBLM_ENOMEM, "ea_create: device allocation of %zu bytes failed",
@@ -626,6 +750,7 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
     ea_destroy(st);
     return rc;
   }
+  s.mig_in_fit = s.mig_out != nullptr && cfg->mig_every > 0;
   hipLaunchKernelGGL(ea_init_kernel, dim3(p.n_lc), dim3(gen_block(p.pop)), 0, s.work, p, s.P,
                      s.lc);
   rc = check_hip(hipGetLastError(), "ea_create init launch");
@@ -709,9 +834,19 @@ extern "C" int ea_best(ea_state* st, double* x, double* chi2, void* stream) {
   if (!st) return set_error(SBLM_ESTATE, "ea_best: null state");
   if (!x) return set_error(SBLM_EINVAL, "ea_best: null x");
   EaStateImpl& s = st->impl;
-  hipLaunchKernelGGL(ea_best_kernel, dim3((s.prm.n_lc + 255) / 256), dim3(256), 0,
-                     (hipStream_t)stream, s.lc, s.prm.n_lc, x, chi2);
+  hipLaunchKernelGGL(ea_best_kernel, dim3((s.n_phys + 255) / 256), dim3(256), 0,
+                     (hipStream_t)stream, s.lc, s.n_phys, s.prm.n_isl, x, chi2);
   return check_hip(hipGetLastError(), "ea_best launch");
+}
+
+extern "C" int ea_records(ea_state* st, double* x, double* chi2, void* stream) {
+  if (!st) return set_error(SBLM_ESTATE, "ea_records: null state");
+  if (!x) return set_error(SBLM_EINVAL, "ea_records: null x");
+  EaStateImpl& s = st->impl;
+  // one record per island: the best-of-islands rule over groups of one
+  hipLaunchKernelGGL(ea_best_kernel, dim3((s.prm.n_lc + 255) / 256), dim3(256), 0,
+                     (hipStream_t)stream, s.lc, s.prm.n_lc, 1, x, chi2);
+  return check_hip(hipGetLastError(), "ea_records launch");
 }
 
 extern "C" int ea_refine(ea_state* st, const nm_config* cfg, int32_t* n_iter,
@@ -720,7 +855,7 @@ extern "C" int ea_refine(ea_state* st, const nm_config* cfg, int32_t* n_iter,
   int rc = nm_check(cfg, "ea_refine");
   if (rc) return rc;
   EaStateImpl& s = st->impl;
-  const int n = s.prm.n_lc;
+  const int n = s.prm.n_lc;  // one simplex per island record
   hipStream_t hs = (hipStream_t)stream;
   double *x0 = nullptr, *x = nullptr, *c = nullptr, *fs = nullptr, *fb = nullptr;
   const size_t nn = (size_t)n;
@@ -731,14 +866,14 @@ extern "C" int ea_refine(ea_state* st, const nm_config* cfg, int32_t* n_iter,
     rc = set_error(SBLM_ENOMEM, "ea_refine: device allocation");
   }
   if (rc == SBLM_OK) {
-    hipLaunchKernelGGL(ea_best_kernel, dim3((n + 255) / 256), dim3(256), 0, hs, s.lc, n, x0,
-                       nullptr);
+    hipLaunchKernelGGL(ea_best_kernel, dim3((n + 255) / 256), dim3(256), 0, hs, s.lc, n, 1,
+                       x0, nullptr);
     rc = check_hip(hipGetLastError(), "ea_refine: launch");
   }
   double span[SBLM_NPAR];
   for (int g = 0; g < SBLM_NPAR; ++g) span[g] = s.cfg.hi[g] - s.cfg.lo[g];
   if (rc == SBLM_OK)
-    rc = nm_run(s.lcs, s.cfg.lo, span, x0, *cfg, x, c, fs, fb, n_iter, stats, hs);
+    rc = nm_run(s.lcs, s.prm.n_isl, s.cfg.lo, span, x0, *cfg, x, c, fs, fb, n_iter, stats, hs);
   if (rc == SBLM_OK) {
     hipLaunchKernelGGL(ea_improve_kernel, dim3((n + 255) / 256), dim3(256), 0, hs, s.lc, n, x,
                        c, fs, fb);
@@ -758,8 +893,25 @@ extern "C" int ea_evaluate(ea_state* st, sblm_stats* stats, void* stream) {
                    "ea_evaluate launch");
 }
 
-// Captures one generation (evaluate + generation kernels on the state's
-// work stream) into an executable graph bound to `stats`.
+extern "C" int ea_migrate(ea_state* st, double* chi2, double* Fs, double* Fb, void* stream) {
+  if (!st) return set_error(SBLM_ESTATE, "ea_migrate: null state");
+  EaStateImpl& s = st->impl;
+  if (!s.mig_out) return set_error(SBLM_ESTATE, "ea_migrate: one island or no migrants");
+  const int n_null = (chi2 == nullptr) + (Fs == nullptr) + (Fb == nullptr);
+  if (n_null == 1 || n_null == 2)
+    return set_error(SBLM_EINVAL, "ea_migrate: give all fitness arrays or none");
+  if (n_null == 3) {
+    chi2 = s.chi2;
+    Fs = s.Fs;
+    Fb = s.Fb;
+  }
+  return check_hip(enqueue_migration(&s, chi2, Fs, Fb, 1, (hipStream_t)stream),
+                   "ea_migrate launch");
+}
+
+// Captures one generation (evaluate, migration when the state has it, and
+// generation kernels on the state's work stream) into an executable graph
+// bound to `stats`.
 static int capture_graph(EaStateImpl& s, sblm_stats* stats) {
   if (s.graph) {
     int rc0 = check_hip(hipStreamSynchronize(s.work), "ea graph re-capture");
@@ -773,6 +925,7 @@ static int capture_graph(EaStateImpl& s, sblm_stats* stats) {
                       "ea graph capture")))
     return rc;
   hipError_t e1 = enqueue_evaluate(&s, stats, s.work);
+  if (e1 == hipSuccess && s.mig_in_fit) e1 = enqueue_migration(&s, s.chi2, s.Fs, s.Fb, 0, s.work);
   hipError_t e2 = enqueue_generation(&s, s.chi2, s.Fs, s.Fb, nullptr, s.work);
   hipError_t e3 = hipStreamEndCapture(s.work, &g);
   if ((rc = check_hip(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3),
@@ -930,19 +1083,23 @@ extern "C" int ea_summary(ea_state* st, ea_lc_summary* out, void* stream) {
                      "ea_summary copy");
   if (!rc) rc = check_hip(hipStreamSynchronize((hipStream_t)stream), "ea_summary sync");
   if (!rc)
-    for (int k = 0; k < n; ++k) {
+    for (int k = 0; k < s.n_phys; ++k) {
+      const int ni = s.prm.n_isl;
+      int v = k * ni;  // the island holding the best record, lowest index first
+      for (int i = 1; i < ni; ++i)
+        if (h[k * ni + i].best_chi2 < h[v].best_chi2) v = k * ni + i;
       ea_lc_summary& o = out[k];
-      o.best_chi2 = h[k].best_chi2;
-      o.best_Fs = h[k].best_Fs;
-      o.best_Fb = h[k].best_Fb;
+      o.best_chi2 = h[v].best_chi2;
+      o.best_Fs = h[v].best_Fs;
+      o.best_Fb = h[v].best_Fb;
       for (int j = 0; j < SBLM_NPAR; ++j)
-        o.best_theta[j] = s.cfg.lo[j] + (s.cfg.hi[j] - s.cfg.lo[j]) * h[k].best_p[j];
-      o.best_gen = h[k].best_gen;
-      o.p_mut = h[k].p_mut;
-      o.stag_count = h[k].stag_count;
-      o.n_restarts = h[k].n_restarts;
-      o.gen = h[k].gen;
-      o.gen_restart = h[k].gen_restart;
+        o.best_theta[j] = s.cfg.lo[j] + (s.cfg.hi[j] - s.cfg.lo[j]) * h[v].best_p[j];
+      o.best_gen = h[v].best_gen;
+      o.p_mut = h[v].p_mut;
+      o.stag_count = h[v].stag_count;
+      o.n_restarts = h[v].n_restarts;
+      o.gen = h[v].gen;
+      o.gen_restart = h[v].gen_restart;
     }
   free(h);
   return rc;

@@ -540,7 +540,7 @@ __device__ __forceinline__ Item item_setup(const FitArgs& a, int64_t wave_item) 
     const int64_t lc = x.ind / a.pop;
     e0 = x.valid ? a.off[lc] : 0;
     e1 = x.valid ? a.off[lc + 1] : 0;
-    if (a.skip && x.valid && a.skip[lc]) e1 = e0;
+    if (a.skip && x.valid && a.skip[x.ind / a.skip_per]) e1 = e0;
   }
   if (!x.valid) e1 = e0;
   x.e0 = e0;

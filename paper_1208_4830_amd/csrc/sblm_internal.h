@@ -41,8 +41,8 @@ struct FitArgs {
   unsigned int* queue;    // nullable: persistent launch, shared work counter
                           // (must read 0 when the kernel starts)
   int32_t async;          // 1: lanes step through their epochs independently
-  const int32_t* skip;    // nullable (CSR only): individuals of lightcurve l
-                          // are evaluated as empty when skip[l] != 0
+  const int32_t* skip;    // nullable (CSR only): individual i is evaluated
+  int32_t skip_per;       // as empty when skip[i / skip_per] != 0
 };
 
 // Launch the FP64 or mixed fitness kernel; chi2 = false writes A/n_img.
@@ -52,9 +52,9 @@ hipError_t launch_fitness(const FitArgs& a, int mode, bool chi2,
 // Batched downhill-simplex refinement (sblm_nm.hip): one simplex per
 // lightcurve from x0 [6][n_lc] (encoded with lo/span); results as for
 // nm_refine.  Allocates and frees its workspace; synchronises `st`.
-int nm_run(const sblm_lcs& lcs, const double* lo, const double* span, const double* x0,
-           const nm_config& cfg, double* x, double* chi2, double* Fs, double* Fb,
-           int32_t* n_iter, sblm_stats* stats, hipStream_t st);
+int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* span,
+           const double* x0, const nm_config& cfg, double* x, double* chi2, double* Fs,
+           double* Fb, int32_t* n_iter, sblm_stats* stats, hipStream_t st);
 int nm_check(const nm_config* cfg, const char* who);
 
 }  // namespace sblm

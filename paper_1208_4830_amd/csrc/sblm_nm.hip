@@ -274,10 +274,12 @@ int nm_check(const nm_config* cfg, const char* who) {
   return SBLM_OK;
 }
 
-int nm_run(const sblm_lcs& lcs, const double* lo, const double* span, const double* x0,
-           const nm_config& cfg, double* x, double* chi2, double* Fs, double* Fb,
-           int32_t* n_iter, sblm_stats* stats, hipStream_t st) {
-  const int n = lcs.n_lc;
+int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* span,
+           const double* x0, const nm_config& cfg, double* x, double* chi2, double* Fs,
+           double* Fb, int32_t* n_iter, sblm_stats* stats, hipStream_t st) {
+  // simplex j = k * reps + i works on lightcurve k: its trial points are
+  // individuals j * NS + slot, that is NS * reps individuals per lightcurve
+  const int n = lcs.n_lc * reps;
   NmWork w;
   memset(&w, 0, sizeof(w));
   w.n = n;
@@ -309,7 +311,7 @@ int nm_run(const sblm_lcs& lcs, const double* lo, const double* span, const doub
     a.span[g] = span[g];
   }
   a.off = lcs.off;
-  a.pop = NS;
+  a.pop = NS * reps;
   a.t = lcs.t;
   a.y = lcs.y;
   a.w = lcs.w;
@@ -317,7 +319,8 @@ int nm_run(const sblm_lcs& lcs, const double* lo, const double* span, const doub
   a.Fs = w.fsT;
   a.Fb = w.fbT;
   a.stats = stats;
-  a.skip = w.done;
+  a.skip = w.done;  // a finished simplex's trial points are not evaluated
+  a.skip_per = NS;
   // rounds are latency-bound (each waits for its longest lightcurve, and
   // later rounds hold only the unfinished simplices): 64 lanes per
   // individual give the shortest chain of epochs per lane
@@ -375,22 +378,31 @@ extern "C" void nm_default_config(nm_config* cfg) {
   cfg->mode = SBLM_FP64;
 }
 
-extern "C" int nm_refine(const sblm_lcs* lcs, const double* lo, const double* hi,
-                         const double* x0, const nm_config* cfg, double* x, double* chi2,
-                         double* Fs, double* Fb, int32_t* n_iter, sblm_stats* stats,
-                         void* stream) {
+extern "C" int nm_refine_multi(const sblm_lcs* lcs, int32_t reps, const double* lo,
+                               const double* hi, const double* x0, const nm_config* cfg,
+                               double* x, double* chi2, double* Fs, double* Fb,
+                               int32_t* n_iter, sblm_stats* stats, void* stream) {
   int rc = nm_check(cfg, "nm_refine");
   if (rc) return rc;
   if (!lcs || !lcs->off || !lcs->t || !lcs->y || !lcs->w)
     return set_error(SBLM_EINVAL, "nm_refine: null lightcurve descriptor or array");
   if (lcs->n_lc < 1) return set_error(SBLM_EINVAL, "nm_refine: n_lc < 1");
-  if (lcs->n_lc > (1 << 24)) return set_error(SBLM_ERANGE, "nm_refine: n_lc beyond 2^24");
+  if (reps < 1) return set_error(SBLM_EINVAL, "nm_refine: reps = %d < 1", reps);
+  if ((int64_t)lcs->n_lc * reps > (1 << 24))
+    return set_error(SBLM_ERANGE, "nm_refine: n_lc * reps beyond 2^24");
   if (!lo || !hi || !x0 || !x) return set_error(SBLM_EINVAL, "nm_refine: null lo, hi, x0 or x");
   double span[SBLM_NPAR];
   for (int g = 0; g < SBLM_NPAR; ++g) {
     if (!(hi[g] > lo[g])) return set_error(SBLM_EINVAL, "nm_refine: hi[%d] <= lo[%d]", g, g);
     span[g] = hi[g] - lo[g];
   }
-  return nm_run(*lcs, lo, span, x0, *cfg, x, chi2, Fs, Fb, n_iter, stats,
+  return nm_run(*lcs, reps, lo, span, x0, *cfg, x, chi2, Fs, Fb, n_iter, stats,
                 (hipStream_t)stream);
+}
+
+extern "C" int nm_refine(const sblm_lcs* lcs, const double* lo, const double* hi,
+                         const double* x0, const nm_config* cfg, double* x, double* chi2,
+                         double* Fs, double* Fb, int32_t* n_iter, sblm_stats* stats,
+                         void* stream) {
+  return nm_refine_multi(lcs, 1, lo, hi, x0, cfg, x, chi2, Fs, Fb, n_iter, stats, stream);
 }

@@ -37,7 +37,8 @@ class ea_config(ctypes.Structure):
                 ("p_mut_max", ctypes.c_double), ("stag_frac", ctypes.c_double),
                 ("stag_window", ctypes.c_int32), ("restart_after", ctypes.c_int32),
                 ("lo", ctypes.c_double * NPAR), ("hi", ctypes.c_double * NPAR),
-                ("mode", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("n_islands", ctypes.c_int32),
+                ("mig_every", ctypes.c_int32), ("n_migrants", ctypes.c_int32)]
 
 
 class nm_config(ctypes.Structure):
@@ -81,6 +82,7 @@ _SIGS = {
     "ea_set_schedule": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)],
     "ea_draws": [ctypes.c_uint64] * 6 + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
     "ea_generation_traced": [ctypes.c_void_p] * 6,
+    "ea_migrate": [ctypes.c_void_p] * 5,
     "sblm_last_error": [],
     "sblm_resample": [ctypes.POINTER(sblm_lcs), ctypes.c_void_p, ctypes.c_void_p,
                       ctypes.c_void_p],
@@ -105,7 +107,13 @@ _SIGS = {
                   ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.POINTER(nm_config),
                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "nm_refine_multi": [ctypes.POINTER(sblm_lcs), ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                        ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+                        ctypes.POINTER(nm_config), ctypes.c_void_p, ctypes.c_void_p,
+                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                        ctypes.c_void_p],
     "ea_best": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "ea_records": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "ea_refine": [ctypes.c_void_p, ctypes.POINTER(nm_config), ctypes.c_void_p, ctypes.c_void_p,
                   ctypes.c_void_p],
     "ea_seed": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
@@ -272,8 +280,9 @@ class EAState:
 
     def view(self, name):
         """Zero-copy torch view of a state buffer ('P' [6][n], 'chi2', 'Fs',
-        'Fb' [n]); valid until close()."""
-        n = self.lcs.n_lc * self.cfg.pop
+        'Fb' [n], n = n_lc * n_islands * pop, island-major within each
+        lightcurve); valid until close()."""
+        n = self.lcs.n_lc * self.cfg.n_islands * self.cfg.pop
         shape = (NPAR, n) if name == "P" else (n,)
         return _device_view(self._ptrs[name], shape)
 
@@ -285,6 +294,15 @@ class EAState:
         _check(load().ea_generation_traced(self.h, _ptr(_dev(chi2)), _ptr(_dev(Fs)),
                                            _ptr(_dev(Fb)), _ptr(_dev(parents, torch.int32)),
                                            _stream(stream)))
+
+    def migrate(self, chi2=None, Fs=None, Fb=None, stream=None):
+        """One ring migration among every lightcurve's islands now, on the
+        given fitness arrays (modified in place) or the state's own."""
+        if chi2 is None:
+            args = (None, None, None)
+        else:
+            args = tuple(_ptr(a) for a in (chi2, Fs, Fb))
+        _check(load().ea_migrate(self.h, *args, _stream(stream)))
 
     def evaluate(self, stats=None, stream=None):
         _check(load().ea_evaluate(self.h, _ptr(stats), _stream(stream)))
@@ -342,10 +360,20 @@ class EAState:
         _check(load().ea_best(self.h, _ptr(x), _ptr(c), _stream(stream)))
         return x, c
 
+    def records(self, stream=None):
+        """(x [6][n], chi2 [n]) of every island's record, n = n_lc * n_islands."""
+        n = self.lcs.n_lc * self.cfg.n_islands
+        x = torch.empty((NPAR, n), dtype=torch.float64, device=self.lcs.t.device)
+        c = torch.empty(n, dtype=torch.float64, device=self.lcs.t.device)
+        _check(load().ea_records(self.h, _ptr(x), _ptr(c), _stream(stream)))
+        return x, c
+
     def refine(self, cfg=None, stats=None, stream=None):
-        """Simplex fine-tuning of every record; returns the steps taken."""
+        """Simplex fine-tuning of every record (one per island); returns the
+        steps taken [n_lc * n_islands]."""
         cfg = cfg or nm_default_config()
-        it = torch.empty(self.lcs.n_lc, dtype=torch.int32, device=self.lcs.t.device)
+        it = torch.empty(self.lcs.n_lc * self.cfg.n_islands, dtype=torch.int32,
+                         device=self.lcs.t.device)
         _check(load().ea_refine(self.h, ctypes.byref(cfg), _ptr(it), _ptr(stats),
                                 _stream(stream)))
         return it
@@ -370,21 +398,24 @@ def nm_default_config():
     return cfg
 
 
-def nm_refine(lcs, lo, hi, x0, cfg=None, stats=None, stream=None):
-    """(x [6][n_lc], chi2, Fs, Fb [n_lc], steps [n_lc] int32) from encoded
-    start points x0 [6][n_lc] in the domain [lo, hi]."""
+def nm_refine(lcs, lo, hi, x0, cfg=None, stats=None, stream=None, reps=1):
+    """(x [6][n], chi2, Fs, Fb [n], steps [n] int32) from encoded start
+    points x0 [6][n] in the domain [lo, hi], n = n_lc * reps: `reps`
+    simplices per lightcurve (simplex k * reps + i on lightcurve k)."""
     cfg = cfg or nm_default_config()
     x0 = _dev(x0)
-    n = lcs.n_lc
+    n = lcs.n_lc * reps
+    if x0.shape != (NPAR, n):
+        raise SblmError(f"x0 must be [6][{n}], got {tuple(x0.shape)}")
     dev = x0.device
     x = torch.empty_like(x0)
     c, fs, fb = (torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
     it = torch.empty(n, dtype=torch.int32, device=dev)
     lo_ = (ctypes.c_double * NPAR)(*[float(v) for v in lo])
     hi_ = (ctypes.c_double * NPAR)(*[float(v) for v in hi])
-    _check(load().nm_refine(ctypes.byref(lcs.desc), lo_, hi_, _ptr(x0), ctypes.byref(cfg),
-                            _ptr(x), _ptr(c), _ptr(fs), _ptr(fb), _ptr(it), _ptr(stats),
-                            _stream(stream)))
+    _check(load().nm_refine_multi(ctypes.byref(lcs.desc), reps, lo_, hi_, _ptr(x0),
+                                  ctypes.byref(cfg), _ptr(x), _ptr(c), _ptr(fs), _ptr(fb),
+                                  _ptr(it), _ptr(stats), _stream(stream)))
     return x, c, fs, fb, it
 
 

@@ -47,3 +47,32 @@ def test_oracle_is_not_imported_by_the_product():
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src, f
                 assert "sblm_oracle" not in src, f
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # sizes and field offsets of the header's structs, as gcc lays them out,
+    # against the ctypes mirrors of the binding
+    import shutil
+    import subprocess
+    from paper_1208_4830_amd import sblm
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    structs = {"ea_config": sblm.ea_config, "nm_config": sblm.nm_config,
+               "ea_lc_summary": sblm.ea_lc_summary, "sblm_lcs": sblm.sblm_lcs}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "sblm.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    for line in out.splitlines():
+        name, field, value = line.split()
+        cls = structs[name]
+        want = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert int(value) == want, (name, field, value, want)

@@ -99,3 +99,36 @@ def test_ea_refine_improves_records_only(hip):
     print(f"success before/after the simplex: {ok_before:.3f} / {ok_after:.3f}")
     assert ok_after >= ok_before
     st.close()
+
+
+def test_several_simplices_per_lightcurve(hip):
+    # nm_refine_multi: three starts per lightcurve (one lightcurve empty);
+    # simplex k * 3 + i follows the oracle simplex on lightcurve k
+    lengths, reps = [200, 0, 150], 3
+    wl = inputs.uniform_workload(43, len(lengths), 200)
+    ts, off = [], [0]
+    for k, L in enumerate(lengths):
+        ts.append(wl.t[k * 200:k * 200 + L])
+        off.append(off[-1] + L)
+    wl.t, wl.off = np.concatenate(ts), np.array(off, np.int64)
+    wl.sfrac, wl.noise = wl.sfrac[:wl.t.size], wl.noise[:wl.t.size]
+    y, w = oracle_lightcurves(wl)
+    lcs = device_lcs(hip, wl, y, w)
+    rng = np.random.default_rng(8)
+    x0 = rng.uniform(0.05, 0.95, (6, len(lengths) * reps))
+    cfg = hip.nm_default_config()
+    cfg.max_iter = 120
+    x, c, fs, fb, it = (a.cpu().numpy() for a in
+                        hip.nm_refine(lcs, LO, HI, torch.tensor(x0, device="cuda"), cfg,
+                                      reps=reps))
+    for k in range(len(lengths)):
+        sl = slice(off[k], off[k + 1])
+        for i in range(reps):
+            j = k * reps + i
+            xr, fr, steps, _, _ = NM.minimise(oracle_f(wl.t[sl], y[sl], w[sl]), x0[:, j],
+                                              cfg.tol_x, cfg.tol_f, cfg.max_iter)
+            assert it[j] == steps, (k, i, it[j], steps)
+            assert np.array_equal(x[:, j], xr), (k, i)
+            assert abs(c[j] - fr) <= 1e-8 * max(abs(fr), 1e-300) + 1e-14 * np.sum(w[sl] * y[sl] ** 2)
+    with pytest.raises(hip.SblmError):  # start points of the wrong shape
+        hip.nm_refine(lcs, LO, HI, torch.tensor(x0[:, :4], device="cuda"), cfg, reps=reps)
