@@ -90,3 +90,38 @@ def minimise(f, x0, tol_x=1e-4, tol_f=1e-4, max_iter=1200):
         steps += 1
         sim, fs = _order(sim, fs)
     return sim[0].copy(), fs[0], steps, sim, fs
+
+
+# ------------------------------------------------------------ iterated simplex
+#
+# The paper's iterated simplex (Sec. 4.1, the second of the compared
+# algorithms) deploys a fresh downhill simplex at each of a number of random
+# starting points in the search space, stops each run at convergence or
+# after 10^4 iterations, and keeps the best.  Readings taken here:
+#   T1  start points are uniform over the encoded domain [0, 1]^6 (the
+#       prior box); start s of lightcurve lc, coordinate g, is the Philox
+#       word of key (seed, lc), counter (0, PURPOSE_START, s, g // 4), word
+#       g % 4, mapped to the open unit interval;
+#   T2  each run is `minimise` above (S1-S2) with its own max_iter;
+#   T3  the result is the lowest value over all runs, the first start in
+#       index order among equal values; the work is the sum of the steps.
+
+PURPOSE_START = 7
+
+
+def start_point(seed, lc, s):
+    from . import oracle as O
+    return np.array([O.u01(O.draw(seed, lc, 0, PURPOSE_START, s, g)) for g in range(N)])
+
+
+def iterated(f, seed, lc, n_starts, tol_x=1e-4, tol_f=1e-4, max_iter=10000):
+    """(best x, best f, total steps, index of the best start) over starts
+    0 .. n_starts - 1 (T1-T3)."""
+    best = (None, np.inf, 0, -1)
+    total = 0
+    for s in range(n_starts):
+        x, fx, steps, _, _ = minimise(f, start_point(seed, lc, s), tol_x, tol_f, max_iter)
+        total += steps
+        if fx < best[1] or best[3] < 0:
+            best = (x, fx, 0, s)
+    return best[0], best[1], total, best[3]

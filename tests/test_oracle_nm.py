@@ -64,3 +64,41 @@ def test_nan_counts_as_worst():
     f = lambda x: float(np.sum((np.asarray(x) - 0.6) ** 2)) if np.max(np.abs(np.asarray(x) - 0.5)) < 0.3 else np.nan
     x, fx, _, _, _ = NM.minimise(f, np.full(6, 0.5), 1e-9, 1e-14, 3000)
     assert np.allclose(x, 0.6, atol=1e-5) and np.isfinite(fx)
+
+
+# ---------------------------------------------------------------- iterated simplex
+
+def test_start_points_are_numpy_philox_words():
+    # T1: start s of lightcurve lc is the block (0, 7, s, g // 4) of Philox
+    # keyed (seed, lc); numpy's generator increments its counter before it
+    # produces a block, so it is set one block back
+    seed, lc, s = 99, 5, 12
+    words = []
+    for blk in range(2):
+        bg = np.random.Philox(key=np.array([seed, lc], dtype=np.uint64),
+                              counter=np.array([2**64 - 1, 6, s, blk], dtype=np.uint64))
+        words += list(bg.random_raw(4))
+    want = np.array([((int(x) >> 12) + 0.5) * 2.0**-52 for x in words[:6]])
+    assert np.array_equal(NM.start_point(seed, lc, s), want)
+
+
+def test_iterated_ties_go_to_the_first_start():
+    # T3 on a constant function: every run ties, the first start wins
+    x, fx, total, s = NM.iterated(lambda x: 1.0, 3, 1, 4, max_iter=200)
+    assert s == 0 and fx == 1.0 and total > 0
+    assert np.max(np.abs(x - NM.start_point(3, 1, 0))) < 0.06
+
+
+def test_iterated_finds_the_global_basin():
+    # two bowls; the lower one at a: the best of several starts sits at a
+    a = np.full(6, 0.25)
+    b = np.full(6, 0.75)
+    f = lambda x: min(np.sum((x - a) ** 2), np.sum((x - b) ** 2) + 0.1)
+    x, fx, total, s = NM.iterated(f, 21, 0, 8, tol_x=1e-7, tol_f=1e-12, max_iter=4000)
+    assert fx < 1e-10 and np.max(np.abs(x - a)) < 1e-5
+    # a single start in the other basin ends at b's value instead
+    for k in range(8):
+        p = NM.start_point(21, 0, k)
+        if np.sum((p - b) ** 2) + 0.1 < np.sum((p - a) ** 2) - 0.3:
+            _, fk, _, _, _ = NM.minimise(f, p, 1e-7, 1e-12, 4000)
+            assert abs(fk - 0.1) < 1e-9
