@@ -90,6 +90,9 @@ def parse():
                     help="generations of the plain-vs-learned comparison on the ragged "
                          "workload (0 = skip it)")
     ap.add_argument("--learned-every", type=int, default=100)
+    ap.add_argument("--iterated", default="16,4,10000",
+                    help="iterated-simplex comparison: slots per lightcurve,runs per slot,"
+                         "max steps per run (empty: skip)")
     ap.add_argument("--islands", default="8,50,2",
                     help="island form for the success comparison: islands,migrate every,"
                          "migrants (empty: skip)")
@@ -280,6 +283,24 @@ def success_run(sblm, torch, lcs, chi2_true, pop, mode, sched, lo, hi, proposals
                               generations=hit_ea[0] if hit_ea else None,
                               gpu_seconds=hit_ea[1] if hit_ea else None,
                               fits_per_hour=per_hour(hit_ea)))
+
+
+def iterated_run(sblm, torch, lcs, chi2_true, lo, hi, reps, runs, max_iter, seed=7):
+    """The paper's iterated simplex (Sec. 4.1) on the GPU fitness: reps * runs
+    random starts per lightcurve, each run to convergence or max_iter steps,
+    the best kept; success and GPU time of the whole call."""
+    cfg = sblm.nm_default_config()
+    cfg.max_iter = max_iter
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, c, _, _, it = sblm.nm_iterated(lcs, lo, hi, reps, runs, seed, cfg)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dict(starts_per_lightcurve=reps * runs, slots=reps, runs_per_slot=runs,
+                max_steps_per_run=max_iter,
+                success=round(float(np.mean(c.cpu().numpy() <= chi2_true + 10.0)), 4),
+                gpu_seconds=round(dt, 3),
+                mean_steps_per_run=round(it.double().mean().item() / (reps * runs), 1))
 
 
 def train_proposals(sblm, torch, args):
@@ -504,6 +525,10 @@ def main():
                                              every=args.success_every, islands=isl)
             success["islands"]["config"] = dict(islands=isl[0], pop_per_island=args.pop // isl[0],
                                                 migrate_every=isl[1], migrants=isl[2])
+        if args.iterated:
+            success["iterated_simplex"] = iterated_run(sblm, torch, lcs, chi2_true, lo, hi,
+                                                       *(int(v) for v in
+                                                         args.iterated.split(",")))
         lrn = success["learned"]["ea_amoeba"]
         if lrn["gpu_seconds"] is not None:  # proposals are part of the learned fit's GPU time
             lrn["gpu_seconds"] += t_inf

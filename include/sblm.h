@@ -373,6 +373,30 @@ int nm_refine_multi(const sblm_lcs* lcs, int32_t reps, const double* lo,
                     double* x, double* chi2, double* Fs, double* Fb,
                     int32_t* n_iter, sblm_stats* stats, void* stream);
 
+/*
+ * nm_iterated -- the iterated simplex (the comparison algorithm of Sec. 4.1):
+ * simplices deployed at random start points, each run ended by convergence
+ * or max_iter steps, the best of all runs kept.  Every lightcurve gets reps
+ * slots; slot i runs starts i, i + reps, ..., i + reps * (runs - 1) one after
+ * another, a slot moving on as soon as its run ends.  Start s of lightcurve
+ * k, coordinate g: ((w >> 12) + 0.5) * 2^-52 for the Philox4x64-10 word
+ * w = word g % 4 of key (seed, k), counter (0, NM_PURPOSE_START, s, g / 4):
+ * uniform over the encoded domain (the prior box).  Each run is the simplex
+ * of nm_refine (settings above, cfg->max_iter per run).
+ *   reps, runs  >= 1; n_lc * reps <= 2^24; runs * (max_iter + 1) < 2^31
+ *   x       [6][n_lc] device out, encoded best point over the reps * runs
+ *           starts (lowest chi^2; the lowest start index among equals)
+ *   chi2, Fs, Fb  [n_lc] device out (nullable)
+ *   n_iter  [n_lc] device int64 out (nullable), steps of all runs
+ * Allocates and frees ~1.2 KB per slot; synchronises `stream`.  Errors:
+ * SBLM_EINVAL, SBLM_ERANGE, SBLM_ENOMEM, SBLM_EDEVICE.
+ */
+#define NM_PURPOSE_START 7
+int nm_iterated(const sblm_lcs* lcs, int32_t reps, int32_t runs, uint64_t seed,
+                const double* lo, const double* hi, const nm_config* cfg, double* x,
+                double* chi2, double* Fs, double* Fb, int64_t* n_iter,
+                sblm_stats* stats, void* stream);
+
 /* ea_best -- the fittest solution seen so far by every lightcurve's EA:
  * x [6][n_lc] device (encoded), chi2 [n_lc] device (nullable).  With
  * islands: the best island record (the lowest island index among equals). */

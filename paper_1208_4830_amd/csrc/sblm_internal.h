@@ -52,9 +52,23 @@ hipError_t launch_fitness(const FitArgs& a, int mode, bool chi2,
 // Batched downhill-simplex refinement (sblm_nm.hip): one simplex per
 // lightcurve from x0 [6][n_lc] (encoded with lo/span); results as for
 // nm_refine.  Allocates and frees its workspace; synchronises `st`.
+// Iterated simplex (nm_iterated): `runs` random starts per slot and where
+// the best per lightcurve goes.
+struct NmIterated {
+  uint64_t seed;
+  int32_t runs;
+  double* x;
+  double* chi2;
+  double* Fs;
+  double* Fb;
+  int64_t* n_iter;
+};
+// One simplex per (lightcurve, rep) from x0, or with `iter` the iterated
+// form from drawn starts (x0 and the per-simplex outputs unused).
 int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* span,
            const double* x0, const nm_config& cfg, double* x, double* chi2, double* Fs,
-           double* Fb, int32_t* n_iter, sblm_stats* stats, hipStream_t st);
+           double* Fb, int32_t* n_iter, sblm_stats* stats, hipStream_t st,
+           const NmIterated* iter = nullptr);
 int nm_check(const nm_config* cfg, const char* who);
 
 }  // namespace sblm

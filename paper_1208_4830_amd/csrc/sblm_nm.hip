@@ -1,7 +1,8 @@
-// sblm_nm.hip -- batched downhill-simplex refinement, one simplex per
-// lightcurve (the amoeba fine-tuning of the EA's fittest solution, Sec. 4.1
-// and the "EA with amoeba" rows of Tables 2-3; method of Nelder & Mead 1965
-// in the form of Lagarias, Reeds, Wright & Wright 1998).
+// sblm_nm.hip -- batched downhill-simplex refinement, one or several
+// simplices per lightcurve (the amoeba fine-tuning of the EA's fittest
+// solution, Sec. 4.1 and the "EA with amoeba" rows of Tables 2-3, and the
+// iterated simplex compared there; method of Nelder & Mead 1965 in the form
+// of Lagarias, Reeds, Wright & Wright 1998).
 //
 // The simplex lives in the EA's encoded domain [0, 1]^6 (Eq. EMMA-encoding):
 // reflection 1, expansion 2, contraction 1/2, shrink 1/2; the initial
@@ -19,11 +20,17 @@
 // six vertices of a shrink are evaluated over the next two rounds, and the
 // seven initial vertices over the first two.  The sequence of simplices is
 // that of the sequential algorithm.
+//
+// Iterated simplex (the comparison algorithm of Sec. 4.1): every slot of a
+// lightcurve runs simplices from random start points one after another; a
+// run that ends records its best vertex and the slot begins the next start
+// in the same round, so no slot waits for the others between runs.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include "sblm_internal.h"
+#include "sblm_rng.h"
 
 namespace sblm {
 namespace {
@@ -48,6 +55,17 @@ struct NmWork {
   int32_t* steps;  // [n]
   int32_t* done;   // [n] 1 once finished: its trial slots are not evaluated
   unsigned int* active;
+  // iterated mode: slot j = k * reps + i of lightcurve k runs the starts
+  // i, i + reps, ..., i + reps * (runs - 1)
+  int32_t iter, reps, runs;
+  uint64_t seed;
+  int32_t* run;    // [n] runs completed
+  int32_t* total;  // [n] steps over the completed runs
+  double* bX;      // [NP][n] best result of the completed runs
+  double* bF;      // [n]
+  double* bFs;
+  double* bFb;
+  int32_t* bS;     // [n] its start index, -1 before the first
 };
 
 __device__ __forceinline__ double clip01(double x) { return fmin(fmax(x, 0.0), 1.0); }
@@ -63,11 +81,10 @@ __device__ __forceinline__ void get_trial(const NmWork& w, int lc, int slot, dou
   for (int g = 0; g < NP; ++g) x[g] = w.T[(int64_t)g * w.n * NS + (int64_t)lc * NS + slot];
 }
 
-__global__ void nm_start_kernel(NmWork w, const double* x0) {
-  const int lc = blockIdx.x * blockDim.x + threadIdx.x;
-  if (lc >= w.n) return;
+// The initial simplex around x (clipped) and a fresh run.
+__device__ void begin_run(const NmWork& w, int lc, const double* x0) {
   double x[NP];
-  for (int g = 0; g < NP; ++g) x[g] = clip01(x0[(int64_t)g * w.n + lc]);
+  for (int g = 0; g < NP; ++g) x[g] = clip01(x0[g]);
   for (int v = 0; v < NV; ++v)
     for (int g = 0; g < NP; ++g) {
       double y = x[g];
@@ -77,6 +94,49 @@ __global__ void nm_start_kernel(NmWork w, const double* x0) {
     }
   w.phase[lc] = PH_INIT1;
   w.steps[lc] = 0;
+}
+
+// Start point of run c of slot lc (iterated mode): start s = i + reps * c of
+// lightcurve k, coordinate g = the open-interval map of the Philox word of
+// key (seed, k), counter (0, NM_PURPOSE_START, s, g / 4), word g % 4.
+__device__ void start_point(const NmWork& w, int lc, int c, double* x) {
+  const int k = lc / w.reps, i = lc - k * w.reps;
+  const Stream rs = {w.seed, (uint64_t)k, 0};
+  const uint64_t s = (uint64_t)i + (uint64_t)w.reps * (uint64_t)c;
+  for (int g = 0; g < NP; ++g) x[g] = u01(rs.draw(NM_PURPOSE_START, s, (uint64_t)g));
+}
+
+// A run of slot lc ends (iterated mode): its best vertex becomes the slot's
+// best when strictly lower (earlier starts win ties within a slot).
+__device__ void end_run(const NmWork& w, int lc) {
+  const int c = w.run[lc];
+  const int i = lc % w.reps;
+  const double f = w.F[lc];
+  if (w.bS[lc] < 0 || f < w.bF[lc]) {
+    for (int g = 0; g < NP; ++g) w.bX[(int64_t)g * w.n + lc] = vtx(w, 0, g, lc);
+    w.bF[lc] = f;
+    w.bFs[lc] = w.FsV[lc];
+    w.bFb[lc] = w.FbV[lc];
+    w.bS[lc] = i + w.reps * c;
+  }
+  w.total[lc] += w.steps[lc];
+  w.run[lc] = c + 1;
+}
+
+__global__ void nm_start_kernel(NmWork w, const double* x0) {
+  const int lc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lc >= w.n) return;
+  double x[NP];
+  if (w.iter) {
+    w.run[lc] = 0;
+    w.total[lc] = 0;
+    w.bS[lc] = -1;
+    w.bF[lc] = INFINITY;
+    start_point(w, lc, 0, x);
+  } else {
+    for (int g = 0; g < NP; ++g) x[g] = x0[(int64_t)g * w.n + lc];
+  }
+  begin_run(w, lc, x);
   w.done[lc] = 0;
 }
 
@@ -99,9 +159,16 @@ __global__ void nm_propose_kernel(NmWork w, double tol_x, double tol_f, int32_t 
       for (int g = 0; g < NP; ++g) dx = fmax(dx, fabs(vtx(w, v, g, lc) - vtx(w, 0, g, lc)));
     }
     if ((!undefined && dx <= tol_x && df <= tol_f) || w.steps[lc] >= max_iter) {
-      ph = PH_DONE;
-      w.phase[lc] = PH_DONE;
-      w.done[lc] = 1;
+      if (w.iter) end_run(w, lc);
+      if (w.iter && w.run[lc] < w.runs) {  // the slot's next start, this round
+        start_point(w, lc, w.run[lc], x);
+        begin_run(w, lc, x);
+        ph = PH_INIT1;
+      } else {
+        ph = PH_DONE;
+        w.phase[lc] = PH_DONE;
+        w.done[lc] = 1;
+      }
     }
   }
   switch (ph) {
@@ -261,6 +328,27 @@ __global__ void nm_finish_kernel(NmWork w, double* x, double* chi2, double* Fs, 
   if (n_iter) n_iter[lc] = w.steps[lc];
 }
 
+// Iterated mode: per lightcurve, the best over its slots (lowest chi^2, then
+// lowest start index) and the steps of all its runs.
+__global__ void nm_best_kernel(NmWork w, double* x, double* chi2, double* Fs, double* Fb,
+                               int64_t* n_iter) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n_lc = w.n / w.reps;
+  if (k >= n_lc) return;
+  int b = k * w.reps;
+  int64_t total = w.total[b];
+  for (int i = 1; i < w.reps; ++i) {
+    const int j = k * w.reps + i;
+    total += w.total[j];
+    if (w.bF[j] < w.bF[b] || (w.bF[j] == w.bF[b] && w.bS[j] < w.bS[b])) b = j;
+  }
+  for (int g = 0; g < NP; ++g) x[(int64_t)g * n_lc + k] = w.bX[(int64_t)g * w.n + b];
+  if (chi2) chi2[k] = w.bF[b];
+  if (Fs) Fs[k] = w.bFs[b];
+  if (Fb) Fb[k] = w.bFb[b];
+  if (n_iter) n_iter[k] = total;
+}
+
 }  // namespace
 
 int nm_check(const nm_config* cfg, const char* who) {
@@ -276,13 +364,18 @@ int nm_check(const nm_config* cfg, const char* who) {
 
 int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* span,
            const double* x0, const nm_config& cfg, double* x, double* chi2, double* Fs,
-           double* Fb, int32_t* n_iter, sblm_stats* stats, hipStream_t st) {
+           double* Fb, int32_t* n_iter, sblm_stats* stats, hipStream_t st,
+           const NmIterated* iter) {
   // simplex j = k * reps + i works on lightcurve k: its trial points are
   // individuals j * NS + slot, that is NS * reps individuals per lightcurve
   const int n = lcs.n_lc * reps;
   NmWork w;
   memset(&w, 0, sizeof(w));
   w.n = n;
+  w.reps = reps;
+  w.iter = iter != nullptr;
+  w.runs = iter ? iter->runs : 1;
+  w.seed = iter ? iter->seed : 0;
   const size_t nn = (size_t)n;
   bool ok = hipMalloc(&w.V, nn * NV * NP * 8) == hipSuccess &&
             hipMalloc(&w.F, nn * NV * 8) == hipSuccess &&
@@ -296,6 +389,11 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
             hipMalloc(&w.steps, nn * 4) == hipSuccess &&
             hipMalloc(&w.done, nn * 4) == hipSuccess &&
             hipMalloc(&w.active, 4) == hipSuccess;
+  if (ok && iter)
+    ok = hipMalloc(&w.run, nn * 4) == hipSuccess && hipMalloc(&w.total, nn * 4) == hipSuccess &&
+         hipMalloc(&w.bX, nn * NP * 8) == hipSuccess && hipMalloc(&w.bF, nn * 8) == hipSuccess &&
+         hipMalloc(&w.bFs, nn * 8) == hipSuccess && hipMalloc(&w.bFb, nn * 8) == hipSuccess &&
+         hipMalloc(&w.bS, nn * 4) == hipSuccess;
   int rc = SBLM_OK;
   if (!ok) {
     (void)hipGetLastError();
@@ -330,8 +428,8 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
     hipLaunchKernelGGL(nm_start_kernel, grid, blk, 0, st, w, x0);
     rc = check_hip(hipGetLastError(), "nm_refine: start");
   }
-  // rounds: 2 for the initial simplex, 1 per step, 2 more per shrink
-  const int64_t max_rounds = 4 + 3 * (int64_t)cfg.max_iter;
+  // rounds per run: 2 for the initial simplex, 1 per step, 2 more per shrink
+  const int64_t max_rounds = (4 + 3 * (int64_t)cfg.max_iter) * w.runs;
   const int chunk = 16;
   for (int64_t r = 0; rc == SBLM_OK && r < max_rounds; r += chunk) {
     for (int k = 0; k < chunk && rc == SBLM_OK; ++k) {
@@ -353,14 +451,19 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
     if (rc == SBLM_OK) rc = check_hip(hipStreamSynchronize(st), "nm_refine: synchronise");
     if (active == 0) break;
   }
-  if (rc == SBLM_OK) {
+  if (rc == SBLM_OK && !iter) {
     hipLaunchKernelGGL(nm_finish_kernel, grid, blk, 0, st, w, x, chi2, Fs, Fb, n_iter);
     rc = check_hip(hipGetLastError(), "nm_refine: finish");
   }
+  if (rc == SBLM_OK && iter) {
+    hipLaunchKernelGGL(nm_best_kernel, dim3((lcs.n_lc + 255) / 256), blk, 0, st, w, iter->x,
+                       iter->chi2, iter->Fs, iter->Fb, iter->n_iter);
+    rc = check_hip(hipGetLastError(), "nm_iterated: finish");
+  }
   if (hipStreamSynchronize(st) != hipSuccess && rc == SBLM_OK)
     rc = check_hip(hipGetLastError(), "nm_refine: synchronise");
-  void* bufs[] = {w.V,     w.F,     w.FsV,  w.FbV,  w.T,      w.cT,
-                  w.fsT,   w.fbT,   w.phase, w.steps, w.done, w.active};
+  void* bufs[] = {w.V,    w.F,    w.FsV,  w.FbV,  w.T,   w.cT,  w.fsT, w.fbT, w.phase, w.steps,
+                  w.done, w.active, w.run, w.total, w.bX, w.bF, w.bFs, w.bFb, w.bS};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   return rc;
@@ -398,6 +501,33 @@ extern "C" int nm_refine_multi(const sblm_lcs* lcs, int32_t reps, const double* 
   }
   return nm_run(*lcs, reps, lo, span, x0, *cfg, x, chi2, Fs, Fb, n_iter, stats,
                 (hipStream_t)stream);
+}
+
+extern "C" int nm_iterated(const sblm_lcs* lcs, int32_t reps, int32_t runs, uint64_t seed,
+                           const double* lo, const double* hi, const nm_config* cfg, double* x,
+                           double* chi2, double* Fs, double* Fb, int64_t* n_iter,
+                           sblm_stats* stats, void* stream) {
+  int rc = nm_check(cfg, "nm_iterated");
+  if (rc) return rc;
+  if (!lcs || !lcs->off || !lcs->t || !lcs->y || !lcs->w)
+    return set_error(SBLM_EINVAL, "nm_iterated: null lightcurve descriptor or array");
+  if (lcs->n_lc < 1) return set_error(SBLM_EINVAL, "nm_iterated: n_lc < 1");
+  if (reps < 1 || runs < 1)
+    return set_error(SBLM_EINVAL, "nm_iterated: reps = %d, runs = %d", reps, runs);
+  if ((int64_t)lcs->n_lc * reps > (1 << 24))
+    return set_error(SBLM_ERANGE, "nm_iterated: n_lc * reps beyond 2^24");
+  if ((int64_t)reps * runs > (1LL << 31) - 1 ||
+      (int64_t)runs * (cfg->max_iter + 1) > (1LL << 31) - 1)
+    return set_error(SBLM_ERANGE, "nm_iterated: too many starts or steps per slot");
+  if (!lo || !hi || !x) return set_error(SBLM_EINVAL, "nm_iterated: null lo, hi or x");
+  double span[SBLM_NPAR];
+  for (int g = 0; g < SBLM_NPAR; ++g) {
+    if (!(hi[g] > lo[g])) return set_error(SBLM_EINVAL, "nm_iterated: hi[%d] <= lo[%d]", g, g);
+    span[g] = hi[g] - lo[g];
+  }
+  NmIterated it = {seed, runs, x, chi2, Fs, Fb, n_iter};
+  return nm_run(*lcs, reps, lo, span, nullptr, *cfg, nullptr, nullptr, nullptr, nullptr, nullptr,
+                stats, (hipStream_t)stream, &it);
 }
 
 extern "C" int nm_refine(const sblm_lcs* lcs, const double* lo, const double* hi,

@@ -112,6 +112,9 @@ _SIGS = {
                         ctypes.POINTER(nm_config), ctypes.c_void_p, ctypes.c_void_p,
                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                         ctypes.c_void_p],
+    "nm_iterated": [ctypes.POINTER(sblm_lcs), ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                    ctypes.POINTER(nm_config)] + [ctypes.c_void_p] * 7,
     "ea_best": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "ea_records": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "ea_refine": [ctypes.c_void_p, ctypes.POINTER(nm_config), ctypes.c_void_p, ctypes.c_void_p,
@@ -416,6 +419,24 @@ def nm_refine(lcs, lo, hi, x0, cfg=None, stats=None, stream=None, reps=1):
     _check(load().nm_refine_multi(ctypes.byref(lcs.desc), reps, lo_, hi_, _ptr(x0),
                                   ctypes.byref(cfg), _ptr(x), _ptr(c), _ptr(fs), _ptr(fb),
                                   _ptr(it), _ptr(stats), _stream(stream)))
+    return x, c, fs, fb, it
+
+
+def nm_iterated(lcs, lo, hi, reps, runs, seed, cfg=None, stats=None, stream=None,
+                device="cuda"):
+    """Iterated simplex: (x [6][n_lc] encoded, chi2, Fs, Fb [n_lc], steps
+    [n_lc] int64) best over reps * runs random starts per lightcurve."""
+    cfg = cfg or nm_default_config()
+    n = lcs.n_lc
+    dev = lcs.t.device if lcs.t is not None else device
+    x = torch.empty((NPAR, n), dtype=torch.float64, device=dev)
+    c, fs, fb = (torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
+    it = torch.empty(n, dtype=torch.int64, device=dev)
+    lo_ = (ctypes.c_double * NPAR)(*[float(v) for v in lo])
+    hi_ = (ctypes.c_double * NPAR)(*[float(v) for v in hi])
+    _check(load().nm_iterated(ctypes.byref(lcs.desc), reps, runs, seed, lo_, hi_,
+                              ctypes.byref(cfg), _ptr(x), _ptr(c), _ptr(fs), _ptr(fb),
+                              _ptr(it), _ptr(stats), _stream(stream)))
     return x, c, fs, fb, it
 
 

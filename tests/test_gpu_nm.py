@@ -132,3 +132,33 @@ def test_several_simplices_per_lightcurve(hip):
             assert abs(c[j] - fr) <= 1e-8 * max(abs(fr), 1e-300) + 1e-14 * np.sum(w[sl] * y[sl] ** 2)
     with pytest.raises(hip.SblmError):  # start points of the wrong shape
         hip.nm_refine(lcs, LO, HI, torch.tensor(x0[:, :4], device="cuda"), cfg, reps=reps)
+
+
+def test_iterated_simplex_matches_oracle(hip):
+    # nm_iterated: 2 slots x 2 runs per lightcurve from Philox starts; the
+    # best run, its start index order on ties and the total steps follow the
+    # oracle's sequential loop over the same starts
+    lengths = [180, 0, 120]
+    wl = inputs.uniform_workload(44, len(lengths), 180)
+    ts, off = [], [0]
+    for k, L in enumerate(lengths):
+        ts.append(wl.t[k * 180:k * 180 + L])
+        off.append(off[-1] + L)
+    wl.t, wl.off = np.concatenate(ts), np.array(off, np.int64)
+    wl.sfrac, wl.noise = wl.sfrac[:wl.t.size], wl.noise[:wl.t.size]
+    y, w = oracle_lightcurves(wl)
+    lcs = device_lcs(hip, wl, y, w)
+    cfg = hip.nm_default_config()
+    cfg.max_iter = 60
+    reps, runs, seed = 2, 2, 1234
+    x, c, fs, fb, it = (a.cpu().numpy() for a in
+                        hip.nm_iterated(lcs, LO, HI, reps, runs, seed, cfg))
+    for k in range(len(lengths)):
+        sl = slice(off[k], off[k + 1])
+        xr, fr, total, s = NM.iterated(oracle_f(wl.t[sl], y[sl], w[sl]), seed, k, reps * runs,
+                                       cfg.tol_x, cfg.tol_f, cfg.max_iter)
+        assert it[k] == total, (k, it[k], total)
+        assert np.array_equal(x[:, k], xr), (k, s)
+        assert abs(c[k] - fr) <= 1e-8 * max(abs(fr), 1e-300) + 1e-14 * np.sum(w[sl] * y[sl] ** 2)
+    with pytest.raises(hip.SblmError):
+        hip.nm_iterated(lcs, LO, HI, 0, runs, seed, cfg)
