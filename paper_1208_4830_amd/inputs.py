@@ -111,3 +111,63 @@ def ragged_workload(seed, n_lc, L_min=200, L_max=5000):
 def population(rng, n_lc, pop):
     """Random encoded population P[6][n_lc*pop], entries in (0,1)."""
     return rng.random((6, n_lc * pop))
+
+
+# ------------------------------------------------ the paper's own experiments
+#
+# Table 1 ranges (the paper's a, b, m0, q, theta, tE, tm are the library's
+# d, u0, m0, q, alpha, tE, t0), 100 points per lightcurve between a start in
+# tm + tE (-3, -2) and an end in tm + tE (2, 3) (Sec. 4.2).  Experiment 1
+# (Table 2): uniform sampling, no noise, no blending.  Experiment 2 (Table
+# 3): times uniform at random in (t_start, t_end), Gaussian magnitude noise
+# and a blend fraction f.  Only draws here; magnitudes, the noise model and
+# fluxes are assembled by the caller.
+
+PAPER_LO = np.array([-1.0, 0.6, 0.001, 0.0, 5.0, -20.0])  # log10 q for q in [0.1, 1]
+PAPER_HI = np.array([0.0, 1.7, 1.0, 2.0 * np.pi, 50.0, 20.0])
+PAPER_M0 = (18.0, 22.0)
+
+
+@dataclass
+class PaperWorkload:
+    """Lightcurves of the paper's experiments before magnitudes are made."""
+    experiment: int       # 1 (Table 2) or 2 (Table 3)
+    theta: np.ndarray     # [6][n_lc] true parameters, library order
+    m0: np.ndarray        # [n_lc] baseline magnitude
+    f: np.ndarray         # [n_lc] blend fraction (1 in experiment 1)
+    t_start: np.ndarray   # [n_lc]
+    t_end: np.ndarray     # [n_lc]
+    off: np.ndarray       # [n_lc+1] CSR offsets (int64)
+    t: np.ndarray         # [off[-1]] epochs
+    noise: np.ndarray     # [off[-1]] standard normal draws (experiment 2)
+
+    @property
+    def n_lc(self):
+        return self.off.shape[0] - 1
+
+
+def paper_workload(seed, n_lc, experiment, L=100):
+    """n_lc lightcurves of experiment 1 or 2, L points each.  q is drawn
+    uniformly in [0.1, 1] (the table's range), the others uniformly in
+    theirs; f ~ U(0, 1] in experiment 2."""
+    if experiment not in (1, 2):
+        raise ValueError("experiment is 1 or 2")
+    rng = np.random.default_rng(seed)
+    theta = np.empty((6, n_lc))
+    theta[0] = np.log10(rng.uniform(0.1, 1.0, n_lc))
+    for j in range(1, 6):
+        theta[j] = rng.uniform(PAPER_LO[j], PAPER_HI[j], n_lc)
+    m0 = rng.uniform(PAPER_M0[0], PAPER_M0[1], n_lc)
+    f = np.ones(n_lc) if experiment == 1 else 1.0 - rng.random(n_lc)
+    tE, tm = theta[4], theta[5]
+    t_start = tm + tE * rng.uniform(-3.0, -2.0, n_lc)
+    t_end = tm + tE * rng.uniform(2.0, 3.0, n_lc)
+    if experiment == 1:
+        k = np.arange(L) / (L - 1)
+        t = t_start[:, None] + (t_end - t_start)[:, None] * k[None, :]
+    else:
+        t = np.sort(t_start[:, None] + (t_end - t_start)[:, None] * rng.random((n_lc, L)),
+                    axis=1)
+    off = np.arange(n_lc + 1, dtype=np.int64) * L
+    return PaperWorkload(experiment, theta, m0, f, t_start, t_end, off, t.ravel(),
+                         rng.standard_normal(n_lc * L))
