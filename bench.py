@@ -93,6 +93,9 @@ def parse():
     ap.add_argument("--iterated", default="16,4,10000",
                     help="iterated-simplex comparison: slots per lightcurve,runs per slot,"
                          "max steps per run (empty: skip)")
+    ap.add_argument("--paper-lc", type=int, default=256,
+                    help="lightcurves per paper-shaped experiment (Tables 2-3); 0 skips")
+    ap.add_argument("--paper-checkpoints", default="500,1000,3000")
     ap.add_argument("--islands", default="8,50,2",
                     help="island form for the success comparison: islands,migrate every,"
                          "migrants (empty: skip)")
@@ -535,6 +538,18 @@ def main():
             lrn["fits_per_hour"] = args.n_lc * 3600.0 / lrn["gpu_seconds"]
         log(f"bench: success: {json.dumps(success)}")
 
+    paper = None
+    if args.paper_lc > 0:
+        from paper_1208_4830_amd import experiments
+        cps = tuple(int(v) for v in args.paper_checkpoints.split(","))
+        paper = {}
+        for exp in (1, 2):
+            log(f"bench: paper experiment {exp} (Table {exp + 1} shape), {args.paper_lc} "
+                f"lightcurves of 100 points, pop 1000")
+            paper[f"experiment_{exp}"] = experiments.run_experiment(
+                sblm, torch, exp, n_lc=args.paper_lc, pop=1000, checkpoints=cps)
+            log(f"bench: paper {exp}: {json.dumps(paper[f'experiment_{exp}'])}")
+
     ragged = None
     learned = None
     if args.ragged_lc > 0:
@@ -584,6 +599,7 @@ def main():
         "forms": forms,
         "ragged": ragged,
         "learned": learned,
+        "paper_tables": paper,
         "roofline": {"bound": "alu", "achieved": main_form["kernel_tflops"],
                      "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": main_form["kernel_tflops"] / PEAK_VALU_TFLOPS,
