@@ -211,3 +211,32 @@ def test_island_config_errors(hip):
     rc = lib.ea_migrate(st.h, ctypes.c_void_p(c.data_ptr()), None, None, None)
     assert rc != 0  # some but not all fitness pointers
     st.close()
+
+
+def test_islands_full_size_sampled(hip):
+    # the batched set (256 lightcurves x 1000 epochs) with the islands of the
+    # bench's comparison (8 x 32 rows, 2 migrants), migrating every
+    # generation, in the bench's schedule; sampled lightcurves follow the
+    # island oracle driven by the device fitness through a migration
+    from paper_1208_4830_amd import inputs
+    wl = inputs.uniform_workload(2, 256, 1000)
+    pop, n_isl, m = 32, 8, 2
+    st, _, _ = _state(hip, wl, pop, 7, n_isl, 1, m)
+    st.set_schedule(16, 4, 1, 0)
+    sample = [0, 97, 255]
+    isls = {k: IS.IslandEA(n_isl, pop, 7, k, 1, m) for k in sample}
+    for g in range(2):
+        st.evaluate()
+        c, f, b = (st.view(n).cpu().numpy().copy() for n in ("chi2", "Fs", "Fb"))
+        st.fit(1)  # evaluates the same rows again, migrates when due, steps
+        for k in sample:
+            sl = slice(k * n_isl * pop, (k + 1) * n_isl * pop)
+            isls[k].generation(c[sl], f[sl], b[sl])
+    torch.cuda.synchronize()
+    _, P, rec = hip.parse_snapshot(st.save())
+    for k in sample:
+        cols = slice(k * n_isl * pop, (k + 1) * n_isl * pop)
+        assert np.array_equal(P[:, cols].T, isls[k].rows()), k
+        i, s = isls[k].best()
+        assert rec["best_chi2"][k * n_isl + i] == s["best_chi2"]
+    st.close()

@@ -162,3 +162,47 @@ def test_iterated_simplex_matches_oracle(hip):
         assert abs(c[k] - fr) <= 1e-8 * max(abs(fr), 1e-300) + 1e-14 * np.sum(w[sl] * y[sl] ** 2)
     with pytest.raises(hip.SblmError):
         hip.nm_iterated(lcs, LO, HI, 0, runs, seed, cfg)
+
+
+def test_multi_and_iterated_full_size_sampled(hip):
+    # the batched set (256 lightcurves x 1000 epochs) in the bench's launch
+    # configurations: 8 simplices per lightcurve (the islands' fine-tuning),
+    # sampled simplices against the oracle; the iterated simplex with 16
+    # slots x 4 runs of up to 10^4 steps, checked by properties on samples
+    wl = inputs.uniform_workload(2, 256, 1000)
+    y, w = oracle_lightcurves(wl)
+    lcs = device_lcs(hip, wl, y, w)
+    rng = np.random.default_rng(12)
+    reps = 8
+    # starts near the truth, as the islands' records are: from random starts
+    # a simplex can meet chi^2 values equal to rounding (flat regions far from
+    # the data), where the accept decisions of two correct evaluations differ;
+    # random starts are covered by the property checks below
+    x_true = (wl.theta - LO[:, None]) / (HI - LO)[:, None]
+    x0 = np.clip(np.repeat(x_true, reps, axis=1)
+                 + rng.normal(scale=0.02, size=(6, wl.n_lc * reps)), 0, 1)
+    cfg = hip.nm_default_config()
+    x, c, fs, fb, it = (a.cpu().numpy() for a in
+                        hip.nm_refine(lcs, LO, HI, torch.tensor(x0, device="cuda"), cfg,
+                                      reps=reps))
+    for j in (5, 1000, 2047):
+        k = j // reps
+        sl = slice(wl.off[k], wl.off[k + 1])
+        xr, fr, steps, _, _ = NM.minimise(oracle_f(wl.t[sl], y[sl], w[sl]), x0[:, j],
+                                          cfg.tol_x, cfg.tol_f, cfg.max_iter)
+        assert it[j] == steps, (j, it[j], steps)
+        assert np.array_equal(x[:, j], xr), j
+        assert abs(c[j] - fr) <= 1e-8 * fr
+    cfg.max_iter = 10000
+    reps, runs, seed = 16, 4, 7
+    x, c, fs, fb, it = (a.cpu().numpy() for a in
+                        hip.nm_iterated(lcs, LO, HI, reps, runs, seed, cfg))
+    for k in (0, 128, 255):
+        sl = slice(wl.off[k], wl.off[k + 1])
+        f = oracle_f(wl.t[sl], y[sl], w[sl])
+        # the reported point has the reported chi^2, no start is fitter than
+        # the result, and every run took at least one step
+        assert abs(f(x[:, k]) - c[k]) <= 1e-8 * c[k]
+        for s in range(reps * runs):
+            assert c[k] <= f(NM.start_point(seed, k, s)) * (1 + 1e-12)
+        assert it[k] >= reps * runs
