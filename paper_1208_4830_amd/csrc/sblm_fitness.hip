@@ -518,8 +518,14 @@ template <int G>
 __device__ __forceinline__ Item item_setup(const FitArgs& a, int64_t wave_item) {
   Item x;
   const int lane = threadIdx.x & 63;
-  x.gl = lane & (G - 1);
-  const int64_t item = wave_item * (64 / G) + (lane / G);
+  int64_t item;
+  if constexpr (G > 64) {  // G / 64 waves per individual: wave item = (individual, part)
+    item = wave_item / (G / 64);
+    x.gl = (int)(wave_item % (G / 64)) * 64 + lane;
+  } else {
+    x.gl = lane & (G - 1);
+    item = wave_item * (64 / G) + (lane / G);
+  }
   x.valid = item < a.n_ind;
   x.ind = x.valid ? (a.order ? (int64_t)a.order[item] : item) : 0;
   // parameters of this individual (uniform within the group)
@@ -571,28 +577,65 @@ __device__ __forceinline__ bool epoch_poly(const Item& x, double t, cx<double>& 
   return deg4;
 }
 
+// Per-lane history of the roots of the two epochs before the current one,
+// kept in LDS (touched once per epoch, at the warm start; in registers it
+// would hold 40 VGPRs through the whole solve).  Dynamic shared memory of
+// ROOT_HIST_BYTES per thread; element [((slot*5 + i)*2 + part) * blockDim.x +
+// thread] holds root i of epoch slot (0: previous but one, 1: the one
+// before), real (part 0) or imaginary (part 1).
+constexpr size_t ROOT_HIST_BYTES = 2 * 5 * 2 * sizeof(double);
+
+// Dynamic shared memory: the root history, then (G > 64) one least-squares
+// state per wave for the merge across the waves of an individual.
+extern __shared__ double fit_dyn_smem[];
+
 // Merge the lanes' least-squares states of each group (fixed tree) and write
-// chi^2, Fs, Fb of the group's individual.
+// chi^2, Fs, Fb of the group's individual.  With G > 64 each wave merges its
+// 64 lanes the same way, and the first wave of the individual then absorbs
+// the states of the others in wave order (all waves of the block pass one
+// barrier here).
 template <int G>
 __device__ __forceinline__ void finish_chi2(const FitArgs& a, const Item& x, Lsq ls) {
+  constexpr int GW = G > 64 ? 64 : G;  // lanes merged by shuffles
   const int gl = x.gl;
   const bool valid = x.valid;
   const int64_t ind = x.ind;
   {
-    // lane gl absorbs lane gl + off: fixed tree inside each group
+    // lane gl absorbs lane gl + off: fixed tree inside each group (wave)
 #pragma unroll
-    for (int off = G / 2; off >= 1; off >>= 1) {
+    for (int off = GW / 2; off >= 1; off >>= 1) {
       Lsq o;
-      o.d1 = grp_shfl_down<G>(ls.d1, off);
-      o.d2 = grp_shfl_down<G>(ls.d2, off);
-      o.r12 = grp_shfl_down<G>(ls.r12, off);
-      o.t1 = grp_shfl_down<G>(ls.t1, off);
-      o.t2 = grp_shfl_down<G>(ls.t2, off);
-      o.sse = grp_shfl_down<G>(ls.sse, off);
-      if (gl < off) {
+      o.d1 = grp_shfl_down<GW>(ls.d1, off);
+      o.d2 = grp_shfl_down<GW>(ls.d2, off);
+      o.r12 = grp_shfl_down<GW>(ls.r12, off);
+      o.t1 = grp_shfl_down<GW>(ls.t1, off);
+      o.t2 = grp_shfl_down<GW>(ls.t2, off);
+      o.sse = grp_shfl_down<GW>(ls.sse, off);
+      if ((gl & (GW - 1)) < off) {
         lsq_include(ls, o.d1, 1.0, o.r12, o.t1);
         lsq_include(ls, o.d2, 0.0, 1.0, o.t2);
         ls.sse += o.sse;
+      }
+    }
+    if constexpr (G > 64) {
+      double* part = fit_dyn_smem + (ROOT_HIST_BYTES / sizeof(double)) * blockDim.x;
+      const int w = threadIdx.x >> 6;
+      if ((threadIdx.x & 63) == 0) {
+        part[w * 6 + 0] = ls.d1;
+        part[w * 6 + 1] = ls.d2;
+        part[w * 6 + 2] = ls.r12;
+        part[w * 6 + 3] = ls.t1;
+        part[w * 6 + 4] = ls.t2;
+        part[w * 6 + 5] = ls.sse;
+      }
+      __syncthreads();
+      if (gl == 0) {
+        for (int p = 1; p < G / 64; ++p) {
+          const double* o = part + (w + p) * 6;
+          lsq_include(ls, o[0], 1.0, o[2], o[3]);
+          lsq_include(ls, o[1], 0.0, 1.0, o[4]);
+          ls.sse += o[5];
+        }
       }
     }
     if (gl == 0 && valid) {
@@ -617,14 +660,6 @@ __device__ __forceinline__ void finish_chi2(const FitArgs& a, const Item& x, Lsq
 
 }
 
-// Per-lane history of the roots of the two epochs before the current one,
-// kept in LDS (touched once per epoch, at the warm start; in registers it
-// would hold 40 VGPRs through the whole solve).  Dynamic shared memory of
-// ROOT_HIST_BYTES per thread; element [((slot*5 + i)*2 + part) * blockDim.x +
-// thread] holds root i of epoch slot (0: previous but one, 1: the one
-// before), real (part 0) or imaginary (part 1).
-constexpr size_t ROOT_HIST_BYTES = 2 * 5 * 2 * sizeof(double);
-
 struct RootHist {
   double* h;
   __device__ __forceinline__ cx<double> get(int slot, int i) const {
@@ -638,8 +673,6 @@ struct RootHist {
     h[((slot * 5 + i) * 2 + 1) * n + threadIdx.x] = v.im;
   }
 };
-
-extern __shared__ double fit_dyn_smem[];
 
 // One wave's share of the work, lockstep form: 64/G individuals (items
 // wave_item*64/G ...); every lane solves its s-th epoch at the same time and
@@ -866,21 +899,21 @@ template <int MODE, bool CHI2, int G, int PERSIST, int ASYNC>
 __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitness_kernel(
     FitArgs a) {
   // (blocks of at most 256 threads: launch_gg refuses larger ones)
-  constexpr int GPW = 64 / G;  // individuals per wave
+  constexpr int GPW = G > 64 ? 1 : 64 / G;  // individuals per wave
   const int lane = threadIdx.x & 63;
   LaneStats st = {0, 0, 0, 0, 0, 0, 0, 0};
   // One-shot grid: wave w takes wave item w (blocks remapped so that
   // consecutive logical blocks sit on one XCD).  Persistent grid: waves take
   // items from a shared counter until it runs past the last one, so every
   // wave reaches the exit.  One call site keeps one inlined copy of the body.
-  const int64_t n_wave_items = (a.n_ind + GPW - 1) / GPW;
-  if (PERSIST) {
+  const int64_t n_wave_items = G > 64 ? a.n_ind * (G / 64) : (a.n_ind + GPW - 1) / GPW;
+  if constexpr (PERSIST) {
     for (;;) {
       unsigned int v = 0;
       if (lane == 0) v = atomicAdd(a.queue, 1u);
       const int64_t wi = (int64_t)__shfl(v, 0, 64);
       if (wi >= n_wave_items) break;
-      if (ASYNC)
+      if constexpr (ASYNC)
         fit_wave_async<MODE, CHI2, G>(a, wi, st);
       else
         fit_wave<MODE, CHI2, G>(a, wi, st);
@@ -891,7 +924,7 @@ __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitn
     const int lb = (xcd < rem) ? xcd * (per + 1) + idx
                                : rem * (per + 1) + (xcd - rem) * per + idx;
     const int64_t wi = (int64_t)lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (ASYNC)
+    if constexpr (ASYNC)
       fit_wave_async<MODE, CHI2, G>(a, wi, st);
     else
       fit_wave<MODE, CHI2, G>(a, wi, st);
@@ -927,30 +960,48 @@ __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitn
 template <int MODE, bool CHI2, int G>
 static hipError_t launch_gg(const FitArgs& a, hipStream_t s, int wpb) {
   if (wpb < 1 || 64 * wpb > SBLM_FIT_MAX_THREADS) return hipErrorInvalidConfiguration;
-  const size_t smem = ROOT_HIST_BYTES * 64 * wpb;
-  const int64_t groups_per_block = (int64_t)wpb * (64 / G);
-  int64_t nblk = (a.n_ind + groups_per_block - 1) / groups_per_block;
-  if (nblk <= 0) return hipSuccess;
-  auto kern = a.async ? (a.queue ? fitness_kernel<MODE, CHI2, G, 1, 1>
-                                 : fitness_kernel<MODE, CHI2, G, 0, 1>)
-                      : (a.queue ? fitness_kernel<MODE, CHI2, G, 1, 0>
-                                 : fitness_kernel<MODE, CHI2, G, 0, 0>);
-  if (a.queue) {  // persistent grid: as many blocks as can be resident
-    int dev = 0, ncu = 0, per_cu = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wpb, smem);
-    if (e != hipSuccess) return e;
-    const int64_t resident = (int64_t)(per_cu > 0 ? per_cu : 1) * ncu;
-    nblk = nblk < resident ? nblk : resident;
+  if constexpr (G > 64) {
+    // several waves per individual: chi^2 only, one-shot grid, lockstep,
+    // whole individuals in every block (their waves meet at the merge)
+    constexpr int P = G / 64;
+    if (!CHI2 || a.queue || a.async || wpb % P != 0) return hipErrorInvalidConfiguration;
+    const size_t smem = ROOT_HIST_BYTES * 64 * wpb + 6 * sizeof(double) * wpb;
+    const int64_t nblk = (a.n_ind * P + wpb - 1) / wpb;
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL((fitness_kernel<MODE, CHI2, G, 0, 0>), dim3((unsigned)nblk),
+                       dim3(64 * wpb), smem, s, a);
+    return hipGetLastError();
+  } else {
+    const size_t smem = ROOT_HIST_BYTES * 64 * wpb;
+    const int64_t groups_per_block = (int64_t)wpb * (64 / G);
+    int64_t nblk = (a.n_ind + groups_per_block - 1) / groups_per_block;
+    if (nblk <= 0) return hipSuccess;
+    auto kern = a.async ? (a.queue ? fitness_kernel<MODE, CHI2, G, 1, 1>
+                                   : fitness_kernel<MODE, CHI2, G, 0, 1>)
+                        : (a.queue ? fitness_kernel<MODE, CHI2, G, 1, 0>
+                                   : fitness_kernel<MODE, CHI2, G, 0, 0>);
+    if (a.queue) {  // persistent grid: as many blocks as can be resident
+      int dev = 0, ncu = 0, per_cu = 0;
+      hipError_t e = hipGetDevice(&dev);
+      if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wpb, smem);
+      if (e != hipSuccess) return e;
+      const int64_t resident = (int64_t)(per_cu > 0 ? per_cu : 1) * ncu;
+      nblk = nblk < resident ? nblk : resident;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(64 * wpb), smem, s, a);
+    return hipGetLastError();
   }
-  hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(64 * wpb), smem, s, a);
-  return hipGetLastError();
 }
 
 template <int MODE, bool CHI2>
 static hipError_t launch_g(const FitArgs& a, hipStream_t s, int wpb) {
+  if constexpr (CHI2) {
+    if (a.lanes_per_ind == 256) return launch_gg<MODE, CHI2, 256>(a, s, wpb);
+    if (a.lanes_per_ind == 128) return launch_gg<MODE, CHI2, 128>(a, s, wpb);
+  }
+  if (a.lanes_per_ind > 64) return hipErrorInvalidConfiguration;
   if (a.lanes_per_ind == 64) return launch_gg<MODE, CHI2, 64>(a, s, wpb);
   if (a.lanes_per_ind == 32) return launch_gg<MODE, CHI2, 32>(a, s, wpb);
   if (a.lanes_per_ind == 8) return launch_gg<MODE, CHI2, 8>(a, s, wpb);

@@ -37,7 +37,9 @@ struct FitArgs {
   sblm_stats* stats;  // nullable
   // schedule
   const int32_t* order;  // nullable: item -> individual permutation
-  int32_t lanes_per_ind;  // 64, 32, 16 or 8 (a power of two dividing 64)
+  int32_t lanes_per_ind;  // 64, 32, 16 or 8 (a power of two dividing 64), or
+                          // 128 / 256: several waves per individual (chi^2
+                          // only, one-shot lockstep, wpb a multiple of G/64)
   unsigned int* queue;    // nullable: persistent launch, shared work counter
                           // (must read 0 when the kernel starts)
   int32_t async;          // 1: lanes step through their epochs independently

@@ -420,9 +420,18 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
   a.skip = w.done;  // a finished simplex's trial points are not evaluated
   a.skip_per = NS;
   // rounds are latency-bound (each waits for its longest lightcurve, and
-  // later rounds hold only the unfinished simplices): 64 lanes per
-  // individual give the shortest chain of epochs per lane
-  a.lanes_per_ind = 64;
+  // later rounds hold only the unfinished simplices): a trial point spread
+  // over several waves shortens the chain of epochs per lane, at the price
+  // of a cold start per lane.  The widest of 256, 128 and 64 lanes that
+  // keeps the launch within 32768 waves (32 per compute unit); measured:
+  // 256 lightcurves x 1000 epochs 0.176 s per pass at 256 lanes (0.251 at
+  // 64), 4096 ragged lightcurves 2.29 s at 128 (2.72 at 64, 2.45 at 256).
+  const int64_t n_trial = (int64_t)n * NS;
+  a.lanes_per_ind = n_trial * 4 <= 32768 ? 256 : n_trial * 2 <= 32768 ? 128 : 64;
+  if (const char* env = getenv("SBLM_NM_LANES")) {
+    const int g = atoi(env);
+    if (g == 64 || g == 128 || g == 256) a.lanes_per_ind = g;
+  }
   const dim3 grid((n + 255) / 256), blk(256);
   if (rc == SBLM_OK) {
     hipLaunchKernelGGL(nm_start_kernel, grid, blk, 0, st, w, x0);

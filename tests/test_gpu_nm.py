@@ -28,8 +28,10 @@ def device_lcs(hip, wl, y, w):
     return hip.Lightcurves(cu(wl.off, torch.int64), cu(wl.t), cu(y), cu(w))
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_simplex_matches_oracle(hip, mode):
+@pytest.mark.parametrize("mode,lanes", [(0, "256"), (1, "256"), (0, "128"), (0, "64")])
+def test_simplex_matches_oracle(hip, mode, lanes, monkeypatch):
+    # lanes: trial points spread over 4, 2 or 1 waves (merged across waves)
+    monkeypatch.setenv("SBLM_NM_LANES", lanes)
     # ragged lengths including an empty lightcurve; starts near the truth,
     # one start on the domain's edges (0 and 1 coordinates)
     lengths = [300, 0, 257, 64, 300, 120, 300, 33]
