@@ -353,8 +353,10 @@ void nm_default_config(nm_config* cfg);
  *   chi2, Fs, Fb  [n_lc] device out (nullable), its chi^2 and fluxes
  *   n_iter  [n_lc] device int32 out (nullable), simplex steps taken
  *   stats   (nullable) fitness counters
- * Allocates and frees a workspace of ~1 KB per lightcurve; synchronises
- * `stream`.  Errors: SBLM_EINVAL, SBLM_ERANGE, SBLM_ENOMEM, SBLM_EDEVICE.
+ * Allocates and frees a workspace of ~1 KB per simplex, plus 80 B per lane of
+ * saved roots (80 KB per simplex at 256 lanes per trial point; at most
+ * 1 GiB, wider batches use fewer lanes); synchronises `stream`.
+ * Errors: SBLM_EINVAL, SBLM_ERANGE, SBLM_ENOMEM, SBLM_EDEVICE.
  */
 int nm_refine(const sblm_lcs* lcs, const double* lo, const double* hi,
               const double* x0, const nm_config* cfg, double* x, double* chi2,
@@ -388,8 +390,9 @@ int nm_refine_multi(const sblm_lcs* lcs, int32_t reps, const double* lo,
  *           starts (lowest chi^2; the lowest start index among equals)
  *   chi2, Fs, Fb  [n_lc] device out (nullable)
  *   n_iter  [n_lc] device int64 out (nullable), steps of all runs
- * Allocates and frees ~1.2 KB per slot; synchronises `stream`.  Errors:
- * SBLM_EINVAL, SBLM_ERANGE, SBLM_ENOMEM, SBLM_EDEVICE.
+ * Allocates and frees ~1.2 KB per slot, plus saved roots as nm_refine;
+ * synchronises `stream`.  Errors: SBLM_EINVAL, SBLM_ERANGE, SBLM_ENOMEM,
+ * SBLM_EDEVICE.
  */
 #define NM_PURPOSE_START 7
 int nm_iterated(const sblm_lcs* lcs, int32_t reps, int32_t runs, uint64_t seed,

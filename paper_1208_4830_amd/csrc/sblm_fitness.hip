@@ -702,7 +702,27 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
     const double t = active ? a.t[k] : t0;
     cx<double> zeta, c[6];
     const bool deg4 = epoch_poly(x, t, zeta, c);
-    const bool warm = have_prev && !deg4 && !prev_deg4;
+    bool warm = have_prev && !deg4 && !prev_deg4;
+    if constexpr (G > 64) {
+      // simplex rounds: a lane's first epoch starts from the roots the lane
+      // found there for the same trial slot in the previous round (the
+      // simplex moves little between rounds), else cold
+      if (s == 0 && a.root_cache && active && !deg4) {
+        const double* rc = a.root_cache + (x.ind * G + x.gl) * 10;
+        cx<double> zc[5];
+        bool fin = true;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          zc[i] = {rc[2 * i], rc[2 * i + 1]};
+          fin = fin && isfinite(zc[i].re) && isfinite(zc[i].im);
+        }
+        if (fin) {
+#pragma unroll
+          for (int i = 0; i < 5; ++i) z[i] = zc[i];
+          warm = true;
+        }
+      }
+    }
     // Warm start: quadratic (Lagrange in t) extrapolation of every root from
     // the three previous epochs when the new epoch lies within their span,
     // else linear from two, scaled by the ratio of epoch spacings (clamped to
@@ -732,6 +752,16 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
     }
     bool ok;
     solve_roots<MODE>(c, deg4, warm, active, z, st, ok);
+    if constexpr (G > 64) {
+      if (s == 0 && a.root_cache && active) {
+        double* rc = a.root_cache + (x.ind * G + x.gl) * 10;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          rc[2 * i] = ok ? z[i].re : NAN;
+          rc[2 * i + 1] = ok ? z[i].im : NAN;
+        }
+      }
+    }
     have_prev3 = have_prev2 && warm && ok;
     have_prev2 = warm && ok;
     t3 = t2;

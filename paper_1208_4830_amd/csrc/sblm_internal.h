@@ -37,6 +37,9 @@ struct FitArgs {
   sblm_stats* stats;  // nullable
   // schedule
   const int32_t* order;  // nullable: item -> individual permutation
+  double* root_cache;     // nullable, G > 64 only: [n_ind][G][10] roots of
+                          // each lane's first epoch, read as its start
+                          // (when finite) and rewritten after the solve
   int32_t lanes_per_ind;  // 64, 32, 16 or 8 (a power of two dividing 64), or
                           // 128 / 256: several waves per individual (chi^2
                           // only, one-shot lockstep, wpb a multiple of G/64)

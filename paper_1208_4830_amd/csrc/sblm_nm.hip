@@ -142,6 +142,12 @@ __global__ void nm_start_kernel(NmWork w, const double* x0) {
 
 __global__ void nm_reset_kernel(unsigned int* active) { *active = 0u; }
 
+// NaN marks an empty root cache entry (the lane starts cold).
+__global__ void nm_nan_fill_kernel(double* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = NAN;
+}
+
 // Trial points of this round.
 __global__ void nm_propose_kernel(NmWork w, double tol_x, double tol_f, int32_t max_iter) {
   const int lc = blockIdx.x * blockDim.x + threadIdx.x;
@@ -401,6 +407,7 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
   }
   FitArgs a;
   memset(&a, 0, sizeof(a));
+  double* root_cache = nullptr;
   a.theta = w.T;
   a.n_ind = (int64_t)n * NS;
   a.encoded = 1;
@@ -421,17 +428,36 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
   a.skip_per = NS;
   // rounds are latency-bound (each waits for its longest lightcurve, and
   // later rounds hold only the unfinished simplices): a trial point spread
-  // over several waves shortens the chain of epochs per lane, at the price
-  // of a cold start per lane.  The widest of 256, 128 and 64 lanes that
-  // keeps the launch within 32768 waves (32 per compute unit); measured:
-  // 256 lightcurves x 1000 epochs 0.176 s per pass at 256 lanes (0.251 at
-  // 64), 4096 ragged lightcurves 2.29 s at 128 (2.72 at 64, 2.45 at 256).
+  // over several waves shortens the chain of epochs per lane, and the root
+  // cache below spares the extra lanes their cold starts.  256 lanes unless
+  // the cache (80 B per lane) would pass 1 GiB, then 128, then 64 without a
+  // cache.  Measured per pass: 256 lightcurves x 1000 epochs 0.155 s at 256
+  // lanes (0.188 at 128, 0.253 at 64), 4096 ragged lightcurves 2.04 s at 256
+  // (2.16 at 128, 2.72 at 64).
   const int64_t n_trial = (int64_t)n * NS;
-  a.lanes_per_ind = n_trial * 4 <= 32768 ? 256 : n_trial * 2 <= 32768 ? 128 : 64;
+  const int64_t cache_max = (int64_t)1 << 30;
+  a.lanes_per_ind = n_trial * 256 * 80 <= cache_max   ? 256
+                    : n_trial * 128 * 80 <= cache_max ? 128
+                                                      : 64;
   if (const char* env = getenv("SBLM_NM_LANES")) {
     const int g = atoi(env);
     if (g == 64 || g == 128 || g == 256) a.lanes_per_ind = g;
   }
+  // with several waves per trial point every lane would start cold once
+  // per round; the root cache lets it start from last round's roots instead
+  const int64_t n_cache = a.lanes_per_ind > 64 ? n_trial * a.lanes_per_ind * 10 : 0;
+  if (rc == SBLM_OK && n_cache > 0) {
+    if (hipMalloc(&root_cache, (size_t)n_cache * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      root_cache = nullptr;
+      rc = set_error(SBLM_ENOMEM, "nm_refine: device allocation");
+    } else {
+      hipLaunchKernelGGL(nm_nan_fill_kernel, dim3((unsigned)((n_cache + 255) / 256)), dim3(256),
+                         0, st, root_cache, n_cache);
+      rc = check_hip(hipGetLastError(), "nm_refine: cache");
+    }
+  }
+  a.root_cache = root_cache;
   const dim3 grid((n + 255) / 256), blk(256);
   if (rc == SBLM_OK) {
     hipLaunchKernelGGL(nm_start_kernel, grid, blk, 0, st, w, x0);
@@ -472,7 +498,8 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
   if (hipStreamSynchronize(st) != hipSuccess && rc == SBLM_OK)
     rc = check_hip(hipGetLastError(), "nm_refine: synchronise");
   void* bufs[] = {w.V,    w.F,    w.FsV,  w.FbV,  w.T,   w.cT,  w.fsT, w.fbT, w.phase, w.steps,
-                  w.done, w.active, w.run, w.total, w.bX, w.bF, w.bFs, w.bFb, w.bS};
+                  w.done, w.active, w.run, w.total, w.bX, w.bF, w.bFs, w.bFb, w.bS,
+                  root_cache};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   return rc;
