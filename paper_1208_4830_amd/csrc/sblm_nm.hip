@@ -140,17 +140,17 @@ __global__ void nm_start_kernel(NmWork w, const double* x0) {
   w.done[lc] = 0;
 }
 
-__global__ void nm_reset_kernel(unsigned int* active) { *active = 0u; }
-
 // NaN marks an empty root cache entry (the lane starts cold).
 __global__ void nm_nan_fill_kernel(double* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = NAN;
 }
 
-// Trial points of this round.
+// Trial points of this round (and the round's active count reset: the
+// update kernel that counts runs after this one on the same stream).
 __global__ void nm_propose_kernel(NmWork w, double tol_x, double tol_f, int32_t max_iter) {
   const int lc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lc == 0) *w.active = 0u;
   if (lc >= w.n) return;
   int ph = w.phase[lc];
   double x[NP];
@@ -226,8 +226,13 @@ struct Vertex {
   double f, fs, fb;
 };
 
-__device__ void load_simplex(const NmWork& w, int lc, Vertex* s) {
+// The simplex lives in registers: every index into Vertex arrays below is a
+// compile-time constant after unrolling (a runtime index would put the
+// array in scratch memory).
+__device__ __forceinline__ void load_simplex(const NmWork& w, int lc, Vertex* s) {
+#pragma unroll
   for (int v = 0; v < NV; ++v) {
+#pragma unroll
     for (int g = 0; g < NP; ++g) s[v].x[g] = vtx(w, v, g, lc);
     s[v].f = w.F[(int64_t)v * w.n + lc];
     s[v].fs = w.FsV[(int64_t)v * w.n + lc];
@@ -235,29 +240,36 @@ __device__ void load_simplex(const NmWork& w, int lc, Vertex* s) {
   }
 }
 
-__device__ void store_simplex(const NmWork& w, int lc, const Vertex* s) {
+// Stores vertex v at place rank[v] (a memory index, so it may be a runtime
+// value).
+__device__ __forceinline__ void store_simplex(const NmWork& w, int lc, const Vertex* s,
+                                              const int* rank) {
+#pragma unroll
   for (int v = 0; v < NV; ++v) {
-    for (int g = 0; g < NP; ++g) vtx(w, v, g, lc) = s[v].x[g];
-    w.F[(int64_t)v * w.n + lc] = s[v].f;
-    w.FsV[(int64_t)v * w.n + lc] = s[v].fs;
-    w.FbV[(int64_t)v * w.n + lc] = s[v].fb;
+    const int r = rank[v];
+#pragma unroll
+    for (int g = 0; g < NP; ++g) vtx(w, r, g, lc) = s[v].x[g];
+    w.F[(int64_t)r * w.n + lc] = s[v].f;
+    w.FsV[(int64_t)r * w.n + lc] = s[v].fs;
+    w.FbV[(int64_t)r * w.n + lc] = s[v].fb;
   }
 }
 
-// stable insertion sort by f (equal values keep their order)
-__device__ void sort_simplex(Vertex* s) {
-  for (int i = 1; i < NV; ++i) {
-    const Vertex key = s[i];
-    int j = i - 1;
-    while (j >= 0 && s[j].f > key.f) {
-      s[j + 1] = s[j];
-      --j;
-    }
-    s[j + 1] = key;
+// Stable sort by f (equal values keep their order): the place of vertex i
+// is the number of vertices with a lower f, or an equal f and a lower index
+// -- the permutation of a stable insertion sort.  The vertices stay where
+// they are; store_simplex writes each to its place.
+__device__ __forceinline__ void rank_simplex(const Vertex* s, int* rank) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    int r = 0;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) r += (s[j].f < s[i].f || (s[j].f == s[i].f && j < i)) ? 1 : 0;
+    rank[i] = r;
   }
 }
 
-__device__ void take_trial(const NmWork& w, int lc, int slot, Vertex& v) {
+__device__ __forceinline__ void take_trial(const NmWork& w, int lc, int slot, Vertex& v) {
   const int64_t i = (int64_t)lc * NS + slot;
   get_trial(w, lc, slot, v.x);
   v.f = finite_or_inf(w.cT[i]);
@@ -265,51 +277,59 @@ __device__ void take_trial(const NmWork& w, int lc, int slot, Vertex& v) {
   v.fb = w.fbT[i];
 }
 
-__global__ void nm_update_kernel(NmWork w) {
+__global__ __launch_bounds__(256) void nm_update_kernel(NmWork w) {
   const int lc = blockIdx.x * blockDim.x + threadIdx.x;
   if (lc >= w.n) return;
   const int ph = w.phase[lc];
   if (ph == PH_DONE) return;
   Vertex s[NV];
   load_simplex(w, lc, s);
+  int rank[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) rank[v] = v;
   int next = ph;
   switch (ph) {
     case PH_INIT1:
+#pragma unroll
       for (int k = 0; k < NS; ++k) take_trial(w, lc, k, s[k]);
       next = PH_INIT2;
       break;
     case PH_INIT2:
+#pragma unroll
       for (int k = 0; k < 3; ++k) take_trial(w, lc, k, s[4 + k]);
-      sort_simplex(s);
+      rank_simplex(s, rank);
       next = PH_STEP;
       break;
     case PH_SHRINK1:
+#pragma unroll
       for (int k = 0; k < NS; ++k) take_trial(w, lc, k, s[1 + k]);
       next = PH_SHRINK2;
       break;
     case PH_SHRINK2:
+#pragma unroll
       for (int k = 0; k < 2; ++k) take_trial(w, lc, k, s[5 + k]);
-      sort_simplex(s);
+      rank_simplex(s, rank);
       next = PH_STEP;
       break;
     case PH_STEP: {
-      Vertex r, e, oc, ic;
-      take_trial(w, lc, 0, r);
-      take_trial(w, lc, 1, e);
-      take_trial(w, lc, 2, oc);
-      take_trial(w, lc, 3, ic);
+      // the decision needs only the four values; then the accepted point
+      const int64_t t0 = (int64_t)lc * NS;
+      const double fr = finite_or_inf(w.cT[t0]), fe = finite_or_inf(w.cT[t0 + 1]);
+      const double foc = finite_or_inf(w.cT[t0 + 2]), fic = finite_or_inf(w.cT[t0 + 3]);
       int accept = -1;  // 0 r, 1 e, 2 oc, 3 ic; -1 shrink
-      if (r.f < s[0].f) accept = (e.f < r.f) ? 1 : 0;
-      else if (r.f < s[NV - 2].f) accept = 0;
-      else if (r.f < s[NV - 1].f) accept = (oc.f <= r.f) ? 2 : -1;
-      else accept = (ic.f < s[NV - 1].f) ? 3 : -1;
+      if (fr < s[0].f) accept = (fe < fr) ? 1 : 0;
+      else if (fr < s[NV - 2].f) accept = 0;
+      else if (fr < s[NV - 1].f) accept = (foc <= fr) ? 2 : -1;
+      else accept = (fic < s[NV - 1].f) ? 3 : -1;
       if (accept >= 0) {
-        s[NV - 1] = accept == 0 ? r : accept == 1 ? e : accept == 2 ? oc : ic;
-        sort_simplex(s);
+        take_trial(w, lc, accept, s[NV - 1]);
+        rank_simplex(s, rank);
         next = PH_STEP;
       } else {
         const double sigma = 0.5;
+#pragma unroll
         for (int v = 1; v < NV; ++v)
+#pragma unroll
           for (int g = 0; g < NP; ++g)
             s[v].x[g] = clip01(s[0].x[g] + sigma * (s[v].x[g] - s[0].x[g]));
         next = PH_SHRINK1;
@@ -318,7 +338,7 @@ __global__ void nm_update_kernel(NmWork w) {
       break;
     }
   }
-  store_simplex(w, lc, s);
+  store_simplex(w, lc, s, rank);
   w.phase[lc] = next;
   atomicAdd(w.active, 1u);
 }
@@ -431,9 +451,9 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
   // over several waves shortens the chain of epochs per lane, and the root
   // cache below spares the extra lanes their cold starts.  256 lanes unless
   // the cache (80 B per lane) would pass 1 GiB, then 128, then 64 without a
-  // cache.  Measured per pass: 256 lightcurves x 1000 epochs 0.155 s at 256
-  // lanes (0.188 at 128, 0.253 at 64), 4096 ragged lightcurves 2.04 s at 256
-  // (2.16 at 128, 2.72 at 64).
+  // cache.  Measured per pass: 256 lightcurves x 1000 epochs 0.118 s at 256
+  // lanes (0.154 at 128, 0.213 at 64), 4096 ragged lightcurves 1.96 s at 256
+  // (2.08 at 128, 2.64 at 64).
   const int64_t n_trial = (int64_t)n * NS;
   const int64_t cache_max = (int64_t)1 << 30;
   a.lanes_per_ind = n_trial * 256 * 80 <= cache_max   ? 256
@@ -468,7 +488,6 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
   const int chunk = 16;
   for (int64_t r = 0; rc == SBLM_OK && r < max_rounds; r += chunk) {
     for (int k = 0; k < chunk && rc == SBLM_OK; ++k) {
-      hipLaunchKernelGGL(nm_reset_kernel, dim3(1), dim3(1), 0, st, w.active);
       hipLaunchKernelGGL(nm_propose_kernel, grid, blk, 0, st, w, cfg.tol_x, cfg.tol_f,
                          cfg.max_iter);
       hipError_t e = hipGetLastError();
