@@ -240,3 +240,24 @@ def test_islands_full_size_sampled(hip):
         i, s = isls[k].best()
         assert rec["best_chi2"][k * n_isl + i] == s["best_chi2"]
     st.close()
+
+
+def test_island_save_load_resume_bit_exact(hip):
+    # a snapshot taken between migrations restores a state whose continued
+    # run (migrations included) is bit-identical to the uninterrupted one
+    wl = csr_workload(14, [90, 150])
+    st_a, _, _ = _state(hip, wl, 16, 21, 3, 2, 2)
+    st_a.fit(5)
+    blob = st_a.save()
+    st_a.fit(6)
+    st_b, _, _ = _state(hip, wl, 16, 21, 3, 2, 2)
+    st_b.load(blob)
+    st_b.fit(6)
+    torch.cuda.synchronize()
+    assert st_a.save() == st_b.save()
+    # a snapshot of another island configuration is refused
+    st_c, _, _ = _state(hip, wl, 16, 21, 3, 3, 2)
+    with pytest.raises(hip.SblmError):
+        st_c.load(blob)
+    for st in (st_a, st_b, st_c):
+        st.close()
