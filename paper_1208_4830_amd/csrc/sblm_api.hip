@@ -25,20 +25,26 @@ int check_hip(hipError_t e, const char* what) {
   return set_error(SBLM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Lanes per individual.  Fewer lanes give every lane a longer chunk of
-// consecutive epochs, so a smaller share of its solves start cold; on the
-// MI355X 16 lanes per individual were fastest for 1000-epoch lightcurves
-// (17.9 vs 16.8 and 15.4 Gmag/s for 32 and 64).  Overridable with
-// SBLM_LANES (8, 16, 32 or 64) for tuning runs.
-static int choose_group(double mean_len) {
+// Lanes per individual of the stateless calls.  Fewer lanes give every lane
+// a longer chunk of consecutive epochs, so a smaller share of its solves
+// start cold: on the MI355X 16 lanes per individual were fastest for a full
+// batch of 1000-epoch lightcurves (17.9 vs 16.8 and 15.4 Gmag/s for 32 and
+// 64).  More lanes give shorter chains of epochs per lane, which pays while
+// the chip would otherwise idle: the widest group that keeps the launch within
+// one full residency (2048 waves: 256 compute units x 4 SIMDs x 2 waves at
+// this kernel's register use), at least 16.  Overridable with SBLM_LANES
+// (8 ... 256) for tuning runs.
+static int choose_group(int64_t n_ind) {
   const char* env = getenv("SBLM_LANES");
   if (env) {
     int g = atoi(env);
-    if (g == 8 || g == 16 || g == 32 || g == 64) return g;
+    if (g == 8 || g == 16 || g == 32 || g == 64 || g == 128 || g == 256) return g;
   }
-  (void)mean_len;
+  for (int g = 256; g >= 32; g >>= 1)
+    if (n_ind * g <= (int64_t)2048 * 64) return g;
   return 16;
 }
+
 
 // Epoch stepping of the stateless calls: lockstep unless SBLM_ASYNC=1 (the
 // asynchronous form measured slower on the MI355X for 200-5000-epoch
@@ -56,6 +62,10 @@ static int waves_per_block() {
   }
   return 4;
 }
+
+// Waves per block for a group of g lanes (several waves per individual need
+// whole individuals in a block).
+static int block_waves(int g) { return g > 64 ? 4 : waves_per_block(); }
 
 }  // namespace sblm
 
@@ -85,9 +95,10 @@ extern "C" int sblm_magnify(const double* theta, int64_t n, const double* t,
   a.A = A;
   a.n_img = n_img;
   a.stats = stats;
-  a.lanes_per_ind = choose_group((double)n_t);
-  a.async = async_stepping();
-  return check_hip(launch_fitness(a, mode, false, (hipStream_t)stream, waves_per_block()),
+  a.lanes_per_ind = choose_group(n);
+  a.async = async_stepping() && a.lanes_per_ind <= 64;
+  return check_hip(launch_fitness(a, mode, false, (hipStream_t)stream,
+                                  block_waves(a.lanes_per_ind)),
                    "sblm_magnify launch");
 }
 
@@ -118,10 +129,9 @@ extern "C" int sblm_chi2(const sblm_lcs* lcs, const double* theta, int32_t pop,
   a.Fs = Fs;
   a.Fb = Fb;
   a.stats = stats;
-  // mean length is not known on the host without a copy; use the group
-  // size that suits ~1000-epoch lightcurves unless overridden
-  a.lanes_per_ind = choose_group(1000.0);
-  a.async = async_stepping();
-  return check_hip(launch_fitness(a, mode, true, (hipStream_t)stream, waves_per_block()),
+  a.lanes_per_ind = choose_group(a.n_ind);
+  a.async = async_stepping() && a.lanes_per_ind <= 64;
+  return check_hip(launch_fitness(a, mode, true, (hipStream_t)stream,
+                                  block_waves(a.lanes_per_ind)),
                    "sblm_chi2 launch");
 }

@@ -991,10 +991,10 @@ template <int MODE, bool CHI2, int G>
 static hipError_t launch_gg(const FitArgs& a, hipStream_t s, int wpb) {
   if (wpb < 1 || 64 * wpb > SBLM_FIT_MAX_THREADS) return hipErrorInvalidConfiguration;
   if constexpr (G > 64) {
-    // several waves per individual: chi^2 only, one-shot grid, lockstep,
-    // whole individuals in every block (their waves meet at the merge)
+    // several waves per individual: one-shot grid, lockstep, whole
+    // individuals in every block (for chi^2 their waves meet at the merge)
     constexpr int P = G / 64;
-    if (!CHI2 || a.queue || a.async || wpb % P != 0) return hipErrorInvalidConfiguration;
+    if (a.queue || a.async || wpb % P != 0) return hipErrorInvalidConfiguration;
     const size_t smem = ROOT_HIST_BYTES * 64 * wpb + 6 * sizeof(double) * wpb;
     const int64_t nblk = (a.n_ind * P + wpb - 1) / wpb;
     if (nblk <= 0) return hipSuccess;
@@ -1027,11 +1027,8 @@ static hipError_t launch_gg(const FitArgs& a, hipStream_t s, int wpb) {
 
 template <int MODE, bool CHI2>
 static hipError_t launch_g(const FitArgs& a, hipStream_t s, int wpb) {
-  if constexpr (CHI2) {
-    if (a.lanes_per_ind == 256) return launch_gg<MODE, CHI2, 256>(a, s, wpb);
-    if (a.lanes_per_ind == 128) return launch_gg<MODE, CHI2, 128>(a, s, wpb);
-  }
-  if (a.lanes_per_ind > 64) return hipErrorInvalidConfiguration;
+  if (a.lanes_per_ind == 256) return launch_gg<MODE, CHI2, 256>(a, s, wpb);
+  if (a.lanes_per_ind == 128) return launch_gg<MODE, CHI2, 128>(a, s, wpb);
   if (a.lanes_per_ind == 64) return launch_gg<MODE, CHI2, 64>(a, s, wpb);
   if (a.lanes_per_ind == 32) return launch_gg<MODE, CHI2, 32>(a, s, wpb);
   if (a.lanes_per_ind == 8) return launch_gg<MODE, CHI2, 8>(a, s, wpb);

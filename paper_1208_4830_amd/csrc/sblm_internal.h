@@ -41,8 +41,8 @@ struct FitArgs {
                           // each lane's first epoch, read as its start
                           // (when finite) and rewritten after the solve
   int32_t lanes_per_ind;  // 64, 32, 16 or 8 (a power of two dividing 64), or
-                          // 128 / 256: several waves per individual (chi^2
-                          // only, one-shot lockstep, wpb a multiple of G/64)
+                          // 128 / 256: several waves per individual (one-shot
+                          // lockstep, wpb a multiple of G/64)
   unsigned int* queue;    // nullable: persistent launch, shared work counter
                           // (must read 0 when the kernel starts)
   int32_t async;          // 1: lanes step through their epochs independently

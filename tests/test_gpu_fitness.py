@@ -153,7 +153,7 @@ def test_chi2_deterministic_and_schedule_independent(hip):
     wl = csr_workload(12, [300, 700, 1000])
     outs = []
     for lanes, asy in (("64", "0"), ("64", "0"), ("32", "0"), ("16", "0"), ("16", "1"),
-                       ("32", "1")):
+                       ("32", "1"), ("256", "0"), ("128", "0")):
         os.environ["SBLM_LANES"], os.environ["SBLM_ASYNC"] = lanes, asy
         try:
             (c, fs, fb), (co, _, _), _ = _chi2_case(hip, wl, pop=8, mode=0)
