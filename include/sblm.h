@@ -266,7 +266,9 @@ int ea_fit(ea_state* st, int32_t n_gen, sblm_stats* stats, void* stream);
 /*
  * ea_autotune -- choose the fitness schedule of this state by timing it on
  * the state's own population and lightcurves (coordinate descent over the
- * epoch stepping {asynchronous, lockstep}, lanes per individual {8, 16, 32, 64},
+ * epoch stepping {asynchronous, lockstep}, lanes per individual {8, 16, 32, 64,
+ * 128, 256} (128 and 256 spread an individual over several waves and go with
+ * four waves per block, the one-shot grid and lockstep stepping),
  * waves per block {1, 2, 4} and a persistent work-counter launch vs a
  * one-shot grid), then re-capture the generation graph with the fastest.
  * Results do not depend on the waves per block or on the launch form; the
@@ -278,8 +280,12 @@ int ea_autotune(ea_state* st, char* report, size_t report_len, void* stream);
 
 /* Current schedule as int32[4] {lanes per individual, waves per block,
  * persistent, asynchronous stepping}; ea_set_schedule validates (lanes
- * 8/16/32/64, waves per block 1/2/4, persistent 0/1, asynchronous 0/1;
- * SBLM_EINVAL otherwise) and installs one (and re-captures the graph). */
+ * 8/16/32/64, waves per block 1/2/4, persistent 0/1, asynchronous 0/1; or
+ * lanes 128/256 with waves per block a multiple of lanes/64, one-shot,
+ * lockstep; SBLM_EINVAL otherwise) and installs one (and re-captures the
+ * graph).  ea_create starts from 16 lanes, 4 waves per block, persistent,
+ * lockstep, or for a state of fewer than 2048*64/32 individuals from the
+ * widest lanes (up to 256) whose waves fit one residency of the chip. */
 int ea_get_schedule(ea_state* st, int32_t* sched);
 int ea_set_schedule(ea_state* st, const int32_t* sched);
 

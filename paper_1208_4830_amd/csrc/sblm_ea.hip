@@ -663,9 +663,19 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
   p.stag_frac = cfg->stag_frac;
   p.seed = seed;
   p.n_ind = (int64_t)p.n_lc * p.pop;
+  // default schedule: 16 lanes per individual on the persistent grid for a
+  // full batch; a small state (its groups would leave the chip idle) takes
+  // the widest group that fits one residency of the chip, spread over the
+  // four waves of a block on the one-shot grid (ea_autotune refines this)
   const char* env = getenv("SBLM_LANES");
   s.lanes = 16;
+  for (int g = 256; g >= 32; g >>= 1)
+    if (p.n_ind * g <= (int64_t)2048 * 64) {
+      s.lanes = g;
+      break;
+    }
   if (env && (atoi(env) == 16 || atoi(env) == 32 || atoi(env) == 64)) s.lanes = atoi(env);
+  if (s.lanes > 64) s.persistent = 0;
   const size_t nb = (size_t)p.n_ind * sizeof(double);
   // longest-processing-time order of the work items: lightcurves by length,
   // longest first (stable), the individuals of each lightcurve (all its
@@ -969,9 +979,11 @@ extern "C" int ea_get_schedule(ea_state* st, int32_t* sched) {
 
 extern "C" int ea_set_schedule(ea_state* st, const int32_t* sched) {
   if (!st || !sched) return set_error(SBLM_EINVAL, "ea_set_schedule: null argument");
-  if ((sched[0] != 8 && sched[0] != 16 && sched[0] != 32 && sched[0] != 64) ||
+  const bool wide = sched[0] == 128 || sched[0] == 256;
+  if ((sched[0] != 8 && sched[0] != 16 && sched[0] != 32 && sched[0] != 64 && !wide) ||
       (sched[1] != 1 && sched[1] != 2 && sched[1] != 4) || (sched[2] != 0 && sched[2] != 1) ||
-      (sched[3] != 0 && sched[3] != 1))
+      (sched[3] != 0 && sched[3] != 1) ||
+      (wide && (sched[1] % (sched[0] / 64) != 0 || sched[2] != 0 || sched[3] != 0)))
     return set_error(SBLM_EINVAL, "ea_set_schedule: bad schedule (%d, %d, %d, %d)", sched[0],
                      sched[1], sched[2], sched[3]);
   EaStateImpl& s = st->impl;
@@ -1017,14 +1029,26 @@ extern "C" int ea_autotune(ea_state* st, char* report, size_t report_len, void* 
   // per individual, waves per block, persistent vs one-shot grid
   int best[4] = {s.lanes, s.wpb, s.persistent, s.async};
   float best_ms = INFINITY;
-  const int lanes_c[4] = {8, 16, 32, 64}, wpb_c[3] = {1, 2, 4}, bin_c[2] = {1, 0};
+  // (128 or 256 lanes spread an individual over several waves: those go
+  // with four waves per block, the one-shot grid and lockstep stepping, and
+  // candidates that break this are skipped)
+  const int lanes_c[6] = {8, 16, 32, 64, 128, 256}, wpb_c[3] = {1, 2, 4}, bin_c[2] = {1, 0};
   const int stage_field[4] = {3, 0, 1, 2};
   for (int stage = 0; stage < 4 && !rc; ++stage) {
     const int field = stage_field[stage];
-    const int nc = field == 0 ? 4 : (field == 1 ? 3 : 2);
+    const int nc = field == 0 ? 6 : (field == 1 ? 3 : 2);
     for (int k = 0; k < nc && !rc; ++k) {
       int cand[4] = {best[0], best[1], best[2], best[3]};
       cand[field] = field == 0 ? lanes_c[k] : (field == 1 ? wpb_c[k] : bin_c[k]);
+      if (cand[0] > 64) {
+        if (field == 0) {
+          cand[1] = 4;
+          cand[2] = 0;
+          cand[3] = 0;
+        } else if (cand[1] != 4 || cand[2] != 0 || cand[3] != 0) {
+          continue;
+        }
+      }
       s.lanes = cand[0];
       s.wpb = cand[1];
       s.persistent = cand[2];

@@ -180,7 +180,8 @@ def test_schedules_agree_and_autotune(hip):
     pop = 32
     blobs = {}
     for sched in [(16, 4, 1, 1), (16, 2, 0, 1), (16, 1, 1, 1), (16, 4, 1, 0), (16, 2, 0, 0),
-                  (32, 4, 1, 1), (64, 2, 0, 0), (8, 4, 1, 0), (8, 1, 0, 0), (8, 2, 1, 1)]:
+                  (32, 4, 1, 1), (64, 2, 0, 0), (8, 4, 1, 0), (8, 1, 0, 0), (8, 2, 1, 1),
+                  (128, 2, 0, 0), (128, 4, 0, 0), (256, 4, 0, 0)]:
         st, y, w = _make_state(hip, wl, pop, seed=21)
         st.set_schedule(*sched)
         assert st.schedule() == sched
@@ -199,17 +200,27 @@ def test_schedules_agree_and_autotune(hip):
     assert blobs[(16, 2, 0, 1)] == ref and blobs[(16, 1, 1, 1)] == ref
     assert blobs[(16, 2, 0, 0)] == blobs[(16, 4, 1, 0)]
     assert blobs[(8, 1, 0, 0)] == blobs[(8, 4, 1, 0)]
+    assert blobs[(128, 2, 0, 0)] == blobs[(128, 4, 0, 0)]  # one or two individuals a block
     st, _, _ = _make_state(hip, wl, pop, seed=21)
+    assert st.schedule() == (256, 4, 0, 0)  # a small state starts wide
     rep = st.autotune()
-    # 2 stepping + 4 lanes + 3 waves-per-block + 2 launch-form candidates
-    assert "chosen:" in rep and len(rep.splitlines()) == 12
     lanes, wpb, pers, asy = st.schedule()
-    assert lanes in (8, 16, 32, 64) and wpb in (1, 2, 4) and pers in (0, 1) and asy in (0, 1)
+    # stepping (only lockstep is valid for the wide start), lanes (6), waves
+    # per block (3, or 1 after a wide choice), launch form (2, or 1), chosen
+    assert "chosen:" in rep and len(rep.splitlines()) == (10 if lanes > 64 else 13)
+    assert lanes in (8, 16, 32, 64, 128, 256) and wpb in (1, 2, 4) and pers in (0, 1)
+    assert asy in (0, 1) and (lanes <= 64 or (wpb == 4 and pers == 0 and asy == 0))
     with pytest.raises(hip.SblmError):  # blocks beyond the kernels' bound
         st.set_schedule(16, 8, 1)
+    for bad in ((256, 2, 0, 0), (256, 4, 1, 0), (128, 4, 0, 1)):
+        with pytest.raises(hip.SblmError):  # wide lanes: whole individuals, one-shot, lockstep
+            st.set_schedule(*bad)
+    st.set_schedule(lanes, wpb, pers, asy)
     st.fit(6)
     if lanes == 16:
         assert st.save() == blobs[(16, 4, 1, asy)]
+    if lanes > 64:
+        assert st.save() == blobs[(lanes, 4, 0, 0)]
 
 
 @pytest.mark.parametrize("mode", [0, 1])
