@@ -462,7 +462,8 @@ struct EaStateImpl {
   int persistent = 1;
   int async = 0;
   int32_t* order = nullptr;    // item -> individual, longest lightcurves first
-  unsigned int* queue = nullptr;
+  unsigned int* queue = nullptr;  // 8 work counters, one per XCD
+  int64_t* xcd_start = nullptr;   // [9] order positions owned by each XCD
   Proposals prop = {};         // attached by ea_seed(..., EA_SEED_AT_RESTARTS)
   int n_phys = 0;              // lightcurves (prm.n_lc counts islands)
   double* mig_out = nullptr;   // migration outboxes (islands with migrants)
@@ -470,7 +471,9 @@ struct EaStateImpl {
   bool mig_in_fit = false;     // ea_fit migrates when due
 };
 
-__global__ void queue_reset_kernel(unsigned int* q) { *q = 0u; }
+__global__ void queue_reset_kernel(unsigned int* q) {
+  if (threadIdx.x < 8) q[threadIdx.x] = 0u;
+}
 
 static size_t gen_smem(int pop) {
   return (size_t)pop * (SBLM_NPAR * sizeof(double) + sizeof(double) + sizeof(int));
@@ -536,7 +539,8 @@ static hipError_t enqueue_evaluate(EaStateImpl* s, sblm_stats* stats,
   a.async = s->async;
   if (s->persistent) {
     a.queue = s->queue;
-    hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(1), 0, st, s->queue);
+    a.xcd_start = s->xcd_start;
+    hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, s->queue);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -623,6 +627,7 @@ extern "C" void ea_destroy(ea_state* st) {
   (void)hipFree(s.lc);
   (void)hipFree(s.order);
   (void)hipFree(s.queue);
+  (void)hipFree(s.xcd_start);
   (void)hipFree(s.mig_out);
   (void)hipFree(s.mig_least);
   (void)hipSetDevice(prev);
@@ -682,6 +687,7 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
   // islands) together
   const int nl = s.n_phys;
   const int popf = p.pop * p.n_isl;
+  int64_t xcd_start_h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   int64_t* off_h = (int64_t*)malloc((size_t)(nl + 1) * sizeof(int64_t));
   int32_t* order_h = (int32_t*)malloc((size_t)p.n_ind * sizeof(int32_t));
   int32_t* lcs_sorted = (int32_t*)malloc((size_t)nl * sizeof(int32_t));
@@ -720,8 +726,32 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
         for (int k = lo; k < hi; ++k) lcs_sorted[k] = tmp[k];
       }
     free(tmp);
-    for (int64_t it = 0; it < p.n_ind; ++it)
-      order_h[it] = lcs_sorted[it / popf] * popf + (int32_t)(it % popf);
+    // lightcurves dealt to the 8 XCDs longest first, each to the XCD with the
+    // least work so far (epochs x individuals, lowest index among equals);
+    // the order lists XCD 0's lightcurves first (longest first), then XCD 1's
+    int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int32_t* xcd_of = (int32_t*)malloc((size_t)nl * sizeof(int32_t));
+    if (!xcd_of) rc = set_error(SBLM_ENOMEM, "ea_create: host allocation");
+    for (int r = 0; !rc && r < nl; ++r) {
+      const int k = lcs_sorted[r];
+      const int64_t L = off_h[k + 1] - off_h[k];
+      int x = 0;
+      for (int y = 1; y < 8; ++y)
+        if (load[y] < load[x]) x = y;
+      xcd_of[k] = x;
+      load[x] += (L > 0 ? L : 1) * popf;
+    }
+    int64_t pos = 0;
+    for (int x = 0; !rc && x < 8; ++x) {
+      xcd_start_h[x] = pos;
+      for (int r = 0; r < nl; ++r) {
+        const int k = lcs_sorted[r];
+        if (xcd_of[k] != x) continue;
+        for (int i = 0; i < popf; ++i) order_h[pos++] = k * popf + i;
+      }
+    }
+    xcd_start_h[8] = pos;
+    free(xcd_of);
   }
   free(off_h);
   free(lcs_sorted);
@@ -734,7 +764,8 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
       hipMalloc(&s.Fs, nb) != hipSuccess || hipMalloc(&s.Fb, nb) != hipSuccess ||
       hipMalloc(&s.lc, (size_t)p.n_lc * sizeof(EaLc)) != hipSuccess ||
       hipMalloc(&s.order, (size_t)p.n_ind * sizeof(int32_t)) != hipSuccess ||
-      hipMalloc(&s.queue, sizeof(unsigned int)) != hipSuccess ||
+      hipMalloc(&s.queue, 8 * sizeof(unsigned int)) != hipSuccess ||
+      hipMalloc(&s.xcd_start, 9 * sizeof(int64_t)) != hipSuccess ||
       (p.n_isl > 1 && cfg->n_migrants > 0 &&
        (hipMalloc(&s.mig_out, (size_t)p.n_lc * cfg->n_migrants * 9 * sizeof(double)) !=
             hipSuccess ||
@@ -752,9 +783,13 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
     ea_destroy(st);
     return rc;
   }
-  rc = check_hip(hipMemcpy(s.order, order_h, (size_t)p.n_ind * sizeof(int32_t),
+  rc = check_hip(hipMemcpy(s.xcd_start, xcd_start_h, 9 * sizeof(int64_t),
                            hipMemcpyHostToDevice),
                  "ea_create order");
+  if (!rc)
+    rc = check_hip(hipMemcpy(s.order, order_h, (size_t)p.n_ind * sizeof(int32_t),
+                             hipMemcpyHostToDevice),
+                   "ea_create order");
   free(order_h);
   if (rc) {
     ea_destroy(st);

@@ -938,15 +938,39 @@ __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitn
   // wave reaches the exit.  One call site keeps one inlined copy of the body.
   const int64_t n_wave_items = G > 64 ? a.n_ind * (G / 64) : (a.n_ind + GPW - 1) / GPW;
   if constexpr (PERSIST) {
-    for (;;) {
-      unsigned int v = 0;
-      if (lane == 0) v = atomicAdd(a.queue, 1u);
-      const int64_t wi = (int64_t)__shfl(v, 0, 64);
-      if (wi >= n_wave_items) break;
-      if constexpr (ASYNC)
-        fit_wave_async<MODE, CHI2, G>(a, wi, st);
-      else
-        fit_wave<MODE, CHI2, G>(a, wi, st);
+    if (a.xcd_start) {
+      // per-XCD queues: first the items of the lightcurves this block's XCD
+      // owns (their epochs stay in its L2; workgroups are dealt to the XCDs
+      // round-robin), then what is left in the other XCDs' queues.  Each
+      // queue is visited until it runs past its last item, so every wave
+      // reaches the exit.
+      const int x0 = blockIdx.x & 7;
+      for (int k = 0; k < 8; ++k) {
+        const int x = (x0 + k) & 7;
+        const int64_t w0 = (a.xcd_start[x] + GPW - 1) / GPW;
+        const int64_t w1 = (a.xcd_start[x + 1] + GPW - 1) / GPW;
+        for (;;) {
+          unsigned int v = 0;
+          if (lane == 0) v = atomicAdd(a.queue + x, 1u);
+          const int64_t wi = w0 + (int64_t)__shfl(v, 0, 64);
+          if (wi >= w1) break;
+          if constexpr (ASYNC)
+            fit_wave_async<MODE, CHI2, G>(a, wi, st);
+          else
+            fit_wave<MODE, CHI2, G>(a, wi, st);
+        }
+      }
+    } else {
+      for (;;) {
+        unsigned int v = 0;
+        if (lane == 0) v = atomicAdd(a.queue, 1u);
+        const int64_t wi = (int64_t)__shfl(v, 0, 64);
+        if (wi >= n_wave_items) break;
+        if constexpr (ASYNC)
+          fit_wave_async<MODE, CHI2, G>(a, wi, st);
+        else
+          fit_wave<MODE, CHI2, G>(a, wi, st);
+      }
     }
   } else {
     const int nb = gridDim.x, b = blockIdx.x;

@@ -43,7 +43,10 @@ struct FitArgs {
   int32_t lanes_per_ind;  // 64, 32, 16 or 8 (a power of two dividing 64), or
                           // 128 / 256: several waves per individual (one-shot
                           // lockstep, wpb a multiple of G/64)
-  unsigned int* queue;    // nullable: persistent launch, shared work counter
+  unsigned int* queue;    // nullable: persistent launch; one shared work
+                          // counter, or with xcd_start one per XCD (8)
+  const int64_t* xcd_start;  // nullable: [9] order positions; the items at
+                             // [xcd_start[x], xcd_start[x+1]) belong to XCD x
                           // (must read 0 when the kernel starts)
   int32_t async;          // 1: lanes step through their epochs independently
   const int32_t* skip;    // nullable (CSR only): individual i is evaluated
