@@ -76,6 +76,13 @@ template <typename T>
 __device__ __forceinline__ T c_norm(cx<T> a) {
   return fma(a.re, a.re, a.im * a.im);
 }
+// Smaller / larger of two values, the non-NaN one if one is NaN (one v_min /
+// v_max where the operands are results of arithmetic, which the compiler knows
+// to be quiet).
+__device__ __forceinline__ double vmin(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ float vmin(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ double vmax(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float vmax(float a, float b) { return fmaxf(a, b); }
 
 // Approximate reciprocal for iteration steps (the fixed point of the
 // iteration does not depend on its accuracy).
@@ -208,25 +215,26 @@ __device__ __forceinline__ bool aberth_sweep(const cx<T> c[6], cx<T> z[5],
   // pairwise terms from the current roots first, so that each root's p, p'
   // is used as soon as it is computed (fewer live registers)
   cx<T> S[5];
-  T rmax[5];  // 1 / (distance to the nearest other root)^2
+  T dmin[5];  // (distance to the nearest other root)^2
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
     S[i] = {(T)0, (T)0};
-    rmax[i] = (T)0;
+    dmin[i] = (T)INFINITY;
   }
 #pragma unroll
   for (int i = 0; i < 5; ++i)
 #pragma unroll
     for (int j = i + 1; j < 5; ++j) {
       const cx<T> dz = c_sub(z[i], z[j]);
-      const T r = rcp_raw(c_norm(dz));
+      const T n = c_norm(dz);
+      const T r = rcp_raw(n);
       const T ire = dz.re * r, iim = -dz.im * r;  // 1/(z_i - z_j)
       S[i].re += ire;
       S[i].im += iim;
       S[j].re -= ire;
       S[j].im -= iim;
-      rmax[i] = r > rmax[i] ? r : rmax[i];
-      rmax[j] = r > rmax[j] ? r : rmax[j];
+      dmin[i] = vmin(n, dmin[i]);
+      dmin[j] = vmin(n, dmin[j]);
     }
   bool conv = true;
   T em = (T)0;
@@ -243,14 +251,14 @@ __device__ __forceinline__ bool aberth_sweep(const cx<T> c[6], cx<T> z[5],
     if (i == 4 && deg4) dz = {(T)0, (T)0};
     z[i] = c_sub(z[i], dz);
     const T zn = c_norm(z[i]);
-    const T sc = zn > (T)1 ? zn : (T)1;
+    const T sc = vmax(zn, (T)1);
     const T e2 = c_norm(dz);
-    // (e^2)^3 (1/s^2)^2 <= tau^2 |z|^2, or e^2 <= 1e-26 |z|^2
-    const bool ok = (e2 * e2 * e2 * (rmax[i] * rmax[i]) <= tau2 * sc) ||
+    // (e^2)^3 <= tau^2 |z|^2 (s^2)^2, or e^2 <= 1e-26 |z|^2
+    const bool ok = (e2 * e2 * e2 <= tau2 * sc * (dmin[i] * dmin[i])) |
                     (e2 <= (T)1e-26 * sc);
-    conv = conv && (ok || (i == 4 && deg4));
+    conv = conv & (ok | (i == 4 && deg4));  // no short-circuit: no branches
     const T er = e2 / sc;
-    em = er > em ? er : em;
+    em = vmax(er, em);
   }
   *emax = em;
   return conv;
@@ -272,12 +280,15 @@ __device__ __forceinline__ double image_eval(cx<double> z, cx<double> zeta, doub
                                              double* iz2, double* ie2) {
   const double x = z.re, y = z.im;
   // a = 1/conj(z) = z / |z|^2 ; b = 1/(d - conj(z))
+  // one reciprocal for both: 1/|z|^2 = |d-z|^2 / P, 1/|d-z|^2 = |z|^2 / P with
+  // P = |z|^2 |d-z|^2 (within range: |z| stays far from the FP64 limits)
   const double n2 = fma(x, x, y * y);
-  const double iz = rcp_acc(n2);
-  const cx<double> a = {x * iz, y * iz};
   const double ex = d - x;
   const double e2 = fma(ex, ex, y * y);
-  const double ie = rcp_acc(e2);
+  const double ip = rcp_acc(n2 * e2);
+  const double iz = e2 * ip;
+  const cx<double> a = {x * iz, y * iz};
+  const double ie = n2 * ip;
   const cx<double> b = {ex * ie, -y * ie};
   res = {fma(-q, b.re, (zeta.re - x) + a.re), fma(-q, b.im, (zeta.im - y) + a.im)};
   const cx<double> b2 = c_mul(b, b);
@@ -733,9 +744,10 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
       double w1 = 1.0, w2 = 0.0, w3 = 0.0;
       if (ex2 && have_prev3 && d12 > 0.0 && d23 > 0.0 && (t - t1) <= d13) {
         const double a1 = t - t1, a2 = t - t2, a3 = t - t3;
-        w1 = a2 * a3 * rcp_fast(d12 * d13);
-        w2 = -a1 * a3 * rcp_fast(d12 * d23);
-        w3 = a1 * a2 * rcp_fast(d13 * d23);
+        const double r = rcp_fast(d12 * d13 * d23);
+        w1 = a2 * a3 * (d23 * r);
+        w2 = -a1 * a3 * (d13 * r);
+        w3 = a1 * a2 * (d12 * r);
       } else if (ex2 && d12 != 0.0) {
         const double r = fmin(fmax((t - t1) / d12, 0.0), 4.0);
         w1 = 1.0 + r;
@@ -835,9 +847,10 @@ __device__ __forceinline__ void fit_wave_async(const FitArgs& a, int64_t wave_it
           const double d12 = t1 - t2, d13 = t1 - t3, d23 = t2 - t3;
           if (nhist >= 3 && d12 > 0.0 && d23 > 0.0 && (t - t1) <= d13) {
             const double a1 = t - t1, a2 = t - t2, a3 = t - t3;
-            w1 = a2 * a3 * rcp_fast(d12 * d13);
-            w2 = -a1 * a3 * rcp_fast(d12 * d23);
-            w3 = a1 * a2 * rcp_fast(d13 * d23);
+            const double r = rcp_fast(d12 * d13 * d23);
+            w1 = a2 * a3 * (d23 * r);
+            w2 = -a1 * a3 * (d13 * r);
+            w3 = a1 * a2 * (d12 * r);
           } else if (nhist >= 2 && d12 > 0.0) {
             const double r = fmin(fmax((t - t1) * rcp_fast(d12), 0.0), 4.0);
             w1 = 1.0 + r;
