@@ -277,6 +277,39 @@ __device__ __forceinline__ void take_trial(const NmWork& w, int lc, int slot, Ve
   v.fb = w.fbT[i];
 }
 
+// A point that coincides with one evaluated before gets that point's value.
+// Clipping to the domain can map a trial point onto a vertex or onto another
+// trial point; evaluated again, its chi^2 would differ at the rounding level
+// (each evaluation starts its root solves from its own cached roots), and an
+// exact tie, which a function decides the same way every time, could go
+// either way.
+__device__ __forceinline__ bool same_point(const double* a, const double* b) {
+  bool eq = true;
+#pragma unroll
+  for (int g = 0; g < NP; ++g) eq = eq & (a[g] == b[g]);
+  return eq;
+}
+
+// Vertices LO..HI-1 (just evaluated) take the value of the first earlier
+// vertex at the same point.
+template <int LO, int HI>
+__device__ __forceinline__ void share_values(Vertex* s) {
+#pragma unroll
+  for (int v = LO; v < HI; ++v) {
+    bool found = false;
+#pragma unroll
+    for (int u = 0; u < v; ++u) {
+      const bool m = !found && same_point(s[v].x, s[u].x);
+      if (m) {
+        s[v].f = s[u].f;
+        s[v].fs = s[u].fs;
+        s[v].fb = s[u].fb;
+      }
+      found = found | m;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void nm_update_kernel(NmWork w) {
   const int lc = blockIdx.x * blockDim.x + threadIdx.x;
   if (lc >= w.n) return;
@@ -292,37 +325,85 @@ __global__ __launch_bounds__(256) void nm_update_kernel(NmWork w) {
     case PH_INIT1:
 #pragma unroll
       for (int k = 0; k < NS; ++k) take_trial(w, lc, k, s[k]);
+      share_values<1, NS>(s);
       next = PH_INIT2;
       break;
     case PH_INIT2:
 #pragma unroll
       for (int k = 0; k < 3; ++k) take_trial(w, lc, k, s[4 + k]);
+      share_values<4, NV>(s);
       rank_simplex(s, rank);
       next = PH_STEP;
       break;
     case PH_SHRINK1:
 #pragma unroll
       for (int k = 0; k < NS; ++k) take_trial(w, lc, k, s[1 + k]);
+      share_values<1, 1 + NS>(s);
       next = PH_SHRINK2;
       break;
     case PH_SHRINK2:
 #pragma unroll
       for (int k = 0; k < 2; ++k) take_trial(w, lc, k, s[5 + k]);
+      share_values<5, NV>(s);
       rank_simplex(s, rank);
       next = PH_STEP;
       break;
     case PH_STEP: {
-      // the decision needs only the four values; then the accepted point
+      // the decision needs only the four values (each trial point at a
+      // vertex or at an earlier trial point takes that point's value); then
+      // the accepted point
       const int64_t t0 = (int64_t)lc * NS;
-      const double fr = finite_or_inf(w.cT[t0]), fe = finite_or_inf(w.cT[t0 + 1]);
-      const double foc = finite_or_inf(w.cT[t0 + 2]), fic = finite_or_inf(w.cT[t0 + 3]);
+      double ft[NS], fst[NS], fbt[NS];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        ft[k] = finite_or_inf(w.cT[t0 + k]);
+        fst[k] = w.fsT[t0 + k];
+        fbt[k] = w.fbT[t0 + k];
+        double xk[NP];
+        get_trial(w, lc, k, xk);
+        bool found = false;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const bool m = !found && same_point(xk, s[v].x);
+          if (m) {
+            ft[k] = s[v].f;
+            fst[k] = s[v].fs;
+            fbt[k] = s[v].fb;
+          }
+          found = found | m;
+        }
+#pragma unroll
+        for (int j = 0; j < k; ++j) {
+          double xj[NP];
+          get_trial(w, lc, j, xj);
+          const bool m = !found && same_point(xk, xj);
+          if (m) {
+            ft[k] = ft[j];
+            fst[k] = fst[j];
+            fbt[k] = fbt[j];
+          }
+          found = found | m;
+        }
+      }
+      const double fr = ft[0], fe = ft[1], foc = ft[2], fic = ft[3];
       int accept = -1;  // 0 r, 1 e, 2 oc, 3 ic; -1 shrink
       if (fr < s[0].f) accept = (fe < fr) ? 1 : 0;
       else if (fr < s[NV - 2].f) accept = 0;
       else if (fr < s[NV - 1].f) accept = (foc <= fr) ? 2 : -1;
       else accept = (fic < s[NV - 1].f) ? 3 : -1;
       if (accept >= 0) {
-        take_trial(w, lc, accept, s[NV - 1]);
+        double fa = ft[0], fsa = fst[0], fba = fbt[0];
+#pragma unroll
+        for (int k = 1; k < NS; ++k)
+          if (accept == k) {
+            fa = ft[k];
+            fsa = fst[k];
+            fba = fbt[k];
+          }
+        get_trial(w, lc, accept, s[NV - 1].x);
+        s[NV - 1].f = fa;
+        s[NV - 1].fs = fsa;
+        s[NV - 1].fb = fba;
         rank_simplex(s, rank);
         next = PH_STEP;
       } else {
