@@ -254,9 +254,9 @@ __device__ __forceinline__ bool aberth_sweep(const cx<T> c[6], cx<T> z[5],
     const T sc = vmax(zn, (T)1);
     const T e2 = c_norm(dz);
     // (e^2)^3 <= tau^2 |z|^2 (s^2)^2, or e^2 <= 1e-26 |z|^2
-    const bool ok = (e2 * e2 * e2 <= tau2 * sc * (dmin[i] * dmin[i])) |
+    const bool ok = (e2 * e2 * e2 <= tau2 * sc * (dmin[i] * dmin[i])) ||
                     (e2 <= (T)1e-26 * sc);
-    conv = conv & (ok | (i == 4 && deg4));  // no short-circuit: no branches
+    conv = conv && (ok || (i == 4 && deg4));
     const T er = e2 / sc;
     em = vmax(er, em);
   }
