@@ -15,7 +15,7 @@ fittest solution at every checkpoint.  Then the ragged batching workload (4096 l
 epochs, population 128) is timed per generation, and on the same lightcurves
 the plain EA is compared with the learned form: a proposal network trained
 on generated lightcurves seeds half of every population (at the start and at
-each restart) and the EA's chi^2 judges.
+each restart) and the EA's chi^2 decides.
 
 Prints ONE JSON line.
 """

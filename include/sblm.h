@@ -433,7 +433,7 @@ int ea_refine(ea_state* st, const nm_config* cfg, int32_t* n_iter, sblm_stats* s
 /*
  * Not part of the paper's method: its neural-network approach (Sec. 4.1) is a
  * competing fitter, whereas this network only proposes starting points for
- * part of the initial population; the EA's chi^2 (Sec. 4.1, 4.4) judges them
+ * part of the initial population; the EA's chi^2 (Sec. 4.1, 4.4) ranks them
  * like any other individual and the uniform rows (Sec. A.1) remain.
  *
  * Input: a lightcurve resampled to MLP_NBINS normalised bins (sblm_resample),

@@ -1,7 +1,7 @@
 """FP64 numpy reference of the learned proposal network (TEST INFRASTRUCTURE).
 
 Not part of the paper's method: the proposal network seeds part of the EA's
-initial population, and the plain EA remains the judge (chi^2) and the
+initial population, and the plain EA's chi^2 still decides, and the EA is the
 fallback.  This module is the oracle of the GPU implementation:
 
 * resampling of a lightcurve to 256 bins over its observed span: the bin

@@ -2,7 +2,7 @@
 //
 // Not part of the paper's method (its neural network is a competing fitter,
 // Sec. 4.1); the network only proposes starting points, and the EA's chi^2
-// (Sec. 4.1, 4.4) stays the judge.  Contents:
+// (Sec. 4.1, 4.4) still decides.  Contents:
 //   * sblm_resample: a lightcurve -> 256 normalised bins;
 //   * mlp_make_data: training lightcurves drawn from the EA's parameter
 //     domain and observed at bin level through the forward model (Sec. 2.2);
