@@ -1,0 +1,42 @@
+"""bench.py's contract on the host (no GPU): the multi-GPU refusal, the peak
+it divides by, and that its HBM-traffic figure belongs to the kernel source it
+ships with."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 2
+    line = json.loads(res.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def test_fp64_vector_peak():
+    # 256 compute units x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz
+    assert bench.PEAK_VALU_TFLOPS == pytest.approx(78.6432)
+
+
+def test_flop_model_of_a_warm_solve():
+    # a magnification with one FP64 sweep: coefficients, the sweep, images with
+    # det J, the least-squares update (the per-item counts stated in the bench)
+    one_sweep = bench.FLOP_COEF + bench.FLOP_SWEEP64 + bench.FLOP_IMAGES + bench.FLOP_LSQ
+    assert one_sweep == 1261
+    assert bench.FLOP_SWEEP32 < bench.FLOP_SWEEP64
+
+
+def test_traffic_figure_matches_the_kernel_source():
+    # the committed rocprofv3 traffic is reported only for the source it was
+    # measured on; a changed kernel must be profiled again
+    assert bench.fitness_traffic() == bench.FITNESS_TRAFFIC["bytes_per_launch"]
+    assert bench.FITNESS_TRAFFIC["bytes_per_launch"] > \
+        bench.FITNESS_TRAFFIC["algorithmic_bytes_per_launch"]
