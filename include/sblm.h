@@ -384,9 +384,12 @@ int nm_refine_multi(const sblm_lcs* lcs, int32_t reps, const double* lo,
 /*
  * nm_iterated -- the iterated simplex (the comparison algorithm of Sec. 4.1):
  * simplices deployed at random start points, each run ended by convergence
- * or max_iter steps, the best of all runs kept.  Every lightcurve gets reps
- * slots; slot i runs starts i, i + reps, ..., i + reps * (runs - 1) one after
- * another, a slot moving on as soon as its run ends.  Start s of lightcurve
+ * or max_iter steps, the best of all runs kept.  Every lightcurve has
+ * reps * runs starts and reps slots: slot i begins with start i, and a slot
+ * whose run ends takes the lightcurve's next unstarted start in the same
+ * round (slots ending together in slot order), so long runs do not hold up
+ * the starts behind them; the result does not depend on which slot ran a
+ * start.  Start s of lightcurve
  * k, coordinate g: ((w >> 12) + 0.5) * 2^-52 for the Philox4x64-10 word
  * w = word g % 4 of key (seed, k), counter (0, NM_PURPOSE_START, s, g / 4):
  * uniform over the encoded domain (the prior box).  Each run is the simplex

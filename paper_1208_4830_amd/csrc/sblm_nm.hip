@@ -55,12 +55,17 @@ struct NmWork {
   int32_t* steps;  // [n]
   int32_t* done;   // [n] 1 once finished: its trial slots are not evaluated
   unsigned int* active;
-  // iterated mode: slot j = k * reps + i of lightcurve k runs the starts
-  // i, i + reps, ..., i + reps * (runs - 1)
+  // iterated mode: slot j = k * reps + i of lightcurve k begins with start
+  // i; a slot whose run ends takes the lightcurve's next unstarted start (the
+  // slots ending in one round in slot order), until reps * runs starts have
+  // been taken.  Each start's run and the best-of rule do not depend on
+  // which slot runs it.
   int32_t iter, reps, runs;
   uint64_t seed;
-  int32_t* run;    // [n] runs completed
-  int32_t* total;  // [n] steps over the completed runs
+  int32_t* run;         // [n] the start the slot runs
+  int32_t* ending;      // [n] the slot's run ended in this round's test
+  int32_t* next_start;  // [n / reps] the lightcurve's next unstarted start
+  int64_t* total;  // [n] steps over the completed runs
   double* bX;      // [NP][n] best result of the completed runs
   double* bF;      // [n]
   double* bFs;
@@ -96,31 +101,28 @@ __device__ void begin_run(const NmWork& w, int lc, const double* x0) {
   w.steps[lc] = 0;
 }
 
-// Start point of run c of slot lc (iterated mode): start s = i + reps * c of
-// lightcurve k, coordinate g = the open-interval map of the Philox word of
-// key (seed, k), counter (0, NM_PURPOSE_START, s, g / 4), word g % 4.
-__device__ void start_point(const NmWork& w, int lc, int c, double* x) {
-  const int k = lc / w.reps, i = lc - k * w.reps;
+// Start s of the lightcurve of slot lc (iterated mode): coordinate g = the
+// open-interval map of the Philox word of key (seed, k), counter
+// (0, NM_PURPOSE_START, s, g / 4), word g % 4.
+__device__ void start_point(const NmWork& w, int lc, int s, double* x) {
+  const int k = lc / w.reps;
   const Stream rs = {w.seed, (uint64_t)k, 0};
-  const uint64_t s = (uint64_t)i + (uint64_t)w.reps * (uint64_t)c;
-  for (int g = 0; g < NP; ++g) x[g] = u01(rs.draw(NM_PURPOSE_START, s, (uint64_t)g));
+  for (int g = 0; g < NP; ++g) x[g] = u01(rs.draw(NM_PURPOSE_START, (uint64_t)s, (uint64_t)g));
 }
 
 // A run of slot lc ends (iterated mode): its best vertex becomes the slot's
-// best when strictly lower (earlier starts win ties within a slot).
+// best when strictly lower (a slot takes its starts in increasing order, so
+// earlier starts win ties within a slot).
 __device__ void end_run(const NmWork& w, int lc) {
-  const int c = w.run[lc];
-  const int i = lc % w.reps;
   const double f = w.F[lc];
   if (w.bS[lc] < 0 || f < w.bF[lc]) {
     for (int g = 0; g < NP; ++g) w.bX[(int64_t)g * w.n + lc] = vtx(w, 0, g, lc);
     w.bF[lc] = f;
     w.bFs[lc] = w.FsV[lc];
     w.bFb[lc] = w.FbV[lc];
-    w.bS[lc] = i + w.reps * c;
+    w.bS[lc] = w.run[lc];
   }
   w.total[lc] += w.steps[lc];
-  w.run[lc] = c + 1;
 }
 
 __global__ void nm_start_kernel(NmWork w, const double* x0) {
@@ -128,11 +130,14 @@ __global__ void nm_start_kernel(NmWork w, const double* x0) {
   if (lc >= w.n) return;
   double x[NP];
   if (w.iter) {
-    w.run[lc] = 0;
+    const int i = lc % w.reps;
+    w.run[lc] = i;
+    w.ending[lc] = 0;
+    if (i == 0) w.next_start[lc / w.reps] = w.reps;
     w.total[lc] = 0;
     w.bS[lc] = -1;
     w.bF[lc] = INFINITY;
-    start_point(w, lc, 0, x);
+    start_point(w, lc, i, x);
   } else {
     for (int g = 0; g < NP; ++g) x[g] = x0[(int64_t)g * w.n + lc];
   }
@@ -146,35 +151,57 @@ __global__ void nm_nan_fill_kernel(double* p, int64_t n) {
   if (i < n) p[i] = NAN;
 }
 
-// Trial points of this round (and the round's active count reset: the
-// update kernel that counts runs after this one on the same stream).
-__global__ void nm_propose_kernel(NmWork w, double tol_x, double tol_f, int32_t max_iter) {
+// The stopping test of this round (and the round's active count reset: the
+// update kernel that counts runs after this one on the same stream).  In
+// iterated mode a run that stops is recorded and its slot marked as ending;
+// the next kernel gives it its next start.
+__global__ void nm_test_kernel(NmWork w, double tol_x, double tol_f, int32_t max_iter) {
   const int lc = blockIdx.x * blockDim.x + threadIdx.x;
   if (lc == 0) *w.active = 0u;
   if (lc >= w.n) return;
+  if (w.iter) w.ending[lc] = 0;
+  if (w.phase[lc] != PH_STEP) return;
+  double dx = 0.0, df = 0.0;
+  bool undefined = false;  // inf - inf: never converged
+  const double f0 = w.F[lc];
+  for (int v = 1; v < NV; ++v) {
+    const double d = fabs(f0 - w.F[(int64_t)v * w.n + lc]);
+    undefined |= isnan(d);
+    df = fmax(df, d);
+    for (int g = 0; g < NP; ++g) dx = fmax(dx, fabs(vtx(w, v, g, lc) - vtx(w, 0, g, lc)));
+  }
+  if ((!undefined && dx <= tol_x && df <= tol_f) || w.steps[lc] >= max_iter) {
+    w.phase[lc] = PH_DONE;
+    if (w.iter) {
+      end_run(w, lc);
+      w.ending[lc] = 1;
+    } else {
+      w.done[lc] = 1;
+    }
+  }
+}
+
+// Trial points of this round.  In iterated mode an ending slot first takes
+// its lightcurve's next unstarted start: the slots of a lightcurve that end
+// in this round take them in slot order (the update kernel then advances the
+// lightcurve's counter), and a slot with none left is done.
+__global__ void nm_propose_kernel(NmWork w) {
+  const int lc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lc >= w.n) return;
   int ph = w.phase[lc];
   double x[NP];
-  if (ph == PH_STEP) {
-    double dx = 0.0, df = 0.0;
-    bool undefined = false;  // inf - inf: never converged
-    const double f0 = w.F[lc];
-    for (int v = 1; v < NV; ++v) {
-      const double d = fabs(f0 - w.F[(int64_t)v * w.n + lc]);
-      undefined |= isnan(d);
-      df = fmax(df, d);
-      for (int g = 0; g < NP; ++g) dx = fmax(dx, fabs(vtx(w, v, g, lc) - vtx(w, 0, g, lc)));
-    }
-    if ((!undefined && dx <= tol_x && df <= tol_f) || w.steps[lc] >= max_iter) {
-      if (w.iter) end_run(w, lc);
-      if (w.iter && w.run[lc] < w.runs) {  // the slot's next start, this round
-        start_point(w, lc, w.run[lc], x);
-        begin_run(w, lc, x);
-        ph = PH_INIT1;
-      } else {
-        ph = PH_DONE;
-        w.phase[lc] = PH_DONE;
-        w.done[lc] = 1;
-      }
+  if (w.iter && w.ending[lc]) {
+    const int k = lc / w.reps, i = lc - k * w.reps;
+    int rank = 0;
+    for (int j = 0; j < i; ++j) rank += w.ending[k * w.reps + j];
+    const int s = w.next_start[k] + rank;
+    if (s < w.reps * w.runs) {
+      w.run[lc] = s;
+      start_point(w, lc, s, x);
+      begin_run(w, lc, x);
+      ph = PH_INIT1;
+    } else {
+      w.done[lc] = 1;
     }
   }
   switch (ph) {
@@ -313,6 +340,12 @@ __device__ __forceinline__ void share_values(Vertex* s) {
 __global__ __launch_bounds__(256) void nm_update_kernel(NmWork w) {
   const int lc = blockIdx.x * blockDim.x + threadIdx.x;
   if (lc >= w.n) return;
+  if (w.iter && lc % w.reps == 0) {  // starts taken by this round's ending slots
+    const int k = lc / w.reps;
+    int taken = 0;
+    for (int j = 0; j < w.reps; ++j) taken += w.ending[k * w.reps + j];
+    w.next_start[k] += taken;
+  }
   const int ph = w.phase[lc];
   if (ph == PH_DONE) return;
   Vertex s[NV];
@@ -497,10 +530,11 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
             hipMalloc(&w.done, nn * 4) == hipSuccess &&
             hipMalloc(&w.active, 4) == hipSuccess;
   if (ok && iter)
-    ok = hipMalloc(&w.run, nn * 4) == hipSuccess && hipMalloc(&w.total, nn * 4) == hipSuccess &&
+    ok = hipMalloc(&w.run, nn * 4) == hipSuccess && hipMalloc(&w.total, nn * 8) == hipSuccess &&
          hipMalloc(&w.bX, nn * NP * 8) == hipSuccess && hipMalloc(&w.bF, nn * 8) == hipSuccess &&
          hipMalloc(&w.bFs, nn * 8) == hipSuccess && hipMalloc(&w.bFb, nn * 8) == hipSuccess &&
-         hipMalloc(&w.bS, nn * 4) == hipSuccess;
+         hipMalloc(&w.bS, nn * 4) == hipSuccess && hipMalloc(&w.ending, nn * 4) == hipSuccess &&
+         hipMalloc(&w.next_start, (size_t)lcs.n_lc * 4) == hipSuccess;
   int rc = SBLM_OK;
   if (!ok) {
     (void)hipGetLastError();
@@ -565,13 +599,19 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
     rc = check_hip(hipGetLastError(), "nm_refine: start");
   }
   // rounds per run: 2 for the initial simplex, 1 per step, 2 more per shrink
-  const int64_t max_rounds = (4 + 3 * (int64_t)cfg.max_iter) * w.runs;
+  // (one slot may run every start of its lightcurve)
+  const int64_t max_rounds =
+      (4 + 3 * (int64_t)cfg.max_iter) * (iter ? (int64_t)w.reps * w.runs : 1);
   const int chunk = 16;
   for (int64_t r = 0; rc == SBLM_OK && r < max_rounds; r += chunk) {
     for (int k = 0; k < chunk && rc == SBLM_OK; ++k) {
-      hipLaunchKernelGGL(nm_propose_kernel, grid, blk, 0, st, w, cfg.tol_x, cfg.tol_f,
+      hipLaunchKernelGGL(nm_test_kernel, grid, blk, 0, st, w, cfg.tol_x, cfg.tol_f,
                          cfg.max_iter);
       hipError_t e = hipGetLastError();
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(nm_propose_kernel, grid, blk, 0, st, w);
+        e = hipGetLastError();
+      }
       if (e == hipSuccess) e = launch_fitness(a, cfg.mode, true, st, 4);
       if (e == hipSuccess) {
         hipLaunchKernelGGL(nm_update_kernel, grid, blk, 0, st, w);
@@ -599,7 +639,7 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
     rc = check_hip(hipGetLastError(), "nm_refine: synchronise");
   void* bufs[] = {w.V,    w.F,    w.FsV,  w.FbV,  w.T,   w.cT,  w.fsT, w.fbT, w.phase, w.steps,
                   w.done, w.active, w.run, w.total, w.bX, w.bF, w.bFs, w.bFb, w.bS,
-                  root_cache};
+                  w.ending, w.next_start, root_cache};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   return rc;
