@@ -208,3 +208,34 @@ def test_multi_and_iterated_full_size_sampled(hip):
         for s in range(reps * runs):
             assert c[k] <= f(NM.start_point(seed, k, s)) * (1 + 1e-12)
         assert it[k] >= reps * runs
+
+
+def test_iterated_simplex_repeatable_and_complete(hip):
+    # slots take the next unstarted start of their lightcurve as their runs
+    # end (3 slots x 3 runs, runs of different lengths): two calls agree bit
+    # for bit, and the result is the oracle's best over all nine starts
+    lengths = [150, 90]
+    wl = inputs.uniform_workload(45, len(lengths), 150)
+    ts, off = [], [0]
+    for k, L in enumerate(lengths):
+        ts.append(wl.t[k * 150:k * 150 + L])
+        off.append(off[-1] + L)
+    wl.t, wl.off = np.concatenate(ts), np.array(off, np.int64)
+    wl.sfrac, wl.noise = wl.sfrac[:wl.t.size], wl.noise[:wl.t.size]
+    y, w = oracle_lightcurves(wl)
+    lcs = device_lcs(hip, wl, y, w)
+    cfg = hip.nm_default_config()
+    cfg.max_iter = 40
+    reps, runs, seed = 3, 3, 99
+    first = [a.cpu().numpy() for a in hip.nm_iterated(lcs, LO, HI, reps, runs, seed, cfg)]
+    second = [a.cpu().numpy() for a in hip.nm_iterated(lcs, LO, HI, reps, runs, seed, cfg)]
+    for a, b in zip(first, second):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    x, c, _, _, it = first
+    for k in range(len(lengths)):
+        sl = slice(off[k], off[k + 1])
+        xr, fr, total, s = NM.iterated(oracle_f(wl.t[sl], y[sl], w[sl]), seed, k, reps * runs,
+                                       cfg.tol_x, cfg.tol_f, cfg.max_iter)
+        assert it[k] == total, (k, it[k], total)
+        assert np.array_equal(x[:, k], xr), (k, s)
+        assert abs(c[k] - fr) <= 1e-8 * max(abs(fr), 1e-300) + 1e-14 * np.sum(w[sl] * y[sl] ** 2)
