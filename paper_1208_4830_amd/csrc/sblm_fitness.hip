@@ -707,10 +707,19 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
   bool have_prev = false, prev_deg4 = false, have_prev2 = false, have_prev3 = false;
   double t1 = 0.0, t2 = 0.0, t3 = 0.0;  // epochs of z, zp and zpp
 
+  // the epoch time one step ahead, the observation at the top of its step:
+  // the loads are in flight during the solve
+  double t_next = (0 < Cg && k0 < k1) ? a.t[k0] : t0;
   for (int64_t s = 0; s < C; ++s) {
     const int64_t k = k0 + s;
     const bool active = (s < Cg) && (k < k1);
-    const double t = active ? a.t[k] : t0;
+    const double t = active ? t_next : t0;
+    t_next = (s + 1 < Cg && k + 1 < k1) ? a.t[k + 1] : t0;
+    double wk = 0.0, yk = 0.0;
+    if (CHI2 && active) {
+      wk = a.w[k];
+      yk = a.y[k];
+    }
     cx<double> zeta, c[6];
     const bool deg4 = epoch_poly(x, t, zeta, c);
     bool warm = have_prev && !deg4 && !prev_deg4;
@@ -786,7 +795,7 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
       const double A = magnification(z, zeta, d, q, deg4, nimg, npol);
       st.polished += npol;
       if (CHI2) {
-        lsq_include(ls, a.w[k], 1.0, A, a.y[k]);
+        lsq_include(ls, wk, 1.0, A, yk);
       } else {
         const int64_t o = ind * a.n_t + (k - e0);
         a.A[o] = A;
