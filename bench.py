@@ -51,7 +51,7 @@ N_GEN_FIT = 500
 # workload and schedule, from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a
 # copy kernel of known size (profiles/fitness_kernel_fp64_256lc_1000ep_pop256_
 # traffic.md).  Valid only for the kernel source it was taken on.
-FITNESS_TRAFFIC = dict(source_sha256_16="526d878095dd16b4", bytes_per_launch=15.40e6,
+FITNESS_TRAFFIC = dict(source_sha256_16="9f43dbfc9d015751", bytes_per_launch=15.35e6,
                        algorithmic_bytes_per_launch=10.86e6)
 
 

@@ -720,6 +720,14 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
       wk = a.w[k];
       yk = a.y[k];
     }
+    // the root history, read before the polynomial is formed (its latency
+    // then overlaps the coefficients)
+    cx<double> hp[5], hpp[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      hp[i] = hist.get(0, i);
+      hpp[i] = hist.get(1, i);
+    }
     cx<double> zeta, c[6];
     const bool deg4 = epoch_poly(x, t, zeta, c);
     bool warm = have_prev && !deg4 && !prev_deg4;
@@ -764,7 +772,7 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
       }
 #pragma unroll
       for (int i = 0; i < 5; ++i) {
-        const cx<double> old = z[i], zp = hist.get(0, i), zpp = hist.get(1, i);
+        const cx<double> old = z[i], zp = hp[i], zpp = hpp[i];
         z[i] = {fma(w1, old.re, fma(w2, zp.re, w3 * zpp.re)),
                 fma(w1, old.im, fma(w2, zp.im, w3 * zpp.im))};
         hist.set(1, i, zp);
