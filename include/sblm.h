@@ -394,7 +394,8 @@ int nm_refine_multi(const sblm_lcs* lcs, int32_t reps, const double* lo,
  * w = word g % 4 of key (seed, k), counter (0, NM_PURPOSE_START, s, g / 4):
  * uniform over the encoded domain (the prior box).  Each run is the simplex
  * of nm_refine (settings above, cfg->max_iter per run).
- *   reps, runs  >= 1; n_lc * reps <= 2^24; runs * (max_iter + 1) < 2^31
+ *   reps, runs  >= 1; n_lc * reps <= 2^24; reps * runs < 2^31;
+ *                runs * (max_iter + 1) < 2^31
  *   x       [6][n_lc] device out, encoded best point over the reps * runs
  *           starts (lowest chi^2; the lowest start index among equals)
  *   chi2, Fs, Fb  [n_lc] device out (nullable)

@@ -194,10 +194,10 @@ __global__ void nm_propose_kernel(NmWork w) {
     const int k = lc / w.reps, i = lc - k * w.reps;
     int rank = 0;
     for (int j = 0; j < i; ++j) rank += w.ending[k * w.reps + j];
-    const int s = w.next_start[k] + rank;
-    if (s < w.reps * w.runs) {
-      w.run[lc] = s;
-      start_point(w, lc, s, x);
+    const int64_t s = (int64_t)w.next_start[k] + rank;
+    if (s < (int64_t)w.reps * w.runs) {
+      w.run[lc] = (int32_t)s;
+      start_point(w, lc, (int)s, x);
       begin_run(w, lc, x);
       ph = PH_INIT1;
     } else {
@@ -344,7 +344,9 @@ __global__ __launch_bounds__(256) void nm_update_kernel(NmWork w) {
     const int k = lc / w.reps;
     int taken = 0;
     for (int j = 0; j < w.reps; ++j) taken += w.ending[k * w.reps + j];
-    w.next_start[k] += taken;
+    // at most reps * runs (< 2^31): the counter never passes the last start
+    const int64_t nx = (int64_t)w.next_start[k] + taken, all = (int64_t)w.reps * w.runs;
+    w.next_start[k] = (int32_t)(nx < all ? nx : all);
   }
   const int ph = w.phase[lc];
   if (ph == PH_DONE) return;

@@ -118,6 +118,9 @@ def test_simplex_arguments():
     long_cfg.max_iter = 1000000
     _expect(lib.nm_iterated(ctypes.byref(lc), 2, 5000, 1, lo, hi, ctypes.byref(long_cfg), FAKE,
                             None, None, None, None, None, None), ERANGE, "per slot")
+    # more than 2^31 - 1 starts per lightcurve (the start counter is 32-bit)
+    _expect(lib.nm_iterated(ctypes.byref(lc), 1 << 16, 1 << 16, 1, lo, hi, ctypes.byref(cfg),
+                            FAKE, None, None, None, None, None, None), ERANGE, "starts")
 
 
 def test_network_arguments():
