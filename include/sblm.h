@@ -255,10 +255,15 @@ int ea_generation(ea_state* st, const double* chi2, const double* Fs,
 int ea_evaluate(ea_state* st, sblm_stats* stats, void* stream);
 
 /*
- * ea_fit -- run n_gen generations, each = ea_evaluate + (when due, the
- * migration of ea_config) + ea_generation on the state's own buffers,
- * replayed from one captured HIP graph.
+ * ea_fit -- run n_gen generations of the evolutionary loop of Appendix A
+ * (evaluate the fitness of every individual, then rank, select, reproduce
+ * and mutate, test for stagnation and restart, repeated generation after
+ * generation), each = ea_evaluate + (when due, the migration of ea_config,
+ * Sec. 5.3) + ea_generation on the state's own buffers, replayed from one
+ * captured HIP graph.
  *   n_gen  >= 0
+ *   stats  nullable device pointer; accumulates the counters of every
+ *          generation's fitness evaluation
  * Errors: SBLM_EINVAL, SBLM_ESTATE, SBLM_EDEVICE.
  */
 int ea_fit(ea_state* st, int32_t n_gen, sblm_stats* stats, void* stream);
@@ -311,11 +316,18 @@ int ea_buffers(ea_state* st, double** P, double** chi2, double** Fs,
  * Synchronises `stream`. */
 int ea_summary(ea_state* st, ea_lc_summary* out, void* stream);
 
-/* Snapshot of the whole state (config, seed, population and per-lightcurve
- * records) into host memory.  With buf == NULL, *len receives the size.
- * Synchronises `stream`.  ea_load restores a snapshot into a state created
- * with the same config, lightcurve count and seed; the continued run is
- * bit-identical to an uninterrupted one. */
+/* ea_save -- snapshot of the whole state (config, seed, population and
+ * per-lightcurve records: the best-ever solution that App. A.7 keeps across
+ * restarts, p_mut, the stagnation counters and the history of best chi^2
+ * the stagnation test reads) into host memory buf (caller-owned, *len
+ * bytes).  With buf == NULL, *len receives the size; SBLM_EINVAL when *len
+ * is too small.  Synchronises `stream`.
+ * ea_load -- restore such a snapshot (host buf of len bytes) into a state
+ * created with the same config, lightcurve count and seed (SBLM_ESTATE
+ * otherwise, or for a short snapshot); the continued run is bit-identical
+ * to an uninterrupted one, since every random draw is keyed by (seed,
+ * lightcurve, generation) and not by the history of calls (App. A.7 resumes
+ * from the saved record). */
 int ea_save(ea_state* st, void* buf, size_t* len, void* stream);
 int ea_load(ea_state* st, const void* buf, size_t len, void* stream);
 

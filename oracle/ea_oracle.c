@@ -139,28 +139,38 @@ static void init_population(const orc_ea_config* cfg, uint64_t seed,
                            (uint64_t)(cfg->pop - 1), (uint64_t)g));
 }
 
-void orc_ea_init(const orc_ea_config* cfg, uint64_t seed, int64_t lc,
-                 double* P, orc_ea_lc* st) {
+/* The configuration limits of this oracle: the generation works in fixed
+ * arrays of ORC_EA_POP_MAX rows and keeps a history of 64 generations. */
+static int config_ok(const orc_ea_config* cfg) {
+  return cfg && cfg->pop >= 2 && cfg->pop <= ORC_EA_POP_MAX &&
+         cfg->stag_window >= 1 && cfg->stag_window <= 63 && cfg->n_tourn >= 0;
+}
+
+int orc_ea_init(const orc_ea_config* cfg, uint64_t seed, int64_t lc,
+                double* P, orc_ea_lc* st) {
+  if (!config_ok(cfg) || !P || !st) return -1;
   memset(st, 0, sizeof(*st));
   st->p_mut = cfg->p_mut0;
   st->best_chi2 = INFINITY;
   st->best_gen = -1;
   for (int k = 0; k < 64; ++k) st->hist[k] = INFINITY;
   init_population(cfg, seed, lc, 0, P);
+  return 0;
 }
 
 static double rank_key(double c) { return isnan(c) ? INFINITY : c; }
 
-void orc_ea_generation(const orc_ea_config* cfg, uint64_t seed, int64_t lc,
-                       double* P, const double* chi2, const double* Fs,
-                       const double* Fb, orc_ea_lc* st, int32_t* parents) {
+int orc_ea_generation(const orc_ea_config* cfg, uint64_t seed, int64_t lc,
+                      double* P, const double* chi2, const double* Fs,
+                      const double* Fb, orc_ea_lc* st, int32_t* parents) {
+  if (!config_ok(cfg) || !P || !chi2 || !Fs || !Fb || !st) return -1;
   const int N = cfg->pop;
   const int64_t gen = st->gen;
   const uint64_t L = (uint64_t)lc, G = (uint64_t)gen;
   int nt = cfg->n_tourn > 0 ? cfg->n_tourn : (N + 24) / 25;
 
   /* (A.3) rank: stable insertion sort of row indices by chi^2 */
-  int perm[1024];
+  int perm[ORC_EA_POP_MAX];
   for (int i = 0; i < N; ++i) perm[i] = i;
   for (int i = 1; i < N; ++i) {
     int v = perm[i], j = i - 1;
@@ -170,7 +180,7 @@ void orc_ea_generation(const orc_ea_config* cfg, uint64_t seed, int64_t lc,
     }
     perm[j + 1] = v;
   }
-  double sorted[1024 * 6];
+  double sorted[ORC_EA_POP_MAX * 6];
   for (int r = 0; r < N; ++r)
     for (int g = 0; g < 6; ++g) sorted[r * 6 + g] = P[perm[r] * 6 + g];
   double b = rank_key(chi2[perm[0]]);
@@ -187,7 +197,7 @@ void orc_ea_generation(const orc_ea_config* cfg, uint64_t seed, int64_t lc,
   st->hist[gen % (W + 1)] = b;
 
   /* (A.4, A.5) selection and reproduction; row 0 keeps the fittest */
-  double next[1024 * 6];
+  double next[ORC_EA_POP_MAX * 6];
   for (int g = 0; g < 6; ++g) next[g] = sorted[g];
   int npair = N / 2;
   for (int k = 0; k < npair; ++k) {
@@ -276,4 +286,5 @@ void orc_ea_generation(const orc_ea_config* cfg, uint64_t seed, int64_t lc,
     }
   }
   st->gen = gen + 1;
+  return 0;
 }

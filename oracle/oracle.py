@@ -70,6 +70,8 @@ def _load():
                                 ctypes.POINTER(EALCState)]
     lib.orc_ea_generation.argtypes = [ctypes.POINTER(EAConfig), ctypes.c_uint64, ctypes.c_int64,
                                       _dp, _dp, _dp, _dp, ctypes.POINTER(EALCState), _i32p]
+    lib.orc_ea_init.restype = ctypes.c_int
+    lib.orc_ea_generation.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -214,13 +216,15 @@ class EA:
 
     def __init__(self, pop, seed, lc, n_tourn=0, p_mut0=0.01, p_mut_min=1e-4, p_mut_max=0.5,
                  stag_frac=0.01, stag_window=10, restart_after=10):
-        assert 2 <= pop <= 1024 and 1 <= stag_window <= 63
         self.cfg = EAConfig(pop, n_tourn, p_mut0, p_mut_min, p_mut_max, stag_frac,
                             stag_window, restart_after)
         self.seed, self.lc, self.pop = seed, lc, pop
         self.P = np.zeros((pop, 6))
         self.st = EALCState()
-        _load().orc_ea_init(ctypes.byref(self.cfg), seed, lc, _p(self.P), ctypes.byref(self.st))
+        rc = _load().orc_ea_init(ctypes.byref(self.cfg), seed, lc, _p(self.P),
+                                 ctypes.byref(self.st))
+        if rc != 0:
+            raise ValueError("orc_ea_init rejected the configuration")
 
     def generation(self, chi2, Fs=None, Fb=None):
         """Advance one generation; returns the parent ranks of every pairing."""
@@ -228,9 +232,11 @@ class EA:
         Fs = _f64(np.zeros(self.pop) if Fs is None else Fs)
         Fb = _f64(np.zeros(self.pop) if Fb is None else Fb)
         parents = np.zeros(2 * (self.pop // 2), dtype=np.int32)
-        _load().orc_ea_generation(ctypes.byref(self.cfg), self.seed, self.lc, _p(self.P),
-                                  _p(chi2), _p(Fs), _p(Fb), ctypes.byref(self.st),
-                                  _p(parents, _i32p))
+        rc = _load().orc_ea_generation(ctypes.byref(self.cfg), self.seed, self.lc,
+                                       _p(self.P), _p(chi2), _p(Fs), _p(Fb),
+                                       ctypes.byref(self.st), _p(parents, _i32p))
+        if rc != 0:
+            raise ValueError("orc_ea_generation rejected the configuration")
         return parents
 
     def summary(self):

@@ -50,10 +50,14 @@ typedef struct {
   double hist[64]; /* best chi^2 of generation g at hist[g % (window+1)] */
 } orc_ea_lc;
 
-void orc_ea_init(const orc_ea_config* cfg, uint64_t seed, int64_t lc,
-                 double* P /* [pop][6] row-major */, orc_ea_lc* st);
-void orc_ea_generation(const orc_ea_config* cfg, uint64_t seed, int64_t lc,
-                       double* P, const double* chi2, const double* Fs,
-                       const double* Fb, orc_ea_lc* st,
-                       int32_t* parents /* nullable [2*floor(pop/2)] ranks */);
+/* Both return 0, or -1 (nothing written) for a null pointer or a
+ * configuration outside 2 <= pop <= ORC_EA_POP_MAX, 1 <= stag_window <= 63,
+ * n_tourn >= 0. */
+#define ORC_EA_POP_MAX 1024
+int orc_ea_init(const orc_ea_config* cfg, uint64_t seed, int64_t lc,
+                double* P /* [pop][6] row-major */, orc_ea_lc* st);
+int orc_ea_generation(const orc_ea_config* cfg, uint64_t seed, int64_t lc,
+                      double* P, const double* chi2, const double* Fs,
+                      const double* Fb, orc_ea_lc* st,
+                      int32_t* parents /* nullable [2*floor(pop/2)] ranks */);
 #endif

@@ -10,6 +10,7 @@ import pytest
 from scipy import stats
 
 import oracle as O
+from oracle import oracle as OO
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -233,3 +234,118 @@ def test_clone_mode_copies_parents_bit_exactly():
                 exp = fma(1.0 - p, X, p) if xs >> 63 else fma(-p, X, p)
                 assert ea.P[slot, g] == min(max(exp, 0.0), 1.0)
     assert nt == 2
+
+
+def _creep_inputs(seed, lc, slot, g):
+    """Sign bit and factor X of the creep of gene g of row `slot` (App. A.6)."""
+    xs = O.draw(seed, lc, 0, 4, slot, 2 * g)
+    X = O.exp2_neg(52.0 * O.u01(O.draw(seed, lc, 0, 4, slot, 2 * g + 1)))
+    return xs >> 63, X
+
+
+def _uncreep(p_out, plus, X):
+    """The gene before a creep with factor X (None where the creep lost it:
+    X close to 1, or the result clamped)."""
+    if X > 0.5 or p_out in (0.0, 1.0):
+        return None
+    return (p_out - X) / (1.0 - X) if plus else p_out / (1.0 - X)
+
+
+def _crossover_generation(pop, seed, lc):
+    ea = O.EA(pop, seed=seed, lc=lc, p_mut0=0.0, p_mut_min=0.0)  # no jumps
+    P_old = ea.P.copy()
+    parents = ea.generation(np.arange(pop, dtype=float))  # identity ranking
+    return P_old, ea.P, parents
+
+
+def test_crossover_binary_mode_swaps_whole_genes():
+    # Bin(1, 1/2) mode (App. A.5): every gene of child 1 is the gene of one
+    # parent, child 2 takes the other parent's, chosen per gene by its own
+    # draw; after the creep the children are the creeps of those genes.
+    seen = {0: 0, 1: 0}
+    n_mode = 0
+    for seed in (21, 22, 23):
+        pop = 64
+        P_old, P, parents = _crossover_generation(pop, seed, 4)
+        for k in range(pop // 2):
+            if O.below(O.draw(seed, 4, 0, 3, k, 0), 3) != 1:
+                continue
+            n_mode += 1
+            pa, pb = P_old[parents[2 * k]], P_old[parents[2 * k + 1]]
+            for g in range(6):
+                f = O.draw(seed, 4, 0, 3, k, 1 + g) >> 63
+                seen[f] += 1
+                src = ((2 * k + 1, pa[g] if f else pb[g]), (2 * k + 2, pb[g] if f else pa[g]))
+                for slot, p in src:
+                    if slot >= pop:
+                        continue
+                    plus, X = _creep_inputs(seed, 4, slot, g)
+                    exp = fma(1.0 - p, X, p) if plus else fma(-p, X, p)
+                    assert P[slot, g] == min(max(exp, 0.0), 1.0)
+    assert n_mode >= 10 and seen[0] > 20 and seen[1] > 20
+
+
+def test_crossover_blend_mode_per_gene_weights():
+    # U(0,1) mode (App. A.5): child 1 = f pa + (1-f) pb, child 2 = f pb +
+    # (1-f) pa, with its own f ~ U(0,1) for every gene.  Checked on the
+    # children recovered from the crept offspring: the sum of the two children
+    # is the sum of the parents, and the weight implied by child 1 is that
+    # gene's own draw.
+    n_checked = 0
+    for seed in (31, 32, 33):
+        pop = 64
+        P_old, P, parents = _crossover_generation(pop, seed, 6)
+        for k in range(pop // 2):
+            if O.below(O.draw(seed, 6, 0, 3, k, 0), 3) != 0:
+                continue
+            s1, s2 = 2 * k + 1, 2 * k + 2
+            if s2 >= pop:
+                continue
+            pa, pb = P_old[parents[2 * k]], P_old[parents[2 * k + 1]]
+            fs = []
+            for g in range(6):
+                c1 = _uncreep(P[s1, g], *_creep_inputs(seed, 6, s1, g))
+                c2 = _uncreep(P[s2, g], *_creep_inputs(seed, 6, s2, g))
+                if c1 is None or c2 is None or abs(pa[g] - pb[g]) < 1e-3:
+                    continue
+                assert abs((c1 + c2) - (pa[g] + pb[g])) < 1e-9
+                lo, hi = min(pa[g], pb[g]), max(pa[g], pb[g])
+                assert lo - 1e-9 <= c1 <= hi + 1e-9
+                f_implied = (c1 - pb[g]) / (pa[g] - pb[g])
+                f_draw = O.u01(O.draw(seed, 6, 0, 3, k, 1 + g))
+                assert abs(f_implied - f_draw) < 1e-6
+                fs.append(f_draw)
+                n_checked += 1
+            # one weight per gene, not one per child
+            if len(fs) >= 2:
+                assert len(set(fs)) == len(fs)
+    assert n_checked >= 30
+
+
+def test_crossover_mode_frequencies():
+    # the mode is uniform over the three forms of App. A.5
+    counts = np.zeros(3)
+    for k in range(3000):
+        counts[O.below(O.draw(5, 1, 0, 3, k, 0), 3)] += 1
+    assert stats.chisquare(counts).pvalue > 1e-3
+
+
+def test_generation_rejects_configurations_beyond_its_arrays():
+    # the C oracle checks its own limits (fixed arrays of 1024 rows), so a
+    # direct caller cannot overflow them
+    import ctypes
+    lib = OO._load()
+    P = np.zeros((1025, 6))
+    chi2 = np.zeros(1025)
+    st = OO.EALCState()
+    for pop, window in ((1025, 10), (1, 10), (16, 64), (16, 0)):
+        cfg = OO.EAConfig(pop, 0, 0.01, 1e-4, 0.5, 0.01, window, 10)
+        assert lib.orc_ea_init(ctypes.byref(cfg), 1, 0, OO._p(P), ctypes.byref(st)) == -1
+        assert lib.orc_ea_generation(ctypes.byref(cfg), 1, 0, OO._p(P), OO._p(chi2), OO._p(chi2),
+                                     OO._p(chi2), ctypes.byref(st), None) == -1
+    cfg = OO.EAConfig(1024, 0, 0.01, 1e-4, 0.5, 0.01, 10, 10)
+    assert lib.orc_ea_init(ctypes.byref(cfg), 1, 0, OO._p(P), ctypes.byref(st)) == 0
+    assert lib.orc_ea_generation(ctypes.byref(cfg), 1, 0, OO._p(P), OO._p(chi2), OO._p(chi2),
+                                 OO._p(chi2), ctypes.byref(st), None) == 0
+    with pytest.raises(ValueError):
+        O.EA(1025, seed=1, lc=0)
