@@ -74,7 +74,9 @@ typedef enum {
 typedef struct {
   unsigned long long n_solves;     /* polynomials solved                      */
   unsigned long long n_iter;       /* simultaneous-iteration sweeps, summed   */
-  unsigned long long n_capped;     /* solves that hit the iteration cap       */
+  unsigned long long n_capped;     /* solves that reached the iteration cap,
+                                      also after the cold retry (see
+                                      n_unsettled)                          */
   unsigned long long n_fallback;   /* MIXED: cold solves whose FP32 roots
                                       needed > 2 FP64 sweeps to converge      */
   unsigned long long n_degree4;    /* leading coefficient negligible          */
@@ -84,6 +86,18 @@ typedef struct {
                                       cost; n_iter is the lanes' own need)    */
   unsigned long long n_iter_fp32;  /* MIXED: the FP32 part of n_iter          */
   unsigned long long n_polished;   /* images refined on the lens equation     */
+  unsigned long long n_retried;    /* warm-started solves that failed and were
+                                      solved again from the cold start        */
+  unsigned long long n_unsettled;  /* capped solves whose roots were not finite
+                                      or still moved by more than 1e-4
+                                      relative in the last sweep: their
+                                      magnification is NaN (n_img 0), and so
+                                      is the chi^2 they enter (it ranks last);
+                                      the other capped solves have stalled at
+                                      the rounding level next to merging
+                                      images (a fold or a cusp of the
+                                      caustic), and their images are refined
+                                      on the lens equation                    */
 } sblm_stats;
 
 /* Ragged batch of lightcurves in CSR form.  Lightcurve k owns epochs
@@ -401,12 +415,13 @@ int nm_refine_multi(const sblm_lcs* lcs, int32_t reps, const double* lo,
  * whose run ends takes the lightcurve's next unstarted start in the same
  * round (slots ending together in slot order), so long runs do not hold up
  * the starts behind them; the result does not depend on which slot ran a
- * start.  Start s of lightcurve
+ * start (the first round of every run starts its root solves cold, never
+ * from roots that another run left in the slot).  Start s of lightcurve
  * k, coordinate g: ((w >> 12) + 0.5) * 2^-52 for the Philox4x64-10 word
  * w = word g % 4 of key (seed, k), counter (0, NM_PURPOSE_START, s, g / 4):
  * uniform over the encoded domain (the prior box).  Each run is the simplex
  * of nm_refine (settings above, cfg->max_iter per run).
- *   reps, runs  >= 1; n_lc * reps <= 2^24; reps * runs < 2^31;
+ *   reps, runs  >= 1; reps <= 1024; n_lc * reps <= 2^24; reps * runs < 2^31;
  *                runs * (max_iter + 1) < 2^31
  *   x       [6][n_lc] device out, encoded best point over the reps * runs
  *           starts (lowest chi^2; the lowest start index among equals)

@@ -162,13 +162,22 @@ __device__ __forceinline__ void horner(const cx<T> c[6], cx<T> z, cx<T>& p,
   }
 }
 
+// A source very close to a lens (within ~1e-3 theta_E of either) gives a
+// small leading coefficient: one root -- always spurious -- lies far out, at
+// about -c4/c5, the others near the lenses.  |c4| > 1e3 |c5| marks it.
+__device__ __forceinline__ bool far_root(const cx<double> c[6]) {
+  return c_norm(c[4]) > 1e6 * c_norm(c[5]);
+}
+
 // Starting points for a cold solve: five points on a circle about the root
 // centroid -c4/(5 c5) of radius (|c0|/|c5|)^(1/5) (geometric mean of the
 // root moduli); for a degree-4 polynomial four points and one root parked
-// far away, where it never moves.
+// far away, where it never moves; with a far root (far_root) the four near
+// roots start as for the degree-4 polynomial and the fifth at -c4/c5, which
+// it would otherwise take the iteration some 50-80 sweeps to walk out to.
 template <typename T>
 __device__ __forceinline__ void cold_start(const cx<T> c[6], bool deg4,
-                                           cx<T> z[5]) {
+                                           cx<T> z[5], bool far = false) {
   // cos/sin of 2 pi k/5 + 0.4 and 2 pi k/4 + 0.4
   const float c5a[5] = {0.92106099f, 0.06083749f, -0.88523008f, -0.62472004f,
                         0.52805164f};
@@ -176,23 +185,29 @@ __device__ __forceinline__ void cold_start(const cx<T> c[6], bool deg4,
                         -0.84920782f};
   const float c4a[4] = {0.92106099f, -0.38941834f, -0.92106099f, 0.38941834f};
   const float s4a[4] = {0.38941834f, 0.92106099f, -0.38941834f, -0.92106099f};
-  const int lead = deg4 ? 4 : 5;
+  const bool four = deg4 || far;
+  const int lead = four ? 4 : 5;
   const float n_lead = (float)c_norm(c[lead]);
   const float n_0 = (float)c_norm(c[0]);
   float ratio = n_0 / n_lead;
   if (!(ratio > 1e-30f) || !(ratio < 1e30f)) ratio = 1.0f;
-  const float R = powf(ratio, deg4 ? 0.125f : 0.1f);
+  const float R = powf(ratio, four ? 0.125f : 0.1f);
   // centroid = -c[lead-1] / (lead c[lead])
   const cx<float> a = {(float)c[lead - 1].re, (float)c[lead - 1].im};
   const cx<float> b = {(float)c[lead].re, (float)c[lead].im};
   const float ib = 1.0f / (fmaf(b.re, b.re, b.im * b.im) * (float)lead);
   const float cen_re = -(a.re * b.re + a.im * b.im) * ib;
   const float cen_im = -(a.im * b.re - a.re * b.im) * ib;
-  if (deg4) {
+  if (four) {
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       z[k] = {(T)(cen_re + R * c4a[k]), (T)(cen_im + R * s4a[k])};
     z[4] = {(T)1e18, (T)1e18};
+    if (far) {  // -c4/c5
+      const T n5 = c_norm(c[5]);
+      z[4] = {-(c[4].re * c[5].re + c[4].im * c[5].im) / n5,
+              -(c[4].im * c[5].re - c[4].re * c[5].im) / n5};
+    }
   } else {
 #pragma unroll
     for (int k = 0; k < 5; ++k)
@@ -438,21 +453,35 @@ __device__ __forceinline__ double grp_shfl_down(double v, int off) {
 }
 
 struct LaneStats {
-  unsigned long long solves, iters, capped, fallback, deg4, wave_iters, iters32, polished;
+  unsigned long long solves, iters, capped, fallback, deg4, wave_iters, iters32, polished,
+      retried, unsettled;
 };
 
-// Solve one polynomial from the roots in z (warm) or from a cold start.
-// Returns the number of FP64-equivalent sweeps this lane needed.
+// A solve that reaches the iteration cap has settled when its roots are
+// finite and its last sweep moved them by less than this much relative
+// (squared, i.e. 1e-4): the iteration has stalled at the rounding level next
+// to a near-multiple root -- two images merging at a fold of the caustic,
+// three at a cusp, where FP64 resolves the roots only to about eps^(1/2) and
+// eps^(1/3) ~ 6e-6 relative and the steps jitter at that level; the
+// accepted images are refined on the lens equation anyway.
+#define SBLM_SETTLED_STEP2 1e-8
+
+// Solve one polynomial from the roots in z (warm) or from a cold start;
+// ok = converged to finite roots; settled = ok, or capped with finite roots
+// that no longer move (see SBLM_SETTLED_STEP2).  `retry` marks a second,
+// cold attempt at an epoch whose warm-started solve failed (it is not
+// counted as another solve).
 template <int MODE>
 __device__ __forceinline__ void solve_roots(const cx<double> c[6], bool deg4,
                                             bool warm, bool active,
                                             cx<double> z[5], LaneStats& st,
-                                            bool& ok) {
+                                            bool& ok, bool& settled, bool retry = false) {
   constexpr int MAXIT64 = 60, MAXIT32 = 30;
   // estimated relative error left after the last step
   const double tau64 = SBLM_ROOT_TAU;
   const float tau32 = 1e-7f;
-  if (!warm && active) cold_start<double>(c, deg4, z);
+  const bool far = !deg4 && far_root(c);
+  if (!warm && active) cold_start<double>(c, deg4, z, far);
   int it_lane = 0, it32_lane = 0, it_wave = 0;
   bool done = !active;
   if (MODE == SBLM_MIXED) {
@@ -464,10 +493,11 @@ __device__ __forceinline__ void solve_roots(const cx<double> c[6], bool deg4,
     for (int i = 0; i < 5; ++i) zf[i] = {(float)z[i].re, (float)z[i].im};
     // The FP32 phase runs the solves that start cold (the long part of the
     // iteration); a warm start is already closer to the roots than FP32 can
-    // resolve, so those solves and degree-4 polynomials (parked root out of
-    // FP32 range) go straight to FP64.  The FP32 phase also ends when its
+    // resolve, so those solves, degree-4 polynomials (parked root out of
+    // FP32 range) and those with a far root (its powers overflow FP32) go
+    // straight to FP64.  The FP32 phase also ends when its
     // steps stop shrinking: the roots are then at the FP32 rounding floor.
-    bool done32 = done || deg4 || warm;
+    bool done32 = done || deg4 || warm || far;
     float prev = INFINITY;
     for (int it = 0; it < MAXIT32; ++it) {
       if (__all(done32)) break;
@@ -485,12 +515,12 @@ __device__ __forceinline__ void solve_roots(const cx<double> c[6], bool deg4,
       for (int i = 0; i < 5; ++i) z[i] = {(double)zf[i].re, (double)zf[i].im};
     }
   }
+  double em_last = INFINITY;
   for (int it = 0; it < MAXIT64; ++it) {
     if (__all(done)) break;
     ++it_wave;
     if (!done) {
-      double em;
-      done = aberth_sweep<double>(c, z, deg4, tau64, &em);
+      done = aberth_sweep<double>(c, z, deg4, tau64, &em_last);
       ++it_lane;
     }
   }
@@ -499,11 +529,11 @@ __device__ __forceinline__ void solve_roots(const cx<double> c[6], bool deg4,
   for (int i = 0; i < 5; ++i)
     finite = finite && isfinite(z[i].re) && isfinite(z[i].im);
   ok = done && finite;
+  settled = finite && (done || em_last <= SBLM_SETTLED_STEP2);
   if (active) {
-    st.solves += 1;
+    st.solves += retry ? 0 : 1;
     st.iters += it_lane + it32_lane;
-    st.capped += done ? 0 : 1;
-    st.deg4 += deg4 ? 1 : 0;
+    st.deg4 += (deg4 && !retry) ? 1 : 0;
     // MIXED: a cold solve whose FP32 result needed more than two FP64 sweeps
     if (MODE == SBLM_MIXED) st.fallback += (!warm && it_lane > 2) ? 1 : 0;
     st.wave_iters += it_wave;
@@ -734,8 +764,11 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
     if constexpr (G > 64) {
       // simplex rounds: a lane's first epoch starts from the roots the lane
       // found there for the same trial slot in the previous round (the
-      // simplex moves little between rounds), else cold
-      if (s == 0 && a.root_cache && active && !deg4) {
+      // simplex moves little between rounds), else cold -- always cold in
+      // the first round of a run, so that a run does not depend on what ran
+      // in its slot before
+      if (s == 0 && a.root_cache && active && !deg4 &&
+          !(a.cold && a.cold[x.ind / a.skip_per])) {
         const double* rc = a.root_cache + (x.ind * G + x.gl) * 10;
         cx<double> zc[5];
         bool fin = true;
@@ -779,8 +812,26 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
         hist.set(0, i, old);
       }
     }
-    bool ok;
-    solve_roots<MODE>(c, deg4, warm, active, z, st, ok);
+    bool ok, settled;
+    solve_roots<MODE>(c, deg4, warm, active, z, st, ok, settled);
+    {
+      // a warm start that did not converge (it came from roots of another
+      // epoch or, in the simplex rounds, of another point): solve again from
+      // the cold start; roots that still have not settled poison the result
+      // (A and with it chi^2 become NaN, which ranks last)
+      const bool retry = active && !ok && warm;
+      if (__any(retry)) {
+        bool ok2, settled2;
+        solve_roots<MODE>(c, deg4, false, retry, z, st, ok2, settled2, true);
+        if (retry) {
+          ok = ok2;
+          settled = settled2;
+          st.retried += 1;
+        }
+      }
+      if (active && !ok) st.capped += 1;
+      if (active && !settled) st.unsettled += 1;
+    }
     if constexpr (G > 64) {
       if (s == 0 && a.root_cache && active) {
         double* rc = a.root_cache + (x.ind * G + x.gl) * 10;
@@ -800,7 +851,11 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
     prev_deg4 = deg4;
     if (active) {
       int nimg, npol = 0;
-      const double A = magnification(z, zeta, d, q, deg4, nimg, npol);
+      double A = magnification(z, zeta, d, q, deg4, nimg, npol);
+      if (!settled) {
+        A = NAN;
+        nimg = 0;
+      }
       st.polished += npol;
       if (CHI2) {
         lsq_include(ls, wk, 1.0, A, yk);
@@ -848,7 +903,9 @@ __device__ __forceinline__ void fit_wave_async(const FitArgs& a, int64_t wave_it
   for (int j = 0; j < 6; ++j) c[j] = {0.0, 0.0};
   bool deg4 = false, in32 = false, warm = false;
   double t = 0.0;
-  int it64 = 0, it32 = 0;
+  int it64 = 0, it32 = 0, it_prior = 0;
+  bool retried = false;
+  double em64 = INFINITY;
   float prev32 = INFINITY;
   unsigned long long passes = 0;
   while (__any(busy)) {
@@ -885,11 +942,14 @@ __device__ __forceinline__ void fit_wave_async(const FitArgs& a, int64_t wave_it
           t3 = t2;
           t2 = t1;
         } else {
-          cold_start<double>(c, deg4, z);
+          cold_start<double>(c, deg4, z, !deg4 && far_root(c));
         }
-        in32 = (MODE == SBLM_MIXED) && !warm && !deg4;
+        in32 = (MODE == SBLM_MIXED) && !warm && !deg4 && !far_root(c);
         it64 = 0;
         it32 = 0;
+        it_prior = 0;
+        retried = false;
+        em64 = INFINITY;
         prev32 = INFINITY;
         need_setup = false;
       }
@@ -910,19 +970,41 @@ __device__ __forceinline__ void fit_wave_async(const FitArgs& a, int64_t wave_it
         ++it32;
         if (d32 || it32 >= MAXIT32) in32 = false;
       } else {
-        double em;
-        conv = aberth_sweep<double>(c, z, deg4, tau64, &em);
+        conv = aberth_sweep<double>(c, z, deg4, tau64, &em64);
         ++it64;
         finished = conv || it64 >= MAXIT64;
       }
+      bool finite = true;
       if (finished) {
-        bool finite = true;
 #pragma unroll
         for (int i = 0; i < 5; ++i)
           finite = finite && isfinite(z[i].re) && isfinite(z[i].im);
+        if (!(conv && finite) && warm && !retried) {
+          // the warm-started solve failed: again from the cold start (see
+          // the lockstep form)
+          cold_start<double>(c, deg4, z, !deg4 && far_root(c));
+          warm = false;
+          retried = true;
+          in32 = (MODE == SBLM_MIXED) && !deg4 && !far_root(c);
+          it_prior += it64 + it32;
+          st.iters32 += it32;
+          it64 = 0;
+          it32 = 0;
+          em64 = INFINITY;
+          prev32 = INFINITY;
+          st.retried += 1;
+          finished = false;
+        }
+      }
+      if (finished) {
         const bool ok = conv && finite;
+        const bool settled = finite && (conv || em64 <= SBLM_SETTLED_STEP2);
         int nimg, npol = 0;
-        const double A = magnification(z, zeta, x.d, x.q, deg4, nimg, npol);
+        double A = magnification(z, zeta, x.d, x.q, deg4, nimg, npol);
+        if (!settled) {
+          A = NAN;
+          nimg = 0;
+        }
         if (CHI2) {
           lsq_include(ls, a.w[k], 1.0, A, a.y[k]);
         } else {
@@ -931,9 +1013,10 @@ __device__ __forceinline__ void fit_wave_async(const FitArgs& a, int64_t wave_it
           if (a.n_img) a.n_img[o] = (int8_t)nimg;
         }
         st.solves += 1;
-        st.iters += it64 + it32;
+        st.iters += it_prior + it64 + it32;
         st.iters32 += it32;
-        st.capped += conv ? 0 : 1;
+        st.capped += ok ? 0 : 1;
+        st.unsettled += settled ? 0 : 1;
         st.deg4 += deg4 ? 1 : 0;
         st.polished += npol;
         if (MODE == SBLM_MIXED) st.fallback += (!warm && it64 > 2) ? 1 : 0;
@@ -961,7 +1044,7 @@ __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitn
   // (blocks of at most 256 threads: launch_gg refuses larger ones)
   constexpr int GPW = G > 64 ? 1 : 64 / G;  // individuals per wave
   const int lane = threadIdx.x & 63;
-  LaneStats st = {0, 0, 0, 0, 0, 0, 0, 0};
+  LaneStats st = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   // One-shot grid: wave w takes wave item w (blocks remapped so that
   // consecutive logical blocks sit on one XCD).  Persistent grid: waves take
   // items from a shared counter until it runs past the last one, so every
@@ -1024,6 +1107,8 @@ __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitn
       st.wave_iters += __shfl_down(st.wave_iters, off, 64);
       st.iters32 += __shfl_down(st.iters32, off, 64);
       st.polished += __shfl_down(st.polished, off, 64);
+      st.retried += __shfl_down(st.retried, off, 64);
+      st.unsettled += __shfl_down(st.unsettled, off, 64);
     }
     if (lane == 0 && st.solves) {
       atomicAdd(&a.stats->n_solves, st.solves);
@@ -1034,6 +1119,8 @@ __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitn
       atomicAdd(&a.stats->n_wave_iter, st.wave_iters);
       if (st.iters32) atomicAdd(&a.stats->n_iter_fp32, st.iters32);
       if (st.polished) atomicAdd(&a.stats->n_polished, st.polished);
+      if (st.retried) atomicAdd(&a.stats->n_retried, st.retried);
+      if (st.unsettled) atomicAdd(&a.stats->n_unsettled, st.unsettled);
     }
   }
 }

@@ -40,6 +40,8 @@ struct FitArgs {
   double* root_cache;     // nullable, G > 64 only: [n_ind][G][10] roots of
                           // each lane's first epoch, read as its start
                           // (when finite) and rewritten after the solve
+  const int32_t* cold;    // nullable (with root_cache): individual i ignores
+                          // the cache when cold[i / skip_per] != 0
   int32_t lanes_per_ind;  // 64, 32, 16 or 8 (a power of two dividing 64), or
                           // 128 / 256: several waves per individual (one-shot
                           // lockstep, wpb a multiple of G/64)

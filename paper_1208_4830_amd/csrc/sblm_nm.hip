@@ -38,6 +38,7 @@ namespace {
 constexpr int NP = SBLM_NPAR;  // 6 coordinates
 constexpr int NV = NP + 1;     // 7 vertices
 constexpr int NS = 4;          // trial slots per lightcurve and round
+constexpr int NM_ITER_REPS_MAX = 1024;  // slots per lightcurve of nm_iterated
 
 enum : int32_t { PH_INIT1 = 0, PH_INIT2, PH_STEP, PH_SHRINK1, PH_SHRINK2, PH_DONE };
 
@@ -54,6 +55,8 @@ struct NmWork {
   int32_t* phase;  // [n]
   int32_t* steps;  // [n]
   int32_t* done;   // [n] 1 once finished: its trial slots are not evaluated
+  int32_t* fresh;  // [n] 1 in the first round of a run: its trial points start
+                   // their root solves cold, not from the slot's root cache
   unsigned int* active;
   // iterated mode: slot j = k * reps + i of lightcurve k begins with start
   // i; a slot whose run ends takes the lightcurve's next unstarted start (the
@@ -99,6 +102,7 @@ __device__ void begin_run(const NmWork& w, int lc, const double* x0) {
     }
   w.phase[lc] = PH_INIT1;
   w.steps[lc] = 0;
+  w.fresh[lc] = 1;
 }
 
 // Start s of the lightcurve of slot lc (iterated mode): coordinate g = the
@@ -348,6 +352,7 @@ __global__ __launch_bounds__(256) void nm_update_kernel(NmWork w) {
     const int64_t nx = (int64_t)w.next_start[k] + taken, all = (int64_t)w.reps * w.runs;
     w.next_start[k] = (int32_t)(nx < all ? nx : all);
   }
+  w.fresh[lc] = 0;
   const int ph = w.phase[lc];
   if (ph == PH_DONE) return;
   Vertex s[NV];
@@ -530,6 +535,7 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
             hipMalloc(&w.phase, nn * 4) == hipSuccess &&
             hipMalloc(&w.steps, nn * 4) == hipSuccess &&
             hipMalloc(&w.done, nn * 4) == hipSuccess &&
+            hipMalloc(&w.fresh, nn * 4) == hipSuccess &&
             hipMalloc(&w.active, 4) == hipSuccess;
   if (ok && iter)
     ok = hipMalloc(&w.run, nn * 4) == hipSuccess && hipMalloc(&w.total, nn * 8) == hipSuccess &&
@@ -595,6 +601,7 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
     }
   }
   a.root_cache = root_cache;
+  a.cold = w.fresh;
   const dim3 grid((n + 255) / 256), blk(256);
   if (rc == SBLM_OK) {
     hipLaunchKernelGGL(nm_start_kernel, grid, blk, 0, st, w, x0);
@@ -639,9 +646,9 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
   }
   if (hipStreamSynchronize(st) != hipSuccess && rc == SBLM_OK)
     rc = check_hip(hipGetLastError(), "nm_refine: synchronise");
-  void* bufs[] = {w.V,    w.F,    w.FsV,  w.FbV,  w.T,   w.cT,  w.fsT, w.fbT, w.phase, w.steps,
-                  w.done, w.active, w.run, w.total, w.bX, w.bF, w.bFs, w.bFb, w.bS,
-                  w.ending, w.next_start, root_cache};
+  void* bufs[] = {w.V,    w.F,      w.FsV, w.FbV,   w.T,  w.cT, w.fsT, w.fbT,
+                  w.phase, w.steps, w.done, w.fresh, w.active, w.run, w.total, w.bX,
+                  w.bF,   w.bFs,    w.bFb, w.bS,    w.ending, w.next_start, root_cache};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   return rc;
@@ -692,6 +699,10 @@ extern "C" int nm_iterated(const sblm_lcs* lcs, int32_t reps, int32_t runs, uint
   if (lcs->n_lc < 1) return set_error(SBLM_EINVAL, "nm_iterated: n_lc < 1");
   if (reps < 1 || runs < 1)
     return set_error(SBLM_EINVAL, "nm_iterated: reps = %d, runs = %d", reps, runs);
+  // the slots of a lightcurve that end in one round rank themselves by a
+  // loop over the lightcurve's earlier slots (O(reps) per slot and round)
+  if (reps > NM_ITER_REPS_MAX)
+    return set_error(SBLM_ERANGE, "nm_iterated: reps = %d beyond %d", reps, NM_ITER_REPS_MAX);
   if ((int64_t)lcs->n_lc * reps > (1 << 24))
     return set_error(SBLM_ERANGE, "nm_iterated: n_lc * reps beyond 2^24");
   if ((int64_t)reps * runs > (1LL << 31) - 1 ||

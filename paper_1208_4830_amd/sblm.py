@@ -55,7 +55,8 @@ class ea_lc_summary(ctypes.Structure):
 
 
 STATS_FIELDS = ("n_solves", "n_iter", "n_capped", "n_fallback", "n_degree4", "n_degenerate",
-                "n_wave_iter", "n_iter_fp32", "n_polished")
+                "n_wave_iter", "n_iter_fp32", "n_polished", "n_retried",
+                "n_unsettled")
 
 _SIGS = {
     "sblm_magnify": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
@@ -181,7 +182,7 @@ def _device_view(ptr, shape, typestr="<f8"):
 
 
 def new_stats(device="cuda"):
-    """Zeroed sblm_stats block (9 x uint64) as an int64 device tensor."""
+    """Zeroed sblm_stats block (one uint64 per field) as an int64 device tensor."""
     return torch.zeros(len(STATS_FIELDS), dtype=torch.int64, device=device)
 
 

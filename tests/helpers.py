@@ -1,5 +1,6 @@
 """Shared helpers of the test-suite: synthetic lightcurves assembled with the
 oracle's magnifications, and the floating-point conditioning of A."""
+import mpmath
 import numpy as np
 
 import oracle as O
@@ -134,3 +135,53 @@ def generic_pairs(rng, n):
     """n (theta, t) pairs from the priors with tau ~ U[-2, 2]."""
     theta = inputs.draw_theta(rng, n)
     return theta, theta[5] + rng.uniform(-2, 2, n) * theta[4]
+
+
+def exact_magnification(zeta, d, q, dps=50):
+    """A and the image count at a source position from dps-digit roots of the
+    quintic, formed by exact polynomial products as in the paper's
+    derivation; zeta, d, q may be floats or mpmath numbers (taken exactly)."""
+    mpmath.mp.dps = dps
+    zeta = mpmath.mpc(zeta)
+    d, q = mpmath.mpf(d), mpmath.mpf(q)
+    w = mpmath.conj(zeta)
+    N = [-d, 1 + q - d * w, w]
+    D = [0, -d, 1]
+    M = [N[k] - d * D[k] for k in range(3)]
+
+    def mul(a, b):
+        o = [0] * (len(a) + len(b) - 1)
+        for i, x in enumerate(a):
+            for j, y in enumerate(b):
+                o[i + j] += x * y
+        return o
+    c = [0] * 6
+    for k, v in enumerate(mul([zeta, -1], mul(N, M))):
+        c[k] += v
+    for k, v in enumerate(mul(M, D)):
+        c[k] += v
+    for k, v in enumerate(mul(N, D)):
+        c[k] += q * v
+    roots = mpmath.polyroots(c[::-1], maxsteps=400, extraprec=400)
+    res = [abs(zeta - z + 1 / mpmath.conj(z) - q / (d - mpmath.conj(z))) for z in roots]
+    order = sorted(range(5), key=lambda k: res[k])
+    n5 = sum(r < mpmath.mpf("1e-6") for r in res) >= 4
+    A = 0
+    for k in (order if n5 else order[:3]):
+        zb = mpmath.conj(roots[k])
+        g = 1 / zb ** 2 + q / (d - zb) ** 2
+        A += 1 / abs(1 - abs(g) ** 2)
+    return float(A), (5 if n5 else 3)
+
+
+def exact_magnification_theta(theta, t, dps=50):
+    """A of the FP64 parameters theta[6] at epoch t with every step after
+    the inputs in dps-digit arithmetic: the source position of Eq. sourcePos
+    from the exact values of log10 q, u0, alpha, tE, t0 and t, so that it is
+    the answer to the FP64 problem, free of any implementation's rounding."""
+    mpmath.mp.dps = dps
+    lq, d, u0, al, tE, t0 = (mpmath.mpf(float(v)) for v in theta)
+    tau = (mpmath.mpf(float(t)) - t0) / tE
+    sa, ca = mpmath.sin(al), mpmath.cos(al)
+    zeta = mpmath.mpc(tau * sa + u0 * ca, -tau * ca + u0 * sa)
+    return exact_magnification(zeta, d, mpmath.power(10, lq), dps)

@@ -64,6 +64,7 @@ def test_struct_layouts_match_the_header(tmp_path):
         lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
         for field, _ in cls._fields_:
             lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines.append('  printf("sblm_stats size %zu\\n", sizeof(sblm_stats));')
     lines += ["  return 0;", "}"]
     src = tmp_path / "layout.c"
     src.write_text("\n".join(lines) + "\n")
@@ -73,6 +74,9 @@ def test_struct_layouts_match_the_header(tmp_path):
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
     for line in out.splitlines():
         name, field, value = line.split()
+        if name == "sblm_stats":  # one uint64 per field of the binding's list
+            assert int(value) == 8 * len(sblm.STATS_FIELDS)
+            continue
         cls = structs[name]
         want = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
         assert int(value) == want, (name, field, value, want)

@@ -80,6 +80,41 @@ def test_magnify_source_on_primary(hip):
     assert hip.stats_dict(st)["n_degree4"] == 2
 
 
+def test_magnify_source_near_a_lens(hip):
+    # sources 1e-3 ... 1e-11 theta_E from the primary or the secondary (one
+    # epoch each, every solve cold): the spurious fifth root lies near
+    # -c4/c5, out to ~1/|zeta|; every solve converges, and A agrees with the
+    # oracle
+    thetas, ts = [], []
+    rng = np.random.default_rng(103)
+    for lq, d in ((0.0, 1.0), (-3.0, 0.5), (-1.0, 2.0)):
+        for r in (1e-3, 1e-5, 1e-7, 1e-9, 1e-11):
+            for lens in (0.0, d):
+                zeta = lens + r * np.exp(1j * rng.uniform(0, 2 * np.pi))
+                al = rng.uniform(0, 2 * np.pi)
+                rot = zeta * np.exp(-1j * al)
+                u0, tau = rot.real, -rot.imag
+                if u0 < 0:
+                    al += np.pi
+                    u0, tau = -u0, -tau
+                tE, t0 = rng.uniform(10, 100), rng.uniform(-10, 10)
+                thetas.append([lq, d, u0, al, tE, t0])
+                ts.append(t0 + tau * tE)
+    theta = np.array(thetas).T
+    for mode in (0, 1):
+        st = hip.new_stats()
+        for i in range(theta.shape[1]):
+            A = hip.sblm_magnify(_cuda(theta[:, i:i + 1]), _cuda([ts[i]]), mode=mode,
+                                 stats=st).cpu().numpy()[0, 0]
+            Ao, _ = O.magnify(theta[:, i:i + 1], np.array([ts[i]]), nthreads=1)
+            assert rel_err(A, Ao[0, 0]) < 1e-9, (i, A, Ao[0, 0])
+        s = hip.stats_dict(st)
+        assert s["n_capped"] == 0 and s["n_unsettled"] == 0, s
+        # the fifth root starts where it lies: no solve needs the 50-80
+        # sweeps that walking it out from the circle start would take
+        assert s["n_iter"] <= 40 * s["n_solves"], s
+
+
 def test_magnify_near_caustics(hip):
     # sources placed within 0.01 theta_E of caustics: agreement to the
     # conditioning of the problem; image counts agree off the ambiguous zone

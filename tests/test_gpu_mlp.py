@@ -130,6 +130,10 @@ def test_forward_matches_oracle(hip, rows):
     net.close()
 
 
+def f32(a):
+    return np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+
+
 def test_gradients_match_oracle(hip):
     rng = np.random.default_rng(8)
     p = M.init_params(rng, scale_out=0.3)
@@ -144,12 +148,76 @@ def test_gradients_match_oracle(hip):
     L = float(loss.cpu())
     print(f"loss gpu {L:.6f} oracle {L_ref:.6f}")
     assert abs(L - L_ref) <= 1e-2 * abs(L_ref)
+    # against FP64 backpropagation of the same network, tensor by tensor
     for k in NAMES:
         a, b = g[k].ravel(), g_ref[k].ravel()
         rel = np.linalg.norm(a - b) / np.linalg.norm(b)
         cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
         print(f"  {k}: rel {rel:.2e} cos {cos:.6f}")
         assert rel < 3e-2 and cos > 0.999, k
+    net.close()
+
+
+def test_gradients_element_wise(hip):
+    # Element by element against the oracle's backpropagation with the
+    # kernels' roundings emulated: hidden activations BF16, output and output
+    # gradient FP32 (the likelihood's gradient from the oracle), BF16 copies
+    # of the output gradient and of the hidden-layer gradients as the
+    # operands of the products; then only the FP32 accumulation order (and a
+    # rare BF16 rounding decided the other way by it) differs.  Each entry's
+    # error is scaled by the sum of the magnitudes of its terms, the
+    # hidden-layer gradients taken at the magnitude of their own terms (where
+    # they cancel to near zero, their rounding is relative to those terms).
+    # Output weights of scale 0.05 give a loss of ~14, where the mixture's
+    # posterior weights are not decided by the last bits of the FP32 outputs
+    # (at scale 0.3 the loss is ~10^6 and one rounding of an output moves a
+    # posterior weight by several per cent).
+    rng = np.random.default_rng(18)
+    p = M.init_params(rng, scale_out=0.05)
+    net = hip.MLP(batch_max=256, seed=1)
+    net.set_params(canon(p).astype(np.float32))
+    x = bf16(rng.normal(size=(256, 256)))
+    y = rng.uniform(0, 1, (256, 7)).astype(np.float32)
+    loss = net.loss_grad(torch.tensor(x, dtype=torch.bfloat16, device="cuda"),
+                         torch.tensor(y, device="cuda"))
+    g = uncanon(net.grad())
+    L = float(loss.cpu())
+    q = gpu_params(p)
+    h1 = bf16(np.maximum(x @ q["W1"] + q["b1"], 0))
+    h2 = bf16(np.maximum(h1 @ q["W2"] + q["b2"], 0))
+    o = f32(h2 @ q["W3"] + q["b3"])
+    L_emu, dO = M.nll(o, y.astype(np.float64))
+    print(f"loss gpu {L:.6f} emulated {L_emu:.6f}")
+    assert abs(L - L_emu) <= 1e-5 * abs(L_emu)
+    dOf = f32(dO)
+    dOb = bf16(dOf)
+    dZ2f = f32((dOb @ q["W3"].T) * (h2 > 0))
+    dZ2b = bf16(dZ2f)
+    dZ1f = f32((dZ2b @ q["W2"].T) * (h1 > 0))
+    dZ1b = bf16(dZ1f)
+    s2 = (np.abs(dOb) @ np.abs(q["W3"]).T) * (h2 > 0)   # magnitude of dZ2's terms
+    s1 = (s2 @ np.abs(q["W2"]).T) * (h1 > 0)             # ... of dZ1's terms
+    emu = {"W3": (h2.T @ dOb, np.abs(h2).T @ np.abs(dOb)),
+           "W2": (h1.T @ dZ2b, np.abs(h1).T @ s2),
+           "W1": (x.T @ dZ1b, np.abs(x).T @ s1),
+           "b3": (dOf.sum(0), np.abs(dOf).sum(0)),
+           "b2": (dZ2f.sum(0), s2.sum(0)),
+           "b1": (dZ1f.sum(0), s1.sum(0))}
+    for k in NAMES:
+        ref, scale = emu[k]
+        e = np.abs(g[k] - ref) / np.maximum(scale, 1e-6 * scale.max())
+        print(f"  {k} element-wise vs emulated: median {np.median(e):.2e} "
+              f"p99.9 {np.quantile(e, 0.999):.2e} max {e.max():.2e}")
+    # One BF16 operand rounded the other way (a hidden activation, or an
+    # output-gradient copy) moves its term by at most 2^-8 of its magnitude:
+    # a flipped activation touches a whole row of its weight gradient, so
+    # the 99.9th percentile may reach 2^-8, and no entry may pass 2.5 such
+    # steps.  A wrong entry (a mis-indexed column, a lost slice of a split
+    # sum) errs by O(1) of its scale.
+    for k in NAMES:
+        ref, scale = emu[k]
+        e = np.abs(g[k] - ref) / np.maximum(scale, 1e-6 * scale.max())
+        assert np.median(e) < 1e-5 and np.quantile(e, 0.999) < 2.0 ** -8 and e.max() < 1e-2, k
     net.close()
 
 

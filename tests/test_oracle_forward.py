@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from tests.helpers import exact_magnification
 
 
 def paczynski(u):
@@ -296,38 +297,7 @@ def test_batched_chi2_matches_single():
 
 
 def _exact_magnification(zeta, d, q, dps=50):
-    """A at a source position from 50-digit roots of the same quintic."""
-    mpmath.mp.dps = dps
-    zeta = mpmath.mpc(zeta.real, zeta.imag)
-    d, q = mpmath.mpf(d), mpmath.mpf(q)
-    w = mpmath.conj(zeta)
-    N = [-d, 1 + q - d * w, w]
-    D = [0, -d, 1]
-    M = [N[k] - d * D[k] for k in range(3)]
-
-    def mul(a, b):
-        o = [0] * (len(a) + len(b) - 1)
-        for i, x in enumerate(a):
-            for j, y in enumerate(b):
-                o[i + j] += x * y
-        return o
-    c = [0] * 6
-    for k, v in enumerate(mul([zeta, -1], mul(N, M))):
-        c[k] += v
-    for k, v in enumerate(mul(M, D)):
-        c[k] += v
-    for k, v in enumerate(mul(N, D)):
-        c[k] += q * v
-    roots = mpmath.polyroots(c[::-1], maxsteps=400, extraprec=400)
-    res = [abs(zeta - z + 1 / mpmath.conj(z) - q / (d - mpmath.conj(z))) for z in roots]
-    order = sorted(range(5), key=lambda k: res[k])
-    n5 = sum(r < mpmath.mpf("1e-6") for r in res) >= 4
-    A = 0
-    for k in (order if n5 else order[:3]):
-        zb = mpmath.conj(roots[k])
-        g = 1 / zb ** 2 + q / (d - zb) ** 2
-        A += 1 / abs(1 - abs(g) ** 2)
-    return float(A), (5 if n5 else 3)
+    return exact_magnification(zeta, d, q, dps)
 
 
 def test_near_caustic_accuracy_against_50_digit_roots():
