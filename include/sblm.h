@@ -396,6 +396,26 @@ int nm_refine(const sblm_lcs* lcs, const double* lo, const double* hi,
               void* stream);
 
 /*
+ * nm_refine_noalloc -- nm_refine for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same simplices, arguments, outputs and errors as
+ * nm_refine, with no hipMalloc, hipFree or other allocation.  The
+ * simplices' state (~0.8 KB per lightcurve) lives in a static device array
+ * of 8 MiB that every GPU the library runs on holds until the process ends,
+ * so 1 <= n_lc <= 10379 (SBLM_ERANGE beyond, with the limit in the message).
+ * Trial points are spread over 64 lanes without saved roots: the results are
+ * those of nm_refine run with 64 lanes per trial point (bit for bit), and
+ * they do not depend on what an earlier call left in the array (every
+ * simplex's state is initialised by the call).  All calls on one GPU share
+ * its array: calls that overlap on one GPU (other streams, other threads)
+ * race and must not be made.  Synchronises `stream`.
+ */
+int nm_refine_noalloc(const sblm_lcs* lcs, const double* lo, const double* hi,
+                      const double* x0, const nm_config* cfg, double* x, double* chi2,
+                      double* Fs, double* Fb, int32_t* n_iter, sblm_stats* stats,
+                      void* stream);
+
+/*
  * nm_refine_multi -- as nm_refine with `reps` independent simplices per
  * lightcurve (several start points: the fittest solution of every island,
  * or the random starts of an iterated simplex).  Simplex j = k * reps + i

@@ -75,10 +75,14 @@ struct NmIterated {
 };
 // One simplex per (lightcurve, rep) from x0, or with `iter` the iterated
 // form from drawn starts (x0 and the per-simplex outputs unused).
+// `workspace` (nullable): a device block of nm_work_bytes(n_lc * reps) bytes
+// that replaces the allocation of the simplices' state; with it the trial
+// points take 64 lanes and no root cache, and nothing is allocated.
 int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* span,
            const double* x0, const nm_config& cfg, double* x, double* chi2, double* Fs,
            double* Fb, int32_t* n_iter, sblm_stats* stats, hipStream_t st,
-           const NmIterated* iter = nullptr);
+           const NmIterated* iter = nullptr, void* workspace = nullptr);
+size_t nm_work_bytes(int64_t n_simplices);
 int nm_check(const nm_config* cfg, const char* who);
 
 }  // namespace sblm

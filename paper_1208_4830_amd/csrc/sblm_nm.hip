@@ -29,6 +29,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "sblm_internal.h"
 #include "sblm_rng.h"
 
@@ -509,10 +511,52 @@ int nm_check(const nm_config* cfg, const char* who) {
   return SBLM_OK;
 }
 
+// The arrays of NmWork for n simplices, carved one after another (each
+// aligned to 256 bytes) from one block at `base`; returns the block's size
+// (with base == nullptr only the size).
+static size_t nm_carve(NmWork& w, char* base, size_t n, bool iter) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  w.V = (double*)take(n * NV * NP * 8);
+  w.F = (double*)take(n * NV * 8);
+  w.FsV = (double*)take(n * NV * 8);
+  w.FbV = (double*)take(n * NV * 8);
+  w.T = (double*)take(n * NS * NP * 8);
+  w.cT = (double*)take(n * NS * 8);
+  w.fsT = (double*)take(n * NS * 8);
+  w.fbT = (double*)take(n * NS * 8);
+  w.phase = (int32_t*)take(n * 4);
+  w.steps = (int32_t*)take(n * 4);
+  w.done = (int32_t*)take(n * 4);
+  w.fresh = (int32_t*)take(n * 4);
+  w.active = (unsigned int*)take(4);
+  if (iter) {
+    w.run = (int32_t*)take(n * 4);
+    w.total = (int64_t*)take(n * 8);
+    w.bX = (double*)take(n * NP * 8);
+    w.bF = (double*)take(n * 8);
+    w.bFs = (double*)take(n * 8);
+    w.bFb = (double*)take(n * 8);
+    w.bS = (int32_t*)take(n * 4);
+    w.ending = (int32_t*)take(n * 4);
+    w.next_start = (int32_t*)take(n * 4);  // n / reps used
+  }
+  return off;
+}
+
+size_t nm_work_bytes(int64_t n_simplices) {
+  NmWork w;
+  return nm_carve(w, nullptr, (size_t)n_simplices, false);
+}
+
 int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* span,
            const double* x0, const nm_config& cfg, double* x, double* chi2, double* Fs,
            double* Fb, int32_t* n_iter, sblm_stats* stats, hipStream_t st,
-           const NmIterated* iter) {
+           const NmIterated* iter, void* workspace) {
   // simplex j = k * reps + i works on lightcurve k: its trial points are
   // individuals j * NS + slot, that is NS * reps individuals per lightcurve
   const int n = lcs.n_lc * reps;
@@ -524,25 +568,15 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
   w.runs = iter ? iter->runs : 1;
   w.seed = iter ? iter->seed : 0;
   const size_t nn = (size_t)n;
-  bool ok = hipMalloc(&w.V, nn * NV * NP * 8) == hipSuccess &&
-            hipMalloc(&w.F, nn * NV * 8) == hipSuccess &&
-            hipMalloc(&w.FsV, nn * NV * 8) == hipSuccess &&
-            hipMalloc(&w.FbV, nn * NV * 8) == hipSuccess &&
-            hipMalloc(&w.T, nn * NS * NP * 8) == hipSuccess &&
-            hipMalloc(&w.cT, nn * NS * 8) == hipSuccess &&
-            hipMalloc(&w.fsT, nn * NS * 8) == hipSuccess &&
-            hipMalloc(&w.fbT, nn * NS * 8) == hipSuccess &&
-            hipMalloc(&w.phase, nn * 4) == hipSuccess &&
-            hipMalloc(&w.steps, nn * 4) == hipSuccess &&
-            hipMalloc(&w.done, nn * 4) == hipSuccess &&
-            hipMalloc(&w.fresh, nn * 4) == hipSuccess &&
-            hipMalloc(&w.active, 4) == hipSuccess;
-  if (ok && iter)
-    ok = hipMalloc(&w.run, nn * 4) == hipSuccess && hipMalloc(&w.total, nn * 8) == hipSuccess &&
-         hipMalloc(&w.bX, nn * NP * 8) == hipSuccess && hipMalloc(&w.bF, nn * 8) == hipSuccess &&
-         hipMalloc(&w.bFs, nn * 8) == hipSuccess && hipMalloc(&w.bFb, nn * 8) == hipSuccess &&
-         hipMalloc(&w.bS, nn * 4) == hipSuccess && hipMalloc(&w.ending, nn * 4) == hipSuccess &&
-         hipMalloc(&w.next_start, (size_t)lcs.n_lc * 4) == hipSuccess;
+  // the workspace: the caller's (nm_refine_noalloc), else one allocation
+  // freed before returning
+  void* block = workspace;
+  bool ok = true;
+  if (!block) ok = hipMalloc(&block, nm_carve(w, nullptr, nn, w.iter)) == hipSuccess;
+  if (ok)
+    nm_carve(w, (char*)block, nn, w.iter);
+  else
+    block = nullptr;
   int rc = SBLM_OK;
   if (!ok) {
     (void)hipGetLastError();
@@ -582,7 +616,8 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
   a.lanes_per_ind = n_trial * 256 * 80 <= cache_max   ? 256
                     : n_trial * 128 * 80 <= cache_max ? 128
                                                       : 64;
-  if (const char* env = getenv("SBLM_NM_LANES")) {
+  if (workspace) a.lanes_per_ind = 64;  // no root cache: nothing to allocate
+  if (const char* env = getenv("SBLM_NM_LANES"); env && !workspace) {
     const int g = atoi(env);
     if (g == 64 || g == 128 || g == 256) a.lanes_per_ind = g;
   }
@@ -646,11 +681,8 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
   }
   if (hipStreamSynchronize(st) != hipSuccess && rc == SBLM_OK)
     rc = check_hip(hipGetLastError(), "nm_refine: synchronise");
-  void* bufs[] = {w.V,    w.F,      w.FsV, w.FbV,   w.T,  w.cT, w.fsT, w.fbT,
-                  w.phase, w.steps, w.done, w.fresh, w.active, w.run, w.total, w.bX,
-                  w.bF,   w.bFs,    w.bFb, w.bS,    w.ending, w.next_start, root_cache};
-  for (void* b : bufs)
-    if (b) (void)hipFree(b);
+  if (block && !workspace) (void)hipFree(block);
+  if (root_cache) (void)hipFree(root_cache);
   return rc;
 }
 
@@ -724,4 +756,83 @@ extern "C" int nm_refine(const sblm_lcs* lcs, const double* lo, const double* hi
                          double* Fs, double* Fb, int32_t* n_iter, sblm_stats* stats,
                          void* stream) {
   return nm_refine_multi(lcs, 1, lo, hi, x0, cfg, x, chi2, Fs, Fb, n_iter, stats, stream);
+}
+
+// ---------------------------------------------------------------------------
+// nm_refine_noalloc: nm_refine without any device allocation.  The simplices'
+// state lives in `scratch`, a static device array of SBLM_NM_SCRATCH_BYTES
+// that every GPU the library runs on holds until the process ends.  In host
+// code `scratch` names a host-side stand-in, not device memory: its device
+// address is taken once per device with hipGetSymbolAddress (with that
+// device current) and only that address is passed to kernels.
+#define SBLM_NM_SCRATCH_BYTES (8u << 20)
+#define SBLM_MAX_DEVICES 64
+
+static __device__ __align__(256) unsigned char scratch[SBLM_NM_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SBLM_MAX_DEVICES];
+
+// Device address of this device's copy of `scratch` (looked up on the first
+// call on the device).
+int scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return check_hip(e, "nm_refine_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= SBLM_MAX_DEVICES)
+    return set_error(SBLM_EDEVICE, "nm_refine_noalloc: device %d beyond %d", dev,
+                     SBLM_MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return check_hip(e, "nm_refine_noalloc: hipGetSymbolAddress");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SBLM_OK;
+}
+
+// The most lightcurves whose simplices fit the scratch array.
+int nm_noalloc_max_lc() {
+  int lo = 0, hi = 1 << 24;
+  while (lo < hi) {
+    const int mid = lo + (hi - lo + 1) / 2;
+    if (nm_work_bytes(mid) <= SBLM_NM_SCRATCH_BYTES)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+}  // namespace
+
+extern "C" int nm_refine_noalloc(const sblm_lcs* lcs, const double* lo, const double* hi,
+                                 const double* x0, const nm_config* cfg, double* x,
+                                 double* chi2, double* Fs, double* Fb, int32_t* n_iter,
+                                 sblm_stats* stats, void* stream) {
+  int rc = nm_check(cfg, "nm_refine_noalloc");
+  if (rc) return rc;
+  if (!lcs || !lcs->off || !lcs->t || !lcs->y || !lcs->w)
+    return set_error(SBLM_EINVAL, "nm_refine_noalloc: null lightcurve descriptor or array");
+  if (lcs->n_lc < 1) return set_error(SBLM_EINVAL, "nm_refine_noalloc: n_lc < 1");
+  const size_t need = nm_work_bytes(lcs->n_lc);
+  if (need > SBLM_NM_SCRATCH_BYTES)
+    return set_error(SBLM_ERANGE,
+                     "nm_refine_noalloc: %d lightcurves need %zu bytes of scratch, beyond its "
+                     "%u bytes (at most %d lightcurves)",
+                     lcs->n_lc, need, SBLM_NM_SCRATCH_BYTES, nm_noalloc_max_lc());
+  if (!lo || !hi || !x0 || !x)
+    return set_error(SBLM_EINVAL, "nm_refine_noalloc: null lo, hi, x0 or x");
+  double span[SBLM_NPAR];
+  for (int g = 0; g < SBLM_NPAR; ++g) {
+    if (!(hi[g] > lo[g]))
+      return set_error(SBLM_EINVAL, "nm_refine_noalloc: hi[%d] <= lo[%d]", g, g);
+    span[g] = hi[g] - lo[g];
+  }
+  void* ws = nullptr;
+  if ((rc = scratch_address(&ws))) return rc;
+  return nm_run(*lcs, 1, lo, span, x0, *cfg, x, chi2, Fs, Fb, n_iter, stats,
+                (hipStream_t)stream, nullptr, ws);
 }

@@ -113,6 +113,11 @@ _SIGS = {
                         ctypes.POINTER(nm_config), ctypes.c_void_p, ctypes.c_void_p,
                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                         ctypes.c_void_p],
+    "nm_refine_noalloc": [ctypes.POINTER(sblm_lcs), ctypes.POINTER(ctypes.c_double),
+                          ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+                          ctypes.POINTER(nm_config), ctypes.c_void_p, ctypes.c_void_p,
+                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                          ctypes.c_void_p],
     "nm_iterated": [ctypes.POINTER(sblm_lcs), ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                     ctypes.POINTER(nm_config)] + [ctypes.c_void_p] * 7,
@@ -420,6 +425,31 @@ def nm_refine(lcs, lo, hi, x0, cfg=None, stats=None, stream=None, reps=1):
     _check(load().nm_refine_multi(ctypes.byref(lcs.desc), reps, lo_, hi_, _ptr(x0),
                                   ctypes.byref(cfg), _ptr(x), _ptr(c), _ptr(fs), _ptr(fb),
                                   _ptr(it), _ptr(stats), _stream(stream)))
+    return x, c, fs, fb, it
+
+
+def nm_refine_noalloc(lcs, lo, hi, x0, cfg=None, out=None, stats=None, stream=None):
+    """nm_refine (one simplex per lightcurve) through the entry point that
+    allocates no device memory.  `out` = (x, chi2, Fs, Fb, steps): caller
+    tensors ([6][n_lc] float64, three [n_lc] float64, [n_lc] int32) written
+    in place; allocated here when None."""
+    cfg = cfg or nm_default_config()
+    x0 = _dev(x0)
+    n = lcs.n_lc
+    if x0.shape != (NPAR, n):
+        raise SblmError(f"x0 must be [6][{n}], got {tuple(x0.shape)}")
+    if out is None:
+        dev = x0.device
+        out = (torch.empty_like(x0),) + tuple(torch.empty(n, dtype=torch.float64, device=dev)
+                                              for _ in range(3)) + \
+            (torch.empty(n, dtype=torch.int32, device=dev),)
+    x, c, fs, fb, it = out
+    lo_ = (ctypes.c_double * NPAR)(*[float(v) for v in lo])
+    hi_ = (ctypes.c_double * NPAR)(*[float(v) for v in hi])
+    _check(load().nm_refine_noalloc(ctypes.byref(lcs.desc), lo_, hi_, _ptr(x0),
+                                    ctypes.byref(cfg), _ptr(_dev(x)), _ptr(_dev(c)),
+                                    _ptr(_dev(fs)), _ptr(_dev(fb)), _ptr(_dev(it, torch.int32)),
+                                    _ptr(stats), _stream(stream)))
     return x, c, fs, fb, it
 
 
