@@ -36,7 +36,13 @@ def test_flop_model_of_a_warm_solve():
 
 def test_traffic_figure_matches_the_kernel_source():
     # the committed rocprofv3 traffic is reported only for the source it was
-    # measured on; a changed kernel must be profiled again
-    assert bench.fitness_traffic() == bench.FITNESS_TRAFFIC["bytes_per_launch"]
+    # measured on; for a changed kernel the bench reports null until it is
+    # profiled again
+    import hashlib
+    src = os.path.join(ROOT, "paper_1208_4830_amd", "csrc", "sblm_fitness.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    want = bench.FITNESS_TRAFFIC["bytes_per_launch"] \
+        if sha == bench.FITNESS_TRAFFIC["source_sha256_16"] else None
+    assert bench.fitness_traffic() == want
     assert bench.FITNESS_TRAFFIC["bytes_per_launch"] > \
         bench.FITNESS_TRAFFIC["algorithmic_bytes_per_launch"]
