@@ -119,8 +119,19 @@ def test_simplex_arguments():
     _expect(lib.nm_iterated(ctypes.byref(lc), 2, 5000, 1, lo, hi, ctypes.byref(long_cfg), FAKE,
                             None, None, None, None, None, None), ERANGE, "per slot")
     # more than 2^31 - 1 starts per lightcurve (the start counter is 32-bit)
-    _expect(lib.nm_iterated(ctypes.byref(lc), 1 << 16, 1 << 16, 1, lo, hi, ctypes.byref(cfg),
+    _expect(lib.nm_iterated(ctypes.byref(lc), 1 << 10, 1 << 21, 1, lo, hi, ctypes.byref(cfg),
                             FAKE, None, None, None, None, None, None), ERANGE, "starts")
+    # more slots per lightcurve than the per-round ranking loop is built for
+    _expect(lib.nm_iterated(ctypes.byref(lc), 1025, 1, 1, lo, hi, ctypes.byref(cfg),
+                            FAKE, None, None, None, None, None, None), ERANGE, "beyond 1024")
+    # the no-alloc simplex: beyond its static array, and the usual checks
+    big = sblm.sblm_lcs(10380, FAKE, FAKE, FAKE, FAKE)
+    _expect(lib.nm_refine_noalloc(ctypes.byref(big), lo, hi, FAKE, ctypes.byref(cfg), FAKE,
+                                  None, None, None, None, None, None), ERANGE, "10379")
+    _expect(lib.nm_refine_noalloc(ctypes.byref(lc), hi, lo, FAKE, ctypes.byref(cfg), FAKE,
+                                  None, None, None, None, None, None), EINVAL, "hi[")
+    _expect(lib.nm_refine_noalloc(ctypes.byref(lc), lo, hi, None, ctypes.byref(cfg), FAKE,
+                                  None, None, None, None, None, None), EINVAL, "null")
 
 
 def test_network_arguments():
