@@ -1,23 +1,26 @@
 """Benchmark of the batched binary-lens fitness + EA generation on one MI355X.
 
-Workload (the batched FP64 fitting configuration): 256 synthetic lightcurves
-of 1000 uniform epochs over t0 +- 2 tE (sigma = 1% of the flux), population
-256 per lightcurve.  A step is one generation of the whole hot path for the
-whole batch: decode, magnification of all 256 x 256 x 1000 (individual,
-epoch) pairs, least-squares fluxes and chi^2, then the EA generation, replayed
-from one HIP graph.  The default run times a full fit (500 generations) in
-the plain FP64 form and in the mixed-precision form, reports the success rate
-(best chi^2 <= chi^2 of the true parameters + 10) and fits/hour, the fitness
-kernel's roofline fraction, and the CPU oracle timed on a bounded sample.
-Time to 90% success is measured for the plain EA and for the learned form
-(proposal seeding), each with the paper's simplex fine-tuning of the
-fittest solution at every checkpoint.  Then the ragged batching workload (4096 lightcurves of 200-5000 irregular
-epochs, population 128) is timed per generation, and on the same lightcurves
-the plain EA is compared with the learned form: a proposal network trained
-on generated lightcurves seeds half of every population (at the start and at
-each restart) and the EA's chi^2 decides.
+Headline workload (the batched FP64 fitting configuration): 256 synthetic
+lightcurves of 1000 uniform epochs over t0 +- 2 tE (sigma = 1% of the flux),
+population 256 per lightcurve.  A step is one generation of the whole hot
+path for the whole batch: decode, magnification of all 256 x 256 x 1000
+(individual, epoch) pairs, least-squares fluxes and chi^2, then the EA
+generation, replayed from one HIP graph.  The default run times a full fit
+(500 generations) in the plain FP64 form and in the mixed-precision form,
+with the fitness kernel's duration stamped on the device inside every
+replayed generation (the roofline), the success rate (best chi^2 <= chi^2 of
+the true parameters + 10) and fits/hour.
 
-Prints ONE JSON line.
+Chosen form (the batching workload): 4096 lightcurves of 200-5000 irregular
+epochs, population 128, autotuned schedule, a full 500-generation fit timed
+the same way.  On the same lightcurves the time to 90% success is measured
+for the plain EA, for the EA seeded by the window alone (the ablation) and
+for the EA seeded by the proposal network (the learned form), each with the
+paper's simplex fine-tuning of the fittest solution at every checkpoint;
+fits/hour at >= 90% success follows.  The CPU oracle is timed on a bounded
+sample of the headline workload.
+
+Prints ONE JSON line (a summary line goes to stderr just before it).
 """
 import argparse
 import json
@@ -30,19 +33,32 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FLOPs of one magnification + fit update as the fitness kernel
-# computes it (counted from its source; fma = 2, reciprocal = 1 plus its
-# Newton refinement steps): source position and polynomial coefficients,
-# per sweep of the simultaneous root iteration over the five roots, image
-# test + det J + magnification, and the weighted least-squares row update.
-FLOP_COEF = 106
-FLOP_SWEEP64 = 760
-FLOP_SWEEP32 = 680
-FLOP_IMAGES = 345
-FLOP_LSQ = 50
-# per image refined on the lens equation: one residual/g evaluation at the
-# root, one Newton step, one evaluation at the new point
-FLOP_POLISH = 150
+# Algorithmic FLOPs per call of the fitness arithmetic, as counted by the
+# counting build of the kernel's own code (paper_1208_4830_amd/csrc/
+# flop_count.cpp over csrc/sblm_math.h; tests/test_flop_count.py checks that
+# these are its output): source position + polynomial, warm start, one
+# simultaneous-iteration sweep (FP64, FP32), image test + det J + sum over
+# three images, one more accepted image, an image refined on the lens
+# equation (one or two Newton steps), one residual evaluation, one
+# least-squares row.  fma = 2, reciprocal estimate = 1.
+FLOP_COUNTS = {"coef": 151, "warm": 73, "sweep64": 696, "sweep32": 691, "images": 380,
+               "image_extra": 10, "refine1": 145, "refine": 227, "eval": 50, "lsq": 48,
+               "newton": 490, "nearest": 70}
+
+
+def flop_per_magnification(sweeps64, sweeps32, refined, newton=0.0, polishes=0.0):
+    """Algorithmic FLOPs of one magnification + fit update at the lanes' own
+    mean counts per solve: FP64 and FP32 sweeps, refined images, FP64 Newton
+    polish passes and polishes (each judged on two sets of nearest-root
+    distances).  Iterations a wavefront runs past a lane's convergence are
+    not credited; three accepted images are counted (a fifth-image epoch
+    costs 2 x image_extra more)."""
+    c = FLOP_COUNTS
+    return (c["coef"] + c["warm"] + sweeps64 * c["sweep64"] + sweeps32 * c["sweep32"]
+            + c["images"] + c["lsq"] + refined * c["refine"] + newton * c["newton"]
+            + polishes * 2 * c["nearest"])
+
+
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (fma) x 2.4 GHz, the same
 # for FP64 and for unpacked FP32 (packed FP32 is not used)
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -78,32 +94,35 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--ragged-lc", type=int, default=4096,
-                    help="lightcurves of the ragged workload (0 = skip it)")
-    ap.add_argument("--ragged-steps", type=int, default=30)
+                    help="lightcurves of the chosen-form (ragged) workload (0 = skip it)")
+    ap.add_argument("--ragged-steps", type=int, default=N_GEN_FIT,
+                    help="generations of the chosen form's timed fit")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tune-after", type=int, default=30,
                     help="generations the scratch state evolves before the autotuner")
     ap.add_argument("--success-max-gen", type=int, default=1600,
-                    help="generation cap of the time-to-90%%-success runs (0 = skip them)")
-    ap.add_argument("--success-every", type=int, default=100)
-    ap.add_argument("--learned-gens", type=int, default=300,
-                    help="generations of the plain-vs-learned comparison on the ragged "
-                         "workload (0 = skip it)")
-    ap.add_argument("--learned-every", type=int, default=100)
-    ap.add_argument("--iterated", default="16,4,10000",
-                    help="iterated-simplex comparison: slots per lightcurve,runs per slot,"
-                         "max steps per run (empty: skip)")
-    ap.add_argument("--paper-lc", type=int, default=256,
+                    help="generation cap of the time-to-90%% success runs on the chosen-form "
+                         "lightcurves (0 = skip them)")
+    ap.add_argument("--success-every", type=int, default=200)
+    ap.add_argument("--success-forms", default="plain,window,learned",
+                    help="forms of the success study: plain EA, window-only seeding, network "
+                         "seeding")
+    ap.add_argument("--iterated", default="",
+                    help="iterated-simplex comparison on the headline lightcurves: slots per "
+                         "lightcurve,runs per slot,max steps per run (e.g. 16,4,10000)")
+    ap.add_argument("--paper-lc", type=int, default=0,
                     help="lightcurves per paper-shaped experiment (Tables 2-3); 0 skips")
     ap.add_argument("--paper-checkpoints", default="500,1000,3000")
-    ap.add_argument("--islands", default="8,50,2",
-                    help="island form for the success comparison: islands,migrate every,"
-                         "migrants (empty: skip)")
+    ap.add_argument("--islands", default="",
+                    help="island form in the success study: islands,migrate every,migrants "
+                         "(e.g. 8,50,2)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device 4 times (a kernel of "
                          "known traffic that scales the profiler's byte counters)")
     ap.add_argument("--train-network", action="store_true",
                     help="train the proposal network even when no success run uses it")
+    ap.add_argument("--precision-pairs", type=int, default=8_000_000,
+                    help="single-epoch pairs of the precision-form comparison (0 skips it)")
     ap.add_argument("--mlp-samples", type=int, default=1 << 20)
     ap.add_argument("--mlp-epochs", type=int, default=32)
     return ap.parse_args()
@@ -134,6 +153,9 @@ def make_batch(sblm, torch, wl):
 
 
 def run_form(sblm, torch, lcs, wl, chi2_true, pop, steps, args, mode, tune=True):
+    """A full fit of `steps` generations, timed: wall time of the replayed
+    graphs, and the fitness kernel's own duration in every one of them
+    (device clock stamped by graph nodes just before and after it)."""
     n_lc = wl.n_lc
     mags_per_gen = pop * int(wl.off[-1])
     cfg = sblm.ea_default_config()
@@ -150,67 +172,72 @@ def run_form(sblm, torch, lcs, wl, chi2_true, pop, steps, args, mode, tune=True)
         report = scratch.autotune()
         log("bench: autotune\n" + report.strip())
     sched = scratch.schedule()
-    # sweeps per solve (lane level) for the algorithmic FLOP count
-    st = sblm.new_stats()
-    scratch.evaluate(stats=st)
-    torch.cuda.synchronize()
-    s = sblm.stats_dict(st)
-    sweeps = s["n_iter"] / max(s["n_solves"], 1)
-    # dominant kernel: fitness evaluation, timed with events on the stream
-    # it is launched on (the current stream)
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.kernel_reps):
-        scratch.evaluate(stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    k_ms = e0.elapsed_time(e1) / args.kernel_reps
     scratch.close()
 
-    # the timed fit: fresh state with the chosen schedule, `steps` generations
+    # the timed fit: fresh state with the chosen schedule, `steps`
+    # generations, fitness counters and kernel stamps on
     state = sblm.EAState(cfg, lcs, 1)
     state.set_schedule(*sched)
+    state.time_fitness(True)
+    st = sblm.new_stats()
+    state.fit(0, stats=st)  # capture the graph with the counters bound
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    state.fit(steps)
+    state.fit(steps, stats=st)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    k_ms_sum, launches = state.fitness_time()
+    k_ms = k_ms_sum / max(launches, 1)
     summ = state.summary()
     best = np.array([summ[k].best_chi2 for k in range(n_lc)])
     success = float(np.mean(best <= chi2_true + 10.0))
+    # cross-check: the same kernel on the final population, HIP events on
+    # the stream it runs on (the state's work stream is joined to it)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    state.evaluate(stream=stream)
+    e0.record(stream)
+    for _ in range(args.kernel_reps):
+        state.evaluate(stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    k_ms_final = e0.elapsed_time(e1) / args.kernel_reps
     state.close()
 
-    polished = s["n_polished"] / max(s["n_solves"], 1)
-    if mode == sblm.FP64:
-        flop = FLOP_COEF + sweeps * FLOP_SWEEP64 + FLOP_IMAGES + FLOP_LSQ
-    else:  # FP32 sweeps, then FP64 sweeps
-        n32 = s["n_iter_fp32"] / max(s["n_solves"], 1)
-        flop = FLOP_COEF + n32 * FLOP_SWEEP32 + (sweeps - n32) * FLOP_SWEEP64 \
-            + FLOP_IMAGES + FLOP_LSQ
-    flop += polished * FLOP_POLISH
+    s = sblm.stats_dict(st)
+    n = max(s["n_solves"], 1)
+    sweeps = s["n_iter"] / n
+    n32 = s["n_iter_fp32"] / n
+    refined = s["n_polished"] / n
+    newton = s["n_newton"] / n
+    # MIXED: every solve with an FP32 phase is polished (all but degree-4
+    # polynomials and far roots, a few in 10^6)
+    polishes = (1.0 - s["n_degree4"] / n) if mode == sblm.MIXED else 0.0
+    flop = flop_per_magnification(sweeps - n32, n32, refined, newton, polishes)
     # what the wavefronts executed: lockstep sweeps (n_wave_iter) instead of
     # the lanes' own need
-    wave = s["n_wave_iter"] / max(s["n_solves"], 1)
-    flop_exec = flop + (wave - sweeps) * FLOP_SWEEP64
+    wave = s["n_wave_iter"] / n
+    flop_exec = flop + (wave - sweeps) * FLOP_COUNTS["sweep64"]
     ms_step = dt * 1e3 / steps
     return dict(
         mags_per_s=mags_per_gen * steps / dt,
         ms_per_step=ms_step,
-        fits_per_hour=n_lc * 3600.0 / (N_GEN_FIT * ms_step / 1e3),
+        fits_per_hour=n_lc * 3600.0 / (steps * ms_step / 1e3),
         success=success, generations=steps,
-        kernel_ms=k_ms, kernel_mags_per_s=mags_per_gen / (k_ms / 1e3),
-        sweeps_per_solve=sweeps, flop_per_mag=flop,
+        kernel_ms=k_ms, kernel_launches=launches, kernel_ms_final_population=k_ms_final,
+        kernel_mags_per_s=mags_per_gen / (k_ms / 1e3),
+        sweeps_per_solve=sweeps, fp32_sweeps_per_solve=n32, flop_per_mag=flop,
+        newton_passes_per_solve=newton,
         kernel_tflops=flop * mags_per_gen / (k_ms / 1e3) / 1e12,
         kernel_tflops_executed=flop_exec * mags_per_gen / (k_ms / 1e3) / 1e12,
-        capped=s["n_capped"], fallback=s["n_fallback"],
-        wave_sweeps_per_solve=s["n_wave_iter"] / max(s["n_solves"], 1),
-        polished_per_solve=s["n_polished"] / max(s["n_solves"], 1),
+        capped=s["n_capped"], unsettled=s["n_unsettled"], fallback=s["n_fallback"],
+        wave_sweeps_per_solve=wave, polished_per_solve=refined,
         schedule=dict(zip(("lanes", "waves_per_block", "persistent", "asynchronous"), sched)))
 
 
 def success_run(sblm, torch, lcs, chi2_true, pop, mode, sched, lo, hi, proposals=None,
-                max_gen=1600, every=100, target=0.9, seed=7, passes=3, islands=None):
+                max_gen=1600, every=100, target=0.9, seed=7, passes=3, islands=None,
+                window=False):
     """EA with optional proposal seeding; at every checkpoint the fittest
     solution of each lightcurve is fine-tuned by `passes` simplex passes, each
     restarted from the last (on a copy: the EA continues untouched), as the
@@ -239,6 +266,12 @@ def success_run(sblm, torch, lcs, chi2_true, pop, mode, sched, lo, hi, proposals
         sync()
         t0 = time.perf_counter()
         state.seed(proposals, cfg.pop // 2, at_restarts=True)
+        sync()
+        ea_s += time.perf_counter() - t0
+    elif window:  # the ablation: seeds from the observation window alone
+        sync()
+        t0 = time.perf_counter()
+        state.seed_window(cfg.pop // 2, at_restarts=True)
         sync()
         ea_s += time.perf_counter() - t0
     nm_cfg = sblm.nm_default_config()
@@ -276,7 +309,7 @@ def success_run(sblm, torch, lcs, chi2_true, pop, mode, sched, lo, hi, proposals
         if hit_nm is not None:
             break
     state.close()
-    per_hour = lambda h: n_lc * 3600.0 / h[1] if h else None
+    per_hour = lambda h: n_lc * 3600.0 / h[1] if h else f"not reached by generation {gens}"
     return dict(target=target, curve=curve,
                 ea_amoeba=dict(reached=hit_nm is not None,
                                generations=hit_nm[0] if hit_nm else None,
@@ -348,35 +381,43 @@ MLP_GEMM_WEIGHTS = 256 * 512 + 512 * 512 + 512 * 128
 PEAK_BF16_TFLOPS = 2500.0
 
 
-def learned_form(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, net, train_info, args):
-    """Plain EA vs the EA whose population is half seeded (and re-seeded at
-    every restart) by the proposal network, both with the simplex
-    fine-tuning at every checkpoint."""
-    out, t_inf = propose(sblm, torch, net, lcs)
-    plain = success_run(sblm, torch, lcs, chi2_true, pop, sblm.FP64, sched, lo, hi,
-                        max_gen=args.learned_gens, every=args.learned_every)
-    learned = success_run(sblm, torch, lcs, chi2_true, pop, sblm.FP64, sched, lo, hi,
-                          proposals=out, max_gen=args.learned_gens, every=args.learned_every)
-    n_lc = len(chi2_true)
-    last_p, last_l = plain["curve"][-1], learned["curve"][-1]
-    # GPU time for the learned form to match the plain form's last success
-    hit = next((c for c in learned["curve"] if c["ea_amoeba"] >= last_p["ea_amoeba"]), None)
-    return dict(
-        workload=f"{n_lc} lightcurves, pop {pop}, {pop // 2} rows seeded at the start and at "
-                 f"every restart; EA + three simplex passes from the fittest solution",
-        training=train_info, inference_seconds=t_inf, plain=plain, learned=learned,
-        learned_matches_plain_last=dict(
-            plain_success=last_p["ea_amoeba"],
-            plain_gpu_seconds=last_p["ea_seconds"] + last_p["amoeba_seconds"],
-            learned_generations=hit["gen"] if hit else None,
-            learned_gpu_seconds=(hit["ea_seconds"] + hit["amoeba_seconds"] + t_inf)
-            if hit else None),
-        gpu_seconds_per_fit_last=dict(
-            plain=(last_p["ea_seconds"] + last_p["amoeba_seconds"]) / n_lc,
-            learned=(last_l["ea_seconds"] + last_l["amoeba_seconds"] + t_inf) / n_lc,
-            learned_with_training=(last_l["ea_seconds"] + last_l["amoeba_seconds"] + t_inf
-                                   + train_info["data_seconds"] + train_info["train_seconds"])
-            / n_lc))
+def success_study(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, net, train_info, args):
+    """Time to 90% success on the chosen-form lightcurves: the plain EA, the
+    EA half seeded (at the start and at every restart) from the observation
+    window alone, and the EA half seeded by the proposal network (the
+    learned form), each with the simplex fine-tuning of the fittest solution
+    at every checkpoint and stopped once 90% of the lightcurves succeed."""
+    forms = [f for f in args.success_forms.split(",") if f]
+    out = dict(workload=f"{len(chi2_true)} lightcurves, pop {pop}, {pop // 2} rows seeded at "
+                        f"the start and at every restart; EA + three simplex passes from the "
+                        f"fittest solution every {args.success_every} generations",
+               training=train_info)
+    t_inf = 0.0
+    for f in forms:
+        log(f"bench: success study, form {f}")
+        kw = {}
+        if f == "learned":
+            props, t_inf = propose(sblm, torch, net, lcs)
+            kw["proposals"] = props
+            out["inference_seconds"] = t_inf
+        elif f == "window":
+            kw["window"] = True
+        r = success_run(sblm, torch, lcs, chi2_true, pop, sblm.FP64, sched, lo, hi,
+                        max_gen=args.success_max_gen, every=args.success_every, **kw)
+        if f == "learned" and r["ea_amoeba"]["reached"]:  # inference is part of its time
+            r["ea_amoeba"]["gpu_seconds"] += t_inf
+            r["ea_amoeba"]["fits_per_hour"] = len(chi2_true) * 3600.0 / \
+                r["ea_amoeba"]["gpu_seconds"]
+        out[f] = r
+        log(f"bench: success {f}: {json.dumps(r)}")
+    if args.islands:
+        isl = tuple(int(v) for v in args.islands.split(","))
+        out["islands"] = success_run(sblm, torch, lcs, chi2_true, pop, sblm.FP64, sched, lo, hi,
+                                     max_gen=args.success_max_gen, every=args.success_every,
+                                     islands=isl)
+        out["islands"]["config"] = dict(islands=isl[0], pop_per_island=pop // isl[0],
+                                        migrate_every=isl[1], migrants=isl[2])
+    return out
 
 
 def cpu_baseline(wl, y, w, pop, target_s):
@@ -466,6 +507,68 @@ def single_fit(sblm, torch, nthreads):
                 chi2_true=c_true)
 
 
+def precision_forms(sblm, torch, lcs, n_lc, args):
+    """FP64 against the precision form (FP32 iteration + FP64 Newton polish)
+    where cold starts dominate: single-epoch magnifications (every solve
+    cold) and the simplex passes (each lane's first epoch of a round starts
+    from the last round's roots, the rest warm)."""
+    from paper_1208_4830_amd import inputs
+    rng = np.random.default_rng(31)
+    n = args.precision_pairs
+    th = inputs.draw_theta(rng, n)
+    th[5] = -rng.uniform(-2.0, 2.0, n) * th[4]  # the epoch t = 0 at tau ~ U[-2, 2]
+    theta = torch.as_tensor(th, device="cuda")
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    A = torch.empty((n, 1), dtype=torch.float64, device="cuda")
+    out = {"single_epoch_magnify": {}, "simplex_pass": {}}
+    for name, mode in (("fp64", sblm.FP64), ("mixed", sblm.MIXED)):
+        st = sblm.new_stats()
+        sblm.sblm_magnify(theta, t, mode=mode, A=A, stats=st)  # warm-up, counters
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        stream = torch.cuda.current_stream()
+        e0.record(stream)
+        for _ in range(3):
+            sblm.sblm_magnify(theta, t, mode=mode, A=A, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        s = sblm.stats_dict(st)
+        out["single_epoch_magnify"][name] = dict(
+            pairs=n, ms=ms, mags_per_s=n / (ms / 1e3),
+            sweeps_per_solve=s["n_iter"] / n, fp32_sweeps_per_solve=s["n_iter_fp32"] / n,
+            newton_passes_per_solve=s["n_newton"] / n, fallback_per_solve=s["n_fallback"] / n)
+    lo, hi = inputs.PRIOR_LO, inputs.PRIOR_HI
+    x0 = torch.as_tensor(np.clip(rng.random((6, n_lc)), 0, 1), device="cuda")
+    for name, mode in (("fp64", sblm.FP64), ("mixed", sblm.MIXED)):
+        cfg = sblm.nm_default_config()
+        cfg.mode = mode
+        cfg.max_iter = 300
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, c, _, _, it = sblm.nm_refine(lcs, lo, hi, x0, cfg)
+        torch.cuda.synchronize()
+        out["simplex_pass"][name] = dict(seconds=time.perf_counter() - t0,
+                                         steps=int(it.sum().item()),
+                                         workload=f"{n_lc} simplices from random starts, "
+                                                  f"<= {cfg.max_iter} steps")
+    for k in out:
+        f64, mx = out[k]["fp64"], out[k]["mixed"]
+        out[k]["mixed_over_fp64_time"] = (mx["ms"] / f64["ms"] if "ms" in mx
+                                          else mx["seconds"] / f64["seconds"])
+    return out
+
+
+def roofline_of(form, kernel):
+    return {"bound": "alu", "achieved": form["kernel_tflops"], "peak": PEAK_VALU_TFLOPS,
+            "unit": "TFLOP/s", "frac": form["kernel_tflops"] / PEAK_VALU_TFLOPS,
+            "kernel": kernel, "kernel_ms": form["kernel_ms"],
+            "kernel_launches": form["kernel_launches"],
+            "flop_per_magnification": form["flop_per_mag"],
+            "executed_tflops": form["kernel_tflops_executed"],
+            "executed_frac": form["kernel_tflops_executed"] / PEAK_VALU_TFLOPS}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -503,40 +606,16 @@ def main():
         log(f"bench: {name}: {json.dumps(forms[name])}")
     main_form = forms.get("fp64") or next(iter(forms.values()))
     lo, hi = inputs.PRIOR_LO, inputs.PRIOR_HI  # the default EA domain
-    # success runs: a fixed schedule (see success_run)
-    sched = (16, 4, 1, 0)
-    net = train_info = None
-    if args.success_max_gen > 0 or args.learned_gens > 0 or args.train_network:
-        log("bench: training the proposal network on generated lightcurves")
-        net, train_info = train_proposals(sblm, torch, args)
-        log(f"bench: training: {json.dumps(train_info)}")
-    success = None
-    if args.success_max_gen > 0:
-        log("bench: time to 90% success, plain and learned, EA + simplex fine-tuning")
-        out_p, t_inf = propose(sblm, torch, net, lcs)
-        success = dict(
-            plain=success_run(sblm, torch, lcs, chi2_true, args.pop, sblm.FP64, sched, lo, hi,
-                              max_gen=args.success_max_gen, every=args.success_every),
-            learned=success_run(sblm, torch, lcs, chi2_true, args.pop, sblm.FP64, sched, lo,
-                                hi, proposals=out_p, max_gen=args.success_max_gen,
-                                every=args.success_every),
-            inference_seconds=t_inf)
-        if args.islands:
-            isl = tuple(int(v) for v in args.islands.split(","))
-            success["islands"] = success_run(sblm, torch, lcs, chi2_true, args.pop, sblm.FP64,
-                                             sched, lo, hi, max_gen=args.success_max_gen,
-                                             every=args.success_every, islands=isl)
-            success["islands"]["config"] = dict(islands=isl[0], pop_per_island=args.pop // isl[0],
-                                                migrate_every=isl[1], migrants=isl[2])
-        if args.iterated:
-            success["iterated_simplex"] = iterated_run(sblm, torch, lcs, chi2_true, lo, hi,
-                                                       *(int(v) for v in
-                                                         args.iterated.split(",")))
-        lrn = success["learned"]["ea_amoeba"]
-        if lrn["gpu_seconds"] is not None:  # proposals are part of the learned fit's GPU time
-            lrn["gpu_seconds"] += t_inf
-            lrn["fits_per_hour"] = args.n_lc * 3600.0 / lrn["gpu_seconds"]
-        log(f"bench: success: {json.dumps(success)}")
+    if args.precision_pairs > 0:
+        log("bench: precision forms where cold starts dominate")
+        forms["cold_dominated"] = precision_forms(sblm, torch, lcs, args.n_lc, args)
+        log(f"bench: cold-dominated: {json.dumps(forms['cold_dominated'])}")
+
+    iterated = None
+    if args.iterated:
+        iterated = iterated_run(sblm, torch, lcs, chi2_true, lo, hi,
+                                *(int(v) for v in args.iterated.split(",")))
+        log(f"bench: iterated simplex: {json.dumps(iterated)}")
 
     paper = None
     if args.paper_lc > 0:
@@ -550,25 +629,36 @@ def main():
                 sblm, torch, exp, n_lc=args.paper_lc, pop=1000, checkpoints=cps)
             log(f"bench: paper {exp}: {json.dumps(paper[f'experiment_{exp}'])}")
 
-    ragged = None
-    learned = None
+    chosen = None
+    study = None
     if args.ragged_lc > 0:
-        log(f"bench: ragged workload, {args.ragged_lc} lightcurves of 200-5000 epochs, pop 128")
+        log(f"bench: chosen form, {args.ragged_lc} lightcurves of 200-5000 epochs, pop 128, "
+            f"{args.ragged_steps} generations")
         wr = inputs.ragged_workload(4, args.ragged_lc)
         yr, wr_w, lcs_r = make_batch(sblm, torch, wr)
         c_true_r, _, _ = sblm.sblm_chi2(lcs_r, torch.as_tensor(wr.theta.copy(), device="cuda"), 1)
-        ragged = run_form(sblm, torch, lcs_r, wr, c_true_r.cpu().numpy(), 128,
-                          args.ragged_steps, args, sblm.FP64)
-        ragged["workload"] = (f"{args.ragged_lc} lightcurves, L ~ U{{200..5000}} "
-                              f"(total {int(wr.off[-1])} epochs), nightly cadence, pop 128")
-        log(f"bench: ragged: {json.dumps(ragged)}")
-        if args.learned_gens > 0:
-            log("bench: learned form (proposal network) vs plain EA on the ragged workload")
-            learned = learned_form(sblm, torch, lcs_r, c_true_r.cpu().numpy(), 128,
-                                   (8, 4, 1, 0), lo, hi, net, train_info, args)
-            log(f"bench: learned: {json.dumps(learned)}")
+        c_true_r = c_true_r.cpu().numpy()
+        chosen = run_form(sblm, torch, lcs_r, wr, c_true_r, 128, args.ragged_steps, args,
+                          sblm.FP64)
+        chosen["workload"] = (f"{args.ragged_lc} lightcurves, L ~ U{{200..5000}} "
+                              f"(total {int(wr.off[-1])} epochs), nightly cadence, pop 128, "
+                              f"FP64, autotuned schedule, {args.ragged_steps} generations")
+        chosen["roofline"] = roofline_of(chosen, "fitness_kernel (FP64, chosen schedule)")
+        log(f"bench: chosen: {json.dumps(chosen)}")
+        if args.success_max_gen > 0:
+            net = train_info = None
+            if "learned" in args.success_forms.split(","):
+                log("bench: training the proposal network on generated lightcurves")
+                net, train_info = train_proposals(sblm, torch, args)
+                log(f"bench: training: {json.dumps(train_info)}")
+            study = success_study(sblm, torch, lcs_r, c_true_r, 128, (8, 4, 1, 0), lo, hi,
+                                  net, train_info, args)
+            if net is not None:
+                net.close()
         del lcs_r
-    if net is not None:
+    elif args.train_network:
+        net, train_info = train_proposals(sblm, torch, args)
+        log(f"bench: training: {json.dumps(train_info)}")
         net.close()
 
     cpu = None
@@ -578,8 +668,20 @@ def main():
         cpu["single_fit"] = single_fit(sblm, torch, cpu["cores"])
         log(f"bench: cpu {json.dumps(cpu)}")
 
+    at90 = None
+    if study:
+        at90 = {f: study[f]["ea_amoeba"]["fits_per_hour"]
+                for f in ("plain", "window", "learned", "islands") if f in study}
+        at90["gpu_seconds"] = {f: study[f]["ea_amoeba"]["gpu_seconds"]
+                               for f in ("plain", "window", "learned", "islands") if f in study}
+        at90["workload"] = "the chosen-form lightcurves (EA + simplex fine-tuning, FP64)"
+    roof = roofline_of(main_form, "fitness_kernel (FP64)")
+    roof["traffic"] = fitness_traffic()
+    roof["traffic_unit"] = "B/launch"
+    roof["algorithmic_bytes"] = FITNESS_TRAFFIC["algorithmic_bytes_per_launch"]
     out = {
-        "metric": "binary-lens magnifications/s (batched fitness + EA generation)",
+        "metric": "binary-lens magnifications/s; fits/hour at >=90% success, plain vs chosen "
+                  "form",
         "value": main_form["mags_per_s"],
         "unit": "magnifications/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -587,30 +689,32 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{args.n_lc} lightcurves x {args.epochs} uniform epochs, "
-                               f"population {args.pop}, FP64 chi^2 with profiled Fs, Fb",
+                               f"population {args.pop}, FP64 chi^2 with profiled Fs, Fb, "
+                               f"{args.steps}-generation fit",
                    "n_lc": args.n_lc, "epochs": args.epochs, "pop": args.pop,
                    "parallelism": "single GPU"},
-        "fits_per_hour": main_form["fits_per_hour"],
-        "fits_per_hour_at_90pct": ({f: success[f]["ea_amoeba"]["fits_per_hour"]
-                                    for f in ("plain", "learned", "islands") if f in success}
-                                   if success else None),
-        "time_to_90pct_success": success,
-        "success_rate": main_form["success"],
-        "forms": forms,
-        "ragged": ragged,
-        "learned": learned,
-        "paper_tables": paper,
-        "roofline": {"bound": "alu", "achieved": main_form["kernel_tflops"],
-                     "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": main_form["kernel_tflops"] / PEAK_VALU_TFLOPS,
-                     "traffic": fitness_traffic(), "traffic_unit": "B/launch",
-                     "algorithmic_bytes": FITNESS_TRAFFIC["algorithmic_bytes_per_launch"],
-                     "executed_tflops": main_form["kernel_tflops_executed"],
-                     "executed_frac": main_form["kernel_tflops_executed"] / PEAK_VALU_TFLOPS,
-                     "kernel": "fitness_kernel (FP64)",
-                     "flop_per_magnification": main_form["flop_per_mag"]},
+        "roofline": roof,
         "cpu_baseline": cpu,
+        "fits_per_hour": main_form["fits_per_hour"],
+        "success_rate": main_form["success"],
+        "chosen_form": chosen,
+        "fits_per_hour_at_90pct": at90,
+        "success_study": study,
+        "forms": forms,
+        "iterated_simplex": iterated,
+        "paper_tables": paper,
     }
+    summary = dict(
+        plain_mags_per_s=main_form["mags_per_s"], plain_ms_per_step=main_form["ms_per_step"],
+        plain_roofline_frac=roof["frac"],
+        mixed_mags_per_s=forms.get("mixed", {}).get("mags_per_s"),
+        chosen_mags_per_s=chosen["mags_per_s"] if chosen else None,
+        chosen_ms_per_step=chosen["ms_per_step"] if chosen else None,
+        chosen_roofline_frac=chosen["roofline"]["frac"] if chosen else None,
+        chosen_fits_per_hour=chosen["fits_per_hour"] if chosen else None,
+        fits_per_hour_at_90pct={k: v for k, v in (at90 or {}).items()
+                                if k not in ("gpu_seconds", "workload")})
+    log("bench: summary " + json.dumps(summary))
     print(json.dumps(out), flush=True)
 
 

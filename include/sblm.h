@@ -64,7 +64,9 @@ typedef enum {
 
 typedef enum {
   SBLM_FP64 = 0,  /* root solve, polish, image test, det J and chi^2 in FP64 */
-  SBLM_MIXED = 1  /* FP32 root solve, FP64 polish / image test / det J / chi^2 */
+  SBLM_MIXED = 1  /* root iteration in FP32, then at most two FP64 Newton
+                     steps per root (FP64 sweeps only where those do not
+                     converge); image test, det J and chi^2 in FP64       */
 } sblm_mode;
 
 #define SBLM_NPAR 6
@@ -77,8 +79,10 @@ typedef struct {
   unsigned long long n_capped;     /* solves that reached the iteration cap,
                                       also after the cold retry (see
                                       n_unsettled)                          */
-  unsigned long long n_fallback;   /* MIXED: cold solves whose FP32 roots
-                                      needed > 2 FP64 sweeps to converge      */
+  unsigned long long n_fallback;   /* MIXED: solves whose FP32 roots were not
+                                      polished to the FP64 tolerance by two
+                                      Newton steps and went on to FP64
+                                      simultaneous-iteration sweeps           */
   unsigned long long n_degree4;    /* leading coefficient negligible          */
   unsigned long long n_degenerate; /* chi^2 fits with a singular 2x2 system   */
   unsigned long long n_wave_iter;  /* sweeps the wavefront executed, summed
@@ -98,6 +102,8 @@ typedef struct {
                                       images (a fold or a cusp of the
                                       caustic), and their images are refined
                                       on the lens equation                    */
+  unsigned long long n_newton;     /* MIXED: FP64 Newton polish passes over the
+                                      five roots, summed                      */
 } sblm_stats;
 
 /* Ragged batch of lightcurves in CSR form.  Lightcurve k owns epochs
@@ -275,12 +281,29 @@ int ea_evaluate(ea_state* st, sblm_stats* stats, void* stream);
  * generation), each = ea_evaluate + (when due, the migration of ea_config,
  * Sec. 5.3) + ea_generation on the state's own buffers, replayed from one
  * captured HIP graph.
- *   n_gen  >= 0
+ *   n_gen  >= 0; 0 only captures the graph (bound to `stats`) when it is
+ *          not captured yet, so that a later timed call replays at once
  *   stats  nullable device pointer; accumulates the counters of every
  *          generation's fitness evaluation
  * Errors: SBLM_EINVAL, SBLM_ESTATE, SBLM_EDEVICE.
  */
 int ea_fit(ea_state* st, int32_t n_gen, sblm_stats* stats, void* stream);
+
+/*
+ * ea_time_fitness -- instrumentation, not part of the method: with enable =
+ * 1 every generation that ea_fit replays stamps the device's constant-rate
+ * wall clock just before and just after its fitness kernel (two one-thread
+ * kernels in the captured graph) and adds the interval to a sum in the
+ * state; enable = 0 removes the stamps.  Either way the sum and the launch
+ * count are cleared (in order on `stream`).  The interval includes the
+ * dispatch gaps next to the kernel (microseconds against milliseconds).
+ * ea_fitness_time -- the sum in milliseconds (host out *ms) and the number
+ * of timed launches (host out *launches) since the last ea_time_fitness;
+ * synchronises the state's work.  Errors: SBLM_EINVAL, SBLM_ESTATE,
+ * SBLM_EDEVICE.
+ */
+int ea_time_fitness(ea_state* st, int32_t enable, void* stream);
+int ea_fitness_time(ea_state* st, double* ms, int64_t* launches);
 
 /*
  * ea_autotune -- choose the fitness schedule of this state by timing it on
@@ -627,8 +650,15 @@ int mlp_train(mlp_net* net, const uint16_t* x, const float* y, int64_t rows,
  * of lightcurve l; re-encoded into the state's domain (Eq. EMMA-encoding) and
  * clamped to [0, 1].  Lightcurves without epochs are left alone.  Seeding
  * before ea_fit takes effect at once (ea_fit evaluates first).
+ * With flags | EA_SEED_WINDOW_ONLY (`out` and ld_out unused, may be NULL /
+ * 0) the rows come from the observation window alone -- the ablation that
+ * separates what the network learns from what the window gives: x_0..x_3 =
+ * u(word 1..4) (uniform over the ranges of log10 q, d, u0, alpha), x_4 =
+ * 0.5 (t0 at the middle of the observed span), x_5 = 0.25 (tE a quarter of
+ * it), through the same target map and encoding.
  */
 #define EA_SEED_AT_RESTARTS 1
+#define EA_SEED_WINDOW_ONLY 2
 int ea_seed(ea_state* st, const float* out, int32_t ld_out, int32_t n_seed,
             int32_t flags, void* stream);
 

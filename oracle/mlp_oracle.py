@@ -172,10 +172,10 @@ P_DATA = 33
 P_SEED = 6
 
 
-def data_window(t0, tE):
-    """First and last instants of t0 +- 2 tE inside a nightly window
-    [n + 0.1, n + 0.1 + 1/3] (days)."""
-    ta, tb = t0 - 2.0 * tE, t0 + 2.0 * tE
+def data_window(t0, tE, a, b):
+    """First and last instants of the observing window [t0 + a tE, t0 + b tE]
+    inside a nightly window [n + 0.1, n + 0.1 + 1/3] (days)."""
+    ta, tb = t0 + a * tE, t0 + b * tE
     na = math.floor(ta - NIGHT0)
     t_first = ta if ta <= na + NIGHT0 + NIGHT_LEN else na + 1.0 + NIGHT0
     nb = math.floor(tb - NIGHT0)
@@ -212,16 +212,21 @@ def poisson_count(c, u, z):
 
 
 def sample_params(seed, s):
-    """(theta[6], Fb, noise fraction, L) of training sample s."""
-    w = [O.draw(seed, s, 0, P_DATA, 0, j) for j in range(9)]
+    """(theta[6], Fb, noise fraction, L, (a, b)) of training sample s: the
+    observing window runs from t0 + a tE to t0 + b tE, a ~ U(-3, -2) and
+    b ~ U(2, 3), the random start and end of the paper's test lightcurves
+    (Sec. 4.2)."""
+    w = [O.draw(seed, s, 0, P_DATA, 0, j) for j in range(11)]
     th = np.array([DATA_LO[g] + (DATA_HI[g] - DATA_LO[g]) * O.u01(w[g]) for g in range(6)])
-    return th, 0.5 * O.u01(w[6]), 0.005 + 0.025 * O.u01(w[7]), 200.0 + O.below(w[8], 4801)
+    win = (-3.0 + O.u01(w[9]), 2.0 + O.u01(w[10]))
+    return (th, 0.5 * O.u01(w[6]), 0.005 + 0.025 * O.u01(w[7]), 200.0 + O.below(w[8], 4801),
+            win)
 
 
-def expected_counts(th, L, nbins=256):
+def expected_counts(th, L, win, nbins=256):
     """Expected epoch count per bin and the window (t_first, span)."""
     tE, t0 = th[4], th[5]
-    t_first, t_last = data_window(t0, tE)
+    t_first, t_last = data_window(t0, tE, *win)
     span = t_last - t_first
     o = np.zeros(nbins)
     dj = np.zeros(nbins)
@@ -238,10 +243,11 @@ def expected_counts(th, L, nbins=256):
     return c, t_first, span
 
 
-def observe(seed, s, th, Fb, sn, L, nbins=256):
-    """Bin-level observation of parameters th (Fs = 1): raw bin values,
-    their filled flags, the targets y[7] and the window (t_first, span)."""
-    c, t_first, span = expected_counts(th, L, nbins)
+def observe(seed, s, th, Fb, sn, L, win, nbins=256):
+    """Bin-level observation of parameters th (Fs = 1) through the window
+    win = (a, b): raw bin values, their filled flags, the targets y[7] and
+    the window (t_first, span)."""
+    c, t_first, span = expected_counts(th, L, win, nbins)
     thp = np.array(th, dtype=float)
     thp[4] = th[4] / span
     thp[5] = (th[5] - t_first) / span
@@ -266,17 +272,19 @@ def observe(seed, s, th, Fb, sn, L, nbins=256):
 
 def make_sample(seed, s, nbins=256):
     """(x[256] normalised bins, y[7] targets) of training sample s."""
-    th, Fb, sn, L = sample_params(seed, s)
-    vals, filled, y, _, _ = observe(seed, s, th, Fb, sn, L, nbins)
+    th, Fb, sn, L, win = sample_params(seed, s)
+    vals, filled, y, _, _ = observe(seed, s, th, Fb, sn, L, win, nbins)
     return fill_and_normalise(vals, filled), y
 
 
 # --------------------------------------------------------------- seeding
 
-def seed_rows(o, t_first, span, lo, hi, seed, lc, n_seed, gen=0):
+def seed_rows(o, t_first, span, lo, hi, seed, lc, n_seed, gen=0, window_only=False):
     """Encoded population rows [n_seed][6] drawn from the mixture o[>=120]
-    with the counters of generation `gen`."""
-    o = np.asarray(o, dtype=float)
+    with the counters of generation `gen`; with window_only (o unused) t0 at
+    the middle of the observed span, tE a quarter of it and the other four
+    parameters uniform over their ranges (the ablation of the learned form)."""
+    o = np.zeros(2 * K * D + K) if window_only else np.asarray(o, dtype=float)
     lmax = max(o[:K])
     e = [math.exp(o[k] - lmax) for k in range(K)]
     S = 0.0
@@ -287,6 +295,14 @@ def seed_rows(o, t_first, span, lo, hi, seed, lc, n_seed, gen=0):
     lo, hi = np.asarray(lo, float), np.asarray(hi, float)
     rows = np.zeros((n_seed, 6))
     for r in range(n_seed):
+        if window_only:
+            # the learned form's ablation: the observation window alone
+            x = np.array([O.u01(O.draw(seed, lc, gen, P_SEED, r, 1 + d)) for d in range(4)]
+                         + [0.5, 0.25])
+            th = np.array([-3.0 + 3.0 * x[0], 0.5 + 1.5 * x[1], 0.5 * x[2], 2.0 * np.pi * x[3],
+                           span * x[5], t_first + span * x[4]])
+            rows[r] = np.minimum(np.maximum((th - lo) / (hi - lo), 0.0), 1.0)
+            continue
         u = O.u01(O.draw(seed, lc, gen, P_SEED, r, 0))
         comp, acc = K - 1, 0.0
         for k in range(K):

@@ -128,19 +128,16 @@ struct Proposals {
   const float* O;  // [n_lc][ld] network outputs, or null (no seeding)
   int32_t ld;
   int32_t n_seed;
+  int32_t window_only;  // 1: rows from the observation window alone (O unused)
   const int64_t* off;
   const double* t;
   double lo[SBLM_NPAR], span[SBLM_NPAR];
 };
 
-__device__ void seed_row(const EaParams& p, double* P, const Proposals& pr,
-                         int64_t lc, int row, int64_t gen) {
-  const int64_t k = lc / p.n_isl;  // the lightcurve of this island
-  const int64_t o0 = pr.off[k], o1 = pr.off[k + 1];
-  if (o1 <= o0) return;
-  const double t_first = pr.t[o0], tspan = pr.t[o1 - 1] - t_first;
-  const Stream rs = {p.seed, (uint64_t)lc, (uint64_t)gen};
-  const float* o = pr.O + k * (int64_t)pr.ld;
+// Row `row`'s draw from the network's proposal mixture o (K logits, K x D
+// means, K x D log standard deviations): component by the first Philox word,
+// then a Gaussian draw by four Box-Muller pairs; x_3 reduced mod 1.
+__device__ void seed_mixture(const float* o, const Stream& rs, int row, double* x) {
   const int K = MLP_K, D = MLP_D;
   double lmax = (double)o[0];
   for (int k = 1; k < K; ++k) lmax = fmax(lmax, (double)o[k]);
@@ -164,10 +161,28 @@ __device__ void seed_row(const EaParams& p, double* P, const Proposals& pr,
     z[2 * i] = rad * cos(2.0 * M_PI * u2);
     z[2 * i + 1] = rad * sin(2.0 * M_PI * u2);
   }
-  double x[MLP_D];
   for (int d = 0; d < D; ++d)
     x[d] = (double)o[K + comp * D + d] + exp((double)o[K + K * D + comp * D + d]) * z[d];
   x[MLP_PERIODIC] -= floor(x[MLP_PERIODIC]);
+}
+
+__device__ void seed_row(const EaParams& p, double* P, const Proposals& pr,
+                         int64_t lc, int row, int64_t gen) {
+  const int64_t k = lc / p.n_isl;  // the lightcurve of this island
+  const int64_t o0 = pr.off[k], o1 = pr.off[k + 1];
+  if (o1 <= o0) return;
+  const double t_first = pr.t[o0], tspan = pr.t[o1 - 1] - t_first;
+  const Stream rs = {p.seed, (uint64_t)lc, (uint64_t)gen};
+  double x[MLP_D];
+  if (pr.window_only) {
+    // the ablation of the learned form: t0 at the middle of the observed
+    // span, tE a quarter of it, the other genes uniform over their range
+    for (int d = 0; d < 4; ++d) x[d] = u01(rs.draw(P_SEED, (uint64_t)row, (uint64_t)(1 + d)));
+    x[4] = 0.5;
+    x[5] = 0.25;
+  } else {
+    seed_mixture(pr.O + k * (int64_t)pr.ld, rs, row, x);
+  }
   double th[SBLM_NPAR];
   th[0] = -3.0 + 3.0 * x[0];
   th[1] = 0.5 + 1.5 * x[1];
@@ -268,7 +283,7 @@ __global__ void ea_generation_kernel(EaParams p, double* P, EaLc* lcs,
 
   if (s_restart) {  // fresh population keyed by the next generation
     init_rows(p, P, lc, gen + 1);
-    if (pr.O) {  // attached proposals re-seed their rows
+    if (pr.O || pr.window_only) {  // attached proposals re-seed their rows
       __syncthreads();
       for (int r = threadIdx.x; r < pr.n_seed; r += blockDim.x) seed_row(p, P, pr, lc, r, gen + 1);
     }
@@ -469,7 +484,30 @@ struct EaStateImpl {
   double* mig_out = nullptr;   // migration outboxes (islands with migrants)
   int32_t* mig_least = nullptr;
   bool mig_in_fit = false;     // ea_fit migrates when due
+  // fitness timing (ea_time_fitness): device wall-clock ticks summed over the
+  // timed launches [0], the start stamp of the current one [1], launches [2]
+  unsigned long long* ticks = nullptr;
+  int time_fitness = 0;
 };
+
+// Device wall-clock stamps around the fitness kernel (one thread): the
+// start stamp, then at the end the interval is added to the sum.  Kernels on
+// one stream run in order, so the interval spans the fitness kernel and the
+// dispatch gaps on either side of it (a few microseconds).
+__global__ void fitness_stamp_kernel(unsigned long long* t, int end) {
+  if (threadIdx.x != 0) return;
+  const unsigned long long now = (unsigned long long)wall_clock64();
+  if (end) {
+    t[0] += now - t[1];
+    t[2] += 1;
+  } else {
+    t[1] = now;
+  }
+}
+
+__global__ void ticks_clear_kernel(unsigned long long* t) {
+  if (threadIdx.x < 4) t[threadIdx.x] = 0ull;
+}
 
 __global__ void queue_reset_kernel(unsigned int* q) {
   if (threadIdx.x < 8) q[threadIdx.x] = 0u;
@@ -515,7 +553,7 @@ static hipError_t enqueue_migration(EaStateImpl* s, double* chi2, double* Fs, do
 }
 
 static hipError_t enqueue_evaluate(EaStateImpl* s, sblm_stats* stats,
-                                   hipStream_t st) {
+                                   hipStream_t st, bool stamped = false) {
   FitArgs a;
   memset(&a, 0, sizeof(a));
   a.theta = s->P;
@@ -544,7 +582,13 @@ static hipError_t enqueue_evaluate(EaStateImpl* s, sblm_stats* stats,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  return launch_fitness(a, s->cfg.mode, true, st, s->wpb);
+  if (!stamped) return launch_fitness(a, s->cfg.mode, true, st, s->wpb);
+  hipLaunchKernelGGL(fitness_stamp_kernel, dim3(1), dim3(64), 0, st, s->ticks, 0);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = launch_fitness(a, s->cfg.mode, true, st, s->wpb);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fitness_stamp_kernel, dim3(1), dim3(64), 0, st, s->ticks, 1);
+  return hipGetLastError();
 }
 
 }  // namespace sblm
@@ -628,6 +672,7 @@ extern "C" void ea_destroy(ea_state* st) {
   (void)hipFree(s.order);
   (void)hipFree(s.queue);
   (void)hipFree(s.xcd_start);
+  (void)hipFree(s.ticks);
   (void)hipFree(s.mig_out);
   (void)hipFree(s.mig_least);
   (void)hipSetDevice(prev);
@@ -766,6 +811,7 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
       hipMalloc(&s.order, (size_t)p.n_ind * sizeof(int32_t)) != hipSuccess ||
       hipMalloc(&s.queue, 8 * sizeof(unsigned int)) != hipSuccess ||
       hipMalloc(&s.xcd_start, 9 * sizeof(int64_t)) != hipSuccess ||
+      hipMalloc(&s.ticks, 4 * sizeof(unsigned long long)) != hipSuccess ||
       (p.n_isl > 1 && cfg->n_migrants > 0 &&
        (hipMalloc(&s.mig_out, (size_t)p.n_lc * cfg->n_migrants * 9 * sizeof(double)) !=
             hipSuccess ||
@@ -844,17 +890,21 @@ extern "C" int ea_seed(ea_state* st, const float* out, int32_t ld_out, int32_t n
                        int32_t flags, void* stream) {
   if (!st) return set_error(SBLM_ESTATE, "ea_seed: null state");
   EaStateImpl& s = st->impl;
-  if (flags & ~EA_SEED_AT_RESTARTS) return set_error(SBLM_EINVAL, "ea_seed: unknown flags");
+  if (flags & ~(EA_SEED_AT_RESTARTS | EA_SEED_WINDOW_ONLY))
+    return set_error(SBLM_EINVAL, "ea_seed: unknown flags");
+  const bool window = (flags & EA_SEED_WINDOW_ONLY) != 0;
   if (n_seed < 0 || n_seed > s.prm.pop)
     return set_error(SBLM_EINVAL, "ea_seed: n_seed = %d outside [0, pop = %d]", n_seed,
                      s.prm.pop);
-  if (n_seed > 0 && !out) return set_error(SBLM_EINVAL, "ea_seed: null network output");
-  if (n_seed > 0 && ld_out < MLP_NOUT)
+  if (n_seed > 0 && !out && !window)
+    return set_error(SBLM_EINVAL, "ea_seed: null network output");
+  if (n_seed > 0 && !window && ld_out < MLP_NOUT)
     return set_error(SBLM_EINVAL, "ea_seed: ld_out = %d < %d", ld_out, MLP_NOUT);
   Proposals pr = {};
-  pr.O = n_seed > 0 ? out : nullptr;
+  pr.O = n_seed > 0 && !window ? out : nullptr;
   pr.ld = ld_out;
   pr.n_seed = n_seed;
+  pr.window_only = n_seed > 0 && window ? 1 : 0;
   pr.off = s.lcs.off;
   pr.t = s.lcs.t;
   for (int g = 0; g < SBLM_NPAR; ++g) {
@@ -869,7 +919,7 @@ extern "C" int ea_seed(ea_state* st, const float* out, int32_t ld_out, int32_t n
     if (rc) return rc;
   }
   const bool attach = (flags & EA_SEED_AT_RESTARTS) && n_seed > 0;
-  const bool was = s.prop.O != nullptr;
+  const bool was = s.prop.O != nullptr || s.prop.window_only;
   s.prop = attach ? pr : Proposals{};
   if ((attach || was) && s.graph) return capture_graph(s, s.graph_stats);
   return SBLM_OK;
@@ -969,7 +1019,7 @@ static int capture_graph(EaStateImpl& s, sblm_stats* stats) {
   if ((rc = check_hip(hipStreamBeginCapture(s.work, hipStreamCaptureModeThreadLocal),
                       "ea graph capture")))
     return rc;
-  hipError_t e1 = enqueue_evaluate(&s, stats, s.work);
+  hipError_t e1 = enqueue_evaluate(&s, stats, s.work, s.time_fitness != 0);
   if (e1 == hipSuccess && s.mig_in_fit) e1 = enqueue_migration(&s, s.chi2, s.Fs, s.Fb, 0, s.work);
   hipError_t e2 = enqueue_generation(&s, s.chi2, s.Fs, s.Fb, nullptr, s.work);
   hipError_t e3 = hipStreamEndCapture(s.work, &g);
@@ -986,11 +1036,11 @@ static int capture_graph(EaStateImpl& s, sblm_stats* stats) {
 extern "C" int ea_fit(ea_state* st, int32_t n_gen, sblm_stats* stats, void* stream) {
   if (!st) return set_error(SBLM_ESTATE, "ea_fit: null state");
   if (n_gen < 0) return set_error(SBLM_EINVAL, "ea_fit: n_gen < 0");
-  if (n_gen == 0) return SBLM_OK;
   EaStateImpl& s = st->impl;
   int rc;
   if (!s.graph || s.graph_stats != stats)
     if ((rc = capture_graph(s, stats))) return rc;
+  if (n_gen == 0) return SBLM_OK;
   hipStream_t caller = (hipStream_t)stream;
   if ((rc = check_hip(hipEventRecord(s.ev_in, caller), "ea_fit event")) ||
       (rc = check_hip(hipStreamWaitEvent(s.work, s.ev_in, 0), "ea_fit wait")))
@@ -1000,6 +1050,44 @@ extern "C" int ea_fit(ea_state* st, int32_t n_gen, sblm_stats* stats, void* stre
   if ((rc = check_hip(hipEventRecord(s.ev_out, s.work), "ea_fit event")) ||
       (rc = check_hip(hipStreamWaitEvent(caller, s.ev_out, 0), "ea_fit wait")))
     return rc;
+  return SBLM_OK;
+}
+
+extern "C" int ea_time_fitness(ea_state* st, int32_t enable, void* stream) {
+  if (!st) return set_error(SBLM_ESTATE, "ea_time_fitness: null state");
+  if (enable != 0 && enable != 1)
+    return set_error(SBLM_EINVAL, "ea_time_fitness: enable = %d", enable);
+  EaStateImpl& s = st->impl;
+  int rc;
+  if ((rc = check_hip(hipEventRecord(s.ev_in, (hipStream_t)stream), "ea_time_fitness event")) ||
+      (rc = check_hip(hipStreamWaitEvent(s.work, s.ev_in, 0), "ea_time_fitness wait")))
+    return rc;
+  hipLaunchKernelGGL(ticks_clear_kernel, dim3(1), dim3(64), 0, s.work, s.ticks);
+  if ((rc = check_hip(hipGetLastError(), "ea_time_fitness clear"))) return rc;
+  if ((rc = check_hip(hipEventRecord(s.ev_out, s.work), "ea_time_fitness event")) ||
+      (rc = check_hip(hipStreamWaitEvent((hipStream_t)stream, s.ev_out, 0),
+                      "ea_time_fitness wait")))
+    return rc;
+  if (s.time_fitness == enable && s.graph) return SBLM_OK;
+  s.time_fitness = enable;
+  return capture_graph(s, s.graph_stats);
+}
+
+extern "C" int ea_fitness_time(ea_state* st, double* ms, int64_t* launches) {
+  if (!st || !ms || !launches) return set_error(SBLM_EINVAL, "ea_fitness_time: null argument");
+  EaStateImpl& s = st->impl;
+  int rc;
+  unsigned long long t[4];
+  int khz = 0;
+  if ((rc = check_hip(hipStreamSynchronize(s.work), "ea_fitness_time sync")) ||
+      (rc = check_hip(hipMemcpy(t, s.ticks, sizeof(t), hipMemcpyDeviceToHost),
+                      "ea_fitness_time copy")) ||
+      (rc = check_hip(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s.device),
+                      "ea_fitness_time clock rate")))
+    return rc;
+  if (khz <= 0) return set_error(SBLM_EDEVICE, "ea_fitness_time: wall clock rate %d kHz", khz);
+  *ms = (double)t[0] / (double)khz;
+  *launches = (int64_t)t[2];
   return SBLM_OK;
 }
 

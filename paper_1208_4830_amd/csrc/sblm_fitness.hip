@@ -48,34 +48,17 @@
 #ifndef SBLM_ROOT_TAU
 #define SBLM_ROOT_TAU 1e-9
 #endif
+// The FP32 iteration of the precision form only has to bring the roots
+// within reach of two FP64 Newton steps (quadratic: an error e0 goes to
+// about e0^2/s, then e0^4/s^3): an estimated error of 1e-5 relative.
+#ifndef SBLM_ROOT_TAU32
+#define SBLM_ROOT_TAU32 1e-5f
+#endif
 
 namespace sblm {
 
-// ---------------------------------------------------------------- complex
-
-template <typename T>
-struct cx {
-  T re, im;
-};
-
-template <typename T>
-__device__ __forceinline__ cx<T> c_sub(cx<T> a, cx<T> b) {
-  return {a.re - b.re, a.im - b.im};
-}
-// a*b + c
-template <typename T>
-__device__ __forceinline__ cx<T> c_fma(cx<T> a, cx<T> b, cx<T> c) {
-  return {fma(a.re, b.re, fma(-a.im, b.im, c.re)),
-          fma(a.re, b.im, fma(a.im, b.re, c.im))};
-}
-template <typename T>
-__device__ __forceinline__ cx<T> c_mul(cx<T> a, cx<T> b) {
-  return {fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
-}
-template <typename T>
-__device__ __forceinline__ T c_norm(cx<T> a) {
-  return fma(a.re, a.re, a.im * a.im);
-}
+// The primitive operations the shared arithmetic (sblm_math.h) takes from
+// its number type, for FP64 and FP32 on the device.
 // Smaller / larger of two values, the non-NaN one if one is NaN (one v_min /
 // v_max where the operands are results of arithmetic, which the compiler knows
 // to be quiet).
@@ -83,91 +66,15 @@ __device__ __forceinline__ double vmin(double a, double b) { return fmin(a, b); 
 __device__ __forceinline__ float vmin(float a, float b) { return fminf(a, b); }
 __device__ __forceinline__ double vmax(double a, double b) { return fmax(a, b); }
 __device__ __forceinline__ float vmax(float a, float b) { return fmaxf(a, b); }
+// Hardware reciprocal estimate (relative error < 5e-8 in FP64).
+__device__ __forceinline__ double rcp_hw(double x) { return __builtin_amdgcn_rcp(x); }
+__device__ __forceinline__ float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Approximate reciprocal for iteration steps (the fixed point of the
-// iteration does not depend on its accuracy).
-__device__ __forceinline__ double rcp_fast(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  return fma(r, fma(-x, r, 1.0), r);
-}
-__device__ __forceinline__ float rcp_fast(float x) {
-  return __builtin_amdgcn_rcpf(x);
-}
-// Raw hardware reciprocal (relative error < 5e-8 in FP64): used only for the
-// pairwise terms of the Aberth correction, whose error scales the size of a
-// correction that is itself second order.
-__device__ __forceinline__ double rcp_raw(double x) { return __builtin_amdgcn_rcp(x); }
-__device__ __forceinline__ float rcp_raw(float x) { return __builtin_amdgcn_rcpf(x); }
-// Reciprocal to about 1 ulp, for det J, image positions and the fit.
-__device__ __forceinline__ double rcp_acc(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return fma(r, fma(-x, r, 1.0), r);
-}
+}  // namespace sblm
 
-// ---------------------------------------------------------------- polynomial
+#include "sblm_math.h"
 
-// Coefficients c[0..5] of the lens polynomial for source zeta, separation d,
-// mass ratio q.  From Eq. (lensing): conj(z) = N(z)/D(z) with
-// N = w z^2 + (1+q-dw) z - d, D = z^2 - d z, w = conj(zeta); substituting
-// back and clearing denominators gives (zeta - z) N M + M D + q N D = 0 with
-// M = N - d D = (w-d) z^2 + (1+q+d^2-dw) z - d.  Expanded here by hand.
-__device__ __forceinline__ void lens_coeffs(cx<double> zeta, double d, double q,
-                                            cx<double> c[6]) {
-  const cx<double> w = {zeta.re, -zeta.im};
-  const double opq = 1.0 + q;
-  const cx<double> n2 = w;
-  const cx<double> n1 = {fma(-d, w.re, opq), -d * w.im};
-  const cx<double> m2 = {w.re - d, w.im};
-  const cx<double> m1 = {fma(-d, w.re, fma(d, d, opq)), -d * w.im};
-  const double dd = d * d;
-  // products of N and M, by power of z (n0 = m0 = -d)
-  const cx<double> nm4 = c_mul(n2, m2);
-  const cx<double> nm3 = c_fma(n2, m1, c_mul(n1, m2));
-  const cx<double> s2 = {n2.re + m2.re, n2.im + m2.im};
-  const cx<double> nm2 = c_fma(n1, m1, cx<double>{-d * s2.re, -d * s2.im});
-  const cx<double> nm1 = {-d * (n1.re + m1.re), -d * (n1.im + m1.im)};
-  // (zeta - z) N M + M D + q N D
-  c[5] = {-nm4.re, -nm4.im};
-  // z^4: zeta nm4 - nm3 + m2 + q n2
-  c[4] = c_fma(zeta, nm4,
-               cx<double>{m2.re + fma(q, n2.re, -nm3.re),
-                          m2.im + fma(q, n2.im, -nm3.im)});
-  // z^3: zeta nm3 - nm2 + (m1 - d m2) + q (n1 - d n2)
-  c[3] = c_fma(zeta, nm3,
-               cx<double>{fma(-d, m2.re, m1.re) +
-                              fma(q, fma(-d, n2.re, n1.re), -nm2.re),
-                          fma(-d, m2.im, m1.im) +
-                              fma(q, fma(-d, n2.im, n1.im), -nm2.im)});
-  // z^2: zeta nm2 - nm1 + (m0 - d m1) + q (n0 - d n1)
-  c[2] = c_fma(zeta, nm2,
-               cx<double>{fma(-d, m1.re, -d) + fma(q, fma(-d, n1.re, -d), -nm1.re),
-                          fma(-d, m1.im, 0.0) + fma(q, -d * n1.im, -nm1.im)});
-  // z^1: zeta nm1 - nm0 - d m0 - q d n0 = zeta nm1 + q d^2
-  c[1] = c_fma(zeta, nm1, cx<double>{q * dd, 0.0});
-  // z^0: zeta nm0 = zeta d^2
-  c[0] = {zeta.re * dd, zeta.im * dd};
-}
-
-// p(z) and p'(z) by Horner's rule.
-template <typename T>
-__device__ __forceinline__ void horner(const cx<T> c[6], cx<T> z, cx<T>& p,
-                                       cx<T>& dp) {
-  dp = c[5];
-  p = c_fma(c[5], z, c[4]);
-#pragma unroll
-  for (int j = 3; j >= 0; --j) {
-    dp = c_fma(dp, z, p);
-    p = c_fma(p, z, c[j]);
-  }
-}
-
-// A source very close to a lens (within ~1e-3 theta_E of either) gives a
-// small leading coefficient: one root -- always spurious -- lies far out, at
-// about -c4/c5, the others near the lenses.  |c4| > 1e3 |c5| marks it.
-__device__ __forceinline__ bool far_root(const cx<double> c[6]) {
-  return c_norm(c[4]) > 1e6 * c_norm(c[5]);
-}
+namespace sblm {
 
 // Starting points for a cold solve: five points on a circle about the root
 // centroid -c4/(5 c5) of radius (|c0|/|c5|)^(1/5) (geometric mean of the
@@ -215,115 +122,10 @@ __device__ __forceinline__ void cold_start(const cx<T> c[6], bool deg4,
   }
 }
 
-// One Ehrlich-Aberth sweep (Jacobi form) over the five roots:
-//   S_i = sum_{j != i} 1/(z_i - z_j),
-//   z_i <- z_i - p(z_i) / (p'(z_i) - p(z_i) S_i),
-// (the usual w/(1 - w S) with w = p/p', written with one complex division).
-// The iteration converges cubically: after a step of length e the error
-// left in z_i is about e^3 / s_i^2, s_i the distance to the nearest other
-// root.  Returns 1 when, for every root, e^3 / (s_i^2 max(1,|z_i|)) <= tau or
-// e <= 1e-13 max(1,|z_i|) (a step at the rounding level, which also ends the
-// slow approach of a double root).  *emax receives max_i e_i^2 / max(1,|z_i|^2).
-template <typename T>
-__device__ __forceinline__ bool aberth_sweep(const cx<T> c[6], cx<T> z[5],
-                                             bool deg4, T tau, T* emax) {
-  // pairwise terms from the current roots first, so that each root's p, p'
-  // is used as soon as it is computed (fewer live registers)
-  cx<T> S[5];
-  T dmin[5];  // (distance to the nearest other root)^2
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    S[i] = {(T)0, (T)0};
-    dmin[i] = (T)INFINITY;
-  }
-#pragma unroll
-  for (int i = 0; i < 5; ++i)
-#pragma unroll
-    for (int j = i + 1; j < 5; ++j) {
-      const cx<T> dz = c_sub(z[i], z[j]);
-      const T n = c_norm(dz);
-      const T r = rcp_raw(n);
-      const T ire = dz.re * r, iim = -dz.im * r;  // 1/(z_i - z_j)
-      S[i].re += ire;
-      S[i].im += iim;
-      S[j].re -= ire;
-      S[j].im -= iim;
-      dmin[i] = vmin(n, dmin[i]);
-      dmin[j] = vmin(n, dmin[j]);
-    }
-  bool conv = true;
-  T em = (T)0;
-  const T tau2 = tau * tau;
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    cx<T> p, dp;
-    horner(c, z[i], p, dp);
-    // den = p' - p S ; dz = p / den
-    const cx<T> pS = c_mul(p, S[i]);
-    const cx<T> den = c_sub(dp, pS);
-    const T r = rcp_fast(c_norm(den));
-    cx<T> dz = {fma(p.re, den.re, p.im * den.im) * r, fma(p.im, den.re, -p.re * den.im) * r};
-    if (i == 4 && deg4) dz = {(T)0, (T)0};
-    z[i] = c_sub(z[i], dz);
-    const T zn = c_norm(z[i]);
-    const T sc = vmax(zn, (T)1);
-    const T e2 = c_norm(dz);
-    // (e^2)^3 <= tau^2 |z|^2 (s^2)^2, or e^2 <= 1e-26 |z|^2
-    const bool ok = (e2 * e2 * e2 <= tau2 * sc * (dmin[i] * dmin[i])) ||
-                    (e2 <= (T)1e-26 * sc);
-    conv = conv && (ok || (i == 4 && deg4));
-    const T er = e2 / sc;
-    em = vmax(er, em);
-  }
-  *emax = em;
-  return conv;
-}
-
-// ---------------------------------------------------------------- images
-
-#define SBLM_IMAGE_TOL2 1e-12 /* residual threshold 1e-6, squared */
-#define SBLM_POLISH_DETJ 0.01 /* images with |det J| below this are refined */
-#define SBLM_POLISH_EST2 1e-24 /* ... and those whose residual could move A by
-                                  more than 1e-12 relative (squared) */
-
-// Lens-equation quantities at a trial image z: the residual
-// r = zeta - z + 1/conj(z) - q/(d - conj(z)) of Eq. (lensing) and
-// g = dzeta/dconj(z) = 1/conj(z)^2 + q/(d - conj(z))^2; returns |r|^2.
-// *iz2, *ie2 receive |1/z|^2 and |1/(d - z)|^2.
-__device__ __forceinline__ double image_eval(cx<double> z, cx<double> zeta, double d,
-                                             double q, cx<double>& res, cx<double>& g,
-                                             double* iz2, double* ie2) {
-  const double x = z.re, y = z.im;
-  // a = 1/conj(z) = z / |z|^2 ; b = 1/(d - conj(z))
-  // one reciprocal for both: 1/|z|^2 = |d-z|^2 / P, 1/|d-z|^2 = |z|^2 / P with
-  // P = |z|^2 |d-z|^2 (within range: |z| stays far from the FP64 limits)
-  const double n2 = fma(x, x, y * y);
-  const double ex = d - x;
-  const double e2 = fma(ex, ex, y * y);
-  const double ip = rcp_acc(n2 * e2);
-  const double iz = e2 * ip;
-  const cx<double> a = {x * iz, y * iz};
-  const double ie = n2 * ip;
-  const cx<double> b = {ex * ie, -y * ie};
-  res = {fma(-q, b.re, (zeta.re - x) + a.re), fma(-q, b.im, (zeta.im - y) + a.im)};
-  const cx<double> b2 = c_mul(b, b);
-  g = c_fma(a, a, cx<double>{q * b2.re, q * b2.im});
-  *iz2 = iz;
-  *ie2 = ie;
-  return c_norm(res);
-}
-
 // Images, det J and the magnification from five FP64 roots.  The image
-// count and the choice of images use the roots' residuals.  An accepted
-// image is then refined by up to two Newton steps on the lens equation
-// itself, dz = (r - g conj(r))/(1 - |g|^2), each kept only if it lowers the
-// residual, when it lies very close to a critical curve (|det J| < 0.01) or
-// when its residual r could move A by more than 1e-12 relative: the image moves
-// by about (1 + |g|) |r| / |det J|, det J by 2 |g| |h| times that
-// (h = dg/dconj(z), |h| <= 2|1/z|^3 + 2q|1/(d-z)|^3) and A_i by A_i^2 times
-// that, with A >= 1.  There the quintic's roots lose accuracy (near-coincident
-// roots next to a caustic, or the root cluster around the secondary lens at
-// small q) while the lens equation does not.
+// count and the choice of images use the roots' residuals (image_score); an
+// accepted image that needs it is refined on the lens equation
+// (refine_image).
 __device__ __forceinline__ double magnification(const cx<double> z[5],
                                                 cx<double> zeta, double d,
                                                 double q, bool deg4,
@@ -331,19 +133,7 @@ __device__ __forceinline__ double magnification(const cx<double> z[5],
   double r2[5], adet[5];
   bool refine[5];
 #pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    cx<double> res, g;
-    double iz2, ie2;
-    r2[i] = image_eval(z[i], zeta, d, q, res, g, &iz2, &ie2);
-    const double gn = c_norm(g);
-    adet[i] = fabs(1.0 - gn);
-    // (dA/A)^2 <= 64 |g|^2 (1 + |g|^2) (|1/z|^6 + q^2 |1/(d-z)|^6) |r|^2 / |det J|^6;
-    // refine when that exceeds SBLM_POLISH_EST2 (compared without dividing)
-    const double a3 = adet[i] * adet[i] * adet[i];
-    const double num =
-        64.0 * gn * (1.0 + gn) * fma(q * q * ie2, ie2 * ie2, iz2 * iz2 * iz2) * r2[i];
-    refine[i] = !(num <= SBLM_POLISH_EST2 * (a3 * a3)) || adet[i] < SBLM_POLISH_DETJ;
-  }
+  for (int i = 0; i < 5; ++i) refine[i] = image_score(z[i], zeta, d, q, &r2[i], &adet[i]);
   if (deg4) r2[4] = INFINITY;
   int below = 0;
 #pragma unroll
@@ -374,29 +164,8 @@ __device__ __forceinline__ double magnification(const cx<double> z[5],
 #pragma unroll
       for (int k = 1; k < 5; ++k)
         if (i == k) zi = z[k];
-      cx<double> res, g;
-      double iz2, ie2;
-      double rn = image_eval(zi, zeta, d, q, res, g, &iz2, &ie2);
       ++npolish;
-      for (int step = 0; step < 2; ++step) {
-        const double det = 1.0 - c_norm(g);
-        const double idet = rcp_acc(det);
-        // dz = (r - g conj(r)) / det
-        const cx<double> gr = c_mul(g, cx<double>{res.re, -res.im});
-        const cx<double> dz = {(res.re - gr.re) * idet, (res.im - gr.im) * idet};
-        const cx<double> zn = {zi.re + dz.re, zi.im + dz.im};
-        cx<double> resn, gn2;
-        const double rnn = image_eval(zn, zeta, d, q, resn, gn2, &iz2, &ie2);
-        if (!(rnn < rn)) break;
-        zi = zn;
-        res = resn;
-        g = gn2;
-        rn = rnn;
-        // Newton converges quadratically: after a step of 1e-10 |z| the next
-        // one would be at the rounding level
-        if (c_norm(dz) <= 1e-20 * c_norm(zi)) break;
-      }
-      A += rcp_acc(fabs(1.0 - c_norm(g)));
+      A += refine_image(zi, zeta, d, q);
     }
   }
   nimg = five ? 5 : 3;
@@ -405,45 +174,7 @@ __device__ __forceinline__ double magnification(const cx<double> z[5],
 
 // ---------------------------------------------------------------- fit
 
-// Square-root-free Givens state for columns (1, A | y): D = diag(d1, d2),
-// unit upper-triangular factor with off-diagonal r12, transformed right-hand
-// side (t1, t2) and the accumulated weighted residual sum of squares.
-struct Lsq {
-  double d1, d2, r12, t1, t2, sse;
-};
-
-// Include the row (x1, x2 | y) with weight w (Gentleman's algorithm).
-__device__ __forceinline__ void lsq_include(Lsq& s, double w, double x1,
-                                            double x2, double y) {
-  if (w == 0.0) return;
-  if (x1 != 0.0) {
-    const double wx = w * x1;
-    const double dp = fma(wx, x1, s.d1);
-    const double r = rcp_acc(dp);
-    const double cb = s.d1 * r, sb = wx * r;
-    w = cb * w;
-    s.d1 = dp;
-    const double xk = x2;
-    x2 = fma(-x1, s.r12, xk);
-    s.r12 = fma(cb, s.r12, sb * xk);
-    const double yk = y;
-    y = fma(-x1, s.t1, yk);
-    s.t1 = fma(cb, s.t1, sb * yk);
-  }
-  if (w == 0.0) return;
-  if (x2 != 0.0) {
-    const double wx = w * x2;
-    const double dp = fma(wx, x2, s.d2);
-    const double r = rcp_acc(dp);
-    const double cb = s.d2 * r, sb = wx * r;
-    w = cb * w;
-    s.d2 = dp;
-    const double yk = y;
-    y = fma(-x2, s.t2, yk);
-    s.t2 = fma(cb, s.t2, sb * yk);
-  }
-  s.sse = fma(w * y, y, s.sse);
-}
+using Lsq = LsqT<double>;
 
 // ---------------------------------------------------------------- kernel
 
@@ -452,9 +183,11 @@ __device__ __forceinline__ double grp_shfl_down(double v, int off) {
   return __shfl_down(v, off, G);
 }
 
+// Per-lane counters (32 bits: a lane's share of one launch stays far below
+// 2^32 events), summed over the wave and added to sblm_stats at the end.
 struct LaneStats {
-  unsigned long long solves, iters, capped, fallback, deg4, wave_iters, iters32, polished,
-      retried, unsettled;
+  unsigned int solves, iters, capped, fallback, deg4, wave_iters, iters32, polished, retried,
+      unsettled, newton;
 };
 
 // A solve that reaches the iteration cap has settled when its roots are
@@ -469,8 +202,8 @@ struct LaneStats {
 // Solve one polynomial from the roots in z (warm) or from a cold start;
 // ok = converged to finite roots; settled = ok, or capped with finite roots
 // that no longer move (see SBLM_SETTLED_STEP2).  `retry` marks a second,
-// cold attempt at an epoch whose warm-started solve failed (it is not
-// counted as another solve).
+// cold attempt at an epoch whose warm-started solve failed (not counted as
+// another solve).
 template <int MODE>
 __device__ __forceinline__ void solve_roots(const cx<double> c[6], bool deg4,
                                             bool warm, bool active,
@@ -479,50 +212,85 @@ __device__ __forceinline__ void solve_roots(const cx<double> c[6], bool deg4,
   constexpr int MAXIT64 = 60, MAXIT32 = 30;
   // estimated relative error left after the last step
   const double tau64 = SBLM_ROOT_TAU;
-  const float tau32 = 1e-7f;
+  const float tau32 = SBLM_ROOT_TAU32;
   const bool far = !deg4 && far_root(c);
   if (!warm && active) cold_start<double>(c, deg4, z, far);
-  int it_lane = 0, it32_lane = 0, it_wave = 0;
-  bool done = !active;
+  unsigned int it_lane = 0, it32_lane = 0, it_wave = 0, newton_lane = 0;
+  bool done = !active, fell_back = false;
   if (MODE == SBLM_MIXED) {
+    // The precision form: the root iteration in FP32 to a loose tolerance,
+    // then at most two FP64 Newton steps on every root, the image test, det J
+    // and the fit in FP64.  A polish that has not converged after two steps
+    // falls back to FP64 Aberth sweeps from the polished roots (counted).
+    // A warm start (the previous epochs' roots, extrapolated) is already as
+    // close as FP32 can resolve and goes straight to the polish; degree-4
+    // polynomials (parked root out of FP32 range) and those with a far root
+    // (its powers overflow FP32) straight to FP64 sweeps.  The FP32
+    // iteration ends at its own convergence test, or, after its first few
+    // sweeps (the global phase, where steps need not shrink), when its steps
+    // stop shrinking (the FP32 rounding floor next to clustered roots).
+    const bool use32 = !deg4 && !far;
     cx<float> cf[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) cf[j] = {(float)c[j].re, (float)c[j].im};
     cx<float> zf[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) zf[i] = {(float)z[i].re, (float)z[i].im};
-    // The FP32 phase runs the solves that start cold (the long part of the
-    // iteration); a warm start is already closer to the roots than FP32 can
-    // resolve, so those solves, degree-4 polynomials (parked root out of
-    // FP32 range) and those with a far root (its powers overflow FP32) go
-    // straight to FP64.  The FP32 phase also ends when its
-    // steps stop shrinking: the roots are then at the FP32 rounding floor.
-    bool done32 = done || deg4 || warm || far;
+    bool done32 = done || !use32 || warm;
     float prev = INFINITY;
     for (int it = 0; it < MAXIT32; ++it) {
       if (__all(done32)) break;
       ++it_wave;
       if (!done32) {
         float em;
-        done32 = aberth_sweep<float>(cf, zf, false, tau32, &em);
-        done32 = done32 || (em > 0.25f * prev);  // |dz| shrank by < 2x
+        done32 = aberth_sweep<true>(cf, zf, false, tau32, &em);
+        done32 = done32 || (it >= 4 && em > 0.25f * prev);  // shrank by < 2x
         prev = em;
         ++it32_lane;
       }
     }
-    if (active && !deg4) {
+    const bool polish = active && use32;
+    if (polish && !warm) {
 #pragma unroll
       for (int i = 0; i < 5; ++i) z[i] = {(double)zf[i].re, (double)zf[i].im};
     }
+    double d2[5];
+    nearest2(z, d2);
+    bool pol_done = !polish;
+    for (int k = 0; k < 2; ++k) {
+      if (__all(pol_done)) break;
+      ++it_wave;
+      if (!pol_done) {
+        pol_done = newton_pass(c, z, d2, tau64);
+        ++newton_lane;
+      }
+    }
+    if (polish) {
+      // Newton steps that drew two roots together (a root taken over by its
+      // neighbour's basin) leave the distinct FP32 roots behind: start the
+      // FP64 iteration afresh
+      double d2n[5];
+      nearest2(z, d2n);
+      bool apart = true;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) apart = apart && (d2n[i] >= 0.25 * d2[i]);
+      if (!apart) cold_start<double>(c, deg4, z, far);
+      done = pol_done && apart;
+      fell_back = !done;
+    }
   }
-  double em_last = INFINITY;
   for (int it = 0; it < MAXIT64; ++it) {
     if (__all(done)) break;
     ++it_wave;
     if (!done) {
-      done = aberth_sweep<double>(c, z, deg4, tau64, &em_last);
+      done = aberth_sweep<false>(c, z, deg4, tau64, (double*)nullptr);
       ++it_lane;
     }
+  }
+  // a capped solve: one more sweep measures how far its roots still move
+  double em_last = 0.0;
+  if (__any(active && !done)) {
+    if (active && !done) (void)aberth_sweep<true>(c, z, deg4, tau64, &em_last);
   }
   bool finite = true;
 #pragma unroll
@@ -534,11 +302,39 @@ __device__ __forceinline__ void solve_roots(const cx<double> c[6], bool deg4,
     st.solves += retry ? 0 : 1;
     st.iters += it_lane + it32_lane;
     st.deg4 += (deg4 && !retry) ? 1 : 0;
-    // MIXED: a cold solve whose FP32 result needed more than two FP64 sweeps
-    if (MODE == SBLM_MIXED) st.fallback += (!warm && it_lane > 2) ? 1 : 0;
+    // MIXED: a polish that needed the FP64 iteration after its two steps
+    if (MODE == SBLM_MIXED) st.fallback += fell_back ? 1 : 0;
     st.wave_iters += it_wave;
     st.iters32 += it32_lane;
+    st.newton += newton_lane;
   }
+}
+
+// The cold second attempt at an epoch whose warm-started solve failed (a
+// warm start from the roots of another epoch or, in the simplex rounds, of
+// another point), called by the whole wave when any lane needs it; lanes
+// with active = 0 only follow along.  Kept out of line: a second inlined
+// copy of the iteration would cost the hot path registers.  Coefficients,
+// roots (in and out) and the lane's counters travel through memory.
+template <int MODE>
+__device__ __noinline__ void cold_retry(const double* cr, double* zr, int deg4, int active,
+                                        unsigned int* counts) {
+  cx<double> c[6], z[5];
+  for (int j = 0; j < 6; ++j) c[j] = {cr[2 * j], cr[2 * j + 1]};
+  for (int i = 0; i < 5; ++i) z[i] = {zr[2 * i], zr[2 * i + 1]};
+  LaneStats st = {};
+  bool ok, settled;
+  solve_roots<MODE>(c, deg4 != 0, false, active != 0, z, st, ok, settled, true);
+  for (int i = 0; i < 5; ++i) {
+    zr[2 * i] = z[i].re;
+    zr[2 * i + 1] = z[i].im;
+  }
+  counts[0] = st.iters;
+  counts[1] = st.wave_iters;
+  counts[2] = st.iters32;
+  counts[3] = st.newton;
+  counts[4] = st.fallback;
+  counts[5] = (ok ? 1u : 0u) | (settled ? 2u : 0u);
 }
 
 #ifndef SBLM_MIN_WAVES_PER_EU
@@ -607,15 +403,9 @@ __device__ __forceinline__ Item item_setup(const FitArgs& a, int64_t wave_item) 
 // Source position (Eq. sourcePos) and lens polynomial at epoch t.
 __device__ __forceinline__ bool epoch_poly(const Item& x, double t, cx<double>& zeta,
                                            cx<double> c[6]) {
-  const double tau = (t - x.t0) * x.itE;
-  zeta = {fma(tau, x.sa, x.u0 * x.ca), fma(-tau, x.ca, x.u0 * x.sa)};
+  zeta = source_position(t, x.t0, x.itE, x.sa, x.ca, x.u0);
   lens_coeffs(zeta, x.d, x.q, c);
-  double cmax = 0.0;
-#pragma unroll
-  for (int j = 0; j < 6; ++j) cmax = fmax(cmax, c_norm(c[j]));
-  const bool deg4 = c_norm(c[5]) <= 1e-24 * cmax;
-  if (deg4) c[5] = {0.0, 0.0};
-  return deg4;
+  return drop_to_degree4(c);
 }
 
 // Per-lane history of the roots of the two epochs before the current one,
@@ -789,25 +579,12 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
     // else linear from two, scaled by the ratio of epoch spacings (clamped to
     // [0, 4]); the history shifts as it is used.
     {
-      const bool ex2 = warm && have_prev2;
-      const double d12 = t1 - t2, d23 = t2 - t3, d13 = t1 - t3;
-      double w1 = 1.0, w2 = 0.0, w3 = 0.0;
-      if (ex2 && have_prev3 && d12 > 0.0 && d23 > 0.0 && (t - t1) <= d13) {
-        const double a1 = t - t1, a2 = t - t2, a3 = t - t3;
-        const double r = rcp_fast(d12 * d13 * d23);
-        w1 = a2 * a3 * (d23 * r);
-        w2 = -a1 * a3 * (d13 * r);
-        w3 = a1 * a2 * (d12 * r);
-      } else if (ex2 && d12 != 0.0) {
-        const double r = fmin(fmax((t - t1) / d12, 0.0), 4.0);
-        w1 = 1.0 + r;
-        w2 = -r;
-      }
+      double w1, w2, w3;
+      warm_weights(t, t1, t2, t3, warm && have_prev2, have_prev3, w1, w2, w3);
 #pragma unroll
       for (int i = 0; i < 5; ++i) {
         const cx<double> old = z[i], zp = hp[i], zpp = hpp[i];
-        z[i] = {fma(w1, old.re, fma(w2, zp.re, w3 * zpp.re)),
-                fma(w1, old.im, fma(w2, zp.im, w3 * zpp.im))};
+        z[i] = extrapolate(old, zp, zpp, w1, w2, w3);
         hist.set(1, i, zp);
         hist.set(0, i, old);
       }
@@ -815,19 +592,36 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
     bool ok, settled;
     solve_roots<MODE>(c, deg4, warm, active, z, st, ok, settled);
     {
-      // a warm start that did not converge (it came from roots of another
-      // epoch or, in the simplex rounds, of another point): solve again from
-      // the cold start; roots that still have not settled poison the result
-      // (A and with it chi^2 become NaN, which ranks last)
-      const bool retry = active && !ok && warm;
-      if (__any(retry)) {
-        bool ok2, settled2;
-        solve_roots<MODE>(c, deg4, false, retry, z, st, ok2, settled2, true);
-        if (retry) {
-          ok = ok2;
-          settled = settled2;
+      // a warm start that did not converge: solve again from the cold
+      // start; roots that still have not settled poison the result (A and
+      // with it chi^2 become NaN, which ranks last)
+      const bool again = active && !ok && warm;
+      if (__any(again)) {
+        double cr[12], zr[10];
+        unsigned int cnt[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+          cr[2 * j] = c[j].re;
+          cr[2 * j + 1] = c[j].im;
+        }
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          zr[2 * i] = z[i].re;
+          zr[2 * i + 1] = z[i].im;
+        }
+        cold_retry<MODE>(cr, zr, deg4 ? 1 : 0, again ? 1 : 0, cnt);
+        if (again) {
+#pragma unroll
+          for (int i = 0; i < 5; ++i) z[i] = {zr[2 * i], zr[2 * i + 1]};
+          ok = (cnt[5] & 1u) != 0;
+          settled = (cnt[5] & 2u) != 0;
+          st.iters += cnt[0];
+          st.iters32 += cnt[2];
+          st.newton += cnt[3];
+          st.fallback += cnt[4];
           st.retried += 1;
         }
+        st.wave_iters += active ? cnt[1] : 0;
       }
       if (active && !ok) st.capped += 1;
       if (active && !settled) st.unsettled += 1;
@@ -882,7 +676,7 @@ __device__ __forceinline__ void fit_wave_async(const FitArgs& a, int64_t wave_it
                                                LaneStats& st) {
   constexpr int MAXIT64 = 60, MAXIT32 = 30;
   const double tau64 = SBLM_ROOT_TAU;
-  const float tau32 = 1e-7f;
+  const float tau32 = SBLM_ROOT_TAU32;
   const Item x = item_setup<G>(a, wave_item);
   Lsq ls = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   cx<double> z[5];  // iterate; the roots of the two epochs before are in LDS
@@ -901,9 +695,15 @@ __device__ __forceinline__ void fit_wave_async(const FitArgs& a, int64_t wave_it
   cx<double> zeta = {0.0, 0.0}, c[6];
 #pragma unroll
   for (int j = 0; j < 6; ++j) c[j] = {0.0, 0.0};
-  bool deg4 = false, in32 = false, warm = false;
+  // phase of the current solve: 0 FP32 iteration, 1 FP64 Newton polish
+  // (MIXED), 2 FP64 iteration
+  bool deg4 = false, warm = false, fell_back = false;
+  int phase = 2;
   double t = 0.0;
-  int it64 = 0, it32 = 0, it_prior = 0;
+  int it64 = 0, it32 = 0, it_prior = 0, nw = 0;
+  double d2[5];  // squared nearest-root distances at the start of the polish
+#pragma unroll
+  for (int i = 0; i < 5; ++i) d2[i] = 0.0;
   bool retried = false;
   double em64 = INFINITY;
   float prev32 = INFINITY;
@@ -917,24 +717,12 @@ __device__ __forceinline__ void fit_wave_async(const FitArgs& a, int64_t wave_it
         warm = nhist >= 1 && !deg4 && !prev_deg4;
         if (warm) {
           // weights of z (epoch t1), zp (t2), zpp (t3)
-          double w1 = 1.0, w2 = 0.0, w3 = 0.0;
-          const double d12 = t1 - t2, d13 = t1 - t3, d23 = t2 - t3;
-          if (nhist >= 3 && d12 > 0.0 && d23 > 0.0 && (t - t1) <= d13) {
-            const double a1 = t - t1, a2 = t - t2, a3 = t - t3;
-            const double r = rcp_fast(d12 * d13 * d23);
-            w1 = a2 * a3 * (d23 * r);
-            w2 = -a1 * a3 * (d13 * r);
-            w3 = a1 * a2 * (d12 * r);
-          } else if (nhist >= 2 && d12 > 0.0) {
-            const double r = fmin(fmax((t - t1) * rcp_fast(d12), 0.0), 4.0);
-            w1 = 1.0 + r;
-            w2 = -r;
-          }
+          double w1, w2, w3;
+          warm_weights(t, t1, t2, t3, nhist >= 2, nhist >= 3, w1, w2, w3);
 #pragma unroll
           for (int i = 0; i < 5; ++i) {
             const cx<double> zp = hist.get(0, i), zpp = hist.get(1, i);
-            const cx<double> p = {fma(w1, z[i].re, fma(w2, zp.re, w3 * zpp.re)),
-                                  fma(w1, z[i].im, fma(w2, zp.im, w3 * zpp.im))};
+            const cx<double> p = extrapolate(z[i], zp, zpp, w1, w2, w3);
             hist.set(1, i, zp);
             hist.set(0, i, z[i]);
             z[i] = p;
@@ -944,9 +732,12 @@ __device__ __forceinline__ void fit_wave_async(const FitArgs& a, int64_t wave_it
         } else {
           cold_start<double>(c, deg4, z, !deg4 && far_root(c));
         }
-        in32 = (MODE == SBLM_MIXED) && !warm && !deg4 && !far_root(c);
+        phase = (MODE == SBLM_MIXED) && !deg4 && !far_root(c) ? (warm ? 1 : 0) : 2;
+        if (phase == 1) nearest2(z, d2);
         it64 = 0;
         it32 = 0;
+        nw = 0;
+        fell_back = false;
         it_prior = 0;
         retried = false;
         em64 = INFINITY;
@@ -954,7 +745,7 @@ __device__ __forceinline__ void fit_wave_async(const FitArgs& a, int64_t wave_it
         need_setup = false;
       }
       bool finished = false, conv = false;
-      if (MODE == SBLM_MIXED && in32) {
+      if (MODE == SBLM_MIXED && phase == 0) {
         // FP32 sweep on the rounded iterate (exactly representable back in FP64)
         cx<float> cf[6], zf[5];
 #pragma unroll
@@ -962,17 +753,41 @@ __device__ __forceinline__ void fit_wave_async(const FitArgs& a, int64_t wave_it
 #pragma unroll
         for (int i = 0; i < 5; ++i) zf[i] = {(float)z[i].re, (float)z[i].im};
         float em;
-        bool d32 = aberth_sweep<float>(cf, zf, false, tau32, &em);
-        d32 = d32 || (em > 0.25f * prev32);
+        bool d32 = aberth_sweep<true>(cf, zf, false, tau32, &em);
+        d32 = d32 || (it32 >= 4 && em > 0.25f * prev32);
         prev32 = em;
 #pragma unroll
         for (int i = 0; i < 5; ++i) z[i] = {(double)zf[i].re, (double)zf[i].im};
         ++it32;
-        if (d32 || it32 >= MAXIT32) in32 = false;
+        if (d32 || it32 >= MAXIT32) {
+          phase = 1;
+          nearest2(z, d2);
+        }
+      } else if (MODE == SBLM_MIXED && phase == 1) {
+        // at most two FP64 Newton steps on every root (see solve_roots)
+        const bool pol = newton_pass(c, z, d2, tau64);
+        ++nw;
+        if (pol || nw >= 2) {
+          double d2n[5];
+          nearest2(z, d2n);
+          bool apart = true;
+#pragma unroll
+          for (int i = 0; i < 5; ++i) apart = apart && (d2n[i] >= 0.25 * d2[i]);
+          if (!apart) cold_start<double>(c, deg4, z, false);
+          if (pol && apart) {
+            conv = true;
+            finished = true;
+          } else {
+            phase = 2;
+            fell_back = true;
+          }
+        }
       } else {
-        conv = aberth_sweep<double>(c, z, deg4, tau64, &em64);
+        conv = aberth_sweep<false>(c, z, deg4, tau64, (double*)nullptr);
         ++it64;
         finished = conv || it64 >= MAXIT64;
+        // a capped solve: one more sweep measures how far its roots still move
+        if (finished && !conv) (void)aberth_sweep<true>(c, z, deg4, tau64, &em64);
       }
       bool finite = true;
       if (finished) {
@@ -985,11 +800,14 @@ __device__ __forceinline__ void fit_wave_async(const FitArgs& a, int64_t wave_it
           cold_start<double>(c, deg4, z, !deg4 && far_root(c));
           warm = false;
           retried = true;
-          in32 = (MODE == SBLM_MIXED) && !deg4 && !far_root(c);
+          phase = (MODE == SBLM_MIXED) && !deg4 && !far_root(c) ? 0 : 2;
           it_prior += it64 + it32;
           st.iters32 += it32;
+          st.newton += nw;
           it64 = 0;
           it32 = 0;
+          nw = 0;
+          fell_back = false;
           em64 = INFINITY;
           prev32 = INFINITY;
           st.retried += 1;
@@ -1019,7 +837,10 @@ __device__ __forceinline__ void fit_wave_async(const FitArgs& a, int64_t wave_it
         st.unsettled += settled ? 0 : 1;
         st.deg4 += deg4 ? 1 : 0;
         st.polished += npol;
-        if (MODE == SBLM_MIXED) st.fallback += (!warm && it64 > 2) ? 1 : 0;
+        if (MODE == SBLM_MIXED) {
+          st.fallback += fell_back ? 1 : 0;
+          st.newton += nw;
+        }
         // z now holds the roots of epoch t
         nhist = ok ? (warm ? (nhist < 3 ? nhist + 1 : 3) : 1) : 0;
         t1 = t;
@@ -1044,7 +865,7 @@ __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitn
   // (blocks of at most 256 threads: launch_gg refuses larger ones)
   constexpr int GPW = G > 64 ? 1 : 64 / G;  // individuals per wave
   const int lane = threadIdx.x & 63;
-  LaneStats st = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  LaneStats st = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   // One-shot grid: wave w takes wave item w (blocks remapped so that
   // consecutive logical blocks sit on one XCD).  Persistent grid: waves take
   // items from a shared counter until it runs past the last one, so every
@@ -1097,30 +918,24 @@ __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitn
       fit_wave<MODE, CHI2, G>(a, wi, st);
   }
   if (a.stats) {
+    // wave sums in 64 bits
+    unsigned long long v[11] = {st.solves,  st.iters,     st.capped,   st.fallback,
+                                st.deg4,    st.wave_iters, st.iters32, st.polished,
+                                st.retried, st.unsettled, st.newton};
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      st.solves += __shfl_down(st.solves, off, 64);
-      st.iters += __shfl_down(st.iters, off, 64);
-      st.capped += __shfl_down(st.capped, off, 64);
-      st.fallback += __shfl_down(st.fallback, off, 64);
-      st.deg4 += __shfl_down(st.deg4, off, 64);
-      st.wave_iters += __shfl_down(st.wave_iters, off, 64);
-      st.iters32 += __shfl_down(st.iters32, off, 64);
-      st.polished += __shfl_down(st.polished, off, 64);
-      st.retried += __shfl_down(st.retried, off, 64);
-      st.unsettled += __shfl_down(st.unsettled, off, 64);
-    }
-    if (lane == 0 && st.solves) {
-      atomicAdd(&a.stats->n_solves, st.solves);
-      atomicAdd(&a.stats->n_iter, st.iters);
-      if (st.capped) atomicAdd(&a.stats->n_capped, st.capped);
-      if (st.fallback) atomicAdd(&a.stats->n_fallback, st.fallback);
-      if (st.deg4) atomicAdd(&a.stats->n_degree4, st.deg4);
-      atomicAdd(&a.stats->n_wave_iter, st.wave_iters);
-      if (st.iters32) atomicAdd(&a.stats->n_iter_fp32, st.iters32);
-      if (st.polished) atomicAdd(&a.stats->n_polished, st.polished);
-      if (st.retried) atomicAdd(&a.stats->n_retried, st.retried);
-      if (st.unsettled) atomicAdd(&a.stats->n_unsettled, st.unsettled);
+    for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+      for (int k = 0; k < 11; ++k) v[k] += __shfl_down(v[k], off, 64);
+    if (lane == 0 && v[0]) {
+      unsigned long long* dst[11] = {&a.stats->n_solves,    &a.stats->n_iter,
+                                     &a.stats->n_capped,    &a.stats->n_fallback,
+                                     &a.stats->n_degree4,   &a.stats->n_wave_iter,
+                                     &a.stats->n_iter_fp32, &a.stats->n_polished,
+                                     &a.stats->n_retried,   &a.stats->n_unsettled,
+                                     &a.stats->n_newton};
+#pragma unroll
+      for (int k = 0; k < 11; ++k)
+        if (v[k]) atomicAdd(dst[k], v[k]);
     }
   }
 }

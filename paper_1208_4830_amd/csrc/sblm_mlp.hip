@@ -514,9 +514,11 @@ __global__ __launch_bounds__(256) void resample_kernel(const int64_t* off,
 //   row 0: words 0..5 the parameters (uniform over the domain below, in the
 //          library's plane order), word 6 Fb ~ U[0, 0.5] (Fs = 1), word 7
 //          the noise fraction s ~ U[0.005, 0.03], word 8 the epoch count
-//          L ~ U{200..5000};
+//          L ~ U{200..5000}, words 9, 10 the start and the end of the
+//          observing window, t0 + a tE and t0 + b tE with a ~ U(-3, -2) and
+//          b ~ U(2, 3) (the random start and end of Sec. 4.2);
 //   row 1 + j: words 0..3 for bin j (Poisson count, two normal deviates).
-// The observing window is t0 +- 2 tE seen through nightly windows
+// The observing window is seen through nightly windows
 // [n + 0.1, n + 0.1 + 1/3] days; t_first, t_last are its first and last
 // observable instants and span = t_last - t_first.  Bin j covers
 // [t_first + span j/256, t_first + span (j+1)/256]; its expected epoch count
@@ -532,8 +534,9 @@ __global__ __launch_bounds__(256) void resample_kernel(const int64_t* off,
 // (t0 - t_first)/span, tE/span, Fs/(Fs + Fb).
 constexpr double NIGHT0 = 0.1, NIGHT_LEN = 1.0 / 3.0;
 
-__device__ void data_window(double t0, double tE, double& t_first, double& t_last) {
-  const double ta = t0 - 2.0 * tE, tb = t0 + 2.0 * tE;
+__device__ void data_window(double t0, double tE, double a, double b, double& t_first,
+                            double& t_last) {
+  const double ta = t0 + a * tE, tb = t0 + b * tE;
   const double na = floor(ta - NIGHT0);
   t_first = (ta <= na + NIGHT0 + NIGHT_LEN) ? ta : na + 1.0 + NIGHT0;
   const double nb = floor(tb - NIGHT0);
@@ -560,8 +563,9 @@ __global__ void data_draw_kernel(uint64_t seed, int64_t first, int n, double* th
   const double Fb = 0.5 * u01(wd[6]);
   const double sn = 0.005 + 0.025 * u01(wd[7]);
   const double L = (double)(200u + below(wd[8], 4801u));
+  const double wa = -3.0 + u01(w2.v[1]), wb = 2.0 + u01(w2.v[2]);
   double t_first, t_last;
-  data_window(th[5], th[4], t_first, t_last);
+  data_window(th[5], th[4], wa, wb, t_first, t_last);
   const double span = t_last - t_first;
   for (int g = 0; g < 4; ++g) theta[(int64_t)g * n + i] = th[g];
   theta[(int64_t)4 * n + i] = th[4] / span;

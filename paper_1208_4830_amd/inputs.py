@@ -37,17 +37,17 @@ def uniform_epochs(theta, L):
     return t0[:, None] - 2.0 * tE[:, None] + 4.0 * tE[:, None] * k[None, :]
 
 
-def irregular_epochs(rng, tE, t0, L):
+def irregular_epochs(rng, tE, t0, L, window=(-2.0, 2.0)):
     """Survey-like cadence for one lightcurve, sorted, length L.
 
-    Nightly 8-hour windows over [t0 - 2 tE, t0 + 2 tE], consecutive points
-    5-30 min apart within a night; 0.9 L points drawn without replacement
-    from that schedule (its spacing is scaled down if it holds fewer points)
-    plus 0.1 L points uniform in [t0 - 0.1 tE, t0 + 0.1 tE].
+    Nightly 8-hour windows over [t0 + a tE, t0 + b tE] ((a, b) = window),
+    consecutive points 5-30 min apart within a night; 0.9 L points drawn
+    without replacement from that schedule (its spacing is scaled down if it
+    holds fewer points) plus 0.1 L points uniform in [t0 - 0.1 tE, t0 + 0.1 tE].
     """
     n_dense = int(round(0.1 * L))
     n_sched = L - n_dense
-    t_a, t_b = t0 - 2.0 * tE, t0 + 2.0 * tE
+    t_a, t_b = t0 + window[0] * tE, t0 + window[1] * tE
     night0 = np.floor(t_a)
     nights = np.arange(night0, np.ceil(t_b) + 1.0)
     expect = len(nights) * (8 * 60) / 17.5
@@ -95,12 +95,17 @@ def uniform_workload(seed, n_lc, L, sigma_frac=0.01):
 
 
 def ragged_workload(seed, n_lc, L_min=200, L_max=5000):
-    """Ragged batch: L ~ U{L_min..L_max}, irregular cadence, s ~ U[0.5%, 3%]."""
+    """Ragged batch: L ~ U{L_min..L_max}, irregular cadence, s ~ U[0.5%, 3%];
+    each lightcurve observed from t0 + a tE to t0 + b tE with a ~ U(-3, -2),
+    b ~ U(2, 3), the random start and end of the paper's test lightcurves
+    (Sec. 4.2)."""
     rng = np.random.default_rng(seed)
     theta = draw_theta(rng, n_lc)
     Fs, Fb = draw_blend(rng, n_lc)
     lens = rng.integers(L_min, L_max + 1, n_lc)
-    ts = [irregular_epochs(rng, theta[4, k], theta[5, k], int(lens[k])) for k in range(n_lc)]
+    wins = np.stack([rng.uniform(-3.0, -2.0, n_lc), rng.uniform(2.0, 3.0, n_lc)], 1)
+    ts = [irregular_epochs(rng, theta[4, k], theta[5, k], int(lens[k]), tuple(wins[k]))
+          for k in range(n_lc)]
     off = np.zeros(n_lc + 1, dtype=np.int64)
     off[1:] = np.cumsum(lens)
     t = np.concatenate(ts)

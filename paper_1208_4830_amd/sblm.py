@@ -18,6 +18,7 @@ FP64, MIXED = 0, 1
 # proposal network sizes (include/sblm.h)
 NBINS, NOUT, NOUT_PAD, NTARGET, NPARAMS = 256, 120, 128, 7, 455800
 SEED_AT_RESTARTS = 1
+SEED_WINDOW_ONLY = 2
 
 _lib = None
 
@@ -56,7 +57,7 @@ class ea_lc_summary(ctypes.Structure):
 
 STATS_FIELDS = ("n_solves", "n_iter", "n_capped", "n_fallback", "n_degree4", "n_degenerate",
                 "n_wave_iter", "n_iter_fp32", "n_polished", "n_retried",
-                "n_unsettled")
+                "n_unsettled", "n_newton")
 
 _SIGS = {
     "sblm_magnify": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
@@ -80,6 +81,9 @@ _SIGS = {
     "ea_destroy": [ctypes.c_void_p],
     "ea_autotune": [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t, ctypes.c_void_p],
     "ea_get_schedule": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)],
+    "ea_time_fitness": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p],
+    "ea_fitness_time": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                        ctypes.POINTER(ctypes.c_int64)],
     "ea_set_schedule": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)],
     "ea_draws": [ctypes.c_uint64] * 6 + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
     "ea_generation_traced": [ctypes.c_void_p] * 6,
@@ -319,6 +323,17 @@ class EAState:
     def fit(self, n_gen, stats=None, stream=None):
         _check(load().ea_fit(self.h, n_gen, _ptr(stats), _stream(stream)))
 
+    def time_fitness(self, enable=True, stream=None):
+        """Stamp the device clock around the fitness kernel of every replayed
+        generation (and clear the sums)."""
+        _check(load().ea_time_fitness(self.h, 1 if enable else 0, _stream(stream)))
+
+    def fitness_time(self):
+        """(milliseconds summed over the timed fitness launches, launches)."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(load().ea_fitness_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
     def autotune(self, stream=None):
         """Time the candidate schedules; returns the report text."""
         buf = ctypes.create_string_buffer(4096)
@@ -360,6 +375,15 @@ class EAState:
         _check(load().ea_seed(self.h, _ptr(out), out.shape[1], n_seed,
                               SEED_AT_RESTARTS if at_restarts else 0, _stream(stream)))
         self._proposals = out if (at_restarts and n_seed > 0) else None
+
+    def seed_window(self, n_seed, at_restarts=False, stream=None):
+        """As seed, with rows drawn from the observation window alone: t0 at
+        the middle of the observed span, tE a quarter of it, the other genes
+        uniform (the ablation of the learned form)."""
+        _check(load().ea_seed(self.h, None, 0, n_seed,
+                              SEED_WINDOW_ONLY | (SEED_AT_RESTARTS if at_restarts else 0),
+                              _stream(stream)))
+        self._proposals = None
 
     def best(self, stream=None):
         """(x [6][n_lc] encoded, chi2 [n_lc]) of every lightcurve's record."""

@@ -260,3 +260,40 @@ def test_ragged_full_size_sampled(hip, mode):
             co, _, _ = O.lsq_chi2(A[0], y[sl], w[sl])
             assert rel_err(c[col], co) < 1e-8, (k, i, c[col], co)
     st.close()
+
+
+def test_fitness_timer_leaves_the_fit_unchanged(hip):
+    # the device-clock stamps around the fitness kernel (ea_time_fitness)
+    # count every replayed launch, give a duration near the event-timed one
+    # of the same kernel, and change nothing in the fit
+    wl = csr_workload(16, [300, 0, 511, 1200, 64])
+    pop = 64
+    st_a, _, _ = _make_state(hip, wl, pop, seed=5)
+    st_b, _, _ = _make_state(hip, wl, pop, seed=5)
+    st_a.time_fitness(True)
+    stats = hip.new_stats()
+    st_a.fit(0, stats=stats)  # captures only
+    assert st_a.fitness_time() == (0.0, 0)
+    st_a.fit(20, stats=stats)
+    st_b.fit(20)
+    torch.cuda.synchronize()
+    assert st_a.save() == st_b.save()
+    ms, n = st_a.fitness_time()
+    assert n == 20 and ms > 0.0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    e0.record(stream)
+    for _ in range(20):
+        st_b.evaluate(stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ev_ms = e0.elapsed_time(e1) / 20
+    print(f"fitness kernel: stamped {ms / n:.4f} ms, events {ev_ms:.4f} ms")
+    assert 0.3 * ev_ms < ms / n < 3.0 * ev_ms
+    # switching the stamps off clears the sums and stops counting
+    st_a.time_fitness(False)
+    st_a.fit(3)
+    assert st_a.fitness_time() == (0.0, 0)
+    assert hip.stats_dict(stats)["n_solves"] > 0
+    st_a.close()
+    st_b.close()

@@ -283,6 +283,38 @@ def test_seeding_matches_oracle(hip):
     st.close()
 
 
+def test_window_seeding_matches_oracle(hip):
+    # the ablation of the learned form: rows from the observation window
+    # alone (t0 mid-span, tE a quarter of the span, the rest uniform)
+    lengths = [40, 0, 300, 1, 1200]
+    lcs, off, (t, y, w) = make_lcs(hip, lengths, seed=14, special=False)
+    cfg = hip.ea_default_config()
+    cfg.pop = 16
+    st = hip.EAState(cfg, lcs, 78)
+    P0 = st.view("P").clone().cpu().numpy()
+    st.seed_window(7)
+    torch.cuda.synchronize()
+    P = st.view("P").cpu().numpy()
+    lo, hi = np.array(cfg.lo[:]), np.array(cfg.hi[:])
+    for k, L in enumerate(lengths):
+        cols = k * 16 + np.arange(16)
+        if L == 0:
+            assert np.array_equal(P[:, cols], P0[:, cols])
+            continue
+        tf = t[off[k]]
+        span = t[off[k + 1] - 1] - tf
+        ref = M.seed_rows(None, tf, span, lo, hi, 78, k, 7, window_only=True)
+        assert np.allclose(P[:, cols[:7]].T, ref, rtol=0, atol=1e-12), k
+        assert np.array_equal(P[:, cols[7:]], P0[:, cols[7:]])
+        # every seeded row puts t0 at mid-span and tE at a quarter of it
+        th = lo[:, None] + (hi - lo)[:, None] * P[:, cols[:7]]
+        te = np.clip(span / 4, lo[4], hi[4])
+        t0 = np.clip(tf + span / 2, lo[5], hi[5])
+        assert np.allclose(th[4], te, atol=1e-9 * (hi[4] - lo[4]))
+        assert np.allclose(th[5], t0, atol=1e-9 * (hi[5] - lo[5]))
+    st.close()
+
+
 def test_restarts_reseed_attached_proposals(hip):
     from oracle import oracle as O
     lengths = [60, 200, 0, 90]
@@ -351,16 +383,21 @@ def test_trained_network_improves_the_ea(hip):
     xr, _ = hip.sblm_resample(lcs)
     out = net.forward(xr)
     success = {}
-    for form in ("plain", "learned"):
+    for form in ("plain", "window", "learned"):
         cfg = hip.ea_default_config()
         cfg.pop = 128
         st = hip.EAState(cfg, lcs, 7)
         if form == "learned":
             st.seed(out, 64, at_restarts=True)
+        elif form == "window":  # the ablation: what the window alone gives
+            st.seed_window(64, at_restarts=True)
         st.fit(150)
         best = np.array([s.best_chi2 for s in st.summary()])
         success[form] = float(np.mean(best <= c_true + 10.0))
         st.close()
     print(f"success after 150 generations: {success}")
+    # the windows are random (t0 + tE (-3..-2) to t0 + tE (2..3)), so the
+    # gain is what the network reads from the lightcurve's shape
     assert success["learned"] >= success["plain"] + 0.05
+    assert success["learned"] >= success["window"] + 0.03
     net.close()

@@ -118,8 +118,9 @@ def test_data_window_lies_in_nights_and_in_the_event_window():
     rng = np.random.default_rng(4)
     for _ in range(500):
         t0, tE = rng.uniform(-10, 10), rng.uniform(10, 100)
-        tf, tl = M.data_window(t0, tE)
-        ta, tb = t0 - 2 * tE, t0 + 2 * tE
+        a, b = rng.uniform(-3, -2), rng.uniform(2, 3)
+        tf, tl = M.data_window(t0, tE, a, b)
+        ta, tb = t0 + a * tE, t0 + b * tE
         assert ta <= tf < ta + 1.0 and tb - 1.0 < tl <= tb
         for x in (tf, tl):
             ph = x - np.floor(x)
@@ -132,9 +133,10 @@ def test_data_window_lies_in_nights_and_in_the_event_window():
 
 def test_expected_counts_add_up_to_the_epoch_count():
     for s in range(6):
-        th, Fb, sn, L = M.sample_params(11, s)
-        c, tf, span = M.expected_counts(th, L)
+        th, Fb, sn, L, win = M.sample_params(11, s)
+        c, tf, span = M.expected_counts(th, L, win)
         assert np.all(c >= 0)
+        assert -3 < win[0] < -2 and 2 < win[1] < 3
         # the dense window t0 +- 0.1 tE lies inside the observed span
         assert abs(c.sum() - L) <= 1e-9 * L
         assert 200 <= L <= 5000 and 0 <= Fb <= 0.5 and 0.005 <= sn <= 0.03
@@ -146,7 +148,7 @@ def test_observed_bins_are_the_forward_model_at_the_bin_centres():
     # checks the window and the rescaled t0, tE that the sampler feeds the
     # forward model
     th = np.array([-1.3, 1.1, 0.15, 2.2, 35.0, -4.0])
-    vals, filled, y, tf, span = M.observe(5, 0, th, 0.2, 1e-13, 3000)
+    vals, filled, y, tf, span = M.observe(5, 0, th, 0.2, 1e-13, 3000, (-2.4, 2.7))
     j = np.flatnonzero(filled)
     assert j.size > 50
     t = tf + span * (j + 0.5) / 256
@@ -157,11 +159,19 @@ def test_observed_bins_are_the_forward_model_at_the_bin_centres():
 
 
 def test_make_sample_is_normalised():
-    for s in range(4):
+    t0_rel, tE_rel = [], []
+    for s in range(40):
         x, y = M.make_sample(2, s)
         assert abs(np.median(x)) < 1e-12 and abs(x.max() - 1) < 1e-12
         assert np.all((y >= 0) & (y <= 1))
-        assert 0.45 < y[4] < 0.55 and 0.24 < y[5] < 0.27
+        # with the window from t0 + a tE to t0 + b tE, a ~ U(-3, -2), b ~
+        # U(2, 3): t0 lies at -a/(b - a) of the span, tE is 1/(b - a) of it
+        # (up to the trimming to nights)
+        assert 0.38 < y[4] < 0.62 and 0.16 < y[5] < 0.26
+        t0_rel.append(y[4])
+        tE_rel.append(y[5])
+    # the window no longer gives t0 and tE away: the targets spread out
+    assert np.std(t0_rel) > 0.03 and np.std(tE_rel) > 0.01
 
 
 # ------------------------------------------------------ seeding pins
