@@ -66,18 +66,25 @@ N_GEN_FIT = 500
 # HBM traffic of one launch of the FP64 chi^2 fitness kernel on the default
 # workload and schedule, from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a
 # copy kernel of known size (profiles/fitness_kernel_fp64_256lc_1000ep_pop256_
-# traffic.md).  Valid only for the kernel source it was taken on.
-FITNESS_TRAFFIC = dict(source_sha256_16="9f43dbfc9d015751", bytes_per_launch=15.35e6,
+# traffic.md).  Valid only for the kernel sources it was taken on (the kernel
+# file and the arithmetic it shares).
+FITNESS_TRAFFIC = dict(source_sha256_16="d08ff5ab774e6c2a", bytes_per_launch=13.69e6,
                        algorithmic_bytes_per_launch=10.86e6)
+FITNESS_SOURCES = ("sblm_fitness.hip", "sblm_math.h")
+
+
+def fitness_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in FITNESS_SOURCES:
+        with open(os.path.join(ROOT, "paper_1208_4830_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def fitness_traffic():
-    import hashlib
-    src = os.path.join(ROOT, "paper_1208_4830_amd", "csrc", "sblm_fitness.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    return FITNESS_TRAFFIC["bytes_per_launch"] if sha == FITNESS_TRAFFIC["source_sha256_16"] \
-        else None
+    return FITNESS_TRAFFIC["bytes_per_launch"] \
+        if fitness_sources_sha() == FITNESS_TRAFFIC["source_sha256_16"] else None
 
 
 def parse():
@@ -125,6 +132,9 @@ def parse():
                     help="single-epoch pairs of the precision-form comparison (0 skips it)")
     ap.add_argument("--mlp-samples", type=int, default=1 << 20)
     ap.add_argument("--mlp-epochs", type=int, default=32)
+    ap.add_argument("--mlp-batch", type=int, default=1024)
+    ap.add_argument("--mlp-lr", type=float, default=2e-3, help="initial learning rate (cosine "
+                    "schedule to 1e-5)")
     return ap.parse_args()
 
 
@@ -347,19 +357,26 @@ def train_proposals(sblm, torch, args):
     xb, _, yt = sblm.mlp_make_data(11, 0, args.mlp_samples)
     sync()
     t_data = time.perf_counter() - t0
-    net = sblm.MLP(batch_max=1024, seed=2)
-    batch = 1024
+    batch = args.mlp_batch
+    net = sblm.MLP(batch_max=batch, seed=2)
     steps = args.mlp_epochs * (args.mlp_samples // batch)
     t0 = time.perf_counter()
-    loss = net.train(xb, yt, batch=batch, epochs=args.mlp_epochs, lr0=2e-3, lr1=1e-5)
+    loss = net.train(xb, yt, batch=batch, epochs=args.mlp_epochs, lr0=args.mlp_lr,
+                     lr1=1e-5)
     sync()
     t_train = time.perf_counter() - t0
     lc = loss.cpu().numpy()
+    # held-out loss: fresh samples of the same generator, no update
+    xh, _, yh = sblm.mlp_make_data(12, 0, 4 * batch)
+    held = float(np.mean([net.loss_grad(xh[i * batch:(i + 1) * batch],
+                                        yh[i * batch:(i + 1) * batch]).item()
+                          for i in range(4)]))
     step_s = t_train / max(steps, 1)
     mfma_tflops = 6.0 * batch * MLP_GEMM_WEIGHTS / step_s / 1e12
     info = dict(samples=args.mlp_samples, epochs=args.mlp_epochs, batch=batch, steps=steps,
                 data_seconds=t_data, train_seconds=t_train, us_per_step=step_s * 1e6,
                 loss_first=float(lc[:16].mean()), loss_last=float(lc[-16:].mean()),
+                loss_held_out=held,
                 mfma_tflops=mfma_tflops, mfma_frac=mfma_tflops / PEAK_BF16_TFLOPS)
     return net, info
 

@@ -351,6 +351,21 @@ struct Item {
   int64_t e0, k0, k1, Cg, C;  // C: longest chunk in the wave
 };
 
+// The transcendental part of an individual's set-up: q = 10^(log10 q),
+// sin and cos of alpha, 1/tE.  Out of line: inlined, the many constants of
+// the exp10 and sincos expansions are hoisted out of the persistent grid's
+// work loop into registers that then spill to scratch memory in every wave.
+struct ItemTrig {
+  double q, sa, ca, itE;
+};
+__device__ __noinline__ ItemTrig item_trig(double lq, double alpha, double tE) {
+  ItemTrig r;
+  r.q = exp10(lq);
+  sincos(alpha, &r.sa, &r.ca);
+  r.itE = 1.0 / tE;
+  return r;
+}
+
 template <int G>
 __device__ __forceinline__ Item item_setup(const FitArgs& a, int64_t wave_item) {
   Item x;
@@ -372,12 +387,14 @@ __device__ __forceinline__ Item item_setup(const FitArgs& a, int64_t wave_item) 
     const double v = x.valid ? a.theta[j * a.n_ind + x.ind] : 0.5;
     th[j] = a.encoded ? a.lo[j] + a.span[j] * v : v;
   }
-  x.q = exp10(th[0]);
+  const ItemTrig tr = item_trig(th[0], th[3], th[4]);
+  x.q = tr.q;
   x.d = th[1];
   x.u0 = th[2];
   x.t0 = th[5];
-  sincos(th[3], &x.sa, &x.ca);
-  x.itE = 1.0 / th[4];
+  x.sa = tr.sa;
+  x.ca = tr.ca;
+  x.itE = tr.itE;
   int64_t e0 = 0, e1 = a.n_t;
   if (a.off) {
     const int64_t lc = x.ind / a.pop;

@@ -26,15 +26,21 @@ def test_fp64_vector_peak():
     assert bench.PEAK_VALU_TFLOPS == pytest.approx(78.6432)
 
 
+def test_traffic_figure_is_current():
+    # the committed figure belongs to the committed kernel sources
+    assert bench.fitness_traffic() == bench.FITNESS_TRAFFIC["bytes_per_launch"]
+
+
 def test_traffic_figure_matches_the_kernel_source():
     # the committed rocprofv3 traffic is reported only for the source it was
     # measured on; for a changed kernel the bench reports null until it is
     # profiled again
     import hashlib
-    src = os.path.join(ROOT, "paper_1208_4830_amd", "csrc", "sblm_fitness.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in ("sblm_fitness.hip", "sblm_math.h"):
+        h.update(open(os.path.join(ROOT, "paper_1208_4830_amd", "csrc", f), "rb").read())
     want = bench.FITNESS_TRAFFIC["bytes_per_launch"] \
-        if sha == bench.FITNESS_TRAFFIC["source_sha256_16"] else None
+        if h.hexdigest()[:16] == bench.FITNESS_TRAFFIC["source_sha256_16"] else None
     assert bench.fitness_traffic() == want
     assert bench.FITNESS_TRAFFIC["bytes_per_launch"] > \
         bench.FITNESS_TRAFFIC["algorithmic_bytes_per_launch"]
