@@ -251,10 +251,9 @@ def success_run(sblm, torch, lcs, chi2_true, pop, mode, sched, lo, hi, proposals
     """EA with optional proposal seeding; at every checkpoint the fittest
     solution of each lightcurve is fine-tuned by `passes` simplex passes, each
     restarted from the last (on a copy: the EA continues untouched), as the
-    paper's "EA with amoeba".  `sched` is fixed, not autotuned: lanes per
-    individual and the epoch stepping change the roots at the rounding level
-    and with them the EA's path, so a fixed schedule makes these runs
-    reproducible on any device.
+    paper's "EA with amoeba".  `sched` is the chosen form's tuned schedule:
+    the knobs the tuner turns change no result bit, so these runs are
+    reproducible whatever it chose.
     Success = chi^2 <= chi^2 of the true parameters + 10.  GPU time of a
     checkpoint = EA time so far + that checkpoint's simplex time.
     islands = (n_islands, migrate every, migrants): the island form with the
@@ -668,7 +667,9 @@ def main():
                 log("bench: training the proposal network on generated lightcurves")
                 net, train_info = train_proposals(sblm, torch, args)
                 log(f"bench: training: {json.dumps(train_info)}")
-            study = success_study(sblm, torch, lcs_r, c_true_r, 128, (8, 4, 1, 0), lo, hi,
+            sched_r = tuple(chosen["schedule"][k] for k in
+                            ("lanes", "waves_per_block", "persistent", "asynchronous"))
+            study = success_study(sblm, torch, lcs_r, c_true_r, 128, sched_r, lo, hi,
                                   net, train_info, args)
             if net is not None:
                 net.close()

@@ -308,15 +308,17 @@ int ea_fitness_time(ea_state* st, double* ms, int64_t* launches);
 /*
  * ea_autotune -- choose the fitness schedule of this state by timing it on
  * the state's own population and lightcurves (coordinate descent over the
- * epoch stepping {asynchronous, lockstep}, lanes per individual {8, 16, 32, 64,
- * 128, 256} (128 and 256 spread an individual over several waves and go with
- * four waves per block, the one-shot grid and lockstep stepping),
- * waves per block {1, 2, 4} and a persistent work-counter launch vs a
- * one-shot grid), then re-capture the generation graph with the fastest.
- * Results do not depend on the waves per block or on the launch form; the
- * lanes per individual and the stepping change the warm starts and so the
- * roots at the rounding level only.  `report` (host, nullable) receives one
- * line per candidate.  Synchronises `stream`.
+ * epoch stepping {asynchronous, lockstep}, waves per block {1, 2, 4} and a
+ * persistent work-counter launch vs a one-shot grid; with 128 or 256 lanes
+ * per individual only the waves per block that hold whole individuals, the
+ * one-shot grid and lockstep stepping), then re-capture the generation graph
+ * with the fastest.  None of these knobs changes a result bit, so a tuned fit
+ * is bit-identical to the untuned one.  The lanes per individual are not
+ * tuned: each lane warm-starts the root solves along its own chunk of a
+ * lightcurve's epochs, so their number decides where the chains of warm
+ * starts begin (roots differ at the rounding level) and is part of the
+ * fit's definition, set at ea_create (see ea_get_schedule).  `report`
+ * (host, nullable) receives one line per candidate.  Synchronises `stream`.
  */
 int ea_autotune(ea_state* st, char* report, size_t report_len, void* stream);
 
@@ -325,9 +327,12 @@ int ea_autotune(ea_state* st, char* report, size_t report_len, void* stream);
  * 8/16/32/64, waves per block 1/2/4, persistent 0/1, asynchronous 0/1; or
  * lanes 128/256 with waves per block a multiple of lanes/64, one-shot,
  * lockstep; SBLM_EINVAL otherwise) and installs one (and re-captures the
- * graph).  ea_create starts from 16 lanes, 4 waves per block, persistent,
- * lockstep, or for a state of fewer than 2048*64/32 individuals from the
- * widest lanes (up to 256) whose waves fit one residency of the chip. */
+ * graph).  Results depend on the lanes per individual only (see
+ * ea_autotune).  ea_create starts from 4 waves per block, lockstep, the
+ * persistent grid, and the fewest lanes in {8, 16, 32, 64} that give 2^20
+ * lanes of work (n_ind x lanes >= 2^20, else 64); a state of at most 2048
+ * individuals takes the widest lanes (up to 256, one-shot grid) with
+ * n_ind x lanes <= 2^17, the lanes of one residency of the chip. */
 int ea_get_schedule(ea_state* st, int32_t* sched);
 int ea_set_schedule(ea_state* st, const int32_t* sched);
 

@@ -680,6 +680,19 @@ extern "C" void ea_destroy(ea_state* st) {
   free(st);
 }
 
+// Lanes per individual of a state of n_ind individuals (see ea_create).
+static int default_lanes(int64_t n_ind) {
+  constexpr int64_t RESIDENT = 2048 * 64;  // lanes of one residency (256 CUs x 8 waves)
+  if (n_ind * 64 <= RESIDENT) {
+    int g = 64;
+    while (g < 256 && n_ind * (2 * g) <= RESIDENT) g *= 2;
+    return g;
+  }
+  for (int g = 8; g < 64; g *= 2)
+    if (n_ind * g >= 8 * RESIDENT) return g;
+  return 64;
+}
+
 extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t seed,
                          ea_state** out) {
   if (!cfg || !lcs || !out) return set_error(SBLM_EINVAL, "ea_create: null argument");
@@ -713,18 +726,17 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
   p.stag_frac = cfg->stag_frac;
   p.seed = seed;
   p.n_ind = (int64_t)p.n_lc * p.pop;
-  // default schedule: 16 lanes per individual on the persistent grid for a
-  // full batch; a small state (its groups would leave the chip idle) takes
-  // the widest group that fits one residency of the chip, spread over the
-  // four waves of a block on the one-shot grid (ea_autotune refines this)
-  const char* env = getenv("SBLM_LANES");
-  s.lanes = 16;
-  for (int g = 256; g >= 32; g >>= 1)
-    if (p.n_ind * g <= (int64_t)2048 * 64) {
-      s.lanes = g;
-      break;
-    }
-  if (env && (atoi(env) == 16 || atoi(env) == 32 || atoi(env) == 64)) s.lanes = atoi(env);
+  // Lanes per individual: each lane owns one contiguous chunk of a
+  // lightcurve's epochs and warm-starts along it, so this number fixes where
+  // the chains of warm starts begin and the merge of the lanes' sums -- it is
+  // part of what the fit computes, and ea_autotune leaves it alone (the
+  // knobs it tunes do not change a bit).  Rule: the fewest of 8 ... 64 lanes
+  // that give the launch 2^20 lanes of work (eight residencies of the chip;
+  // fewer lanes mean longer chunks, so fewer cold starts); a small state,
+  // whose 64-lane groups would not fill one residency, takes the widest
+  // group (up to 256 lanes, over several waves) that fits one, spread over
+  // the four waves of a block on the one-shot grid.
+  s.lanes = default_lanes(p.n_ind);
   if (s.lanes > 64) s.persistent = 0;
   const size_t nb = (size_t)p.n_ind * sizeof(double);
   // longest-processing-time order of the work items: lightcurves by length,
@@ -1148,30 +1160,24 @@ extern "C" int ea_autotune(ea_state* st, char* report, size_t report_len, void* 
   char buf[2048];
   int len = 0;
   buf[0] = 0;
-  // coordinate descent: epoch stepping (asynchronous or lockstep), lanes
-  // per individual, waves per block, persistent vs one-shot grid
+  // coordinate descent over the knobs that leave every result bit as it is:
+  // epoch stepping (asynchronous or lockstep), waves per block, persistent
+  // vs one-shot grid.  The lanes per individual stay (see ea_create).
   int best[4] = {s.lanes, s.wpb, s.persistent, s.async};
   float best_ms = INFINITY;
   // (128 or 256 lanes spread an individual over several waves: those go
-  // with four waves per block, the one-shot grid and lockstep stepping, and
-  // candidates that break this are skipped)
-  const int lanes_c[6] = {8, 16, 32, 64, 128, 256}, wpb_c[3] = {1, 2, 4}, bin_c[2] = {1, 0};
-  const int stage_field[4] = {3, 0, 1, 2};
-  for (int stage = 0; stage < 4 && !rc; ++stage) {
+  // with whole individuals per block, the one-shot grid and lockstep
+  // stepping, and candidates that break this are skipped)
+  const int wpb_c[3] = {1, 2, 4}, bin_c[2] = {1, 0};
+  const int stage_field[3] = {3, 1, 2};
+  for (int stage = 0; stage < 3 && !rc; ++stage) {
     const int field = stage_field[stage];
-    const int nc = field == 0 ? 6 : (field == 1 ? 3 : 2);
+    const int nc = field == 1 ? 3 : 2;
     for (int k = 0; k < nc && !rc; ++k) {
       int cand[4] = {best[0], best[1], best[2], best[3]};
-      cand[field] = field == 0 ? lanes_c[k] : (field == 1 ? wpb_c[k] : bin_c[k]);
-      if (cand[0] > 64) {
-        if (field == 0) {
-          cand[1] = 4;
-          cand[2] = 0;
-          cand[3] = 0;
-        } else if (cand[1] != 4 || cand[2] != 0 || cand[3] != 0) {
-          continue;
-        }
-      }
+      cand[field] = field == 1 ? wpb_c[k] : bin_c[k];
+      if (cand[0] > 64 && (cand[1] % (cand[0] / 64) != 0 || cand[2] != 0 || cand[3] != 0))
+        continue;
       s.lanes = cand[0];
       s.wpb = cand[1];
       s.persistent = cand[2];

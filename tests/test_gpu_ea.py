@@ -172,55 +172,70 @@ def test_fit_improves_and_best_is_monotone(hip, mode):
     assert best[-1] < best[0] and np.isfinite(best[-1]) and chi2_true > 0
 
 
-def test_schedules_agree_and_autotune(hip):
-    # the waves per block and the launch form (persistent work counter or a
-    # one-shot grid) do not change any result bit; lanes per individual only
-    # change the warm-start chunks (roots at the rounding level)
+# every schedule ea_set_schedule accepts, by lanes per individual
+_SCHEDULES = {g: [(g, wpb, pers, asy) for wpb in (1, 2, 4) for pers in (1, 0) for asy in (0, 1)]
+              for g in (8, 16, 32, 64)}
+_SCHEDULES[128] = [(128, 2, 0, 0), (128, 4, 0, 0)]
+_SCHEDULES[256] = [(256, 4, 0, 0)]
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_schedules_agree_and_autotune(hip, mode):
+    # The knobs the autotuner turns -- epoch stepping (lockstep or
+    # asynchronous), waves per block, persistent or one-shot grid -- do not
+    # change a result bit, in either precision form: a fit is the same under
+    # every schedule with the same lanes per individual (those set where each
+    # lane's chain of warm starts begins, so they are part of the fit).
     wl = csr_workload(9, [0, 5, 64, 201, 777, 1500, 3000])
     pop = 32
+    lanes_all = (8, 16, 32, 64, 128, 256) if mode == 0 else (16, 128)
     blobs = {}
-    for sched in [(16, 4, 1, 1), (16, 2, 0, 1), (16, 1, 1, 1), (16, 4, 1, 0), (16, 2, 0, 0),
-                  (32, 4, 1, 1), (64, 2, 0, 0), (8, 4, 1, 0), (8, 1, 0, 0), (8, 2, 1, 1),
-                  (128, 2, 0, 0), (128, 4, 0, 0), (256, 4, 0, 0)]:
-        st, y, w = _make_state(hip, wl, pop, seed=21)
-        st.set_schedule(*sched)
-        assert st.schedule() == sched
-        st.fit(6)
-        blobs[sched] = st.save()
-        st.evaluate()
-        c = st.view("chi2").cpu().numpy().copy()
-        P = st.view("P").cpu().numpy()
-        theta = O.decode(P, np.array(st.cfg.lo[:]), np.array(st.cfg.hi[:]))
-        co, _, _ = O.chi2(wl.off, wl.t, y, w, theta, pop)
-        scale = np.array([np.sum(w[wl.off[k]:wl.off[k + 1]] * y[wl.off[k]:wl.off[k + 1]] ** 2)
-                          for k in range(wl.n_lc)]).repeat(pop)
-        assert np.all(np.abs(c - co) <= 1e-8 * co + 1e-14 * scale)
-        st.close()
-    ref = blobs[(16, 4, 1, 1)]
-    assert blobs[(16, 2, 0, 1)] == ref and blobs[(16, 1, 1, 1)] == ref
-    assert blobs[(16, 2, 0, 0)] == blobs[(16, 4, 1, 0)]
-    assert blobs[(8, 1, 0, 0)] == blobs[(8, 4, 1, 0)]
-    assert blobs[(128, 2, 0, 0)] == blobs[(128, 4, 0, 0)]  # one or two individuals a block
-    st, _, _ = _make_state(hip, wl, pop, seed=21)
+    for g in lanes_all:
+        for sched in _SCHEDULES[g]:
+            if mode == 1 and g == 16 and sched[1] == 2:
+                continue  # (bounded run time; every stepping and grid form is still covered)
+            st, y, w = _make_state(hip, wl, pop, seed=21, mode=mode)
+            st.set_schedule(*sched)
+            assert st.schedule() == sched
+            st.fit(6)
+            blobs[sched] = st.save()
+            if sched == _SCHEDULES[g][0]:
+                # one schedule per lanes value against the oracle's chi^2
+                st.evaluate()
+                c = st.view("chi2").cpu().numpy().copy()
+                P = st.view("P").cpu().numpy()
+                theta = O.decode(P, np.array(st.cfg.lo[:]), np.array(st.cfg.hi[:]))
+                co, _, _ = O.chi2(wl.off, wl.t, y, w, theta, pop)
+                scale = np.array([np.sum(w[wl.off[k]:wl.off[k + 1]] * y[wl.off[k]:wl.off[k + 1]] ** 2)
+                                  for k in range(wl.n_lc)]).repeat(pop)
+                tol = 1e-8 if mode == 0 else 1e-6
+                assert np.all(np.abs(c - co) <= tol * co + 1e-14 * scale), sched
+            st.close()
+        ref = blobs[_SCHEDULES[g][0]]
+        for sched in _SCHEDULES[g]:
+            if sched in blobs:
+                assert blobs[sched] == ref, (sched, _SCHEDULES[g][0])
+    # the autotuner keeps the lanes and lands on a schedule of the same bits
+    st, _, _ = _make_state(hip, wl, pop, seed=21, mode=mode)
     assert st.schedule() == (256, 4, 0, 0)  # a small state starts wide
+    st.set_schedule(16, 4, 1, 0)
     rep = st.autotune()
     lanes, wpb, pers, asy = st.schedule()
-    # stepping (only lockstep is valid for the wide start), lanes (6), waves
-    # per block (3, or 1 after a wide choice), launch form (2, or 1), chosen
-    assert "chosen:" in rep and len(rep.splitlines()) == (10 if lanes > 64 else 13)
-    assert lanes in (8, 16, 32, 64, 128, 256) and wpb in (1, 2, 4) and pers in (0, 1)
-    assert asy in (0, 1) and (lanes <= 64 or (wpb == 4 and pers == 0 and asy == 0))
+    # stepping (2), waves per block (3), launch form (2), chosen
+    assert "chosen:" in rep and len(rep.splitlines()) == 8
+    assert lanes == 16 and wpb in (1, 2, 4) and pers in (0, 1) and asy in (0, 1)
+    st.fit(6)
+    assert st.save() == blobs[(16, 4, 1, 0)]
+    st.close()
+    st, _, _ = _make_state(hip, wl, pop, seed=21, mode=mode)
+    rep = st.autotune()  # wide: waves per block 4 only (one-shot, lockstep)
+    assert st.schedule() == (256, 4, 0, 0) and len(rep.splitlines()) == 4
     with pytest.raises(hip.SblmError):  # blocks beyond the kernels' bound
         st.set_schedule(16, 8, 1)
     for bad in ((256, 2, 0, 0), (256, 4, 1, 0), (128, 4, 0, 1)):
         with pytest.raises(hip.SblmError):  # wide lanes: whole individuals, one-shot, lockstep
             st.set_schedule(*bad)
-    st.set_schedule(lanes, wpb, pers, asy)
-    st.fit(6)
-    if lanes == 16:
-        assert st.save() == blobs[(16, 4, 1, asy)]
-    if lanes > 64:
-        assert st.save() == blobs[(lanes, 4, 0, 0)]
+    st.close()
 
 
 @pytest.mark.parametrize("mode", [0, 1])
