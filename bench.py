@@ -68,7 +68,7 @@ N_GEN_FIT = 500
 # copy kernel of known size (profiles/fitness_kernel_fp64_256lc_1000ep_pop256_
 # traffic.md).  Valid only for the kernel sources it was taken on (the kernel
 # file and the arithmetic it shares).
-FITNESS_TRAFFIC = dict(source_sha256_16="d08ff5ab774e6c2a", bytes_per_launch=13.69e6,
+FITNESS_TRAFFIC = dict(source_sha256_16="44c704e6ee184008", bytes_per_launch=13.68e6,
                        algorithmic_bytes_per_launch=10.86e6)
 FITNESS_SOURCES = ("sblm_fitness.hip", "sblm_math.h")
 
@@ -113,7 +113,7 @@ def parse():
     ap.add_argument("--success-every", type=int, default=200)
     ap.add_argument("--success-forms", default="plain,window,learned",
                     help="forms of the success study: plain EA, window-only seeding, network "
-                         "seeding")
+                         "seeding, network seeding on islands (learned_islands)")
     ap.add_argument("--iterated", default="",
                     help="iterated-simplex comparison on the headline lightcurves: slots per "
                          "lightcurve,runs per slot,max steps per run (e.g. 16,4,10000)")
@@ -122,7 +122,8 @@ def parse():
     ap.add_argument("--paper-checkpoints", default="500,1000,3000")
     ap.add_argument("--islands", default="",
                     help="island form in the success study: islands,migrate every,migrants "
-                         "(e.g. 8,50,2)")
+                         "(e.g. 8,50,2); also the islands of the learned_islands form "
+                         "(default 4,50,2)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device 4 times (a kernel of "
                          "known traffic that scales the profiler's byte counters)")
@@ -409,25 +410,34 @@ def success_study(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, net, train_in
                         f"fittest solution every {args.success_every} generations",
                training=train_info)
     t_inf = 0.0
+    props = None
+    isl = tuple(int(v) for v in (args.islands or "4,50,2").split(","))
     for f in forms:
         log(f"bench: success study, form {f}")
         kw = {}
-        if f == "learned":
-            props, t_inf = propose(sblm, torch, net, lcs)
+        if f in ("learned", "learned_islands"):
+            if props is None:
+                props, t_inf = propose(sblm, torch, net, lcs)
+                out["inference_seconds"] = t_inf
             kw["proposals"] = props
-            out["inference_seconds"] = t_inf
         elif f == "window":
             kw["window"] = True
+        if f == "learned_islands":
+            # the learned form on islands: half of every island's rows seeded,
+            # a simplex from every island's record at each checkpoint
+            kw["islands"] = isl
         r = success_run(sblm, torch, lcs, chi2_true, pop, sblm.FP64, sched, lo, hi,
                         max_gen=args.success_max_gen, every=args.success_every, **kw)
-        if f == "learned" and r["ea_amoeba"]["reached"]:  # inference is part of its time
+        if f == "learned_islands":
+            r["config"] = dict(islands=isl[0], pop_per_island=pop // isl[0],
+                               migrate_every=isl[1], migrants=isl[2])
+        if f.startswith("learned") and r["ea_amoeba"]["reached"]:  # inference is its time too
             r["ea_amoeba"]["gpu_seconds"] += t_inf
             r["ea_amoeba"]["fits_per_hour"] = len(chi2_true) * 3600.0 / \
                 r["ea_amoeba"]["gpu_seconds"]
         out[f] = r
         log(f"bench: success {f}: {json.dumps(r)}")
     if args.islands:
-        isl = tuple(int(v) for v in args.islands.split(","))
         out["islands"] = success_run(sblm, torch, lcs, chi2_true, pop, sblm.FP64, sched, lo, hi,
                                      max_gen=args.success_max_gen, every=args.success_every,
                                      islands=isl)
@@ -663,7 +673,7 @@ def main():
         log(f"bench: chosen: {json.dumps(chosen)}")
         if args.success_max_gen > 0:
             net = train_info = None
-            if "learned" in args.success_forms.split(","):
+            if any(f.startswith("learned") for f in args.success_forms.split(",")):
                 log("bench: training the proposal network on generated lightcurves")
                 net, train_info = train_proposals(sblm, torch, args)
                 log(f"bench: training: {json.dumps(train_info)}")
@@ -688,10 +698,10 @@ def main():
 
     at90 = None
     if study:
-        at90 = {f: study[f]["ea_amoeba"]["fits_per_hour"]
-                for f in ("plain", "window", "learned", "islands") if f in study}
-        at90["gpu_seconds"] = {f: study[f]["ea_amoeba"]["gpu_seconds"]
-                               for f in ("plain", "window", "learned", "islands") if f in study}
+        forms_done = [f for f in ("plain", "window", "learned", "learned_islands", "islands")
+                      if f in study]
+        at90 = {f: study[f]["ea_amoeba"]["fits_per_hour"] for f in forms_done}
+        at90["gpu_seconds"] = {f: study[f]["ea_amoeba"]["gpu_seconds"] for f in forms_done}
         at90["workload"] = "the chosen-form lightcurves (EA + simplex fine-tuning, FP64)"
     roof = roofline_of(main_form, "fitness_kernel (FP64)")
     roof["traffic"] = fitness_traffic()

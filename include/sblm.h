@@ -311,8 +311,10 @@ int ea_fitness_time(ea_state* st, double* ms, int64_t* launches);
  * epoch stepping {asynchronous, lockstep}, waves per block {1, 2, 4} and a
  * persistent work-counter launch vs a one-shot grid; with 128 or 256 lanes
  * per individual only the waves per block that hold whole individuals, the
- * one-shot grid and lockstep stepping), then re-capture the generation graph
- * with the fastest.  None of these knobs changes a result bit, so a tuned fit
+ * one-shot grid and lockstep stepping), starting from the current schedule
+ * and moving only to a candidate more than 2% faster (so that repeated tuning
+ * settles on the same choice despite timing jitter), then re-capture the
+ * generation graph.  None of these knobs changes a result bit, so a tuned fit
  * is bit-identical to the untuned one.  The lanes per individual are not
  * tuned: each lane warm-starts the root solves along its own chunk of a
  * lightcurve's epochs, so their number decides where the chains of warm
@@ -321,6 +323,26 @@ int ea_fitness_time(ea_state* st, double* ms, int64_t* launches);
  * (host, nullable) receives one line per candidate.  Synchronises `stream`.
  */
 int ea_autotune(ea_state* st, char* report, size_t report_len, void* stream);
+
+/*
+ * ea_autotune_cached -- ea_autotune with a kept choice (App. A's fits are
+ * run again and again on workloads of one shape).  `path` (host string)
+ * names a text file of earlier choices, one line per device and workload:
+ * a 64-bit key in hex (FNV-1a of the device's architecture and compute-unit
+ * count and of the state's workload: precision form, population, islands,
+ * lightcurve count, lanes per individual, and how many lightcurves have
+ * floor(log2(L + 1)) = b for every b), then lanes, waves per block,
+ * persistent, asynchronous, then the key's text.  A key found in the file
+ * installs its schedule without timing (*tuned = 0, nullable); else the
+ * state is tuned as by ea_autotune and a line appended (*tuned = 1).  A kept
+ * schedule changes no result bit against the untuned one.  Lines that do
+ * not parse are skipped.  Errors: those of ea_autotune and ea_set_schedule;
+ * SBLM_ESTATE for a null state; SBLM_EINVAL for a null or empty path, a
+ * file that cannot be appended, or an entry whose lanes differ from the
+ * state's.  Calls that append to one file at once may interleave lines.
+ */
+int ea_autotune_cached(ea_state* st, const char* path, int32_t* tuned, char* report,
+                       size_t report_len, void* stream);
 
 /* Current schedule as int32[4] {lanes per individual, waves per block,
  * persistent, asynchronous stepping}; ea_set_schedule validates (lanes
@@ -413,9 +435,15 @@ void nm_default_config(nm_config* cfg);
  *   chi2, Fs, Fb  [n_lc] device out (nullable), its chi^2 and fluxes
  *   n_iter  [n_lc] device int32 out (nullable), simplex steps taken
  *   stats   (nullable) fitness counters
- * Allocates and frees a workspace of ~1 KB per simplex, plus 80 B per lane of
- * saved roots (80 KB per simplex at 256 lanes per trial point; at most
- * 1 GiB, wider batches use fewer lanes); synchronises `stream`.
+ * Allocates and frees a workspace of ~1 KB per simplex, a work order of
+ * 16 B per simplex, and saved roots of 80 B per lane: the trial points of a
+ * round are spread over 64, 128 or 256 lanes each, the fewest that give
+ * 2^19 lanes for the simplices still running (read every 16 rounds), each
+ * width with its own saved roots (140 KB per simplex for the three; where
+ * they would pass 1 GiB, one width: 256 lanes, else 128, else 64 without
+ * saved roots).  The widths change results at the rounding level only, and
+ * are a function of the simplices, so calls are repeatable.  Synchronises
+ * `stream`.
  * Errors: SBLM_EINVAL, SBLM_ERANGE, SBLM_ENOMEM, SBLM_EDEVICE.
  */
 int nm_refine(const sblm_lcs* lcs, const double* lo, const double* hi,

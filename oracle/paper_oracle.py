@@ -72,8 +72,12 @@ def chi2_mag(m_obs, sigma, m_model):
     return float(np.sum(r * r))
 
 
-def success(experiment, theta_fit, Fs, Fb, A_fit, m_obs, sigma, m_true, theta_true, m0, f):
-    """(weak, strict, Delta chi^2 / nu) of one fitted model (P5)."""
+def success(experiment, theta_fit, Fs, Fb, A_fit, m_obs, sigma, m_true, theta_true, m0, f,
+            lens_only=False):
+    """(weak, strict, Delta chi^2 / nu) of one fitted model (P5).  With
+    lens_only the strict test leaves out the photometric parameters m0 and f
+    (which the fit profiles instead of searching) and checks the six lens and
+    trajectory parameters only."""
     N = len(m_obs)
     nu = N - (7 if experiment == 1 else 8)
     mf = fitted_m0_f(Fs, Fb)
@@ -90,9 +94,10 @@ def success(experiment, theta_fit, Fs, Fb, A_fit, m_obs, sigma, m_true, theta_tr
     errs = [abs(q_fit - q_true) / q_true]
     for j in (1, 2, 4):  # d, u0, tE
         errs.append(abs(theta_fit[j] - theta_true[j]) / abs(theta_true[j]))
-    errs.append(abs(m0_fit - m0) / abs(m0))
-    if experiment == 2:
-        errs.append(abs(f_fit - f) / abs(f))
+    if not lens_only:
+        errs.append(abs(m0_fit - m0) / abs(m0))
+        if experiment == 2:
+            errs.append(abs(f_fit - f) / abs(f))
     errs.append(abs(theta_fit[5] - theta_true[5]) / theta_true[4])
     da = (theta_fit[3] - theta_true[3]) % (2.0 * math.pi)
     errs.append(min(da, 2.0 * math.pi - da) / (2.0 * math.pi))

@@ -15,6 +15,7 @@
 // with explicit fused multiply-adds and compiled without contraction, so the
 // result is the same on any IEEE-754 machine given the same fitness.
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -481,6 +482,8 @@ struct EaStateImpl {
   int64_t* xcd_start = nullptr;   // [9] order positions owned by each XCD
   Proposals prop = {};         // attached by ea_seed(..., EA_SEED_AT_RESTARTS)
   int n_phys = 0;              // lightcurves (prm.n_lc counts islands)
+  // the workload as the schedule cache keys it (ea_autotune_cached)
+  char sig[320] = {0};
   double* mig_out = nullptr;   // migration outboxes (islands with migrants)
   int32_t* mig_least = nullptr;
   bool mig_in_fit = false;     // ea_fit migrates when due
@@ -764,6 +767,21 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
         rc = set_error(SBLM_EINVAL, "ea_create: offsets not non-decreasing from 0");
         break;
       }
+  if (!rc) {
+    // workload signature: precision form, population, islands, lightcurves,
+    // and how many lightcurves have floor(log2(L + 1)) = b
+    int hist[64] = {0};
+    for (int k = 0; k < nl; ++k) {
+      uint64_t v = (uint64_t)(off_h[k + 1] - off_h[k]) + 1;
+      int b = 0;
+      while (v >>= 1) ++b;
+      ++hist[b];
+    }
+    int n = snprintf(s.sig, sizeof(s.sig), "mode=%d pop=%d islands=%d n_lc=%d L2:",
+                     cfg->mode, p.pop, p.n_isl, nl);
+    for (int b = 0; b < 64 && n > 0 && n < (int)sizeof(s.sig) - 16; ++b)
+      if (hist[b]) n += snprintf(s.sig + n, sizeof(s.sig) - n, " %d:%d", b, hist[b]);
+  }
   if (!rc) {
     for (int k = 0; k < nl; ++k) lcs_sorted[k] = k;
     // stable bottom-up merge sort, longest first
@@ -1165,6 +1183,11 @@ extern "C" int ea_autotune(ea_state* st, char* report, size_t report_len, void* 
   // vs one-shot grid.  The lanes per individual stay (see ea_create).
   int best[4] = {s.lanes, s.wpb, s.persistent, s.async};
   float best_ms = INFINITY;
+  rc = time_evaluate(s, e0, e1, 2, &best_ms);
+  if (!rc)
+    len += snprintf(buf + len, sizeof(buf) - len,
+                    "start: lanes=%d wpb=%d persistent=%d async=%d: %.3f ms\n", best[0], best[1],
+                    best[2], best[3], best_ms);
   // (128 or 256 lanes spread an individual over several waves: those go
   // with whole individuals per block, the one-shot grid and lockstep
   // stepping, and candidates that break this are skipped)
@@ -1189,7 +1212,15 @@ extern "C" int ea_autotune(ea_state* st, char* report, size_t report_len, void* 
         len += snprintf(buf + len, sizeof(buf) - len,
                         "lanes=%d wpb=%d persistent=%d async=%d: %.3f ms\n", cand[0], cand[1],
                         cand[2], cand[3], ms);
-      if (ms < best_ms) {
+      // a candidate replaces the current schedule only when it is faster by
+      // more than 2% (timings of one schedule vary by ~1% from one try to the
+      // next), so that the choice is stable from one run to the next; the
+      // current schedule keeps its best time
+      const bool same = cand[0] == best[0] && cand[1] == best[1] && cand[2] == best[2] &&
+                        cand[3] == best[3];
+      if (same) {
+        best_ms = ms < best_ms ? ms : best_ms;
+      } else if (ms < 0.98f * best_ms) {
         best_ms = ms;
         for (int f = 0; f < 4; ++f) best[f] = cand[f];
       }
@@ -1213,6 +1244,58 @@ extern "C" int ea_autotune(ea_state* st, char* report, size_t report_len, void* 
   if (!rc) rc = check_hip(hipEventRecord(s.ev_out, s.work), "ea_autotune event");
   if (!rc) rc = check_hip(hipStreamWaitEvent((hipStream_t)stream, s.ev_out, 0), "ea_autotune wait");
   return rc;
+}
+
+// 64-bit FNV-1a hash of a string.
+static uint64_t fnv1a64(const char* x, uint64_t h = 0xcbf29ce484222325ull) {
+  for (; *x; ++x) h = (h ^ (uint64_t)(unsigned char)*x) * 0x100000001b3ull;
+  return h;
+}
+
+extern "C" int ea_autotune_cached(ea_state* st, const char* path, int32_t* tuned, char* report,
+                                  size_t report_len, void* stream) {
+  if (!st) return set_error(SBLM_ESTATE, "ea_autotune_cached: null state");
+  if (!path || !path[0]) return set_error(SBLM_EINVAL, "ea_autotune_cached: null path");
+  EaStateImpl& s = st->impl;
+  hipDeviceProp_t prop;
+  int rc = check_hip(hipGetDeviceProperties(&prop, s.device), "ea_autotune_cached device");
+  if (rc) return rc;
+  char dev[160];
+  snprintf(dev, sizeof(dev), "%s cu=%d lanes=%d ", prop.gcnArchName, prop.multiProcessorCount,
+           s.lanes);
+  const uint64_t key = fnv1a64(s.sig, fnv1a64(dev));
+  // look the key up: lines "<16 hex digits> lanes wpb persistent async ..."
+  FILE* f = fopen(path, "r");
+  if (f) {
+    char line[640];
+    while (fgets(line, sizeof(line), f)) {
+      unsigned long long k = 0;
+      int32_t sc[4];
+      if (sscanf(line, "%16llx %d %d %d %d", &k, &sc[0], &sc[1], &sc[2], &sc[3]) != 5 ||
+          (uint64_t)k != key)
+        continue;
+      fclose(f);
+      if (sc[0] != s.lanes)  // another rule's lanes: a different fit, not a schedule
+        return set_error(SBLM_EINVAL, "ea_autotune_cached: %s: entry %016llx has lanes %d, "
+                         "the state %d", path, k, sc[0], s.lanes);
+      if ((rc = ea_set_schedule(st, sc))) return rc;
+      if (tuned) *tuned = 0;
+      if (report && report_len)
+        snprintf(report, report_len, "kept: lanes=%d wpb=%d persistent=%d async=%d\n", sc[0],
+                 sc[1], sc[2], sc[3]);
+      return SBLM_OK;
+    }
+    fclose(f);
+  }
+  if ((rc = ea_autotune(st, report, report_len, stream))) return rc;
+  if (tuned) *tuned = 1;
+  f = fopen(path, "a");
+  if (!f) return set_error(SBLM_EINVAL, "ea_autotune_cached: cannot append to %s", path);
+  const int ok = fprintf(f, "%016llx %d %d %d %d %s%s\n", (unsigned long long)key, s.lanes,
+                         s.wpb, s.persistent, s.async, dev, s.sig) > 0;
+  if (fclose(f) != 0 || !ok)
+    return set_error(SBLM_EINVAL, "ea_autotune_cached: cannot append to %s", path);
+  return SBLM_OK;
 }
 
 extern "C" int ea_buffers(ea_state* st, double** P, double** chi2, double** Fs,

@@ -568,14 +568,15 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
     cx<double> zeta, c[6];
     const bool deg4 = epoch_poly(x, t, zeta, c);
     bool warm = have_prev && !deg4 && !prev_deg4;
-    if constexpr (G > 64) {
+    bool cached = false;  // started from the root cache (not a solved epoch)
+    if constexpr (G >= 64) {
       // simplex rounds: a lane's first epoch starts from the roots the lane
       // found there for the same trial slot in the previous round (the
       // simplex moves little between rounds), else cold -- always cold in
       // the first round of a run, so that a run does not depend on what ran
       // in its slot before
       if (s == 0 && a.root_cache && active && !deg4 &&
-          !(a.cold && a.cold[x.ind / a.skip_per])) {
+          !(a.cold && a.cold[x.ind / a.cold_per])) {
         const double* rc = a.root_cache + (x.ind * G + x.gl) * 10;
         cx<double> zc[5];
         bool fin = true;
@@ -588,6 +589,7 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
 #pragma unroll
           for (int i = 0; i < 5; ++i) z[i] = zc[i];
           warm = true;
+          cached = true;
         }
       }
     }
@@ -643,7 +645,7 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
       if (active && !ok) st.capped += 1;
       if (active && !settled) st.unsettled += 1;
     }
-    if constexpr (G > 64) {
+    if constexpr (G >= 64) {
       if (s == 0 && a.root_cache && active) {
         double* rc = a.root_cache + (x.ind * G + x.gl) * 10;
 #pragma unroll
@@ -653,8 +655,10 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
         }
       }
     }
+    // (roots started from the cache follow no solved epoch: the next epoch
+    // extrapolates from this one alone)
     have_prev3 = have_prev2 && warm && ok;
-    have_prev2 = warm && ok;
+    have_prev2 = warm && !cached && ok;
     t3 = t2;
     t2 = t1;
     t1 = t;
@@ -884,9 +888,10 @@ __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitn
   const int lane = threadIdx.x & 63;
   LaneStats st = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   // One-shot grid: wave w takes wave item w (blocks remapped so that
-  // consecutive logical blocks sit on one XCD).  Persistent grid: waves take
-  // items from a shared counter until it runs past the last one, so every
-  // wave reaches the exit.  One call site keeps one inlined copy of the body.
+  // consecutive logical blocks sit on one XCD, unless a work order is
+  // given).  Persistent grid: waves take items from a shared counter until
+  // it runs past the last one, so every wave reaches the exit.  One call
+  // site keeps one inlined copy of the body.
   const int64_t n_wave_items = G > 64 ? a.n_ind * (G / 64) : (a.n_ind + GPW - 1) / GPW;
   if constexpr (PERSIST) {
     if (a.xcd_start) {
@@ -924,10 +929,14 @@ __global__ __launch_bounds__(256, PERSIST ? 2 : SBLM_MIN_WAVES_PER_EU) void fitn
       }
     }
   } else {
+    // (with a work order, longest first, blocks keep the hardware order:
+    // consecutive items, of similar length, go to different XCDs, where the
+    // remap would put the longest eighth of the work on one of them)
     const int nb = gridDim.x, b = blockIdx.x;
     const int per = nb / 8, rem = nb % 8, xcd = b % 8, idx = b / 8;
-    const int lb = (xcd < rem) ? xcd * (per + 1) + idx
-                               : rem * (per + 1) + (xcd - rem) * per + idx;
+    const int lb = a.order ? b
+                   : (xcd < rem) ? xcd * (per + 1) + idx
+                                 : rem * (per + 1) + (xcd - rem) * per + idx;
     const int64_t wi = (int64_t)lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if constexpr (ASYNC)
       fit_wave_async<MODE, CHI2, G>(a, wi, st);

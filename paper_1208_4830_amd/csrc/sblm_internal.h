@@ -37,11 +37,12 @@ struct FitArgs {
   sblm_stats* stats;  // nullable
   // schedule
   const int32_t* order;  // nullable: item -> individual permutation
-  double* root_cache;     // nullable, G > 64 only: [n_ind][G][10] roots of
+  double* root_cache;     // nullable, G >= 64 only: [n_ind][G][10] roots of
                           // each lane's first epoch, read as its start
                           // (when finite) and rewritten after the solve
   const int32_t* cold;    // nullable (with root_cache): individual i ignores
-                          // the cache when cold[i / skip_per] != 0
+                          // the cache when cold[i / cold_per] != 0
+  int64_t cold_per;
   int32_t lanes_per_ind;  // 64, 32, 16 or 8 (a power of two dividing 64), or
                           // 128 / 256: several waves per individual (one-shot
                           // lockstep, wpb a multiple of G/64)

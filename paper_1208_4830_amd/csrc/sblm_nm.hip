@@ -31,6 +31,8 @@
 
 #include <mutex>
 
+#include <algorithm>
+
 #include "sblm_internal.h"
 #include "sblm_rng.h"
 
@@ -603,27 +605,42 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
   a.stats = stats;
   a.skip = w.done;  // a finished simplex's trial points are not evaluated
   a.skip_per = NS;
-  // rounds are latency-bound (each waits for its longest lightcurve, and
-  // later rounds hold only the unfinished simplices): a trial point spread
-  // over several waves shortens the chain of epochs per lane, and the root
-  // cache below spares the extra lanes their cold starts.  256 lanes unless
-  // the cache (80 B per lane) would pass 1 GiB, then 128, then 64 without a
-  // cache.  Measured per pass: 256 lightcurves x 1000 epochs 0.118 s at 256
-  // lanes (0.154 at 128, 0.213 at 64), 4096 ragged lightcurves 1.96 s at 256
-  // (2.08 at 128, 2.64 at 64).
+  a.cold_per = NS;
+  // Lanes per trial point.  While most simplices are still running a
+  // round is bound by its work, and 64 lanes (long chains of warm-started
+  // epochs per lane, one wave per trial point) do it fastest; later rounds
+  // hold few unfinished simplices and are bound by the chain of epochs of
+  // their longest lightcurve, which 128 or 256 lanes (several waves per
+  // trial point) shorten.  So the lanes follow the number of simplices that
+  // ran in the last round (read every 16 rounds): the fewest of 64, 128, 256
+  // that give the launch 2^19 lanes, else 256.  Every width keeps the roots
+  // of each lane's first epoch (80 B per lane and trial slot) and starts
+  // there in its next round (the simplex moves little between rounds; a
+  // cache of a width not used for a while is only a poorer start).  The
+  // choice depends on the simplices alone, so results are deterministic.
+  // Without room for the three caches (1 GiB) a fixed width: 256 lanes,
+  // else 128, else 64 without a cache; the allocation-free entry point and
+  // SBLM_NM_LANES fix it too (a cache only above 64 lanes).
   const int64_t n_trial = (int64_t)n * NS;
   const int64_t cache_max = (int64_t)1 << 30;
-  a.lanes_per_ind = n_trial * 256 * 80 <= cache_max   ? 256
-                    : n_trial * 128 * 80 <= cache_max ? 128
-                                                      : 64;
-  if (workspace) a.lanes_per_ind = 64;  // no root cache: nothing to allocate
-  if (const char* env = getenv("SBLM_NM_LANES"); env && !workspace) {
+  int fixed_g = 0;
+  if (workspace) {
+    fixed_g = 64;
+  } else if (const char* env = getenv("SBLM_NM_LANES")) {
     const int g = atoi(env);
-    if (g == 64 || g == 128 || g == 256) a.lanes_per_ind = g;
+    if (g == 64 || g == 128 || g == 256) fixed_g = g;
   }
-  // with several waves per trial point every lane would start cold once
-  // per round; the root cache lets it start from last round's roots instead
-  const int64_t n_cache = a.lanes_per_ind > 64 ? n_trial * a.lanes_per_ind * 10 : 0;
+  if (!fixed_g && n_trial * (64 + 128 + 256) * 80 > cache_max)
+    fixed_g = n_trial * 256 * 80 <= cache_max ? 256 : n_trial * 128 * 80 <= cache_max ? 128 : 64;
+  // cache of width 64 << i at root_cache + cache_off[i] (-1: none)
+  int64_t cache_off[3] = {-1, -1, -1}, n_cache = 0;
+  for (int i = 0; i < 3; ++i) {
+    const int g = 64 << i;
+    if (fixed_g ? (g == fixed_g && g > 64) : true) {
+      cache_off[i] = n_cache;
+      n_cache += n_trial * g * 10;
+    }
+  }
   if (rc == SBLM_OK && n_cache > 0) {
     if (hipMalloc(&root_cache, (size_t)n_cache * sizeof(double)) != hipSuccess) {
       (void)hipGetLastError();
@@ -635,7 +652,56 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
       rc = check_hip(hipGetLastError(), "nm_refine: cache");
     }
   }
-  a.root_cache = root_cache;
+  // Work order of the trial points, longest lightcurve first (stable), a
+  // simplex's four trial points together: one round launches every trial
+  // point at once, over lightcurves of very different lengths, and a long
+  // one dispatched last would hold the round up.  (Not with a caller's
+  // workspace: the order changes no result, only the balance.)
+  int32_t* order = nullptr;
+  if (rc == SBLM_OK && !workspace && lcs.n_lc > 1) {
+    const int nl = lcs.n_lc;
+    int64_t* off_h = (int64_t*)malloc((size_t)(nl + 1) * sizeof(int64_t));
+    int32_t* lc_h = (int32_t*)malloc((size_t)nl * sizeof(int32_t));
+    int32_t* ord_h = (int32_t*)malloc((size_t)n_trial * sizeof(int32_t));
+    if (!off_h || !lc_h || !ord_h) {
+      rc = set_error(SBLM_ENOMEM, "nm_refine: host allocation");
+    } else {
+      rc = check_hip(hipMemcpyAsync(off_h, lcs.off, (size_t)(nl + 1) * sizeof(int64_t),
+                                    hipMemcpyDeviceToHost, st),
+                     "nm_refine: offsets");
+      if (rc == SBLM_OK) rc = check_hip(hipStreamSynchronize(st), "nm_refine: offsets");
+    }
+    if (rc == SBLM_OK) {
+      for (int k = 0; k < nl; ++k) lc_h[k] = k;
+      std::stable_sort(lc_h, lc_h + nl, [&](int32_t i, int32_t j) {
+        return off_h[i + 1] - off_h[i] > off_h[j + 1] - off_h[j];
+      });
+      int64_t o = 0;
+      for (int r = 0; r < nl; ++r)
+        for (int64_t j = (int64_t)lc_h[r] * reps; j < (int64_t)(lc_h[r] + 1) * reps; ++j)
+          for (int slot = 0; slot < NS; ++slot) ord_h[o++] = (int32_t)(j * NS + slot);
+      if (hipMalloc(&order, (size_t)n_trial * sizeof(int32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        order = nullptr;
+        rc = set_error(SBLM_ENOMEM, "nm_refine: device allocation");
+      } else {
+        rc = check_hip(hipMemcpyAsync(order, ord_h, (size_t)n_trial * sizeof(int32_t),
+                                      hipMemcpyHostToDevice, st),
+                       "nm_refine: order");
+        if (rc == SBLM_OK) rc = check_hip(hipStreamSynchronize(st), "nm_refine: order");
+      }
+    }
+    free(off_h);
+    free(lc_h);
+    free(ord_h);
+  }
+  a.order = order;
+  auto set_lanes = [&](int g) {
+    a.lanes_per_ind = g;
+    const int i = g == 64 ? 0 : g == 128 ? 1 : 2;
+    a.root_cache = (root_cache && cache_off[i] >= 0) ? root_cache + cache_off[i] : nullptr;
+  };
+  set_lanes(fixed_g ? fixed_g : 64);
   a.cold = w.fresh;
   const dim3 grid((n + 255) / 256), blk(256);
   if (rc == SBLM_OK) {
@@ -647,7 +713,13 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
   const int64_t max_rounds =
       (4 + 3 * (int64_t)cfg.max_iter) * (iter ? (int64_t)w.reps * w.runs : 1);
   const int chunk = 16;
+  unsigned int active = (unsigned int)n;  // simplices that ran in the last round
   for (int64_t r = 0; rc == SBLM_OK && r < max_rounds; r += chunk) {
+    if (!fixed_g) {
+      const int64_t want = (int64_t)1 << 19;
+      const int64_t tp = (int64_t)active * NS;
+      set_lanes(tp * 64 >= want ? 64 : tp * 128 >= want ? 128 : 256);
+    }
     for (int k = 0; k < chunk && rc == SBLM_OK; ++k) {
       hipLaunchKernelGGL(nm_test_kernel, grid, blk, 0, st, w, cfg.tol_x, cfg.tol_f,
                          cfg.max_iter);
@@ -663,7 +735,6 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
       }
       rc = check_hip(e, "nm_refine: round");
     }
-    unsigned int active = 1;
     if (rc == SBLM_OK)
       rc = check_hip(hipMemcpyAsync(&active, w.active, 4, hipMemcpyDeviceToHost, st),
                      "nm_refine: copy");
@@ -683,6 +754,7 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
     rc = check_hip(hipGetLastError(), "nm_refine: synchronise");
   if (block && !workspace) (void)hipFree(block);
   if (root_cache) (void)hipFree(root_cache);
+  if (order) (void)hipFree(order);
   return rc;
 }
 

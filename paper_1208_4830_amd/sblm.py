@@ -80,6 +80,8 @@ _SIGS = {
     "ea_load": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "ea_destroy": [ctypes.c_void_p],
     "ea_autotune": [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t, ctypes.c_void_p],
+    "ea_autotune_cached": [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
+                           ctypes.c_char_p, ctypes.c_size_t, ctypes.c_void_p],
     "ea_get_schedule": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)],
     "ea_time_fitness": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p],
     "ea_fitness_time": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
@@ -334,10 +336,17 @@ class EAState:
         _check(load().ea_fitness_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
-    def autotune(self, stream=None):
-        """Time the candidate schedules; returns the report text."""
+    def autotune(self, stream=None, cache=None):
+        """Time the candidate schedules; returns the report text.  With
+        `cache` (a file path) a choice kept there for this device and
+        workload is installed instead, or the new choice is appended."""
         buf = ctypes.create_string_buffer(4096)
-        _check(load().ea_autotune(self.h, buf, len(buf), _stream(stream)))
+        if cache is None:
+            _check(load().ea_autotune(self.h, buf, len(buf), _stream(stream)))
+        else:
+            tuned = ctypes.c_int32(-1)
+            _check(load().ea_autotune_cached(self.h, os.fsencode(cache), ctypes.byref(tuned),
+                                             buf, len(buf), _stream(stream)))
         return buf.value.decode()
 
     def schedule(self):

@@ -221,21 +221,56 @@ def test_schedules_agree_and_autotune(hip, mode):
     st.set_schedule(16, 4, 1, 0)
     rep = st.autotune()
     lanes, wpb, pers, asy = st.schedule()
-    # stepping (2), waves per block (3), launch form (2), chosen
-    assert "chosen:" in rep and len(rep.splitlines()) == 8
+    # the start, stepping (2), waves per block (3), launch form (2), chosen
+    assert "chosen:" in rep and len(rep.splitlines()) == 9
     assert lanes == 16 and wpb in (1, 2, 4) and pers in (0, 1) and asy in (0, 1)
     st.fit(6)
     assert st.save() == blobs[(16, 4, 1, 0)]
     st.close()
     st, _, _ = _make_state(hip, wl, pop, seed=21, mode=mode)
     rep = st.autotune()  # wide: waves per block 4 only (one-shot, lockstep)
-    assert st.schedule() == (256, 4, 0, 0) and len(rep.splitlines()) == 4
+    assert st.schedule() == (256, 4, 0, 0) and len(rep.splitlines()) == 5
     with pytest.raises(hip.SblmError):  # blocks beyond the kernels' bound
         st.set_schedule(16, 8, 1)
     for bad in ((256, 2, 0, 0), (256, 4, 1, 0), (128, 4, 0, 1)):
         with pytest.raises(hip.SblmError):  # wide lanes: whole individuals, one-shot, lockstep
             st.set_schedule(*bad)
     st.close()
+
+
+def test_autotune_keeps_its_choice(hip, tmp_path):
+    # ea_autotune_cached: the first state of a workload is tuned and its
+    # choice kept in the file; a second state of the same workload installs
+    # it without timing, and the fit is the same bits either way
+    wl = csr_workload(9, [0, 5, 64, 201, 777, 1500, 3000])
+    path = tmp_path / "schedules.txt"
+    st1, _, _ = _make_state(hip, wl, 32, seed=21)
+    st1.set_schedule(16, 4, 1, 0)
+    rep1 = st1.autotune(cache=path)
+    assert "chosen:" in rep1
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].split()[1:5] == [str(v) for v in st1.schedule()]
+    st1.fit(6)
+    st2, _, _ = _make_state(hip, wl, 32, seed=21)
+    st2.set_schedule(16, 1, 0, 1)  # what the kept choice replaces
+    assert st2.autotune(cache=path).startswith("kept:")
+    assert st2.schedule() == st1.schedule() and len(path.read_text().splitlines()) == 1
+    st2.fit(6)
+    assert st2.save() == st1.save()
+    # another workload (population) is another key: tuned and appended
+    st3, _, _ = _make_state(hip, wl, 48, seed=21)
+    assert "chosen:" in st3.autotune(cache=path)
+    assert len(path.read_text().splitlines()) == 2
+    # a kept entry whose lanes differ from the state's is refused (the lanes
+    # are part of the fit, not of the schedule); the first matching line wins
+    key = lines[0].split()[0]
+    path.write_text(f"{key} 64 4 1 0 edited\n" + path.read_text())
+    st4, _, _ = _make_state(hip, wl, 32, seed=21)
+    st4.set_schedule(16, 4, 1, 0)  # (the key covers the state's lanes)
+    with pytest.raises(hip.SblmError, match="lanes"):
+        st4.autotune(cache=path)
+    for st in (st1, st2, st3, st4):
+        st.close()
 
 
 @pytest.mark.parametrize("mode", [0, 1])

@@ -55,6 +55,7 @@ def test_harness_matches_oracle(hip, experiment):
         _, fs, fb = hip.sblm_chi2(obs["lcs"], torch.as_tensor(th, device="cuda"), 1)
         fs, fb = fs.cpu().numpy(), fb.cpu().numpy()
         weak, strict, dchi = E.evaluate(hip, torch, wl, obs, th, fs, fb)
+        _, strict_l, _ = E.evaluate(hip, torch, wl, obs, th, fs, fb, lens_only=True)
         for k in range(wl.n_lc):
             sl = slice(wl.off[k], wl.off[k + 1])
             m_true, m_obs, sigma = _oracle_obs(wl, k)
@@ -67,6 +68,9 @@ def test_harness_matches_oracle(hip, experiment):
             assert abs(dchi[k] - d_o) <= 1e-7 * abs(d_o) + 1e-9, (scale, k)
             if abs(d_o - 1.0) > 1e-6:
                 assert (weak[k], strict[k]) == (w_o, s_o), (scale, k)
+                l_o = P.success(experiment, th[:, k], fs[k], fb[k], A[0], m_obs, sigma, m_true,
+                                wl.theta[:, k], wl.m0[k], wl.f[k], lens_only=True)[1]
+                assert strict_l[k] == l_o, (scale, k)
 
 
 def test_experiment_runs_end_to_end(hip):
@@ -77,5 +81,6 @@ def test_experiment_runs_end_to_end(hip):
     for r in out["checkpoints"]:
         for form in ("ea", "ea_amoeba"):
             s, w = r[form]["strict"]["all"], r[form]["weak"]["all"]
-            assert 0.0 <= s <= w <= 1.0
+            sl = r[form]["strict_lens"]["all"]
+            assert 0.0 <= s <= sl <= w <= 1.0
     assert 0.0 <= out["iterated_simplex"]["weak"]["all"] <= 1.0

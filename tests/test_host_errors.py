@@ -86,7 +86,8 @@ def test_ea_domain_and_state_errors():
     for call in (lambda: lib.ea_generation(None, FAKE, FAKE, FAKE, None),
                  lambda: lib.ea_fit(None, 1, None, None),
                  lambda: lib.ea_migrate(None, None, None, None, None),
-                 lambda: lib.ea_refine(None, None, None, None, None)):
+                 lambda: lib.ea_refine(None, None, None, None, None),
+                 lambda: lib.ea_autotune_cached(None, b"/tmp/x", None, None, 0, None)):
         assert call() == ESTATE
 
 

@@ -93,6 +93,23 @@ def test_success_criterion(experiment):
     # a model with negative flux somewhere fails
     assert P.success(experiment, theta, -Fs, Fb, A, m_true, sigma, m_true, theta, m0, f)[:2] \
         == (False, False)
+    # the lens-only strict test: the true lens with a blend fraction 20% off
+    # (same m0; errors so large that the weak test passes) passes it and,
+    # with blending, fails the full strict test
+    tot, f2, big = Fs + Fb, f * 0.8, np.full(100, 10.0)
+    r = P.success(experiment, theta, f2 * tot, (1 - f2) * tot, A, m_true, big, m_true,
+                  theta, m0, f, lens_only=True)
+    full = P.success(experiment, theta, f2 * tot, (1 - f2) * tot, A, m_true, big, m_true,
+                     theta, m0, f)
+    assert r[:2] == (True, True) and full[:2] == (True, experiment == 1)
+    # a lens parameter 11% off fails the lens-only test, 9% off passes it
+    th = theta.copy()
+    th[2] *= 1.11
+    assert P.success(experiment, th, Fs, Fb, A, m_true, sigma, m_true, theta, m0, f,
+                     lens_only=True)[:2] == (True, False)
+    th[2] = theta[2] * 1.09
+    assert P.success(experiment, th, Fs, Fb, A, m_true, sigma, m_true, theta, m0, f,
+                     lens_only=True)[:2] == (True, True)
 
 
 def test_peak_count_against_scipy_prominence():
