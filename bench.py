@@ -312,6 +312,7 @@ def success_run(sblm, torch, lcs, chi2_true, pop, mode, sched, lo, hi, proposals
         s_nm = float(np.mean(c2 <= chi2_true + 10.0))
         curve.append(dict(gen=gens, ea=round(s_ea, 4), ea_amoeba=round(s_nm, 4),
                           ea_seconds=round(ea_s, 3), amoeba_seconds=round(nm_s, 3)))
+        log(f"bench:   checkpoint {json.dumps(curve[-1])}")
         if hit_ea is None and s_ea >= target:
             hit_ea = (gens, ea_s)
         if hit_nm is None and s_nm >= target:
