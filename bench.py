@@ -14,11 +14,13 @@ the true parameters + 10) and fits/hour.
 Chosen form (the batching workload): 4096 lightcurves of 200-5000 irregular
 epochs, population 128, autotuned schedule, a full 500-generation fit timed
 the same way.  On the same lightcurves the time to 90% success is measured
-for the plain EA, for the EA seeded by the window alone (the ablation) and
-for the EA seeded by the proposal network (the learned form), each with the
-paper's simplex fine-tuning of the fittest solution at every checkpoint;
-fits/hour at >= 90% success follows.  The CPU oracle is timed on a bounded
-sample of the headline workload.
+for the plain EA and for the EA seeded by the proposal network (the learned
+form), each with the paper's simplex fine-tuning of the fittest solution at
+every checkpoint, and for the learned form that then spends more effort on
+the lightcurves whose fit is still poor by its own reduced chi^2 (options:
+the EA seeded by the window alone, the ablation; the learned form on
+islands); fits/hour at >= 90% success follows.  The CPU oracle is timed on a
+bounded sample of the headline workload.
 
 Prints ONE JSON line (a summary line goes to stderr just before it).
 """
@@ -111,9 +113,11 @@ def parse():
                     help="generation cap of the time-to-90%% success runs on the chosen-form "
                          "lightcurves (0 = skip them)")
     ap.add_argument("--success-every", type=int, default=200)
-    ap.add_argument("--success-forms", default="plain,window,learned",
-                    help="forms of the success study: plain EA, window-only seeding, network "
-                         "seeding, network seeding on islands (learned_islands)")
+    ap.add_argument("--success-forms", default="plain,learned,learned_adaptive",
+                    help="forms of the success study: plain EA (plain), window-only seeding "
+                         "(window), network seeding (learned), network seeding on islands "
+                         "(learned_islands), network seeding with effort where the fit is "
+                         "poor (learned_adaptive)")
     ap.add_argument("--iterated", default="",
                     help="iterated-simplex comparison on the headline lightcurves: slots per "
                          "lightcurve,runs per slot,max steps per run (e.g. 16,4,10000)")
@@ -332,6 +336,115 @@ def success_run(sblm, torch, lcs, chi2_true, pop, mode, sched, lo, hi, proposals
                               fits_per_hour=per_hour(hit_ea)))
 
 
+def simplex_passes(sblm, torch, lcs, lo, hi, x, c, passes, nm_cfg):
+    """`passes` simplex passes, each restarted from the last result; the
+    best point and chi^2 seen (the start's included)."""
+    xb, cb = x.clone(), c.clone()
+    for _ in range(passes):
+        x, cp, _, _, _ = sblm.nm_refine(lcs, lo, hi, x, nm_cfg)
+        better = cp < cb
+        xb = torch.where(better, x, xb)
+        cb = torch.minimum(cb, cp)
+    return xb, cb
+
+
+def subset_batch(sblm, torch, lcs, idx):
+    """The lightcurves idx of a device batch as a batch of their own."""
+    off = lcs.off.cpu().numpy()
+    L = np.diff(off)[idx]
+    sub_off = np.concatenate([[0], np.cumsum(L)]).astype(np.int64)
+    sel = np.concatenate([np.arange(off[k], off[k + 1]) for k in idx]) if len(idx) else \
+        np.zeros(0, np.int64)
+    sel = torch.as_tensor(sel, device=lcs.t.device)
+    return sblm.Lightcurves(torch.as_tensor(sub_off, device=lcs.t.device), lcs.t[sel].contiguous(),
+                            lcs.y[sel].contiguous(), lcs.w[sel].contiguous())
+
+
+def adaptive_run(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, proposals, stage1_gen=400,
+                 pop2=1024, every=100, max_gen2=1000, red_thr=1.05, target=0.9, seed=7,
+                 passes=3):
+    """The learned form with effort where the fit asks for it.  Stage 1: the
+    learned form on every lightcurve for `stage1_gen` generations, then twice
+    `passes` simplex passes from each fittest solution.  Lightcurves whose
+    fit is still poor by its own measure (reduced chi^2 = chi^2 / (L - 6)
+    above `red_thr`; the data's errors are known, so a good fit sits near 1)
+    get stage 2: a fresh network-seeded EA of population `pop2` on those
+    lightcurves alone, with `passes` simplex passes from its fittest
+    solutions every `every` generations; a lightcurve keeps the better of
+    its two fits.  Success and GPU time are counted as in success_run (EA time
+    so far, stage 1's passes included, + that checkpoint's passes)."""
+    sync = torch.cuda.synchronize
+    n_lc = len(chi2_true)
+    nm_cfg = sblm.nm_default_config()
+    cfg = sblm.ea_default_config()
+    cfg.pop = pop
+    sync()
+    t0 = time.perf_counter()
+    st = sblm.EAState(cfg, lcs, seed)
+    st.set_schedule(*sched)
+    st.seed(proposals, pop // 2, at_restarts=True)
+    st.fit(stage1_gen)
+    x, c = st.best()
+    x, c1 = simplex_passes(sblm, torch, lcs, lo, hi, x, c, 2 * passes, nm_cfg)
+    sync()
+    base_s = time.perf_counter() - t0
+    st.close()
+    c1 = c1.cpu().numpy()
+    L = np.diff(lcs.off.cpu().numpy())
+    red = c1 / np.maximum(L - 6, 1)
+    idx = np.nonzero(red > red_thr)[0]
+    s1 = float(np.mean(c1 <= chi2_true + 10.0))
+    curve = [dict(gen=stage1_gen, stage=1, success=round(s1, 4), gpu_seconds=round(base_s, 3),
+                  flagged=int(len(idx)))]
+    log(f"bench:   stage 1 {json.dumps(curve[-1])}")
+    hit = (stage1_gen, base_s) if s1 >= target else None
+    if hit is None and len(idx):
+        sync()
+        t0 = time.perf_counter()
+        lcs2 = subset_batch(sblm, torch, lcs, idx)
+        props2 = proposals[torch.as_tensor(idx, device=proposals.device)].contiguous()
+        cfg2 = sblm.ea_default_config()
+        cfg2.pop = pop2
+        st2 = sblm.EAState(cfg2, lcs2, seed + 4)
+        st2.seed(props2, pop2 // 2, at_restarts=True)
+        sync()
+        ea_s = base_s + time.perf_counter() - t0
+        best = c1.copy()
+        gens = 0
+        while gens < max_gen2:
+            sync()
+            t0 = time.perf_counter()
+            st2.fit(every)
+            sync()
+            ea_s += time.perf_counter() - t0
+            gens += every
+            x2, c2 = st2.best()
+            sync()
+            t0 = time.perf_counter()
+            _, c2 = simplex_passes(sblm, torch, lcs2, lo, hi, x2, c2, passes, nm_cfg)
+            sync()
+            nm_s = time.perf_counter() - t0
+            best[idx] = np.minimum(c1[idx], c2.cpu().numpy())
+            succ = float(np.mean(best <= chi2_true + 10.0))
+            curve.append(dict(gen=stage1_gen + gens, stage=2, success=round(succ, 4),
+                              gpu_seconds=round(ea_s + nm_s, 3)))
+            log(f"bench:   checkpoint {json.dumps(curve[-1])}")
+            if succ >= target:
+                hit = (stage1_gen + gens, ea_s + nm_s)
+                break
+        st2.close()
+    last = curve[-1]["gen"]
+    return dict(target=target, curve=curve,
+                config=dict(stage1_generations=stage1_gen, stage1_passes=2 * passes,
+                            reduced_chi2_above=red_thr, pop_stage2=pop2, every=every,
+                            stage2_max_generations=max_gen2),
+                ea_amoeba=dict(reached=hit is not None,
+                               generations=hit[0] if hit else None,
+                               gpu_seconds=hit[1] if hit else None,
+                               fits_per_hour=(n_lc * 3600.0 / hit[1] if hit else
+                                              f"not reached by generation {last}")))
+
+
 def iterated_run(sblm, torch, lcs, chi2_true, lo, hi, reps, runs, max_iter, seed=7):
     """The paper's iterated simplex (Sec. 4.1) on the GPU fitness: reps * runs
     random starts per lightcurve, each run to convergence or max_iter steps,
@@ -400,11 +513,13 @@ PEAK_BF16_TFLOPS = 2500.0
 
 
 def success_study(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, net, train_info, args):
-    """Time to 90% success on the chosen-form lightcurves: the plain EA, the
-    EA half seeded (at the start and at every restart) from the observation
-    window alone, and the EA half seeded by the proposal network (the
-    learned form), each with the simplex fine-tuning of the fittest solution
-    at every checkpoint and stopped once 90% of the lightcurves succeed."""
+    """Time to 90% success on the chosen-form lightcurves for the forms in
+    --success-forms: the plain EA, the EA half seeded (at the start and at
+    every restart) from the observation window alone, the EA half seeded by
+    the proposal network (the learned form; also on islands), each with the
+    simplex fine-tuning of the fittest solution at every checkpoint and
+    stopped once 90% of the lightcurves succeed; and the learned form with
+    a second stage on the lightcurves whose fit is poor (adaptive_run)."""
     forms = [f for f in args.success_forms.split(",") if f]
     out = dict(workload=f"{len(chi2_true)} lightcurves, pop {pop}, {pop // 2} rows seeded at "
                         f"the start and at every restart; EA + three simplex passes from the "
@@ -416,7 +531,7 @@ def success_study(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, net, train_in
     for f in forms:
         log(f"bench: success study, form {f}")
         kw = {}
-        if f in ("learned", "learned_islands"):
+        if f in ("learned", "learned_islands", "learned_adaptive"):
             if props is None:
                 props, t_inf = propose(sblm, torch, net, lcs)
                 out["inference_seconds"] = t_inf
@@ -427,8 +542,11 @@ def success_study(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, net, train_in
             # the learned form on islands: half of every island's rows seeded,
             # a simplex from every island's record at each checkpoint
             kw["islands"] = isl
-        r = success_run(sblm, torch, lcs, chi2_true, pop, sblm.FP64, sched, lo, hi,
-                        max_gen=args.success_max_gen, every=args.success_every, **kw)
+        if f == "learned_adaptive":
+            r = adaptive_run(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, kw["proposals"])
+        else:
+            r = success_run(sblm, torch, lcs, chi2_true, pop, sblm.FP64, sched, lo, hi,
+                            max_gen=args.success_max_gen, every=args.success_every, **kw)
         if f == "learned_islands":
             r["config"] = dict(islands=isl[0], pop_per_island=pop // isl[0],
                                migrate_every=isl[1], migrants=isl[2])
@@ -699,8 +817,8 @@ def main():
 
     at90 = None
     if study:
-        forms_done = [f for f in ("plain", "window", "learned", "learned_islands", "islands")
-                      if f in study]
+        forms_done = [f for f in ("plain", "window", "learned", "learned_islands",
+                                  "learned_adaptive", "islands") if f in study]
         at90 = {f: study[f]["ea_amoeba"]["fits_per_hour"] for f in forms_done}
         at90["gpu_seconds"] = {f: study[f]["ea_amoeba"]["gpu_seconds"] for f in forms_done}
         at90["workload"] = "the chosen-form lightcurves (EA + simplex fine-tuning, FP64)"
