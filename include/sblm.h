@@ -653,7 +653,16 @@ int mlp_adam_step(mlp_net* net, float lr, void* stream);
  * mlp_train -- epochs x floor(rows/batch) steps of mlp_loss_grad + Adam
  * over consecutive batches of (x, y), the learning rate following a cosine
  * from lr0 (first step) to lr1 (last step).  loss (nullable, device float
- * [epochs*floor(rows/batch)]) receives the loss of every step.
+ * [epochs*floor(rows/batch)]) receives the loss of every step.  The steps
+ * are the ones that mlp_loss_grad and mlp_adam_step would take one call at
+ * a time, bit for bit; here one step is captured as a HIP graph (batch
+ * gather, forward, likelihood, backward, Adam, all reading the step index
+ * from device memory) and replayed on the net's own stream, which follows
+ * `stream` and which `stream` then waits for.  The graph is kept with the
+ * net for later calls of the same shape and data; step buffers of 16 B per
+ * step grow as needed (with a synchronisation of the net's stream).
+ * Errors: SBLM_EINVAL, SBLM_ERANGE (more than 2^31 steps), SBLM_ENOMEM,
+ * SBLM_EDEVICE.
  */
 int mlp_train(mlp_net* net, const uint16_t* x, const float* y, int64_t rows,
               int32_t batch, int32_t epochs, float lr0, float lr1, float* loss,

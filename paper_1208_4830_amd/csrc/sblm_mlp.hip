@@ -126,12 +126,26 @@ __device__ __forceinline__ void store_tile(uint16_t* S, const uint4* v) {
 
 // TKS: k values per LDS stage (32 or 128); deeper stages keep more loads in
 // flight per round trip, which is what bounds these small GEMMs.
+// Up to three independent products of one shape class in one launch (the
+// three weight gradients of a step): blockIdx.x runs over the output tiles
+// of problem 0, then 1, then 2 (first[p] = its first block), blockIdx.z over
+// the K ranges, which all problems share.
+struct GemmGroup {
+  GemmArgs g[3];
+  int first[4];
+  int nprob;
+};
+
 template <bool AK, bool BK, int TKS>
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmGroup gg) {
   constexpr int STRIDE = TKS + 8;  // padded LDS row (elements)
   __shared__ __attribute__((aligned(16))) uint16_t sA[2][TM * STRIDE];
   __shared__ __attribute__((aligned(16))) uint16_t sB[2][TM * STRIDE];
-  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TM;
+  int prob = 0;
+  while (prob + 1 < gg.nprob && (int)blockIdx.x >= gg.first[prob + 1]) ++prob;
+  const GemmArgs& g = gg.g[prob];
+  const int tile = (int)blockIdx.x - gg.first[prob], ntn = g.N / TM;
+  const int m0 = (tile / ntn) * TM, n0 = (tile % ntn) * TM;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int nst = g.K / TKS / gridDim.z;  // stages of this K range
@@ -141,32 +155,37 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 
-  uint4 ra[TKS / 32], rb[TKS / 32];
-  load_tile<AK, TKS>(g.A, g.lda, m0, kb, ra);
-  load_tile<BK, TKS>(g.B, g.ldb, n0, kb, rb);
-  store_tile<AK, TKS>(sA[0], ra);
-  store_tile<BK, TKS>(sB[0], rb);
-  __syncthreads();
-  for (int s = 0; s < nst; ++s) {
-    const int cur = s & 1;
-    if (s + 1 < nst) {
-      load_tile<AK, TKS>(g.A, g.lda, m0, kb + (s + 1) * TKS, ra);
-      load_tile<BK, TKS>(g.B, g.ldb, n0, kb + (s + 1) * TKS, rb);
-    }
-    const uint16_t* pa = sA[cur] + (wm + (lane & 31)) * STRIDE + 8 * (lane >> 5);
-    const uint16_t* pb = sB[cur] + (wn + (lane & 31)) * STRIDE + 8 * (lane >> 5);
+  // the MFMAs of the stage in LDS buffer `buf`
+  auto mfma_stage = [&](int buf) {
+    const uint16_t* pa = sA[buf] + (wm + (lane & 31)) * STRIDE + 8 * (lane >> 5);
+    const uint16_t* pb = sB[buf] + (wn + (lane & 31)) * STRIDE + 8 * (lane >> 5);
 #pragma unroll
     for (int kk = 0; kk < TKS; kk += 16) {
       const bf16x8 a = *(const bf16x8*)(pa + kk);
       const bf16x8 b = *(const bf16x8*)(pb + kk);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
-    if (s + 1 < nst) {
-      store_tile<AK, TKS>(sA[cur ^ 1], ra);
-      store_tile<BK, TKS>(sB[cur ^ 1], rb);
-    }
+  };
+  uint4 ra[TKS / 32], rb[TKS / 32];
+  load_tile<AK, TKS>(g.A, g.lda, m0, kb, ra);
+  load_tile<BK, TKS>(g.B, g.ldb, n0, kb, rb);
+  store_tile<AK, TKS>(sA[0], ra);
+  store_tile<BK, TKS>(sB[0], rb);
+  __syncthreads();
+  // software pipeline: the next stage's loads are in flight during this
+  // stage's MFMAs; the last stage is peeled off, so the staging registers
+  // are written on every pass of the loop (a conditional load kept them in
+  // scratch memory, and the loads were waited for at once)
+  for (int s = 0; s + 1 < nst; ++s) {
+    const int cur = s & 1;
+    load_tile<AK, TKS>(g.A, g.lda, m0, kb + (s + 1) * TKS, ra);
+    load_tile<BK, TKS>(g.B, g.ldb, n0, kb + (s + 1) * TKS, rb);
+    mfma_stage(cur);
+    store_tile<AK, TKS>(sA[cur ^ 1], ra);
+    store_tile<BK, TKS>(sB[cur ^ 1], rb);
     __syncthreads();
   }
+  mfma_stage((nst - 1) & 1);
 
   // lane l, register r holds C[(r%4) + 8(r/4) + 4(l/32)][l%32] of the wave
   const int n = n0 + wn + (lane & 31);
@@ -186,22 +205,36 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
 }
 
 template <int TKS>
-hipError_t gemm_t(const GemmArgs& g, bool ak, bool bk, hipStream_t st) {
-  const dim3 grid(g.N / TM, g.M / TM, g.ksplit > 1 ? g.ksplit : 1);
+hipError_t gemm_t(const GemmGroup& gg, bool ak, bool bk, hipStream_t st) {
+  const int ks = gg.g[0].ksplit > 1 ? gg.g[0].ksplit : 1;
+  const dim3 grid(gg.first[gg.nprob], 1, ks);
   if (ak && !bk)
-    hipLaunchKernelGGL((gemm_bf16_kernel<true, false, TKS>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<true, false, TKS>), grid, dim3(256), 0, st, gg);
   else if (ak && bk)
-    hipLaunchKernelGGL((gemm_bf16_kernel<true, true, TKS>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<true, true, TKS>), grid, dim3(256), 0, st, gg);
   else if (!ak && !bk)
-    hipLaunchKernelGGL((gemm_bf16_kernel<false, false, TKS>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<false, false, TKS>), grid, dim3(256), 0, st, gg);
   else
-    hipLaunchKernelGGL((gemm_bf16_kernel<false, true, TKS>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<false, true, TKS>), grid, dim3(256), 0, st, gg);
   return hipGetLastError();
 }
 
+// C = A B for n (1..3) problems with the same operand layouts, K and K split.
+hipError_t gemm_group(const GemmArgs* gs, int n, bool ak, bool bk, hipStream_t st) {
+  GemmGroup gg;
+  memset(&gg, 0, sizeof(gg));
+  gg.nprob = n;
+  gg.first[0] = 0;
+  for (int i = 0; i < n; ++i) {
+    gg.g[i] = gs[i];
+    gg.first[i + 1] = gg.first[i] + (gs[i].N / TM) * (gs[i].M / TM);
+  }
+  const int ks = gs[0].ksplit > 1 ? gs[0].ksplit : 1;
+  return (gs[0].K / ks) % 128 == 0 ? gemm_t<128>(gg, ak, bk, st) : gemm_t<32>(gg, ak, bk, st);
+}
+
 hipError_t gemm(const GemmArgs& g, bool ak, bool bk, hipStream_t st) {
-  const int ks = g.ksplit > 1 ? g.ksplit : 1;
-  return (g.K / ks) % 128 == 0 ? gemm_t<128>(g, ak, bk, st) : gemm_t<32>(g, ak, bk, st);
+  return gemm_group(&g, 1, ak, bk, st);
 }
 
 // --------------------------------------------------- mixture likelihood
@@ -375,6 +408,79 @@ __global__ void adam_kernel(float* p, const float* g, float* m, float* v,
     p[i] = pi;
     pb[i] = f2bf(pi);
   }
+}
+
+// The split-K partials of the three weight gradients of one step (a buffer
+// each), for the graph form of training: the Adam kernel sums them.
+struct KParts {
+  const float* part[3];
+  int64_t off[3];  // first parameter of the tensor
+  int64_t mn[3];   // its elements
+  int ks;          // partials per tensor (1: none, the GEMM wrote the gradient)
+};
+
+// adam_kernel for a step of the captured training graph: the step's learning
+// rate and bias-correction factors are read from sched[3k .. 3k+2] (k = the
+// device step counter), and a weight tensor's gradient is first summed over
+// its split-K partials, in range order (as splitk_reduce sums them), and
+// stored to g.
+__global__ void adam_graph_kernel(float* p, float* g, float* m, float* v, uint16_t* pb,
+                                  int64_t n, const float* sched, const int64_t* dstep,
+                                  KParts kp, float b1, float b2, float omb1, float omb2,
+                                  float eps) {
+  const int64_t k = *dstep;
+  const float lr = sched[3 * k], c1 = sched[3 * k + 1], c2 = sched[3 * k + 2];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float gi = 0.0f;
+    bool summed = false;
+    if (kp.ks > 1) {
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int64_t j = i - kp.off[t];
+        if (j >= 0 && j < kp.mn[t]) {
+          float sum = kp.part[t][j];
+          for (int z = 1; z < kp.ks; ++z) sum += kp.part[t][(int64_t)z * kp.mn[t] + j];
+          g[i] = sum;
+          gi = sum;
+          summed = true;
+        }
+      }
+    }
+    if (!summed) gi = g[i];
+    const float mi = b1 * m[i] + omb1 * gi;
+    const float vi = b2 * v[i] + omb2 * (gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    p[i] = pi;
+    pb[i] = f2bf(pi);
+  }
+}
+
+// First node of a training step: batch k mod per of (x, y) into the net's
+// own buffers, k = the device step counter.
+__global__ void batch_gather_kernel(const uint16_t* x, const float* y, int64_t per, int batch,
+                                    const int64_t* dstep, uint16_t* xb, float* yb) {
+  const int64_t r0 = (*dstep % per) * batch;
+  const uint4* xs = (const uint4*)(x + r0 * NB);
+  uint4* xd = (uint4*)xb;
+  const int64_t nx = (int64_t)batch * NB / 8, ny = (int64_t)batch * DM;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nx + ny;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < nx)
+      xd[i] = xs[i];
+    else
+      yb[i - nx] = y[r0 * DM + (i - nx)];
+  }
+}
+
+// Last node of a training step: the step's loss to losses[k], k + 1 to the
+// counter.
+__global__ void step_advance_kernel(int64_t* dstep, const float* loss_slot, float* losses) {
+  const int64_t k = *dstep;
+  losses[k] = *loss_slot;
+  *dstep = k + 1;
 }
 
 __global__ void to_bf16_kernel(const float* p, uint16_t* pb, int64_t n) {
@@ -672,19 +778,41 @@ struct mlp_net {
   float *dz2f = nullptr, *dz1f = nullptr;  // [batch_max][512]
   uint16_t *dz2b = nullptr, *dz1b = nullptr;
   float* lrow = nullptr;      // [batch_max]
-  float* kpart = nullptr;     // split-K partials, [KSPLIT_MAX][512 * 512]
-  float* cpart = nullptr;     // column-sum partials, [CS_RC][COLS_ALL]
+  float* kpart = nullptr;     // split-K partials: [KSPLIT_MAX][512 * 512], the
+                              // first of three buffers (W2, then W3, W1)
+  float* cpart = nullptr;     // column-sum partials, [CS_RC][COLS_ALL] + a loss slot
+  // the training graph (mlp_train) and what it reads
+  float* ybuf = nullptr;      // [batch_max][7]
+  int64_t* dstep = nullptr;   // device step counter of the graph
+  float* sched = nullptr;     // [sched_cap][3]: learning rate, c1, c2 per step
+  float* losses = nullptr;    // [sched_cap]
+  int64_t sched_cap = 0;
+  hipStream_t work = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t train_exec = nullptr;
+  int64_t train_key[4] = {0, 0, 0, 0};  // batch, split, rows per epoch, sched buffer
 };
 
 constexpr int KSPLIT_MAX = 8;
 constexpr int COLS_ALL = NOP + NH + NH + 1;  // b3, b2, b1 gradients and the loss
 
+// Split-K partial buffers of the three weight gradients (one block).
+constexpr int64_t KPART_W2 = 0;
+constexpr int64_t KPART_W3 = KPART_W2 + (int64_t)KSPLIT_MAX * NH * NH;
+constexpr int64_t KPART_W1 = KPART_W3 + (int64_t)KSPLIT_MAX * NH * NOP;
+constexpr int64_t KPART_ALL = KPART_W1 + (int64_t)KSPLIT_MAX * NB * NH;
+
 static void net_free(mlp_net* n) {
-  void* ptrs[] = {n->p,    n->g,    n->m,    n->v,    n->pb,   n->xbuf,
-                  n->h1,   n->h2,   n->o,    n->dof,  n->dob,  n->dz2f,
-                  n->dz1f, n->dz2b, n->dz1b, n->lrow, n->kpart, n->cpart};
+  if (n->train_exec) (void)hipGraphExecDestroy(n->train_exec);
+  void* ptrs[] = {n->p,    n->g,    n->m,    n->v,     n->pb,    n->xbuf,  n->h1,
+                  n->h2,   n->o,    n->dof,  n->dob,   n->dz2f,  n->dz1f,  n->dz2b,
+                  n->dz1b, n->lrow, n->kpart, n->cpart, n->ybuf, n->dstep, n->sched,
+                  n->losses};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+  if (n->ev_in) (void)hipEventDestroy(n->ev_in);
+  if (n->ev_out) (void)hipEventDestroy(n->ev_out);
+  if (n->work) (void)hipStreamDestroy(n->work);
 }
 
 static int grid_for(int64_t n) {
@@ -723,8 +851,13 @@ extern "C" int mlp_create(int32_t batch_max, uint64_t seed, mlp_net** out) {
             hipMalloc(&n->dz2b, B * NH * 2) == hipSuccess &&
             hipMalloc(&n->dz1b, B * NH * 2) == hipSuccess &&
             hipMalloc(&n->lrow, B * 4) == hipSuccess &&
-            hipMalloc(&n->kpart, (size_t)KSPLIT_MAX * NH * NH * 4) == hipSuccess &&
-            hipMalloc(&n->cpart, (size_t)CS_RC * COLS_ALL * 4) == hipSuccess;
+            hipMalloc(&n->kpart, (size_t)KPART_ALL * 4) == hipSuccess &&
+            hipMalloc(&n->cpart, ((size_t)CS_RC * COLS_ALL + 1) * 4) == hipSuccess &&
+            hipMalloc(&n->ybuf, B * DM * 4) == hipSuccess &&
+            hipMalloc(&n->dstep, 8) == hipSuccess &&
+            hipStreamCreateWithFlags(&n->work, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&n->ev_in, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&n->ev_out, hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     net_free(n);
@@ -870,8 +1003,18 @@ extern "C" int mlp_forward(mlp_net* n, const uint16_t* x, int64_t rows, float* o
   return SBLM_OK;
 }
 
+// K ranges of the weight-gradient products for a batch of `rows`: at least
+// 128 rows each (more workgroups, shorter chains).
+static int ksplit_for(int rows) {
+  int ks = 1;
+  while (ks < KSPLIT_MAX && rows % (64 * ks) == 0 && rows / (2 * ks) >= 128) ks *= 2;
+  return ks;
+}
+
+// Loss and gradient of a batch.  fold: leave the weight gradients as split-K
+// partials (summed by adam_graph_kernel) instead of reducing them here.
 static hipError_t loss_grad(mlp_net* n, const uint16_t* x, const float* y, int rows,
-                            float* loss, hipStream_t st) {
+                            float* loss, hipStream_t st, bool fold = false) {
   hipError_t e = forward_rows(n, x, rows, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(mlp_nll_kernel, dim3((rows * 8 + 255) / 256), dim3(256), 0, st, n->o, y,
@@ -890,23 +1033,28 @@ static hipError_t loss_grad(mlp_net* n, const uint16_t* x, const float* y, int r
   if ((e = gemm(g, true, true, st)) != hipSuccess) return e;
   // weight gradients: gW = (layer input)^T dZ, a contraction over the batch,
   // cut into K ranges of at least 128 rows (more workgroups, shorter chains)
-  int ks = 1;
-  while (ks < KSPLIT_MAX && rows % (64 * ks) == 0 && rows / (2 * ks) >= 128) ks *= 2;
+  const int ks = ksplit_for(rows);
   struct { const uint16_t* A; int64_t lda; const uint16_t* B; int64_t ldb; int M, N;
-           float* out; } wg[3] = {
-      {n->h2, NH, n->dob, NOP, NH, NOP, n->g + OFF_W3},
-      {n->h1, NH, n->dz2b, NH, NH, NH, n->g + OFF_W2},
-      {x, NB, n->dz1b, NH, NB, NH, n->g + OFF_W1}};
+           float* out; float* part; } wg[3] = {
+      {n->h2, NH, n->dob, NOP, NH, NOP, n->g + OFF_W3, n->kpart + KPART_W3},
+      {n->h1, NH, n->dz2b, NH, NH, NH, n->g + OFF_W2, n->kpart + KPART_W2},
+      {x, NB, n->dz1b, NH, NB, NH, n->g + OFF_W1, n->kpart + KPART_W1}};
+  // the three products in one launch (independent once dZ1 is known)
+  GemmArgs gw[3];
   for (int i = 0; i < 3; ++i) {
-    memset(&g, 0, sizeof(g));
-    g.A = wg[i].A; g.lda = wg[i].lda; g.B = wg[i].B; g.ldb = wg[i].ldb;
-    g.M = wg[i].M; g.N = wg[i].N; g.K = rows; g.ldc = wg[i].N; g.ksplit = ks;
-    g.Cf = ks > 1 ? n->kpart : wg[i].out;
-    if ((e = gemm(g, false, false, st)) != hipSuccess) return e;
-    if (ks > 1) {
+    memset(&gw[i], 0, sizeof(gw[i]));
+    gw[i].A = wg[i].A; gw[i].lda = wg[i].lda; gw[i].B = wg[i].B; gw[i].ldb = wg[i].ldb;
+    gw[i].M = wg[i].M; gw[i].N = wg[i].N; gw[i].K = rows; gw[i].ldc = wg[i].N;
+    gw[i].ksplit = ks;
+    gw[i].Cf = ks > 1 ? wg[i].part : wg[i].out;
+  }
+  if ((e = gemm_group(gw, 3, false, false, st)) != hipSuccess) return e;
+  for (int i = 0; i < 3; ++i) {
+    const GemmArgs& g = gw[i];
+    if (ks > 1 && !fold) {
       const int64_t mn = (int64_t)g.M * g.N;
-      hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for(mn)), dim3(256), 0, st, n->kpart,
-                         ks, mn, wg[i].out);
+      hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for(mn)), dim3(256), 0, st,
+                         wg[i].part, ks, mn, wg[i].out);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
@@ -950,6 +1098,57 @@ extern "C" int mlp_adam_step(mlp_net* n, float lr, void* stream) {
   return check_hip(adam(n, lr, (hipStream_t)stream), "mlp_adam_step");
 }
 
+// The captured training step: batch gather, forward, likelihood, backward,
+// Adam with the split-K sums, step advance.  Every pointer it holds belongs
+// to the net (the caller's data is read through the gather node), so one
+// graph serves every step of a call and later calls with the same shape.
+static hipError_t capture_train(mlp_net* n, const uint16_t* x, const float* y, int64_t per,
+                                int batch) {
+  hipStream_t w = n->work;
+  const int ks = ksplit_for(batch);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(w, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  const int64_t nx = (int64_t)batch * NB / 8 + (int64_t)batch * DM;
+  hipLaunchKernelGGL(batch_gather_kernel, dim3(grid_for(nx)), dim3(256), 0, w, x, y, per, batch,
+                     n->dstep, n->xbuf, n->ybuf);
+  e = hipGetLastError();
+  float* loss_slot = n->cpart + (int64_t)CS_RC * COLS_ALL;
+  if (e == hipSuccess) e = loss_grad(n, n->xbuf, n->ybuf, batch, loss_slot, w, true);
+  if (e == hipSuccess) {
+    const double b1 = 0.9, b2 = 0.999;
+    KParts kp;
+    kp.part[0] = n->kpart + KPART_W3;
+    kp.part[1] = n->kpart + KPART_W2;
+    kp.part[2] = n->kpart + KPART_W1;
+    kp.off[0] = OFF_W3;
+    kp.off[1] = OFF_W2;
+    kp.off[2] = OFF_W1;
+    kp.mn[0] = (int64_t)NH * NOP;
+    kp.mn[1] = (int64_t)NH * NH;
+    kp.mn[2] = (int64_t)NB * NH;
+    kp.ks = ks;
+    hipLaunchKernelGGL(adam_graph_kernel, dim3(grid_for(NP_DEV)), dim3(256), 0, w, n->p, n->g,
+                       n->m, n->v, n->pb, NP_DEV, n->sched, n->dstep, kp, (float)b1, (float)b2,
+                       (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(1), 0, w, n->dstep, loss_slot,
+                       n->losses);
+    e = hipGetLastError();
+  }
+  const hipError_t e_end = hipStreamEndCapture(w, &graph);
+  if (e == hipSuccess) e = e_end;
+  if (e == hipSuccess) {
+    if (n->train_exec) (void)hipGraphExecDestroy(n->train_exec);
+    n->train_exec = nullptr;
+    e = hipGraphInstantiate(&n->train_exec, graph, nullptr, nullptr, 0);
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  return e;
+}
+
 extern "C" int mlp_train(mlp_net* n, const uint16_t* x, const float* y, int64_t rows,
                          int32_t batch, int32_t epochs, float lr0, float lr1,
                          float* loss, void* stream) {
@@ -963,19 +1162,69 @@ extern "C" int mlp_train(mlp_net* n, const uint16_t* x, const float* y, int64_t 
                      (long long)rows);
   if (!(lr0 >= 0.0f) || !(lr1 >= 0.0f))
     return set_error(SBLM_EINVAL, "mlp_train: learning rates must be >= 0");
-  hipStream_t st = (hipStream_t)stream;
   const int64_t per = rows / batch;
   const int64_t total = per * epochs;
+  if (total > ((int64_t)1 << 31))
+    return set_error(SBLM_ERANGE, "mlp_train: %lld steps beyond 2^31", (long long)total);
+  if (total == 0) return SBLM_OK;
+  hipStream_t st = (hipStream_t)stream;
+  // the step schedule on the host, as mlp_adam_step computes it: cosine
+  // learning rate, bias corrections of step t = (steps so far) + k + 1
+  float* sched_h = (float*)malloc((size_t)total * 3 * sizeof(float));
+  if (!sched_h) return set_error(SBLM_ENOMEM, "mlp_train: host allocation");
+  const double b1 = 0.9, b2 = 0.999;
   for (int64_t k = 0; k < total; ++k) {
-    const int64_t r0 = (k % per) * batch;
     const double fr = total > 1 ? (double)k / (double)(total - 1) : 0.0;
-    const float lr = (float)(lr1 + 0.5 * (lr0 - lr1) * (1.0 + cos(M_PI * fr)));
-    hipError_t e = loss_grad(n, x + r0 * NB, y + r0 * DM, batch, loss ? loss + k : nullptr,
-                             st);
-    if (e == hipSuccess) e = adam(n, lr, st);
-    if (e != hipSuccess) return check_hip(e, "mlp_train");
+    const double t = (double)(n->step + k + 1);
+    sched_h[3 * k] = (float)(lr1 + 0.5 * (lr0 - lr1) * (1.0 + cos(M_PI * fr)));
+    sched_h[3 * k + 1] = (float)(1.0 / (1.0 - pow(b1, t)));
+    sched_h[3 * k + 2] = (float)(1.0 / (1.0 - pow(b2, t)));
   }
-  return SBLM_OK;
+  int rc = SBLM_OK;
+  // the net's work stream follows the caller's
+  rc = check_hip(hipEventRecord(n->ev_in, st), "mlp_train: event");
+  if (!rc) rc = check_hip(hipStreamWaitEvent(n->work, n->ev_in, 0), "mlp_train: wait");
+  if (!rc && total > n->sched_cap) {
+    // larger step buffers: the graph holds the old ones, so it is captured again
+    rc = check_hip(hipStreamSynchronize(n->work), "mlp_train: synchronise");
+    if (!rc) {
+      if (n->sched) (void)hipFree(n->sched);
+      if (n->losses) (void)hipFree(n->losses);
+      n->sched = nullptr;
+      n->losses = nullptr;
+      n->sched_cap = 0;
+      if (hipMalloc(&n->sched, (size_t)total * 3 * sizeof(float)) != hipSuccess ||
+          hipMalloc(&n->losses, (size_t)total * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = set_error(SBLM_ENOMEM, "mlp_train: device allocation");
+      } else {
+        n->sched_cap = total;
+      }
+    }
+  }
+  if (!rc)
+    rc = check_hip(hipMemcpy(n->sched, sched_h, (size_t)total * 3 * sizeof(float),
+                             hipMemcpyHostToDevice),
+                   "mlp_train: schedule");
+  free(sched_h);
+  const int64_t key[4] = {batch, (int64_t)(uintptr_t)x ^ ((int64_t)(uintptr_t)y << 1), per,
+                          (int64_t)(uintptr_t)n->sched};
+  if (!rc && (!n->train_exec || memcmp(key, n->train_key, sizeof(key)) != 0)) {
+    rc = check_hip(capture_train(n, x, y, per, batch), "mlp_train: capture");
+    if (!rc) memcpy(n->train_key, key, sizeof(key));
+  }
+  // the step counter restarts at 0 (outside the graph)
+  if (!rc) rc = check_hip(hipMemsetAsync(n->dstep, 0, 8, n->work), "mlp_train: counter");
+  for (int64_t k = 0; !rc && k < total; ++k)
+    rc = check_hip(hipGraphLaunch(n->train_exec, n->work), "mlp_train: step");
+  if (!rc && loss)
+    rc = check_hip(hipMemcpyAsync(loss, n->losses, (size_t)total * sizeof(float),
+                                  hipMemcpyDeviceToDevice, n->work),
+                   "mlp_train: losses");
+  if (!rc) n->step += total;
+  if (!rc) rc = check_hip(hipEventRecord(n->ev_out, n->work), "mlp_train: event");
+  if (!rc) rc = check_hip(hipStreamWaitEvent(st, n->ev_out, 0), "mlp_train: wait");
+  return rc;
 }
 
 // ---------------------------------------------------------- resampling

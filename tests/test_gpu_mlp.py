@@ -2,6 +2,8 @@
 resampling, training samples, the network's forward pass, gradients and
 Adam step, and the seeding draws; training is deterministic and lowers the
 loss."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -251,6 +253,40 @@ def test_training_is_deterministic_and_lowers_the_loss(hip):
     assert np.array_equal(nets[0].get_params(), nets[1].get_params())
     for n in nets:
         n.close()
+
+
+def test_training_graph_equals_stepping_through_the_api(hip):
+    # mlp_train replays one captured step (batch gather, forward, likelihood,
+    # backward, Adam with the split-K sums, step advance); it must give the
+    # parameters and losses of the same steps taken one call at a time
+    # (mlp_loss_grad + mlp_adam_step with the cosine learning rate), bit for
+    # bit, and continue the step count (Adam's bias correction) across calls
+    xb, _, y = hip.mlp_make_data(5, 0, 1024)
+    a, b = hip.MLP(batch_max=256, seed=9), hip.MLP(batch_max=256, seed=9)
+    f32 = lambda v: float(np.float32(v))
+    lr0, lr1 = f32(1e-3), f32(1e-4)
+
+    def steps_by_hand(batch, epochs):
+        per = 1024 // batch
+        total = per * epochs
+        out = []
+        for k in range(total):
+            r0 = (k % per) * batch
+            fr = k / (total - 1) if total > 1 else 0.0
+            lr = f32(lr1 + 0.5 * (lr0 - lr1) * (1.0 + math.cos(math.pi * fr)))
+            out.append(b.loss_grad(xb[r0:r0 + batch], y[r0:r0 + batch]).item())
+            b.adam_step(lr)
+        return np.array(out, np.float32)
+
+    for batch, epochs in ((256, 2), (256, 1), (128, 1)):  # split-K 2; again; new graph
+        la = a.train(xb, y, batch=batch, epochs=epochs, lr0=lr0, lr1=lr1).cpu().numpy()
+        lb = steps_by_hand(batch, epochs)
+        torch.cuda.synchronize()
+        assert np.array_equal(la, lb), (batch, epochs)
+        assert np.array_equal(a.get_params(), b.get_params()), (batch, epochs)
+        assert np.array_equal(a.grad(), b.grad()), (batch, epochs)
+    a.close()
+    b.close()
 
 
 def test_seeding_matches_oracle(hip):
