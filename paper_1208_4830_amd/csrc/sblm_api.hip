@@ -25,24 +25,17 @@ int check_hip(hipError_t e, const char* what) {
   return set_error(SBLM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Lanes per individual of the stateless calls.  Fewer lanes give every lane
-// a longer chunk of consecutive epochs, so a smaller share of its solves
-// start cold: on the MI355X 16 lanes per individual were fastest for a full
-// batch of 1000-epoch lightcurves (17.9 vs 16.8 and 15.4 Gmag/s for 32 and
-// 64).  More lanes give shorter chains of epochs per lane, which pays while
-// the chip would otherwise idle: the widest group that keeps the launch within
-// one full residency (2048 waves: 256 compute units x 4 SIMDs x 2 waves at
-// this kernel's register use), at least 16.  Overridable with SBLM_LANES
-// (8 ... 256) for tuning runs.
+// Lanes per individual of the stateless calls: the rule of the EA states
+// (default_lanes), so that sblm_chi2 of a population equals the state's own
+// evaluation bit for bit.  Overridable with SBLM_LANES (8 ... 256) for tuning
+// runs.
 static int choose_group(int64_t n_ind) {
   const char* env = getenv("SBLM_LANES");
   if (env) {
     int g = atoi(env);
     if (g == 8 || g == 16 || g == 32 || g == 64 || g == 128 || g == 256) return g;
   }
-  for (int g = 256; g >= 32; g >>= 1)
-    if (n_ind * g <= (int64_t)2048 * 64) return g;
-  return 16;
+  return default_lanes(n_ind);
 }
 
 

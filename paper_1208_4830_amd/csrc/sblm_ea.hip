@@ -471,8 +471,9 @@ struct EaStateImpl {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipGraphExec_t graph = nullptr;
   sblm_stats* graph_stats = nullptr;
-  // fitness schedule (chosen by ea_autotune): lanes per individual, waves
-  // per block, persistent launch with a work counter
+  // fitness schedule: lanes per individual (default_lanes at creation),
+  // waves per block, persistent launch with work counters, stepping (the
+  // last three chosen by ea_autotune)
   int lanes = 16;
   int wpb = 4;
   int persistent = 1;
@@ -681,19 +682,6 @@ extern "C" void ea_destroy(ea_state* st) {
   (void)hipSetDevice(prev);
   st->~ea_state();
   free(st);
-}
-
-// Lanes per individual of a state of n_ind individuals (see ea_create).
-static int default_lanes(int64_t n_ind) {
-  constexpr int64_t RESIDENT = 2048 * 64;  // lanes of one residency (256 CUs x 8 waves)
-  if (n_ind * 64 <= RESIDENT) {
-    int g = 64;
-    while (g < 256 && n_ind * (2 * g) <= RESIDENT) g *= 2;
-    return g;
-  }
-  for (int g = 8; g < 64; g *= 2)
-    if (n_ind * g >= 8 * RESIDENT) return g;
-  return 64;
 }
 
 extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t seed,

@@ -57,6 +57,24 @@ struct FitArgs {
 };
 
 // Launch the FP64 or mixed fitness kernel; chi2 = false writes A/n_img.
+// Lanes per individual for a launch of n_ind individuals: the fewest of 8,
+// 16, 32, 64 that give the launch 2^20 lanes of work (fewer lanes, longer
+// chains of warm-started epochs per lane, fewer cold starts); a launch whose
+// 64-lane groups would not fill one residency of the chip (2^17 lanes: 256
+// compute units x 8 waves) takes the widest group, up to 256 lanes over
+// several waves, that fits one.
+inline int default_lanes(int64_t n_ind) {
+  constexpr int64_t RESIDENT = 2048 * 64;
+  if (n_ind * 64 <= RESIDENT) {
+    int g = 64;
+    while (g < 256 && n_ind * (2 * g) <= RESIDENT) g *= 2;
+    return g;
+  }
+  for (int g = 8; g < 64; g *= 2)
+    if (n_ind * g >= 8 * RESIDENT) return g;
+  return 64;
+}
+
 hipError_t launch_fitness(const FitArgs& a, int mode, bool chi2,
                           hipStream_t stream, int waves_per_block);
 

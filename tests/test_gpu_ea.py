@@ -309,6 +309,12 @@ def test_ragged_full_size_sampled(hip, mode):
             A, _ = O.magnify(th, wl.t[sl])
             co, _, _ = O.lsq_chi2(A[0], y[sl], w[sl])
             assert rel_err(c[col], co) < 1e-8, (k, i, c[col], co)
+    # the stateless call on the decoded population takes the state's lanes
+    # per individual (8 here) and gives its chi^2 bit for bit
+    assert st.schedule()[0] == 8
+    theta = O.decode(P, lo, hi)
+    c_api, _, _ = hip.sblm_chi2(lcs, _cuda(theta), 128, mode)
+    assert np.array_equal(c_api.cpu().numpy(), c)
     st.close()
 
 
