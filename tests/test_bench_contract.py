@@ -37,7 +37,7 @@ def test_traffic_figure_matches_the_kernel_source():
     # profiled again
     import hashlib
     h = hashlib.sha256()
-    for f in ("sblm_fitness.hip", "sblm_math.h"):
+    for f in ("sblm_fitness.hip", "sblm_math.h", "sblm_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_1208_4830_amd", "csrc", f), "rb").read())
     want = bench.FITNESS_TRAFFIC["bytes_per_launch"] \
         if h.hexdigest()[:16] == bench.FITNESS_TRAFFIC["source_sha256_16"] else None
