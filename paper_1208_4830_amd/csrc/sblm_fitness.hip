@@ -594,9 +594,8 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
       }
     }
     // Warm start: quadratic (Lagrange in t) extrapolation of every root from
-    // the three previous epochs when the new epoch lies within their span,
-    // else linear from two, scaled by the ratio of epoch spacings (clamped to
-    // [0, 4]); the history shifts as it is used.
+    // the three previous epochs, else linear from two (warm_weights); the
+    // history shifts as it is used.
     {
       double w1, w2, w3;
       warm_weights(t, t1, t2, t3, warm && have_prev2, have_prev3, w1, w2, w3);
@@ -689,9 +688,8 @@ __device__ __forceinline__ void fit_wave(const FitArgs& a, int64_t wave_item,
 // its next epoch as soon as its own solve has converged, so a wavefront pays
 // for the lanes' own sweeps (plus the epoch set-up and image work of the
 // lanes finishing in a pass) instead of the slowest lane of every epoch.
-// The warm start is a quadratic extrapolation of the roots of the last three
-// epochs (Lagrange in t) when the new epoch lies within their span, else
-// the linear one of the lockstep form.
+// The warm start is that of the lockstep form (warm_weights), and so is
+// every lane's arithmetic: the two forms give the same results bit for bit.
 template <int MODE, bool CHI2, int G>
 __device__ __forceinline__ void fit_wave_async(const FitArgs& a, int64_t wave_item,
                                                LaneStats& st) {

@@ -401,16 +401,21 @@ SBLM_FN void lsq_include(LsqT<R>& s, R w, R x1, R x2, R y) {
 
 // Weights (w1, w2, w3) of the roots of the three previous epochs t1 > t2 >
 // t3 for the start at epoch t: quadratic (Lagrange in t) extrapolation when
-// all three are known (have3) and t lies within their span, else linear from
-// two (have2), scaled by the ratio of epoch spacings clamped to [0, 4], else
-// the previous roots themselves.
+// all three are known (have3), however far t lies beyond them; else linear
+// from two (have2), scaled by the ratio of epoch spacings clamped to [0, 4];
+// else the previous roots themselves.  Across a gap in the cadence (a night
+// between two runs of epochs minutes apart) the root paths are smooth, and
+// the curvature the three close epochs give carries the start to within one
+// sweep, where the linear start, clamped, left most such epochs two or three
+// sweeps short; a poor start over a very long gap costs sweeps, or a cold
+// retry, never a wrong root.
 template <typename R>
 SBLM_FN void warm_weights(R t, R t1, R t2, R t3, bool have2, bool have3, R& w1, R& w2, R& w3) {
   w1 = R(1.0);
   w2 = R(0.0);
   w3 = R(0.0);
   const R d12 = t1 - t2, d23 = t2 - t3, d13 = t1 - t3;
-  if (have2 && have3 && d12 > R(0.0) && d23 > R(0.0) && (t - t1) <= d13) {
+  if (have2 && have3 && d12 > R(0.0) && d23 > R(0.0)) {
     const R a1 = t - t1, a2 = t - t2, a3 = t - t3;
     const R r = rcp_fast(d12 * d13 * d23);
     w1 = a2 * a3 * (d23 * r);
