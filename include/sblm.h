@@ -435,15 +435,19 @@ void nm_default_config(nm_config* cfg);
  *   chi2, Fs, Fb  [n_lc] device out (nullable), its chi^2 and fluxes
  *   n_iter  [n_lc] device int32 out (nullable), simplex steps taken
  *   stats   (nullable) fitness counters
+ * A round evaluates, per running simplex, its step's reflection (then, in
+ * the next round, the one other point the step needs) while more than 256
+ * simplices run, else all four points of a step at once; either way the
+ * simplices are those of the sequential method.
  * Allocates and frees a workspace of ~1 KB per simplex, a work order of
- * 16 B per simplex, and saved roots of 80 B per lane: the trial points of a
+ * 32 B per simplex, and saved roots of 80 B per lane: the trial points of a
  * round are spread over 64, 128 or 256 lanes each, the fewest that give
- * 2^19 lanes for the simplices still running (read every 16 rounds), each
+ * 2^19 lanes for the round's trial points (read every 16 rounds), each
  * width with its own saved roots (140 KB per simplex for the three; where
  * they would pass 1 GiB, one width: 256 lanes, else 128, else 64 without
- * saved roots).  The widths change results at the rounding level only, and
- * are a function of the simplices, so calls are repeatable.  Synchronises
- * `stream`.
+ * saved roots).  The widths and the form of a round change results at the
+ * rounding level only, and are a function of the simplices, so calls are
+ * repeatable.  Synchronises `stream`.
  * Errors: SBLM_EINVAL, SBLM_ERANGE, SBLM_ENOMEM, SBLM_EDEVICE.
  */
 int nm_refine(const sblm_lcs* lcs, const double* lo, const double* hi,
@@ -458,7 +462,7 @@ int nm_refine(const sblm_lcs* lcs, const double* lo, const double* hi,
  * nm_refine, with no hipMalloc, hipFree or other allocation.  The
  * simplices' state (~0.8 KB per lightcurve) lives in a static device array
  * of 8 MiB that every GPU the library runs on holds until the process ends,
- * so 1 <= n_lc <= 10379 (SBLM_ERANGE beyond, with the limit in the message).
+ * so 1 <= n_lc <= 9936 (SBLM_ERANGE beyond, with the limit in the message).
  * Trial points are spread over 64 lanes without saved roots: the results are
  * those of nm_refine run with 64 lanes per trial point (bit for bit), and
  * they do not depend on what an earlier call left in the array (every

@@ -13,13 +13,20 @@
 // every vertex is within tol_x of the best in every coordinate and within
 // tol_f in chi^2, or after max_iter steps.
 //
-// Device form: each round evaluates four trial points per lightcurve in one
-// launch of the fitness kernel -- the reflection and, speculatively, the
-// expansion and both contractions, since all four depend only on the current
-// simplex -- so one round is one simplex step whatever branch it takes.  The
-// six vertices of a shrink are evaluated over the next two rounds, and the
-// seven initial vertices over the first two.  The sequence of simplices is
-// that of the sequential algorithm.
+// Device form: a round is one launch of the fitness kernel over the trial
+// points that the running simplices need, in one of two forms chosen per
+// round by the number of running simplices.  While many run, a round is
+// bound by its work: a step evaluates the reflection alone and, in the next
+// round, the one other point that the reflection's value asks for (the
+// expansion, or the outside or the inside contraction), if any -- about 1.6
+// points per step.  While few run, a round is bound by the latency of its
+// longest lightcurve: a step evaluates the reflection and, speculatively,
+// the expansion and both contractions in one round, since all four depend
+// only on the current simplex.  The six vertices of a shrink are evaluated
+// over the next two rounds, and the seven initial vertices over the first
+// two.  Only the needed trial points are launched in full (the others are
+// evaluated as empty), packed to the front of the launch in the work order.
+// Either way the sequence of simplices is that of the sequential algorithm.
 //
 // Iterated simplex (the comparison algorithm of Sec. 4.1): every slot of a
 // lightcurve runs simplices from random start points one after another; a
@@ -44,7 +51,22 @@ constexpr int NV = NP + 1;     // 7 vertices
 constexpr int NS = 4;          // trial slots per lightcurve and round
 constexpr int NM_ITER_REPS_MAX = 1024;  // slots per lightcurve of nm_iterated
 
-enum : int32_t { PH_INIT1 = 0, PH_INIT2, PH_STEP, PH_SHRINK1, PH_SHRINK2, PH_DONE };
+// A step in the two-round form waits in PH_WAIT_E, _OC or _IC for its second
+// point, which goes in trial slot 1, 2 or 3 (the slot the speculative form
+// gives the same point, so a slot's root cache holds roots of like points).
+enum : int32_t {
+  PH_INIT1 = 0,
+  PH_INIT2,
+  PH_STEP,
+  PH_SHRINK1,
+  PH_SHRINK2,
+  PH_WAIT_E,
+  PH_WAIT_OC,
+  PH_WAIT_IC,
+  PH_DONE
+};
+constexpr int COMPACT_CHUNK = 4096;  // trial points per block of the work-order packing
+constexpr int COMPACT_ONE = 16384;   // at most this many: one block packs them all
 
 struct NmWork {
   int32_t n;       // lightcurves
@@ -56,9 +78,12 @@ struct NmWork {
   double* cT;      // [n * NS] trial chi^2
   double* fsT;
   double* fbT;
+  double* rF;      // [3][n] chi^2, Fs, Fb of the reflection of a waiting step
   int32_t* phase;  // [n]
   int32_t* steps;  // [n]
-  int32_t* done;   // [n] 1 once finished: its trial slots are not evaluated
+  int32_t* skipT;  // [n * NS] 1: the trial slot is not needed in this round
+                   // (evaluated as empty)
+  int32_t spec;    // this round's form of a step: 1 four points at once
   int32_t* fresh;  // [n] 1 in the first round of a run: its trial points start
                    // their root solves cold, not from the slot's root cache
   unsigned int* active;
@@ -150,7 +175,6 @@ __global__ void nm_start_kernel(NmWork w, const double* x0) {
     for (int g = 0; g < NP; ++g) x[g] = x0[(int64_t)g * w.n + lc];
   }
   begin_run(w, lc, x);
-  w.done[lc] = 0;
 }
 
 // NaN marks an empty root cache entry (the lane starts cold).
@@ -183,16 +207,44 @@ __global__ void nm_test_kernel(NmWork w, double tol_x, double tol_f, int32_t max
     if (w.iter) {
       end_run(w, lc);
       w.ending[lc] = 1;
-    } else {
-      w.done[lc] = 1;
     }
   }
 }
 
-// Trial points of this round.  In iterated mode an ending slot first takes
-// its lightcurve's next unstarted start: the slots of a lightcurve that end
-// in this round take them in slot order (the update kernel then advances the
-// lightcurve's counter), and a slot with none left is done.
+// The centroid of the best six vertices and the worst vertex.
+__device__ __forceinline__ void centroid(const NmWork& w, int lc, double* xbar, double* xw) {
+  for (int g = 0; g < NP; ++g) {
+    double sum = vtx(w, 0, g, lc);
+    for (int v = 1; v < NV - 1; ++v) sum += vtx(w, v, g, lc);
+    xbar[g] = sum / NP;
+    xw[g] = vtx(w, NV - 1, g, lc);
+  }
+}
+
+// Point k of a step: 0 reflection, 1 expansion, 2 outside and 3 inside
+// contraction (coefficients 1, 2 and 1/2), clipped to the domain.
+__device__ __forceinline__ void step_point(const double* xbar, const double* xw, int k,
+                                           double* x) {
+  const double rho = 1.0, chi = 2.0, psi = 0.5;
+  for (int g = 0; g < NP; ++g) {
+    double y;
+    if (k == 0)
+      y = (1 + rho) * xbar[g] - rho * xw[g];
+    else if (k == 1)
+      y = (1 + rho * chi) * xbar[g] - rho * chi * xw[g];
+    else if (k == 2)
+      y = (1 + psi * rho) * xbar[g] - psi * rho * xw[g];
+    else
+      y = (1 - psi) * xbar[g] + psi * xw[g];
+    x[g] = clip01(y);
+  }
+}
+
+// Trial points of this round, and which slots it evaluates.  In iterated
+// mode an ending slot first takes its lightcurve's next unstarted start: the
+// slots of a lightcurve that end in this round take them in slot order (the
+// update kernel then advances the lightcurve's counter), and a slot with
+// none left stays done.
 __global__ void nm_propose_kernel(NmWork w) {
   const int lc = blockIdx.x * blockDim.x + threadIdx.x;
   if (lc >= w.n) return;
@@ -208,10 +260,9 @@ __global__ void nm_propose_kernel(NmWork w) {
       start_point(w, lc, (int)s, x);
       begin_run(w, lc, x);
       ph = PH_INIT1;
-    } else {
-      w.done[lc] = 1;
     }
   }
+  int need = 0;  // bit s: slot s is evaluated
   switch (ph) {
     case PH_INIT1:
     case PH_SHRINK1:
@@ -220,33 +271,39 @@ __global__ void nm_propose_kernel(NmWork w) {
         for (int g = 0; g < NP; ++g) x[g] = vtx(w, v, g, lc);
         put_trial(w, lc, s, x);
       }
+      need = 0xF;
       break;
     case PH_INIT2:
     case PH_SHRINK2:
+      // vertices 4..6 (initial) or 5..6 (shrink)
       for (int s = 0; s < NS; ++s) {
         const int v = (ph == PH_INIT2) ? (s < 3 ? 4 + s : 6) : (s < 2 ? 5 + s : 6);
         for (int g = 0; g < NP; ++g) x[g] = vtx(w, v, g, lc);
         put_trial(w, lc, s, x);
       }
+      need = (ph == PH_INIT2) ? 0x7 : 0x3;
       break;
     case PH_STEP: {
       double xbar[NP], xw[NP];
-      for (int g = 0; g < NP; ++g) {
-        double sum = vtx(w, 0, g, lc);
-        for (int v = 1; v < NV - 1; ++v) sum += vtx(w, v, g, lc);
-        xbar[g] = sum / NP;
-        xw[g] = vtx(w, NV - 1, g, lc);
+      centroid(w, lc, xbar, xw);
+      const int kn = w.spec ? NS : 1;
+      for (int k = 0; k < kn; ++k) {
+        step_point(xbar, xw, k, x);
+        put_trial(w, lc, k, x);
       }
-      // reflection, expansion, outside and inside contraction
-      const double rho = 1.0, chi = 2.0, psi = 0.5;
-      for (int g = 0; g < NP; ++g) x[g] = clip01((1 + rho) * xbar[g] - rho * xw[g]);
-      put_trial(w, lc, 0, x);
-      for (int g = 0; g < NP; ++g) x[g] = clip01((1 + rho * chi) * xbar[g] - rho * chi * xw[g]);
-      put_trial(w, lc, 1, x);
-      for (int g = 0; g < NP; ++g) x[g] = clip01((1 + psi * rho) * xbar[g] - psi * rho * xw[g]);
-      put_trial(w, lc, 2, x);
-      for (int g = 0; g < NP; ++g) x[g] = clip01((1 - psi) * xbar[g] + psi * xw[g]);
-      put_trial(w, lc, 3, x);
+      need = w.spec ? 0xF : 0x1;
+      break;
+    }
+    case PH_WAIT_E:
+    case PH_WAIT_OC:
+    case PH_WAIT_IC: {
+      // the step's second point (the reflection stays in slot 0)
+      double xbar[NP], xw[NP];
+      centroid(w, lc, xbar, xw);
+      const int k = 1 + (ph - PH_WAIT_E);
+      step_point(xbar, xw, k, x);
+      put_trial(w, lc, k, x);
+      need = 1 << k;
       break;
     }
     default:  // done: the best vertex, so that the slots stay valid inputs
@@ -254,6 +311,134 @@ __global__ void nm_propose_kernel(NmWork w) {
       for (int s = 0; s < NS; ++s) put_trial(w, lc, s, x);
       break;
   }
+  for (int s = 0; s < NS; ++s) w.skipT[(int64_t)lc * NS + s] = ((need >> s) & 1) ? 0 : 1;
+}
+
+// Work order of a round: the entries of the fixed order (longest lightcurve
+// first) whose trial slot is needed, in that order, then the others, in
+// that order.  Every wave takes PACK_ROWS rows of 64 consecutive entries
+// (coalesced loads, held in registers); a ballot per row gives each lane the
+// needed entries before it.  Up to COMPACT_ONE entries one block of 16 waves
+// does it; beyond, two launches of 4-wave blocks: the needed entries per
+// block of COMPACT_CHUNK, then each block places its entries after those of
+// the blocks before it.
+constexpr int PACK_ROWS = 16;  // 1024 entries per wave
+
+__device__ __forceinline__ int pack_load(const int32_t* __restrict__ skip,
+                                         const int32_t* __restrict__ ord0, int64_t n,
+                                         int64_t wbase, int32_t* e, bool* need) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < PACK_ROWS; ++i) {
+    const int64_t j = wbase + i * 64 + lane;
+    e[i] = (j < n) ? ord0[j] : -1;
+  }
+  int c = 0;
+#pragma unroll
+  for (int i = 0; i < PACK_ROWS; ++i) {
+    need[i] = e[i] >= 0 && !skip[e[i]];
+    c += __popcll(__ballot(need[i]));
+  }
+  return c;  // the wave's needed entries (the same in every lane)
+}
+
+// The wave's entries to their places: k needed entries precede the wave's
+// first entry, total in all.
+__device__ __forceinline__ void pack_store(int32_t* __restrict__ ord, int64_t wbase, int64_t k,
+                                           int64_t total, const int32_t* e, const bool* need) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int i = 0; i < PACK_ROWS; ++i) {
+    const unsigned long long m = __ballot(need[i]);
+    const int64_t kb = k + __popcll(m & below);  // needed entries before entry j
+    const int64_t j = wbase + i * 64 + lane;
+    if (e[i] >= 0) {
+      if (need[i])
+        ord[kb] = e[i];
+      else
+        ord[total + (j - kb)] = e[i];  // j - kb: the skipped entries before j
+    }
+    k += __popcll(m);
+  }
+}
+
+// Needed entries before this wave within the block (exclusive), and the
+// block's total, from every wave's count.
+template <int NW>
+__device__ __forceinline__ int wave_prefix(int c, int32_t* sh, int& block_total) {
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[wv] = c;
+  __syncthreads();
+  int before = 0, all = 0;
+#pragma unroll
+  for (int v = 0; v < NW; ++v) {
+    before += (v < wv) ? sh[v] : 0;
+    all += sh[v];
+  }
+  block_total = all;
+  return before;
+}
+
+__global__ __launch_bounds__(1024) void nm_pack_kernel(const int32_t* __restrict__ skip,
+                                                       const int32_t* __restrict__ ord0,
+                                                       int64_t n, int32_t* __restrict__ ord) {
+  __shared__ int32_t sh[16];
+  const int64_t wbase = (int64_t)(threadIdx.x >> 6) * (PACK_ROWS * 64);
+  int32_t e[PACK_ROWS];
+  bool need[PACK_ROWS];
+  const int c = pack_load(skip, ord0, n, wbase, e, need);
+  int total = 0;
+  const int before = wave_prefix<16>(c, sh, total);
+  pack_store(ord, wbase, before, total, e, need);
+}
+
+__global__ __launch_bounds__(256) void nm_count_kernel(const int32_t* __restrict__ skip,
+                                                       const int32_t* __restrict__ ord0,
+                                                       int64_t n, int32_t* counts) {
+  __shared__ int32_t sh[4];
+  const int64_t wbase =
+      (int64_t)blockIdx.x * COMPACT_CHUNK + (int64_t)(threadIdx.x >> 6) * (PACK_ROWS * 64);
+  int32_t e[PACK_ROWS];
+  bool need[PACK_ROWS];
+  const int c = pack_load(skip, ord0, n, wbase, e, need);
+  int total = 0;
+  wave_prefix<4>(c, sh, total);
+  if (threadIdx.x == 0) counts[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void nm_place_kernel(const int32_t* __restrict__ skip,
+                                                       const int32_t* __restrict__ ord0,
+                                                       int64_t n, const int32_t* counts,
+                                                       int32_t* __restrict__ ord) {
+  __shared__ int64_t red[2][256];
+  __shared__ int32_t sh[4];
+  const int nb = gridDim.x, b = blockIdx.x, t = threadIdx.x;
+  const int64_t wbase = (int64_t)b * COMPACT_CHUNK + (int64_t)(t >> 6) * (PACK_ROWS * 64);
+  int32_t e[PACK_ROWS];
+  bool need[PACK_ROWS];
+  const int c = pack_load(skip, ord0, n, wbase, e, need);
+  // needed entries before this block, and in all
+  int64_t before = 0, total = 0;
+  for (int i = t; i < nb; i += 256) {
+    total += counts[i];
+    if (i < b) before += counts[i];
+  }
+  red[0][t] = before;
+  red[1][t] = total;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      red[0][t] += red[0][t + o];
+      red[1][t] += red[1][t + o];
+    }
+    __syncthreads();
+  }
+  before = red[0][0];
+  total = red[1][0];
+  int block_total = 0;
+  const int in_block = wave_prefix<4>(c, sh, block_total);
+  pack_store(ord, wbase, before + in_block, total, e, need);
 }
 
 struct Vertex {
@@ -345,6 +530,34 @@ __device__ __forceinline__ void share_values(Vertex* s) {
   }
 }
 
+__device__ __forceinline__ void copy_value(Vertex& d, const Vertex& src) {
+  d.f = src.f;
+  d.fs = src.fs;
+  d.fb = src.fb;
+}
+
+// A trial point at a vertex takes the first such vertex's value.
+__device__ __forceinline__ bool at_vertex(Vertex& t, const Vertex* s) {
+  bool found = false;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const bool m = !found && same_point(t.x, s[v].x);
+    if (m) copy_value(t, s[v]);
+    found = found | m;
+  }
+  return found;
+}
+
+// Shrink towards the best vertex (coefficient 1/2); the moved vertices are
+// evaluated in the next two rounds.
+__device__ __forceinline__ void shrink(Vertex* s) {
+  const double sigma = 0.5;
+#pragma unroll
+  for (int v = 1; v < NV; ++v)
+#pragma unroll
+    for (int g = 0; g < NP; ++g) s[v].x[g] = clip01(s[0].x[g] + sigma * (s[v].x[g] - s[0].x[g]));
+}
+
 __global__ __launch_bounds__(256) void nm_update_kernel(NmWork w) {
   const int lc = blockIdx.x * blockDim.x + threadIdx.x;
   if (lc >= w.n) return;
@@ -392,71 +605,97 @@ __global__ __launch_bounds__(256) void nm_update_kernel(NmWork w) {
       rank_simplex(s, rank);
       next = PH_STEP;
       break;
-    case PH_STEP: {
-      // the decision needs only the four values (each trial point at a
-      // vertex or at an earlier trial point takes that point's value); then
-      // the accepted point
-      const int64_t t0 = (int64_t)lc * NS;
-      double ft[NS], fst[NS], fbt[NS];
+    case PH_STEP:
+      if (w.spec) {
+        // the decision needs only the four values (each trial point at a
+        // vertex or at an earlier trial point takes that point's value);
+        // then the accepted point
+        Vertex t[NS];
 #pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        ft[k] = finite_or_inf(w.cT[t0 + k]);
-        fst[k] = w.fsT[t0 + k];
-        fbt[k] = w.fbT[t0 + k];
-        double xk[NP];
-        get_trial(w, lc, k, xk);
-        bool found = false;
+        for (int k = 0; k < NS; ++k) {
+          take_trial(w, lc, k, t[k]);
+          bool found = false;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const bool m = !found && same_point(xk, s[v].x);
-          if (m) {
-            ft[k] = s[v].f;
-            fst[k] = s[v].fs;
-            fbt[k] = s[v].fb;
+          for (int v = 0; v < NV; ++v) {
+            const bool m = !found && same_point(t[k].x, s[v].x);
+            if (m) copy_value(t[k], s[v]);
+            found = found | m;
           }
-          found = found | m;
+#pragma unroll
+          for (int j = 0; j < k; ++j) {
+            const bool m = !found && same_point(t[k].x, t[j].x);
+            if (m) copy_value(t[k], t[j]);
+            found = found | m;
+          }
         }
+        const double fr = t[0].f;
+        int accept = -1;  // 0 r, 1 e, 2 oc, 3 ic; -1 shrink
+        if (fr < s[0].f) accept = (t[1].f < fr) ? 1 : 0;
+        else if (fr < s[NV - 2].f) accept = 0;
+        else if (fr < s[NV - 1].f) accept = (t[2].f <= fr) ? 2 : -1;
+        else accept = (t[3].f < s[NV - 1].f) ? 3 : -1;
+        if (accept >= 0) {
 #pragma unroll
-        for (int j = 0; j < k; ++j) {
-          double xj[NP];
-          get_trial(w, lc, j, xj);
-          const bool m = !found && same_point(xk, xj);
-          if (m) {
-            ft[k] = ft[j];
-            fst[k] = fst[j];
-            fbt[k] = fbt[j];
-          }
-          found = found | m;
+          for (int k = 0; k < NS; ++k)
+            if (accept == k) s[NV - 1] = t[k];
+          rank_simplex(s, rank);
+          next = PH_STEP;
+        } else {
+          shrink(s);
+          next = PH_SHRINK1;
+        }
+        w.steps[lc] += 1;
+      } else {
+        // the reflection alone (at a vertex: that vertex's value); it
+        // decides the step or which point the step needs next
+        Vertex r;
+        take_trial(w, lc, 0, r);
+        at_vertex(r, s);
+        if (r.f < s[0].f) {
+          next = PH_WAIT_E;
+        } else if (r.f < s[NV - 2].f) {
+          s[NV - 1] = r;
+          rank_simplex(s, rank);
+          w.steps[lc] += 1;
+          next = PH_STEP;
+        } else {
+          next = (r.f < s[NV - 1].f) ? PH_WAIT_OC : PH_WAIT_IC;
+        }
+        if (next != PH_STEP) {
+          w.rF[lc] = r.f;
+          w.rF[(int64_t)w.n + lc] = r.fs;
+          w.rF[2 * (int64_t)w.n + lc] = r.fb;
         }
       }
-      const double fr = ft[0], fe = ft[1], foc = ft[2], fic = ft[3];
-      int accept = -1;  // 0 r, 1 e, 2 oc, 3 ic; -1 shrink
-      if (fr < s[0].f) accept = (fe < fr) ? 1 : 0;
-      else if (fr < s[NV - 2].f) accept = 0;
-      else if (fr < s[NV - 1].f) accept = (foc <= fr) ? 2 : -1;
-      else accept = (fic < s[NV - 1].f) ? 3 : -1;
-      if (accept >= 0) {
-        double fa = ft[0], fsa = fst[0], fba = fbt[0];
-#pragma unroll
-        for (int k = 1; k < NS; ++k)
-          if (accept == k) {
-            fa = ft[k];
-            fsa = fst[k];
-            fba = fbt[k];
-          }
-        get_trial(w, lc, accept, s[NV - 1].x);
-        s[NV - 1].f = fa;
-        s[NV - 1].fs = fsa;
-        s[NV - 1].fb = fba;
+      break;
+    case PH_WAIT_E:
+    case PH_WAIT_OC:
+    case PH_WAIT_IC: {
+      // the second point of a step (at a vertex or at the reflection: that
+      // point's value), then the step's outcome as in the four-point form
+      Vertex r, t;
+      get_trial(w, lc, 0, r.x);
+      r.f = w.rF[lc];
+      r.fs = w.rF[(int64_t)w.n + lc];
+      r.fb = w.rF[2 * (int64_t)w.n + lc];
+      const int k = 1 + (ph - PH_WAIT_E);
+      take_trial(w, lc, k, t);
+      if (!at_vertex(t, s) && same_point(t.x, r.x)) copy_value(t, r);
+      bool take_t, take_r = false;
+      if (ph == PH_WAIT_E) {
+        take_t = t.f < r.f;
+        take_r = !take_t;
+      } else if (ph == PH_WAIT_OC) {
+        take_t = t.f <= r.f;
+      } else {
+        take_t = t.f < s[NV - 1].f;
+      }
+      if (take_t || take_r) {
+        s[NV - 1] = take_t ? t : r;
         rank_simplex(s, rank);
         next = PH_STEP;
       } else {
-        const double sigma = 0.5;
-#pragma unroll
-        for (int v = 1; v < NV; ++v)
-#pragma unroll
-          for (int g = 0; g < NP; ++g)
-            s[v].x[g] = clip01(s[0].x[g] + sigma * (s[v].x[g] - s[0].x[g]));
+        shrink(s);
         next = PH_SHRINK1;
       }
       w.steps[lc] += 1;
@@ -531,9 +770,10 @@ static size_t nm_carve(NmWork& w, char* base, size_t n, bool iter) {
   w.cT = (double*)take(n * NS * 8);
   w.fsT = (double*)take(n * NS * 8);
   w.fbT = (double*)take(n * NS * 8);
+  w.rF = (double*)take(n * 3 * 8);
   w.phase = (int32_t*)take(n * 4);
   w.steps = (int32_t*)take(n * 4);
-  w.done = (int32_t*)take(n * 4);
+  w.skipT = (int32_t*)take(n * NS * 4);
   w.fresh = (int32_t*)take(n * 4);
   w.active = (unsigned int*)take(4);
   if (iter) {
@@ -603,8 +843,8 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
   a.Fs = w.fsT;
   a.Fb = w.fbT;
   a.stats = stats;
-  a.skip = w.done;  // a finished simplex's trial points are not evaluated
-  a.skip_per = NS;
+  a.skip = w.skipT;  // trial slots this round does not need
+  a.skip_per = 1;
   a.cold_per = NS;
   // Lanes per trial point.  While most simplices are still running a
   // round is bound by its work, and 64 lanes (long chains of warm-started
@@ -613,14 +853,15 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
   // their longest lightcurve, which 128 or 256 lanes (several waves per
   // trial point) shorten.  So the lanes follow the number of simplices that
   // ran in the last round (read every 16 rounds): the fewest of 64, 128, 256
-  // that give the launch 2^19 lanes, else 256.  Every width keeps the roots
-  // of each lane's first epoch (80 B per lane and trial slot) and starts
-  // there in its next round (the simplex moves little between rounds; a
-  // cache of a width not used for a while is only a poorer start).  The
-  // choice depends on the simplices alone, so results are deterministic.
-  // Without room for the three caches (1 GiB) a fixed width: 256 lanes,
-  // else 128, else 64 without a cache; the allocation-free entry point and
-  // SBLM_NM_LANES fix it too (a cache only above 64 lanes).
+  // that give the round's trial points 2^19 lanes, else 256.  Every width
+  // keeps the roots of each lane's first epoch (80 B per lane and trial
+  // slot) and starts there in its next round (the simplex moves little
+  // between rounds; a cache of a width not used for a while is only a
+  // poorer start).  The choice depends on the simplices alone, so results
+  // are deterministic.  Without room for the three caches (1 GiB) a fixed
+  // width: 256 lanes, else 128, else 64 without a cache; the
+  // allocation-free entry point and SBLM_NM_LANES fix it too (a cache only
+  // above 64 lanes).
   const int64_t n_trial = (int64_t)n * NS;
   const int64_t cache_max = (int64_t)1 << 30;
   int fixed_g = 0;
@@ -632,6 +873,20 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
   }
   if (!fixed_g && n_trial * (64 + 128 + 256) * 80 > cache_max)
     fixed_g = n_trial * 256 * 80 <= cache_max ? 256 : n_trial * 128 * 80 <= cache_max ? 128 : 64;
+  // The offsets on the host, for the work order below.
+  const int nl = lcs.n_lc;
+  int64_t* off_h = nullptr;
+  if (rc == SBLM_OK && !workspace) {
+    off_h = (int64_t*)malloc((size_t)(nl + 1) * sizeof(int64_t));
+    if (!off_h) {
+      rc = set_error(SBLM_ENOMEM, "nm_refine: host allocation");
+    } else {
+      rc = check_hip(hipMemcpyAsync(off_h, lcs.off, (size_t)(nl + 1) * sizeof(int64_t),
+                                    hipMemcpyDeviceToHost, st),
+                     "nm_refine: offsets");
+      if (rc == SBLM_OK) rc = check_hip(hipStreamSynchronize(st), "nm_refine: offsets");
+    }
+  }
   // cache of width 64 << i at root_cache + cache_off[i] (-1: none)
   int64_t cache_off[3] = {-1, -1, -1}, n_cache = 0;
   for (int i = 0; i < 3; ++i) {
@@ -655,22 +910,19 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
   // Work order of the trial points, longest lightcurve first (stable), a
   // simplex's four trial points together: one round launches every trial
   // point at once, over lightcurves of very different lengths, and a long
-  // one dispatched last would hold the round up.  (Not with a caller's
-  // workspace: the order changes no result, only the balance.)
-  int32_t* order = nullptr;
-  if (rc == SBLM_OK && !workspace && lcs.n_lc > 1) {
-    const int nl = lcs.n_lc;
-    int64_t* off_h = (int64_t*)malloc((size_t)(nl + 1) * sizeof(int64_t));
+  // one dispatched last would hold the round up.  Each round packs the
+  // slots it needs to the front of this order (`ord`), so that the blocks
+  // of the launch hold needed trial points only and the others end at once.
+  // (Not with a caller's workspace: the order changes no result, only the
+  // balance.)
+  int32_t* order = nullptr;  // [n_trial] fixed order, then [n_trial] packed, then counts
+  int32_t* ord = nullptr;
+  int32_t* counts = nullptr;
+  const int64_t n_blk = (n_trial + COMPACT_CHUNK - 1) / COMPACT_CHUNK;
+  if (rc == SBLM_OK && !workspace) {
     int32_t* lc_h = (int32_t*)malloc((size_t)nl * sizeof(int32_t));
     int32_t* ord_h = (int32_t*)malloc((size_t)n_trial * sizeof(int32_t));
-    if (!off_h || !lc_h || !ord_h) {
-      rc = set_error(SBLM_ENOMEM, "nm_refine: host allocation");
-    } else {
-      rc = check_hip(hipMemcpyAsync(off_h, lcs.off, (size_t)(nl + 1) * sizeof(int64_t),
-                                    hipMemcpyDeviceToHost, st),
-                     "nm_refine: offsets");
-      if (rc == SBLM_OK) rc = check_hip(hipStreamSynchronize(st), "nm_refine: offsets");
-    }
+    if (!lc_h || !ord_h) rc = set_error(SBLM_ENOMEM, "nm_refine: host allocation");
     if (rc == SBLM_OK) {
       for (int k = 0; k < nl; ++k) lc_h[k] = k;
       std::stable_sort(lc_h, lc_h + nl, [&](int32_t i, int32_t j) {
@@ -680,22 +932,24 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
       for (int r = 0; r < nl; ++r)
         for (int64_t j = (int64_t)lc_h[r] * reps; j < (int64_t)(lc_h[r] + 1) * reps; ++j)
           for (int slot = 0; slot < NS; ++slot) ord_h[o++] = (int32_t)(j * NS + slot);
-      if (hipMalloc(&order, (size_t)n_trial * sizeof(int32_t)) != hipSuccess) {
+      if (hipMalloc(&order, (size_t)(2 * n_trial + n_blk) * sizeof(int32_t)) != hipSuccess) {
         (void)hipGetLastError();
         order = nullptr;
         rc = set_error(SBLM_ENOMEM, "nm_refine: device allocation");
       } else {
+        ord = order + n_trial;
+        counts = ord + n_trial;
         rc = check_hip(hipMemcpyAsync(order, ord_h, (size_t)n_trial * sizeof(int32_t),
                                       hipMemcpyHostToDevice, st),
                        "nm_refine: order");
         if (rc == SBLM_OK) rc = check_hip(hipStreamSynchronize(st), "nm_refine: order");
       }
     }
-    free(off_h);
     free(lc_h);
     free(ord_h);
   }
-  a.order = order;
+  free(off_h);
+  a.order = ord;
   auto set_lanes = [&](int g) {
     a.lanes_per_ind = g;
     const int i = g == 64 ? 0 : g == 128 ? 1 : 2;
@@ -708,16 +962,28 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
     hipLaunchKernelGGL(nm_start_kernel, grid, blk, 0, st, w, x0);
     rc = check_hip(hipGetLastError(), "nm_refine: start");
   }
-  // rounds per run: 2 for the initial simplex, 1 per step, 2 more per shrink
-  // (one slot may run every start of its lightcurve)
+  // The form of a step, per 16 rounds: one point at a time while more than
+  // spec_max simplices ran in the last block of rounds (bound by work), all
+  // four at once below (bound by latency).  SBLM_NM_SPEC_MAX overrides the
+  // threshold (0: always one at a time; large: always all four); results do
+  // not depend on it.
+  int64_t spec_max = 256;
+  if (const char* env = getenv("SBLM_NM_SPEC_MAX")) spec_max = atoll(env);
+  int want_log2 = 19;
+  if (const char* env = getenv("SBLM_NM_WANT_LOG2")) want_log2 = atoi(env);
+  if (want_log2 < 10 || want_log2 > 30) want_log2 = 19;
+  // rounds per run: 2 for the initial simplex, at most 2 per step, 2 more per
+  // shrink (one slot may run every start of its lightcurve)
   const int64_t max_rounds =
-      (4 + 3 * (int64_t)cfg.max_iter) * (iter ? (int64_t)w.reps * w.runs : 1);
+      (4 + 4 * (int64_t)cfg.max_iter) * (iter ? (int64_t)w.reps * w.runs : 1);
   const int chunk = 16;
   unsigned int active = (unsigned int)n;  // simplices that ran in the last round
   for (int64_t r = 0; rc == SBLM_OK && r < max_rounds; r += chunk) {
+    w.spec = (int64_t)active <= spec_max ? 1 : 0;
     if (!fixed_g) {
-      const int64_t want = (int64_t)1 << 19;
-      const int64_t tp = (int64_t)active * NS;
+      // trial points of a round: four per simplex, or about one
+      const int64_t want = (int64_t)1 << want_log2;
+      const int64_t tp = (int64_t)active * (w.spec ? NS : 1);
       set_lanes(tp * 64 >= want ? 64 : tp * 128 >= want ? 128 : 256);
     }
     for (int k = 0; k < chunk && rc == SBLM_OK; ++k) {
@@ -727,6 +993,20 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
       if (e == hipSuccess) {
         hipLaunchKernelGGL(nm_propose_kernel, grid, blk, 0, st, w);
         e = hipGetLastError();
+      }
+      if (e == hipSuccess && ord && n_trial <= COMPACT_ONE) {
+        hipLaunchKernelGGL(nm_pack_kernel, dim3(1), dim3(1024), 0, st, w.skipT, order, n_trial,
+                           ord);
+        e = hipGetLastError();
+      } else if (e == hipSuccess && ord) {
+        hipLaunchKernelGGL(nm_count_kernel, dim3((unsigned)n_blk), dim3(256), 0, st, w.skipT,
+                           order, n_trial, counts);
+        e = hipGetLastError();
+        if (e == hipSuccess) {
+          hipLaunchKernelGGL(nm_place_kernel, dim3((unsigned)n_blk), dim3(256), 0, st, w.skipT,
+                             order, n_trial, counts, ord);
+          e = hipGetLastError();
+        }
       }
       if (e == hipSuccess) e = launch_fitness(a, cfg.mode, true, st, 4);
       if (e == hipSuccess) {

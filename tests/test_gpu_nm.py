@@ -28,10 +28,26 @@ def device_lcs(hip, wl, y, w):
     return hip.Lightcurves(cu(wl.off, torch.int64), cu(wl.t), cu(y), cu(w))
 
 
-@pytest.mark.parametrize("mode,lanes", [(0, "256"), (1, "256"), (0, "128"), (0, "64")])
-def test_simplex_matches_oracle(hip, mode, lanes, monkeypatch):
+# SBLM_NM_SPEC_MAX: "0" evaluates one point of a step per round (the
+# reflection, then the one other point it asks for), a large value all four
+# at once; the sequence of simplices is the same
+ONE, FOUR = "0", "1000000000"
+_ORACLE_RUNS = {}
+
+
+def _oracle_minimise(key, f, x0, cfg):
+    if key not in _ORACLE_RUNS:
+        _ORACLE_RUNS[key] = NM.minimise(f, x0, cfg.tol_x, cfg.tol_f, cfg.max_iter)
+    return _ORACLE_RUNS[key]
+
+
+@pytest.mark.parametrize("mode,lanes,form", [(0, "256", FOUR), (0, "256", ONE), (1, "256", ONE),
+                                             (1, "256", FOUR), (0, "128", ONE), (0, "64", ONE),
+                                             (0, "64", FOUR)])
+def test_simplex_matches_oracle(hip, mode, lanes, form, monkeypatch):
     # lanes: trial points spread over 4, 2 or 1 waves (merged across waves)
     monkeypatch.setenv("SBLM_NM_LANES", lanes)
+    monkeypatch.setenv("SBLM_NM_SPEC_MAX", form)
     # ragged lengths including an empty lightcurve; starts near the truth,
     # one start on the domain's edges (0 and 1 coordinates)
     lengths = [300, 0, 257, 64, 300, 120, 300, 33]
@@ -59,8 +75,8 @@ def test_simplex_matches_oracle(hip, mode, lanes, monkeypatch):
     assert hip.stats_dict(st)["n_capped"] == 0
     for k in range(len(lengths)):
         sl = slice(off[k], off[k + 1])
-        xr, fr, steps, _, _ = NM.minimise(oracle_f(wl.t[sl], y[sl], w[sl]), x0[:, k],
-                                          cfg.tol_x, cfg.tol_f, cfg.max_iter)
+        xr, fr, steps, _, _ = _oracle_minimise(("matches", k), oracle_f(wl.t[sl], y[sl], w[sl]),
+                                               x0[:, k], cfg)
         # the simplices follow from the accept/shrink decisions alone: the
         # same decisions give bit-identical vertices
         assert it[k] == steps, (k, it[k], steps)
@@ -108,9 +124,12 @@ def test_ea_refine_improves_records_only(hip):
     st.close()
 
 
-def test_several_simplices_per_lightcurve(hip):
+@pytest.mark.parametrize("form", [ONE, FOUR])
+def test_several_simplices_per_lightcurve(hip, form, monkeypatch):
     # nm_refine_multi: three starts per lightcurve (one lightcurve empty);
-    # simplex k * 3 + i follows the oracle simplex on lightcurve k
+    # simplex k * 3 + i follows the oracle simplex on lightcurve k, with a
+    # step's points evaluated one per round or all four at once
+    monkeypatch.setenv("SBLM_NM_SPEC_MAX", form)
     lengths, reps = [200, 0, 150], 3
     wl = inputs.uniform_workload(43, len(lengths), 200)
     ts, off = [], [0]
@@ -132,8 +151,8 @@ def test_several_simplices_per_lightcurve(hip):
         sl = slice(off[k], off[k + 1])
         for i in range(reps):
             j = k * reps + i
-            xr, fr, steps, _, _ = NM.minimise(oracle_f(wl.t[sl], y[sl], w[sl]), x0[:, j],
-                                              cfg.tol_x, cfg.tol_f, cfg.max_iter)
+            xr, fr, steps, _, _ = _oracle_minimise(("several", j), oracle_f(wl.t[sl], y[sl], w[sl]),
+                                                   x0[:, j], cfg)
             assert it[j] == steps, (k, i, it[j], steps)
             assert np.array_equal(x[:, j], xr), (k, i)
             assert abs(c[j] - fr) <= 1e-8 * max(abs(fr), 1e-300) + 1e-14 * np.sum(w[sl] * y[sl] ** 2)
@@ -141,10 +160,12 @@ def test_several_simplices_per_lightcurve(hip):
         hip.nm_refine(lcs, LO, HI, torch.tensor(x0[:, :4], device="cuda"), cfg, reps=reps)
 
 
-def test_iterated_simplex_matches_oracle(hip):
+@pytest.mark.parametrize("form", [ONE, FOUR])
+def test_iterated_simplex_matches_oracle(hip, form, monkeypatch):
     # nm_iterated: 2 slots x 2 runs per lightcurve from Philox starts; the
     # best run, its start index order on ties and the total steps follow the
     # oracle's sequential loop over the same starts
+    monkeypatch.setenv("SBLM_NM_SPEC_MAX", form)
     lengths = [180, 0, 120]
     wl = inputs.uniform_workload(44, len(lengths), 180)
     ts, off = [], [0]
@@ -285,3 +306,44 @@ def test_iterated_simplex_independent_of_slots(hip):
             assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
     with pytest.raises(hip.SblmError):
         hip.nm_iterated(lcs, LO, HI, 1025, 1, seed, cfg)
+
+
+def test_work_order_packing_beyond_one_block(hip, monkeypatch):
+    # 4200 lightcurves x 4 simplices = 67 200 trial slots, beyond what one
+    # block packs (65 536): the two-launch packing.  At 64 lanes (no saved
+    # roots) a simplex's chi^2 values depend on its points alone, so every
+    # simplex must match, bit for bit, the same simplex run in a small call
+    # (one-block packing, four points per step), and one the oracle
+    monkeypatch.setenv("SBLM_NM_LANES", "64")
+    n_lc, L, reps = 4200, 40, 4
+    wl = inputs.uniform_workload(47, n_lc, L)
+    y, w = oracle_lightcurves(wl)
+    lcs = device_lcs(hip, wl, y, w)
+    rng = np.random.default_rng(14)
+    x_true = (wl.theta - LO[:, None]) / (HI - LO)[:, None]
+    x0 = np.clip(np.repeat(x_true, reps, axis=1)
+                 + rng.normal(scale=0.05, size=(6, n_lc * reps)), 0, 1)
+    cfg = hip.nm_default_config()
+    cfg.max_iter = 40
+    big = [a.cpu().numpy() for a in
+           hip.nm_refine(lcs, LO, HI, torch.tensor(x0, device="cuda"), cfg, reps=reps)]
+    assert int(big[4].min()) > 0
+    for k in (0, 1234, n_lc - 1):
+        sl = slice(wl.off[k], wl.off[k + 1])
+        one = hip.Lightcurves(torch.tensor([0, L], dtype=torch.int64, device="cuda"),
+                              torch.tensor(wl.t[sl], device="cuda"),
+                              torch.tensor(y[sl], device="cuda"),
+                              torch.tensor(w[sl], device="cuda"))
+        cols = slice(k * reps, (k + 1) * reps)
+        small = [a.cpu().numpy() for a in
+                 hip.nm_refine(one, LO, HI, torch.tensor(x0[:, cols].copy(), device="cuda"), cfg,
+                               reps=reps)]
+        for u, v in zip(big, small):
+            ref = np.ascontiguousarray(u[:, cols] if u.ndim == 2 else u[cols])
+            assert np.array_equal(ref.view(np.uint8), np.ascontiguousarray(v).view(np.uint8)), k
+    j = 1234 * reps + 2
+    sl = slice(wl.off[1234], wl.off[1235])
+    xr, fr, steps, _, _ = NM.minimise(oracle_f(wl.t[sl], y[sl], w[sl]), x0[:, j],
+                                      cfg.tol_x, cfg.tol_f, cfg.max_iter)
+    assert big[4][j] == steps
+    assert np.array_equal(big[0][:, j], xr)

@@ -128,7 +128,7 @@ def test_simplex_arguments():
     # the no-alloc simplex: beyond its static array, and the usual checks
     big = sblm.sblm_lcs(10380, FAKE, FAKE, FAKE, FAKE)
     _expect(lib.nm_refine_noalloc(ctypes.byref(big), lo, hi, FAKE, ctypes.byref(cfg), FAKE,
-                                  None, None, None, None, None, None), ERANGE, "10379")
+                                  None, None, None, None, None, None), ERANGE, "9936")
     _expect(lib.nm_refine_noalloc(ctypes.byref(lc), hi, lo, FAKE, ctypes.byref(cfg), FAKE,
                                   None, None, None, None, None, None), EINVAL, "hi[")
     _expect(lib.nm_refine_noalloc(ctypes.byref(lc), lo, hi, None, ctypes.byref(cfg), FAKE,

@@ -13,7 +13,7 @@ from tests.helpers import oracle_lightcurves
 pytestmark = pytest.mark.gpu
 
 LO, HI = inputs.PRIOR_LO, inputs.PRIOR_HI
-MAX_LC = 10379  # lightcurves whose simplices fit the 8 MiB array
+MAX_LC = 9936  # lightcurves whose simplices fit the 8 MiB array
 
 
 def _lightcurves(hip, lengths, seed):
@@ -62,7 +62,7 @@ def test_noalloc_refine_rejects_beyond_the_array(hip):
     lcs = hip.Lightcurves(cu(np.zeros(n + 1, np.int64), torch.int64), cu(np.zeros(1)),
                           cu(np.zeros(1)), cu(np.zeros(1)))
     x0 = torch.full((6, n), 0.5, dtype=torch.float64, device="cuda")
-    with pytest.raises(hip.SblmError, match="10379"):
+    with pytest.raises(hip.SblmError, match="9936"):
         hip.nm_refine_noalloc(lcs, LO, HI, x0)
     # the largest batch it takes: MAX_LC empty lightcurves run to completion
     lcs = hip.Lightcurves(cu(np.zeros(MAX_LC + 1, np.int64), torch.int64), cu(np.zeros(1)),
