@@ -362,8 +362,9 @@ __global__ void colsum_stage2(ColSegs cs, const float* part, int ncol_all) {
   cs.s[sg].out[c - cs.col0[sg]] = t;
 }
 
-// part must hold CS_RC x (total columns) floats.
-hipError_t colsums(ColSegs cs, float* part, hipStream_t st) {
+// part must hold CS_RC x (total columns) floats.  stage2 = false leaves the
+// partials for the captured training step's Adam kernel to add.
+hipError_t colsums(ColSegs cs, float* part, hipStream_t st, bool stage2 = true) {
   cs.tile0[0] = 0;
   cs.col0[0] = 0;
   for (int i = 0; i < cs.nseg; ++i) {
@@ -374,7 +375,7 @@ hipError_t colsums(ColSegs cs, float* part, hipStream_t st) {
   hipLaunchKernelGGL(colsum_stage1, dim3(cs.tile0[cs.nseg], CS_RC), dim3(256), 0, st, cs, part,
                      ncol_all);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !stage2) return e;
   hipLaunchKernelGGL(colsum_stage2, dim3((ncol_all + 255) / 256), dim3(256), 0, st, cs, part,
                      ncol_all);
   return hipGetLastError();
@@ -419,15 +420,27 @@ struct KParts {
   int ks;          // partials per tensor (1: none, the GEMM wrote the gradient)
 };
 
+// The column-sum partials of one step (colsum_stage1 without its second
+// stage): the three bias gradients and the loss.
+struct CParts {
+  const float* part;  // [CS_RC][ncol_all]
+  int ncol_all;
+  int64_t off[3];     // first parameter of b3, b2, b1
+  int ncol[3];
+  int col0[3];        // their first columns in part
+  int loss_col;
+};
+
 // adam_kernel for a step of the captured training graph: the step's learning
 // rate and bias-correction factors are read from sched[3k .. 3k+2] (k = the
-// device step counter), and a weight tensor's gradient is first summed over
-// its split-K partials, in range order (as splitk_reduce sums them), and
-// stored to g.
+// device step counter); a weight tensor's gradient is first summed over its
+// split-K partials, in range order (as splitk_reduce sums them), a bias
+// gradient over its column-sum partials, in row-chunk order (as
+// colsum_stage2 sums them), and stored to g.
 __global__ void adam_graph_kernel(float* p, float* g, float* m, float* v, uint16_t* pb,
                                   int64_t n, const float* sched, const int64_t* dstep,
-                                  KParts kp, float b1, float b2, float omb1, float omb2,
-                                  float eps) {
+                                  KParts kp, CParts cp, float b1, float b2, float omb1,
+                                  float omb2, float eps) {
   const int64_t k = *dstep;
   const float lr = sched[3 * k], c1 = sched[3 * k + 1], c2 = sched[3 * k + 2];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -447,6 +460,18 @@ __global__ void adam_graph_kernel(float* p, float* g, float* m, float* v, uint16
         }
       }
     }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int64_t j = i - cp.off[t];
+      if (j >= 0 && j < cp.ncol[t]) {
+        const int c = cp.col0[t] + (int)j;
+        float sum = cp.part[c];
+        for (int rc = 1; rc < CS_RC; ++rc) sum += cp.part[(int64_t)rc * cp.ncol_all + c];
+        g[i] = sum;
+        gi = sum;
+        summed = true;
+      }
+    }
     if (!summed) gi = g[i];
     const float mi = b1 * m[i] + omb1 * gi;
     const float vi = b2 * v[i] + omb2 * (gi * gi);
@@ -456,6 +481,17 @@ __global__ void adam_graph_kernel(float* p, float* g, float* m, float* v, uint16
     p[i] = pi;
     pb[i] = f2bf(pi);
   }
+}
+
+// Last node of a training step: the step's loss (its column-sum partials
+// added in row-chunk order, as colsum_stage2 adds them) to losses[k], and
+// k + 1 to the counter.
+__global__ void step_advance_kernel(int64_t* dstep, CParts cp, float* losses) {
+  const int64_t k = *dstep;
+  float t = cp.part[cp.loss_col];
+  for (int rc = 1; rc < CS_RC; ++rc) t += cp.part[(int64_t)rc * cp.ncol_all + cp.loss_col];
+  losses[k] = t;
+  *dstep = k + 1;
 }
 
 // First node of a training step: batch k mod per of (x, y) into the net's
@@ -473,14 +509,6 @@ __global__ void batch_gather_kernel(const uint16_t* x, const float* y, int64_t p
     else
       yb[i - nx] = y[r0 * DM + (i - nx)];
   }
-}
-
-// Last node of a training step: the step's loss to losses[k], k + 1 to the
-// counter.
-__global__ void step_advance_kernel(int64_t* dstep, const float* loss_slot, float* losses) {
-  const int64_t k = *dstep;
-  losses[k] = *loss_slot;
-  *dstep = k + 1;
 }
 
 __global__ void to_bf16_kernel(const float* p, uint16_t* pb, int64_t n) {
@@ -1012,7 +1040,8 @@ static int ksplit_for(int rows) {
 }
 
 // Loss and gradient of a batch.  fold: leave the weight gradients as split-K
-// partials (summed by adam_graph_kernel) instead of reducing them here.
+// partials and the bias gradients and the loss as column-sum partials (all
+// summed by adam_graph_kernel) instead of reducing them here.
 static hipError_t loss_grad(mlp_net* n, const uint16_t* x, const float* y, int rows,
                             float* loss, hipStream_t st, bool fold = false) {
   hipError_t e = forward_rows(n, x, rows, st);
@@ -1067,7 +1096,7 @@ static hipError_t loss_grad(mlp_net* n, const uint16_t* x, const float* y, int r
   cs.s[3] = {n->lrow, 1, 1, loss ? loss : n->cpart};  // unused slot when no loss
   cs.nseg = loss ? 4 : 3;
   cs.nrow = rows;
-  return colsums(cs, n->cpart, st);
+  return colsums(cs, n->cpart, st, !fold);
 }
 
 extern "C" int mlp_loss_grad(mlp_net* n, const uint16_t* x, const float* y, int32_t rows,
@@ -1099,7 +1128,8 @@ extern "C" int mlp_adam_step(mlp_net* n, float lr, void* stream) {
 }
 
 // The captured training step: batch gather, forward, likelihood, backward,
-// Adam with the split-K sums, step advance.  Every pointer it holds belongs
+// Adam with the split-K and column sums, the loss and the step advance.
+// Every pointer it holds belongs
 // to the net (the caller's data is read through the gather node), so one
 // graph serves every step of a call and later calls with the same shape.
 static hipError_t capture_train(mlp_net* n, const uint16_t* x, const float* y, int64_t per,
@@ -1128,15 +1158,28 @@ static hipError_t capture_train(mlp_net* n, const uint16_t* x, const float* y, i
     kp.mn[1] = (int64_t)NH * NH;
     kp.mn[2] = (int64_t)NB * NH;
     kp.ks = ks;
+    // the column sums' partials as loss_grad left them (b3, b2, b1, loss)
+    CParts cp;
+    cp.part = n->cpart;
+    cp.ncol_all = COLS_ALL;
+    cp.off[0] = OFF_B3;
+    cp.off[1] = OFF_B2;
+    cp.off[2] = OFF_B1;
+    cp.ncol[0] = NOP;
+    cp.ncol[1] = NH;
+    cp.ncol[2] = NH;
+    cp.col0[0] = 0;
+    cp.col0[1] = NOP;
+    cp.col0[2] = NOP + NH;
+    cp.loss_col = NOP + 2 * NH;
     hipLaunchKernelGGL(adam_graph_kernel, dim3(grid_for(NP_DEV)), dim3(256), 0, w, n->p, n->g,
-                       n->m, n->v, n->pb, NP_DEV, n->sched, n->dstep, kp, (float)b1, (float)b2,
-                       (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f);
+                       n->m, n->v, n->pb, NP_DEV, n->sched, n->dstep, kp, cp, (float)b1,
+                       (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f);
     e = hipGetLastError();
-  }
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(1), 0, w, n->dstep, loss_slot,
-                       n->losses);
-    e = hipGetLastError();
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(1), 0, w, n->dstep, cp, n->losses);
+      e = hipGetLastError();
+    }
   }
   const hipError_t e_end = hipStreamEndCapture(w, &graph);
   if (e == hipSuccess) e = e_end;
