@@ -1,5 +1,7 @@
 """Shared helpers of the test-suite: synthetic lightcurves assembled with the
 oracle's magnifications, and the floating-point conditioning of A."""
+import os
+
 import mpmath
 import numpy as np
 
@@ -185,3 +187,13 @@ def exact_magnification_theta(theta, t, dps=50):
     sa, ca = mpmath.sin(al), mpmath.cos(al)
     zeta = mpmath.mpc(tau * sa + u0 * ca, -tau * ca + u0 * sa)
     return exact_magnification(zeta, d, mpmath.power(10, lq), dps)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden_rows(name):
+    """Rows of a fixture under tests/golden/ (whitespace-separated fields,
+    '#' comment lines skipped)."""
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [line.split() for line in f if line.strip() and not line.startswith("#")]

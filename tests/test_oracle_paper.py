@@ -8,15 +8,41 @@ import pytest
 from scipy.signal import find_peaks
 
 from oracle import paper_oracle as P
+from paper_1208_4830_amd import inputs
+from tests.helpers import golden_rows
 
 
 def test_noise_model_worked_value():
-    # the paper's example: about 0.1% error at m_I ~ 14 (1.18e-3 mag)
-    s = float(P.noise_sigma(14.0))
-    assert 1.17e-3 < s < 1.19e-3
+    g = {r[0]: float(r[1]) for r in golden_rows("noise_model.txt")}
+    # the paper's remark: an error of the order of 0.1% at m_I ~ 14
+    s = float(P.noise_sigma(g["example_m_I"]))
+    assert 0.5 * g["example_sigma_order"] < s < 2.0 * g["example_sigma_order"]
+    # the printed coefficients: 10^(0.3416 * 14 - 7.7095) = 1.18e-3 mag, and
     # one magnitude fainter multiplies sigma by 10^0.3416
-    assert math.isclose(float(P.noise_sigma(19.0) / P.noise_sigma(18.0)), 10 ** 0.3416,
+    assert 1.17e-3 < s < 1.19e-3
+    assert math.isclose(s, 10 ** (g["slope"] * 14.0 + g["intercept"]), rel_tol=1e-12)
+    assert math.isclose(float(P.noise_sigma(19.0) / P.noise_sigma(18.0)), 10 ** g["slope"],
                         rel_tol=1e-12)
+
+
+def test_paper_workload_draws_within_table1():
+    # the paper-shaped inputs use Table 1's ranges (q searched as log10 q)
+    rows = {r[1]: (float(r[3]), float(r[4])) for r in golden_rows("table1_parameter_ranges.txt")}
+    names = ["q", "d", "u0", "alpha", "tE", "t0"]
+    for j, nm in enumerate(names):
+        lo, hi = rows[nm]
+        if nm == "q":
+            lo, hi = math.log10(lo), math.log10(hi)
+        assert math.isclose(inputs.PAPER_LO[j], lo, abs_tol=1e-15), nm
+        assert math.isclose(inputs.PAPER_HI[j], hi, rel_tol=1e-15, abs_tol=1e-15), nm
+    assert inputs.PAPER_M0 == rows["m0"]
+    wl = inputs.paper_workload(3, 500, 2)
+    th = wl.theta
+    for j, nm in enumerate(names):
+        lo, hi = rows[nm]
+        v = 10 ** th[j] if nm == "q" else th[j]
+        tol = 1e-12 * max(abs(lo), abs(hi))
+        assert np.all(v >= lo - tol) and np.all(v <= hi + tol), nm
 
 
 def test_magnitudes_and_fluxes():
