@@ -362,7 +362,7 @@ def subset_batch(sblm, torch, lcs, idx):
 
 def adaptive_run(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, proposals, stage1_gen=400,
                  pop2=1024, every=100, max_gen2=1000, red_thr=1.05, target=0.9, seed=7,
-                 passes=3):
+                 passes=3, freeze=True):
     """The learned form with effort where the fit asks for it.  Stage 1: the
     learned form on every lightcurve for `stage1_gen` generations, then twice
     `passes` simplex passes from each fittest solution.  Lightcurves whose
@@ -370,9 +370,13 @@ def adaptive_run(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, proposals, sta
     above `red_thr`; the data's errors are known, so a good fit sits near 1)
     get stage 2: a fresh network-seeded EA of population `pop2` on those
     lightcurves alone, with `passes` simplex passes from its fittest
-    solutions every `every` generations; a lightcurve keeps the better of
-    its two fits.  Success and GPU time are counted as in success_run (EA time
-    so far, stage 1's passes included, + that checkpoint's passes)."""
+    solutions every `every` generations; a lightcurve keeps the best of its
+    fits.  With `freeze`, a stage-2 lightcurve whose best fit has come down
+    to the threshold is frozen (ea_freeze): its EA stops and later passes
+    skip it, so the remaining effort goes to the fits still poor.  GPU time:
+    the EA time so far, stage 1's passes included, plus the stage-2 passes
+    (all checkpoints' with `freeze`, since frozen fits come from earlier
+    checkpoints; else that checkpoint's, as in success_run)."""
     sync = torch.cuda.synchronize
     n_lc = len(chi2_true)
     nm_cfg = sblm.nm_default_config()
@@ -391,8 +395,8 @@ def adaptive_run(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, proposals, sta
     st.close()
     c1 = c1.cpu().numpy()
     L = np.diff(lcs.off.cpu().numpy())
-    red = c1 / np.maximum(L - 6, 1)
-    idx = np.nonzero(red > red_thr)[0]
+    dof = np.maximum(L - 6, 1)
+    idx = np.nonzero(c1 / dof > red_thr)[0]
     s1 = float(np.mean(c1 <= chi2_true + 10.0))
     curve = [dict(gen=stage1_gen, stage=1, success=round(s1, 4), gpu_seconds=round(base_s, 3),
                   flagged=int(len(idx)))]
@@ -409,7 +413,9 @@ def adaptive_run(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, proposals, sta
         st2.seed(props2, pop2 // 2, at_restarts=True)
         sync()
         ea_s = base_s + time.perf_counter() - t0
+        nm_all = 0.0
         best = c1.copy()
+        frozen = np.zeros(len(idx), np.int32)
         gens = 0
         while gens < max_gen2:
             sync()
@@ -419,25 +425,43 @@ def adaptive_run(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, proposals, sta
             ea_s += time.perf_counter() - t0
             gens += every
             x2, c2 = st2.best()
+            run = np.nonzero(frozen == 0)[0]
             sync()
             t0 = time.perf_counter()
-            _, c2 = simplex_passes(sblm, torch, lcs2, lo, hi, x2, c2, passes, nm_cfg)
+            if freeze and len(run) < len(idx):
+                sel = torch.as_tensor(run, device=x2.device)
+                _, c2r = simplex_passes(sblm, torch, subset_batch(sblm, torch, lcs2, run), lo, hi,
+                                        x2[:, sel].contiguous(), c2[sel].contiguous(), passes,
+                                        nm_cfg)
+            else:
+                _, c2r = simplex_passes(sblm, torch, lcs2, lo, hi, x2, c2, passes, nm_cfg)
             sync()
             nm_s = time.perf_counter() - t0
-            best[idx] = np.minimum(c1[idx], c2.cpu().numpy())
+            nm_all += nm_s
+            c2r = c2r.cpu().numpy()
+            if freeze:
+                best[idx[run]] = np.minimum(best[idx[run]], c2r)
+            else:
+                best[idx] = np.minimum(c1[idx], c2r)
             succ = float(np.mean(best <= chi2_true + 10.0))
+            spent = ea_s + (nm_all if freeze else nm_s)
             curve.append(dict(gen=stage1_gen + gens, stage=2, success=round(succ, 4),
-                              gpu_seconds=round(ea_s + nm_s, 3)))
+                              gpu_seconds=round(spent, 3), running=int(len(run))))
             log(f"bench:   checkpoint {json.dumps(curve[-1])}")
             if succ >= target:
-                hit = (stage1_gen + gens, ea_s + nm_s)
+                hit = (stage1_gen + gens, spent)
                 break
+            if freeze:
+                frozen = (best[idx] / dof[idx] <= red_thr).astype(np.int32)
+                if frozen.all():
+                    break
+                st2.freeze(frozen)
         st2.close()
     last = curve[-1]["gen"]
     return dict(target=target, curve=curve,
                 config=dict(stage1_generations=stage1_gen, stage1_passes=2 * passes,
                             reduced_chi2_above=red_thr, pop_stage2=pop2, every=every,
-                            stage2_max_generations=max_gen2),
+                            stage2_max_generations=max_gen2, freeze=freeze),
                 ea_amoeba=dict(reached=hit is not None,
                                generations=hit[0] if hit else None,
                                gpu_seconds=hit[1] if hit else None,

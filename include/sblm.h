@@ -290,6 +290,22 @@ int ea_evaluate(ea_state* st, sblm_stats* stats, void* stream);
 int ea_fit(ea_state* st, int32_t n_gen, sblm_stats* stats, void* stream);
 
 /*
+ * ea_freeze -- stop or resume the EA of chosen lightcurves in a batch (for a
+ * caller that has settled some fits and keeps evolving the rest; the paper's
+ * loop of App. A runs per lightcurve, so the others are unaffected).
+ *   mask  HOST int32[n_lc]: nonzero freezes lightcurve k, 0 lets it run
+ * A frozen lightcurve's population, records and generation counter stay as
+ * they are: later generations skip its selection, offspring and migration,
+ * and its fitness evaluations treat it as empty (its per-row chi2, Fs, Fb in
+ * ea_buffers then read 0 until it runs again; ea_best and ea_records keep its
+ * records).  Every other lightcurve evolves bit for bit as without the
+ * freeze.  Copies the mask in order on `stream` and synchronises `stream`;
+ * the mask is not part of ea_save's snapshot (ea_load leaves it as it is).
+ * Errors: SBLM_ESTATE (null state), SBLM_EINVAL (null mask), SBLM_EDEVICE.
+ */
+int ea_freeze(ea_state* st, const int32_t* mask, void* stream);
+
+/*
  * ea_time_fitness -- instrumentation, not part of the method: with enable =
  * 1 every generation that ea_fit replays stamps the device's constant-rate
  * wall clock just before and just after its fitness kernel (two one-thread

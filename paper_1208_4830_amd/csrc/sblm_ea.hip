@@ -74,6 +74,9 @@ struct EaParams {
   double p_mut0, p_mut_min, p_mut_max, stag_frac;
   uint64_t seed;
   int64_t n_ind;  // n_lc * pop (all islands)
+  // [n_lc / n_isl] nonzero: the lightcurve is frozen (ea_freeze) and its
+  // generations, migrations and fitness evaluations are skipped
+  const int32_t* frozen = nullptr;
 };
 
 // Sec. A.1: rows i < pop/2 uniform, row i + pop/2 = 1 - row i, odd last row
@@ -221,6 +224,7 @@ __global__ void ea_generation_kernel(EaParams p, double* P, EaLc* lcs,
   __shared__ int s_restart;
 
   const int64_t lc = blockIdx.x;
+  if (p.frozen && p.frozen[lc / p.n_isl]) return;  // the whole block
   const int64_t base = lc * N;
   EaLc& st = lcs[lc];
   const int64_t gen = st.gen;
@@ -415,7 +419,7 @@ __device__ __forceinline__ bool migration_due(const MigArgs& a, int64_t gen) {
 __global__ void ea_emigrate_kernel(EaParams p, const double* P, const EaLc* lcs, MigArgs a) {
   extern __shared__ double skey[];  // [pop]
   const int64_t v = blockIdx.x;
-  if (!migration_due(a, lcs[v].gen)) return;
+  if (!migration_due(a, lcs[v].gen) || (p.frozen && p.frozen[v / p.n_isl])) return;
   const int N = p.pop;
   const int64_t base = v * N;
   for (int i = threadIdx.x; i < N; i += blockDim.x) skey[i] = rank_key(a.chi2[base + i]);
@@ -440,7 +444,7 @@ __global__ void ea_emigrate_kernel(EaParams p, const double* P, const EaLc* lcs,
 
 __global__ void ea_immigrate_kernel(EaParams p, double* P, const EaLc* lcs, MigArgs a) {
   const int64_t v = blockIdx.x;
-  if (!migration_due(a, lcs[v].gen)) return;
+  if (!migration_due(a, lcs[v].gen) || (p.frozen && p.frozen[v / p.n_isl])) return;
   const int64_t k = v / p.n_isl;
   const int i = (int)(v - k * p.n_isl);
   const int64_t src = k * p.n_isl + (i + p.n_isl - 1) % p.n_isl;
@@ -483,6 +487,7 @@ struct EaStateImpl {
   int64_t* xcd_start = nullptr;   // [9] order positions owned by each XCD
   Proposals prop = {};         // attached by ea_seed(..., EA_SEED_AT_RESTARTS)
   int n_phys = 0;              // lightcurves (prm.n_lc counts islands)
+  int32_t* frozen = nullptr;   // [n_phys] ea_freeze's mask
   // the workload as the schedule cache keys it (ea_autotune_cached)
   char sig[320] = {0};
   double* mig_out = nullptr;   // migration outboxes (islands with migrants)
@@ -579,6 +584,8 @@ static hipError_t enqueue_evaluate(EaStateImpl* s, sblm_stats* stats,
   a.lanes_per_ind = s->lanes;
   a.order = s->order;
   a.async = s->async;
+  a.skip = s->frozen;  // a frozen lightcurve's rows are evaluated as empty
+  a.skip_per = a.pop;
   if (s->persistent) {
     a.queue = s->queue;
     a.xcd_start = s->xcd_start;
@@ -679,6 +686,7 @@ extern "C" void ea_destroy(ea_state* st) {
   (void)hipFree(s.ticks);
   (void)hipFree(s.mig_out);
   (void)hipFree(s.mig_least);
+  (void)hipFree(s.frozen);
   (void)hipSetDevice(prev);
   st->~ea_state();
   free(st);
@@ -830,6 +838,7 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
       hipMalloc(&s.queue, 8 * sizeof(unsigned int)) != hipSuccess ||
       hipMalloc(&s.xcd_start, 9 * sizeof(int64_t)) != hipSuccess ||
       hipMalloc(&s.ticks, 4 * sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&s.frozen, (size_t)s.n_phys * sizeof(int32_t)) != hipSuccess ||
       (p.n_isl > 1 && cfg->n_migrants > 0 &&
        (hipMalloc(&s.mig_out, (size_t)p.n_lc * cfg->n_migrants * 9 * sizeof(double)) !=
             hipSuccess ||
@@ -855,10 +864,13 @@ extern "C" int ea_create(const ea_config* cfg, const sblm_lcs* lcs, uint64_t see
                              hipMemcpyHostToDevice),
                    "ea_create order");
   free(order_h);
+  if (!rc)
+    rc = check_hip(hipMemset(s.frozen, 0, (size_t)s.n_phys * sizeof(int32_t)), "ea_create mask");
   if (rc) {
     ea_destroy(st);
     return rc;
   }
+  p.frozen = s.frozen;
   s.mig_in_fit = s.mig_out != nullptr && cfg->mig_every > 0;
   hipLaunchKernelGGL(ea_init_kernel, dim3(p.n_lc), dim3(gen_block(p.pop)), 0, s.work, p, s.P,
                      s.lc);
@@ -941,6 +953,18 @@ extern "C" int ea_seed(ea_state* st, const float* out, int32_t ld_out, int32_t n
   s.prop = attach ? pr : Proposals{};
   if ((attach || was) && s.graph) return capture_graph(s, s.graph_stats);
   return SBLM_OK;
+}
+
+extern "C" int ea_freeze(ea_state* st, const int32_t* mask, void* stream) {
+  if (!st) return set_error(SBLM_ESTATE, "ea_freeze: null state");
+  if (!mask) return set_error(SBLM_EINVAL, "ea_freeze: null mask");
+  EaStateImpl& s = st->impl;
+  const hipStream_t q = (hipStream_t)stream;
+  int rc = check_hip(hipMemcpyAsync(s.frozen, mask, (size_t)s.n_phys * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, q),
+                     "ea_freeze copy");
+  if (!rc) rc = check_hip(hipStreamSynchronize(q), "ea_freeze synchronise");
+  return rc;
 }
 
 extern "C" int ea_best(ea_state* st, double* x, double* chi2, void* stream) {

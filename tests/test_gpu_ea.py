@@ -156,6 +156,57 @@ def test_save_load_resume_bit_exact(hip):
         st3.load(snap)
 
 
+@pytest.mark.parametrize("n_isl", [1, 2])
+def test_freeze_skips_only_the_frozen_lightcurves(hip, n_isl):
+    # two lightcurves frozen after 6 generations (with islands: migration
+    # every 3 generations), one of them resumed after 12: the others evolve
+    # bit for bit as in a fit without the freeze; a frozen lightcurve's
+    # population and records stay as they were; the resumed one continues as
+    # the unfrozen fit did from the same point
+    wl = csr_workload(10, [150, 300, 0, 220, 180, 260])
+    pop, n = 32, 6
+    kw = dict(n_islands=2, mig_every=3, n_migrants=2) if n_isl > 1 else {}
+    a, _, _ = _make_state(hip, wl, pop, seed=3, **kw)
+    b, _, _ = _make_state(hip, wl, pop, seed=3, **kw)
+    rows, recs = pop * n_isl, n_isl
+
+    def snap(st):
+        _, P, rec = hip.parse_snapshot(st.save())
+        return P, rec
+
+    def part(P, rec, k):
+        return P[:, k * rows:(k + 1) * rows].copy(), rec[k * recs:(k + 1) * recs].tobytes()
+
+    a.fit(6)
+    b.fit(6)
+    P6, r6 = snap(b)
+    frozen = [0, 1, 0, 0, 1, 0]
+    b.freeze(frozen)
+    a.fit(6)
+    b.fit(6)
+    Pa, ra = snap(a)
+    Pb, rb = snap(b)
+    x_b, c_b = (t.cpu().numpy() for t in b.best())
+    for k in range(n):
+        pb, qb = part(Pb, rb, k)
+        pr, qr = part(P6, r6, k) if frozen[k] else part(Pa, ra, k)
+        assert np.array_equal(pb, pr) and qb == qr, k
+    # ea_best of a frozen lightcurve: its record from before the freeze
+    for k in (1, 4):
+        best6 = min(r6[k * recs:(k + 1) * recs]["best_chi2"])
+        assert c_b[k] == best6
+    # resume lightcurve 1 for 6 generations: as the unfrozen fit's 6 to 12
+    b.freeze([0, 0, 0, 0, 1, 0])
+    b.fit(6)
+    Pb2, rb2 = snap(b)
+    p1, q1 = part(Pb2, rb2, 1)
+    pa1, qa1 = part(Pa, ra, 1)
+    assert np.array_equal(p1, pa1) and q1 == qa1
+    pb4, qb4 = part(Pb2, rb2, 4)
+    p64, q64 = part(P6, r6, 4)
+    assert np.array_equal(pb4, p64) and qb4 == q64
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_fit_improves_and_best_is_monotone(hip, mode):
     # one paper-shaped lightcurve: 400 uniform epochs over t0 +- 2 tE,
