@@ -17,7 +17,8 @@ the same way.  On the same lightcurves the time to 90% success is measured
 for the plain EA and for the EA seeded by the proposal network (the learned
 form), each with the paper's simplex fine-tuning of the fittest solution at
 every checkpoint, and for the learned form that then spends more effort on
-the lightcurves whose fit is still poor by its own reduced chi^2 (options:
+the lightcurves whose fit is still poor by its own reduced chi^2, freezing
+each in the batch once its fit is good (options:
 the EA seeded by the window alone, the ablation; the learned form on
 islands); fits/hour at >= 90% success follows.  The CPU oracle is timed on a
 bounded sample of the headline workload.
