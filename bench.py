@@ -363,7 +363,7 @@ def subset_batch(sblm, torch, lcs, idx):
 
 def adaptive_run(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, proposals, stage1_gen=400,
                  pop2=1024, every=100, max_gen2=1000, red_thr=1.05, target=0.9, seed=7,
-                 passes=3, freeze=True):
+                 passes=3, freeze=True, stage1_every=None):
     """The learned form with effort where the fit asks for it.  Stage 1: the
     learned form on every lightcurve for `stage1_gen` generations, then twice
     `passes` simplex passes from each fittest solution.  Lightcurves whose
@@ -372,11 +372,14 @@ def adaptive_run(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, proposals, sta
     get stage 2: a fresh network-seeded EA of population `pop2` on those
     lightcurves alone, with `passes` simplex passes from its fittest
     solutions every `every` generations; a lightcurve keeps the best of its
-    fits.  With `freeze`, a stage-2 lightcurve whose best fit has come down
-    to the threshold is frozen (ea_freeze): its EA stops and later passes
-    skip it, so the remaining effort goes to the fits still poor.  GPU time:
-    the EA time so far, stage 1's passes included, plus the stage-2 passes
-    (all checkpoints' with `freeze`, since frozen fits come from earlier
+    fits.  With `freeze`, a lightcurve whose best fit has come down to the
+    threshold is frozen (ea_freeze): its EA stops and later passes skip it,
+    so the remaining effort goes to the fits still poor; with `stage1_every`
+    stage 1 also takes `passes` passes every so many generations and freezes
+    the same way (off by default: the threshold is loose enough that stage-1
+    fits frozen there would still have improved).  GPU time: the EA
+    time so far, stage 1's passes included, plus the stage-2 passes (all
+    checkpoints' with `freeze`, since frozen fits come from earlier
     checkpoints; else that checkpoint's, as in success_run)."""
     sync = torch.cuda.synchronize
     n_lc = len(chi2_true)
@@ -388,19 +391,42 @@ def adaptive_run(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, proposals, sta
     st = sblm.EAState(cfg, lcs, seed)
     st.set_schedule(*sched)
     st.seed(proposals, pop // 2, at_restarts=True)
-    st.fit(stage1_gen)
-    x, c = st.best()
-    x, c1 = simplex_passes(sblm, torch, lcs, lo, hi, x, c, 2 * passes, nm_cfg)
+    L = np.diff(lcs.off.cpu().numpy())
+    dof = np.maximum(L - 6, 1)
+    c1 = np.full(n_lc, np.inf)
+    frozen1 = np.zeros(n_lc, np.int32)
+    curve = []
+    g1 = 0
+    while g1 < stage1_gen:
+        step = min(stage1_every, stage1_gen - g1) if (freeze and stage1_every) else stage1_gen
+        st.fit(step)
+        g1 += step
+        x, c = st.best()
+        run = np.nonzero(frozen1 == 0)[0]
+        npass = 2 * passes if g1 >= stage1_gen else passes
+        if len(run) < n_lc:
+            sel = torch.as_tensor(run, device=x.device)
+            _, cr = simplex_passes(sblm, torch, subset_batch(sblm, torch, lcs, run), lo, hi,
+                                   x[:, sel].contiguous(), c[sel].contiguous(), npass, nm_cfg)
+        else:
+            _, cr = simplex_passes(sblm, torch, lcs, lo, hi, x, c, npass, nm_cfg)
+        c1[run] = np.minimum(c1[run], cr.cpu().numpy())
+        if g1 < stage1_gen:
+            frozen1 = (c1 / dof <= red_thr).astype(np.int32)
+            st.freeze(frozen1)
+            sync()
+            curve.append(dict(gen=g1, stage=1, success=round(float(np.mean(c1 <= chi2_true + 10.0)),
+                                                             4),
+                              gpu_seconds=round(time.perf_counter() - t0, 3),
+                              running=int(len(run))))
+            log(f"bench:   checkpoint {json.dumps(curve[-1])}")
     sync()
     base_s = time.perf_counter() - t0
     st.close()
-    c1 = c1.cpu().numpy()
-    L = np.diff(lcs.off.cpu().numpy())
-    dof = np.maximum(L - 6, 1)
     idx = np.nonzero(c1 / dof > red_thr)[0]
     s1 = float(np.mean(c1 <= chi2_true + 10.0))
-    curve = [dict(gen=stage1_gen, stage=1, success=round(s1, 4), gpu_seconds=round(base_s, 3),
-                  flagged=int(len(idx)))]
+    curve.append(dict(gen=stage1_gen, stage=1, success=round(s1, 4), gpu_seconds=round(base_s, 3),
+                      running=int(len(run)), flagged=int(len(idx))))
     log(f"bench:   stage 1 {json.dumps(curve[-1])}")
     hit = (stage1_gen, base_s) if s1 >= target else None
     if hit is None and len(idx):
@@ -462,7 +488,8 @@ def adaptive_run(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, proposals, sta
     return dict(target=target, curve=curve,
                 config=dict(stage1_generations=stage1_gen, stage1_passes=2 * passes,
                             reduced_chi2_above=red_thr, pop_stage2=pop2, every=every,
-                            stage2_max_generations=max_gen2, freeze=freeze),
+                            stage2_max_generations=max_gen2, freeze=freeze,
+                            stage1_every=stage1_every if freeze else None),
                 ea_amoeba=dict(reached=hit is not None,
                                generations=hit[0] if hit else None,
                                gpu_seconds=hit[1] if hit else None,
