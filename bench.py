@@ -363,7 +363,7 @@ def subset_batch(sblm, torch, lcs, idx):
 
 def adaptive_run(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, proposals, stage1_gen=400,
                  pop2=1024, every=100, max_gen2=1000, red_thr=1.05, target=0.9, seed=7,
-                 passes=3, freeze=True, stage1_every=None):
+                 passes=3, freeze=True, stage1_every=None, freeze_thr=None):
     """The learned form with effort where the fit asks for it.  Stage 1: the
     learned form on every lightcurve for `stage1_gen` generations, then twice
     `passes` simplex passes from each fittest solution.  Lightcurves whose
@@ -383,6 +383,7 @@ def adaptive_run(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, proposals, sta
     checkpoints; else that checkpoint's, as in success_run)."""
     sync = torch.cuda.synchronize
     n_lc = len(chi2_true)
+    fthr = red_thr if freeze_thr is None else freeze_thr  # reduced chi^2 that freezes
     nm_cfg = sblm.nm_default_config()
     cfg = sblm.ea_default_config()
     cfg.pop = pop
@@ -412,7 +413,7 @@ def adaptive_run(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, proposals, sta
             _, cr = simplex_passes(sblm, torch, lcs, lo, hi, x, c, npass, nm_cfg)
         c1[run] = np.minimum(c1[run], cr.cpu().numpy())
         if g1 < stage1_gen:
-            frozen1 = (c1 / dof <= red_thr).astype(np.int32)
+            frozen1 = (c1 / dof <= fthr).astype(np.int32)
             st.freeze(frozen1)
             sync()
             curve.append(dict(gen=g1, stage=1, success=round(float(np.mean(c1 <= chi2_true + 10.0)),
@@ -479,7 +480,7 @@ def adaptive_run(sblm, torch, lcs, chi2_true, pop, sched, lo, hi, proposals, sta
                 hit = (stage1_gen + gens, spent)
                 break
             if freeze:
-                frozen = (best[idx] / dof[idx] <= red_thr).astype(np.int32)
+                frozen = (best[idx] / dof[idx] <= fthr).astype(np.int32)
                 if frozen.all():
                     break
                 st2.freeze(frozen)
