@@ -294,6 +294,7 @@ int ea_fit(ea_state* st, int32_t n_gen, sblm_stats* stats, void* stream);
  * caller that has settled some fits and keeps evolving the rest; the paper's
  * loop of App. A runs per lightcurve, so the others are unaffected).
  *   mask  HOST int32[n_lc]: nonzero freezes lightcurve k, 0 lets it run
+ *   n_lc  the mask's length, which must be the state's lightcurve count
  * A frozen lightcurve's population, records and generation counter stay as
  * they are: later generations skip its selection, offspring and migration,
  * and its fitness evaluations treat it as empty (its per-row chi2, Fs, Fb in
@@ -301,9 +302,10 @@ int ea_fit(ea_state* st, int32_t n_gen, sblm_stats* stats, void* stream);
  * records).  Every other lightcurve evolves bit for bit as without the
  * freeze.  Copies the mask in order on `stream` and synchronises `stream`;
  * the mask is not part of ea_save's snapshot (ea_load leaves it as it is).
- * Errors: SBLM_ESTATE (null state), SBLM_EINVAL (null mask), SBLM_EDEVICE.
+ * Errors: SBLM_ESTATE (null state), SBLM_EINVAL (null mask or another
+ * length), SBLM_EDEVICE.
  */
-int ea_freeze(ea_state* st, const int32_t* mask, void* stream);
+int ea_freeze(ea_state* st, const int32_t* mask, int32_t n_lc, void* stream);
 
 /*
  * ea_time_fitness -- instrumentation, not part of the method: with enable =

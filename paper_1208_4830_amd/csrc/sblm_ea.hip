@@ -955,10 +955,13 @@ extern "C" int ea_seed(ea_state* st, const float* out, int32_t ld_out, int32_t n
   return SBLM_OK;
 }
 
-extern "C" int ea_freeze(ea_state* st, const int32_t* mask, void* stream) {
+extern "C" int ea_freeze(ea_state* st, const int32_t* mask, int32_t n_lc, void* stream) {
   if (!st) return set_error(SBLM_ESTATE, "ea_freeze: null state");
   if (!mask) return set_error(SBLM_EINVAL, "ea_freeze: null mask");
   EaStateImpl& s = st->impl;
+  if (n_lc != s.n_phys)
+    return set_error(SBLM_EINVAL, "ea_freeze: mask of %d entries for %d lightcurves", n_lc,
+                     s.n_phys);
   const hipStream_t q = (hipStream_t)stream;
   int rc = check_hip(hipMemcpyAsync(s.frozen, mask, (size_t)s.n_phys * sizeof(int32_t),
                                     hipMemcpyHostToDevice, q),

@@ -128,7 +128,8 @@ _SIGS = {
                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                     ctypes.POINTER(nm_config)] + [ctypes.c_void_p] * 7,
     "ea_best": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
-    "ea_freeze": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p],
+    "ea_freeze": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                  ctypes.c_void_p],
     "ea_records": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "ea_refine": [ctypes.c_void_p, ctypes.POINTER(nm_config), ctypes.c_void_p, ctypes.c_void_p,
                   ctypes.c_void_p],
@@ -400,10 +401,8 @@ class EAState:
         n_lc host ints."""
         import numpy as np
         m = np.ascontiguousarray(np.asarray(mask, dtype=np.int32).reshape(-1))
-        if m.size != self.lcs.n_lc:
-            raise SblmError(f"freeze: mask of {m.size} entries for {self.lcs.n_lc} lightcurves")
         _check(load().ea_freeze(self.h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                _stream(stream)))
+                                m.size, _stream(stream)))
 
     def best(self, stream=None):
         """(x [6][n_lc] encoded, chi2 [n_lc]) of every lightcurve's record."""

@@ -205,6 +205,8 @@ def test_freeze_skips_only_the_frozen_lightcurves(hip, n_isl):
     pb4, qb4 = part(Pb2, rb2, 4)
     p64, q64 = part(P6, r6, 4)
     assert np.array_equal(pb4, p64) and qb4 == q64
+    with pytest.raises(hip.SblmError):  # a mask of another length
+        b.freeze([0, 1])
 
 
 @pytest.mark.parametrize("mode", [0, 1])

@@ -88,7 +88,7 @@ def test_ea_domain_and_state_errors():
                  lambda: lib.ea_migrate(None, None, None, None, None),
                  lambda: lib.ea_refine(None, None, None, None, None),
                  lambda: lib.ea_autotune_cached(None, b"/tmp/x", None, None, 0, None),
-                 lambda: lib.ea_freeze(None, None, None)):
+                 lambda: lib.ea_freeze(None, None, 0, None)):
         assert call() == ESTATE
 
 
