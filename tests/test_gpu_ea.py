@@ -207,6 +207,11 @@ def test_freeze_skips_only_the_frozen_lightcurves(hip, n_isl):
     assert np.array_equal(pb4, p64) and qb4 == q64
     with pytest.raises(hip.SblmError):  # a mask of another length
         b.freeze([0, 1])
+    # everything frozen: generations change nothing
+    b.freeze([1] * n)
+    before = b.save()
+    b.fit(3)
+    assert b.save() == before
 
 
 @pytest.mark.parametrize("mode", [0, 1])
