@@ -969,9 +969,6 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
   // not depend on it.
   int64_t spec_max = 256;
   if (const char* env = getenv("SBLM_NM_SPEC_MAX")) spec_max = atoll(env);
-  int want_log2 = 19;
-  if (const char* env = getenv("SBLM_NM_WANT_LOG2")) want_log2 = atoi(env);
-  if (want_log2 < 10 || want_log2 > 30) want_log2 = 19;
   // rounds per run: 2 for the initial simplex, at most 2 per step, 2 more per
   // shrink (one slot may run every start of its lightcurve)
   const int64_t max_rounds =
@@ -982,7 +979,7 @@ int nm_run(const sblm_lcs& lcs, int32_t reps, const double* lo, const double* sp
     w.spec = (int64_t)active <= spec_max ? 1 : 0;
     if (!fixed_g) {
       // trial points of a round: four per simplex, or about one
-      const int64_t want = (int64_t)1 << want_log2;
+      const int64_t want = (int64_t)1 << 19;
       const int64_t tp = (int64_t)active * (w.spec ? NS : 1);
       set_lanes(tp * 64 >= want ? 64 : tp * 128 >= want ? 128 : 256);
     }
