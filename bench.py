@@ -169,9 +169,10 @@ def make_batch(sblm, torch, wl):
 
 
 def run_form(sblm, torch, lcs, wl, chi2_true, pop, steps, args, mode, tune=True):
-    """A full fit of `steps` generations, timed: wall time of the replayed
-    graphs, and the fitness kernel's own duration in every one of them
-    (device clock stamped by graph nodes just before and after it)."""
+    """A fit of `args.warmup` untimed generations, then `steps` timed ones:
+    wall time of the replayed graphs, and the fitness kernel's own duration
+    in every one of them (device clock stamped by graph nodes just before
+    and after it)."""
     n_lc = wl.n_lc
     mags_per_gen = pop * int(wl.off[-1])
     cfg = sblm.ea_default_config()
@@ -190,13 +191,18 @@ def run_form(sblm, torch, lcs, wl, chi2_true, pop, steps, args, mode, tune=True)
     sched = scratch.schedule()
     scratch.close()
 
-    # the timed fit: fresh state with the chosen schedule, `steps`
-    # generations, fitness counters and kernel stamps on
+    # the timed fit: fresh state with the chosen schedule, fitness counters
+    # and kernel stamps on; its first `warmup` generations untimed (the
+    # stamps' sums and the counters cleared after them), then `steps` timed
     state = sblm.EAState(cfg, lcs, 1)
     state.set_schedule(*sched)
     state.time_fitness(True)
     st = sblm.new_stats()
     state.fit(0, stats=st)  # capture the graph with the counters bound
+    if args.warmup > 0:
+        state.fit(args.warmup, stats=st)
+        state.time_fitness(True)
+        st.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     state.fit(steps, stats=st)
@@ -239,7 +245,7 @@ def run_form(sblm, torch, lcs, wl, chi2_true, pop, steps, args, mode, tune=True)
         mags_per_s=mags_per_gen * steps / dt,
         ms_per_step=ms_step,
         fits_per_hour=n_lc * 3600.0 / (steps * ms_step / 1e3),
-        success=success, generations=steps,
+        success=success, generations=steps, warmup_generations=args.warmup,
         kernel_ms=k_ms, kernel_launches=launches, kernel_ms_final_population=k_ms_final,
         kernel_mags_per_s=mags_per_gen / (k_ms / 1e3),
         sweeps_per_solve=sweeps, fp32_sweeps_per_solve=n32, flop_per_mag=flop,
