@@ -71,7 +71,7 @@ N_GEN_FIT = 500
 # copy kernel of known size (profiles/fitness_kernel_fp64_256lc_1000ep_pop256_
 # traffic.md).  Valid only for the kernel sources it was taken on (the kernel
 # file and the arithmetic it shares).
-FITNESS_TRAFFIC = dict(source_sha256_16="3eb16ce76bfdd35b", bytes_per_launch=13.64e6,
+FITNESS_TRAFFIC = dict(source_sha256_16="3eb16ce76bfdd35b", bytes_per_launch=13.75e6,
                        algorithmic_bytes_per_launch=10.86e6)
 FITNESS_SOURCES = ("sblm_fitness.hip", "sblm_math.h", "sblm_internal.h")
 
